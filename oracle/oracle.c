@@ -1,0 +1,477 @@
+/*
+ * Batched Krylov oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, sequential FP64 implementation of what the fused batched
+ * solver computes, written from the paper (Nguyen, Nayak, Anzt, "Porting
+ * Batched Iterative Solvers onto Intel GPUs with SYCL", SC-W 2023) and the
+ * textbook methods it composes (Saad 2003; van der Vorst 1992).  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never does.  It shares no code with the HIP library.
+ *
+ * Rules kept on purpose so a reader can check it by eye:
+ *   - every sum is a left-to-right loop in storage order, no blocking;
+ *   - built with -ffp-contract=off: products are rounded before they are added;
+ *   - one system at a time; OpenMP only distributes whole systems.
+ *
+ * Readings of the paper used here (it is silent on them):
+ *   - stop test: ||r||_2 <= tol * ||b||_2 on the recurrence residual, then a
+ *     confirmation on the true residual b - A x; if that fails and iterations
+ *     remain, the method restarts from the true residual;
+ *   - BiCGSTAB and GMRES are right-preconditioned, so the monitored residual is
+ *     the unpreconditioned one; CG follows Sec. 3.5, Alg. 1, step for step;
+ *   - a BiCGSTAB half step that already meets the test counts as a full
+ *     iteration; GMRES counts Arnoldi steps across restarts;
+ *   - breakdown means an exact zero of the quantity that is divided by;
+ *   - scalar Jacobi uses 1 where the diagonal entry is zero or not stored;
+ *   - ||b|| = 0 returns x = 0 with zero iterations, converged.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_CSR = 0, OR_ELL = 1 };
+enum { OR_CG = 0, OR_BICGSTAB = 1, OR_GMRES = 2 };
+enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1 };
+enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_BREAKDOWN = 2, OR_NONFINITE = 3 };
+
+/* One system's matrix: the shared pattern plus this system's values.
+ * BatchCsr (Sec. 3.1): row_ptr[n+1], col[nnz], val[nnz].
+ * BatchEll (Sec. 3.1): ecol[W][n] slot-major ("column-major" in the paper),
+ * padding marked by column -1, val[W][n] in the same layout.              */
+typedef struct {
+    int fmt, n, width;
+    const int *row_ptr, *col, *ecol;
+    const double *val;
+} or_mat;
+
+/* y = A x, each row summed in storage order. */
+static void spmv(const or_mat *A, const double *x, double *y)
+{
+    int n = A->n;
+    if (A->fmt == OR_CSR) {
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                acc += A->val[k] * x[A->col[k]];
+            y[i] = acc;
+        }
+    } else {
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int s = 0; s < A->width; ++s) {
+                int c = A->ecol[(size_t)s * n + i];
+                if (c >= 0) acc += A->val[(size_t)s * n + i] * x[c];
+            }
+            y[i] = acc;
+        }
+    }
+}
+
+static double dot(int n, const double *a, const double *b)
+{
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += a[i] * b[i];
+    return acc;
+}
+
+static double nrm2(int n, const double *a) { return sqrt(dot(n, a, a)); }
+
+/* Scalar Jacobi (Tab. 2): d_i = 1 / a_ii, or 1 if a_ii is zero or absent. */
+static void jacobi_diag(const or_mat *A, int precond, double *d)
+{
+    int n = A->n;
+    for (int i = 0; i < n; ++i) d[i] = 1.0;
+    if (precond != OR_PREC_JACOBI) return;
+    for (int i = 0; i < n; ++i) {
+        double a = 0.0;
+        int found = 0;
+        if (A->fmt == OR_CSR) {
+            for (int k = A->row_ptr[i]; k < A->row_ptr[i + 1] && !found; ++k)
+                if (A->col[k] == i) { a = A->val[k]; found = 1; }
+        } else {
+            for (int s = 0; s < A->width && !found; ++s)
+                if (A->ecol[(size_t)s * n + i] == i) { a = A->val[(size_t)s * n + i]; found = 1; }
+        }
+        if (found && a != 0.0) d[i] = 1.0 / a;
+    }
+}
+
+/* r = b - A x, returns ||r||_2; t is scratch. */
+static double true_residual(const or_mat *A, const double *b, const double *x,
+                            double *r, double *t)
+{
+    spmv(A, x, t);
+    for (int i = 0; i < A->n; ++i) r[i] = b[i] - t[i];
+    return nrm2(A->n, r);
+}
+
+typedef struct { int iters, status; double resid; } or_result;
+
+/* Common exit: report the true relative residual of the returned x. */
+static or_result finish(const or_mat *A, const double *b, const double *x, double bn,
+                        int k, int status, double *r, double *t)
+{
+    or_result res;
+    res.iters = k;
+    res.status = status;
+    res.resid = true_residual(A, b, x, r, t) / bn;
+    return res;
+}
+
+/* ---- CG: Sec. 3.5, Alg. 1, with the relative-residual stop test -------- */
+static or_result solve_cg(const or_mat *A, const double *d, const double *b, double *x,
+                          double bn, double tol, int max_iter, double *ws)
+{
+    int n = A->n, k = 0, r_true;
+    double *r = ws, *z = ws + n, *p = ws + 2 * n, *t = ws + 3 * n;
+    double rho, rn, lim = tol * bn;
+
+    rn = true_residual(A, b, x, r, t);
+    r_true = 1;
+restart:
+    for (int i = 0; i < n; ++i) z[i] = d[i] * r[i];
+    for (int i = 0; i < n; ++i) p[i] = z[i];
+    rho = dot(n, r, z);
+    for (;;) {
+        if (!isfinite(rn) || !isfinite(rho)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (rn <= lim) {
+            if (r_true) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            rn = true_residual(A, b, x, r, t);
+            r_true = 1;
+            if (rn <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+            goto restart;
+        }
+        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+        if (rho == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        spmv(A, p, t);                                   /* t = A p          */
+        double pt = dot(n, p, t);
+        if (!isfinite(pt)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (pt == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        double alpha = rho / pt;                         /* alpha = rho/(p.t) */
+        for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * t[i];
+        r_true = 0;
+        for (int i = 0; i < n; ++i) z[i] = d[i] * r[i]; /* z = precond(r)   */
+        double rho_new = dot(n, r, z);
+        rn = nrm2(n, r);
+        double beta = rho_new / rho;
+        for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+        k += 1;
+    }
+}
+
+/* ---- BiCGSTAB, right-preconditioned (van der Vorst 1992) --------------- */
+static or_result solve_bicgstab(const or_mat *A, const double *d, const double *b, double *x,
+                                double bn, double tol, int max_iter, double *ws)
+{
+    int n = A->n, k = 0, r_true;
+    double *r = ws, *rh = ws + n, *p = ws + 2 * n, *v = ws + 3 * n;
+    double *ph = ws + 4 * n, *s = ws + 5 * n, *sh = ws + 6 * n, *t = ws + 7 * n;
+    double rho0, alpha, omega, rn, lim = tol * bn;
+
+    rn = true_residual(A, b, x, r, t);
+    r_true = 1;
+restart:
+    for (int i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+    rho0 = alpha = omega = 1.0;
+    for (;;) {
+        if (!isfinite(rn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (rn <= lim) {
+            if (r_true) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            rn = true_residual(A, b, x, r, t);
+            r_true = 1;
+            if (rn <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+            goto restart;
+        }
+        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+        k += 1;
+        double rho = dot(n, rh, r);
+        if (!isfinite(rho)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (rho == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        double beta = (rho / rho0) * (alpha / omega);
+        for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        for (int i = 0; i < n; ++i) ph[i] = d[i] * p[i];
+        spmv(A, ph, v);                                  /* v = A M p        */
+        double sigma = dot(n, rh, v);
+        if (!isfinite(sigma)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (sigma == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        alpha = rho / sigma;
+        for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        double sn = nrm2(n, s);
+        if (!isfinite(sn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (sn <= lim) {                                 /* half-step exit   */
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
+            for (int i = 0; i < n; ++i) r[i] = s[i];
+            r_true = 0;
+            rn = sn;
+            continue;
+        }
+        for (int i = 0; i < n; ++i) sh[i] = d[i] * s[i];
+        spmv(A, sh, t);                                  /* t = A M s        */
+        double tt = dot(n, t, t), ts = dot(n, t, s);
+        if (!isfinite(tt) || !isfinite(ts)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        omega = (tt == 0.0) ? 0.0 : ts / tt;
+        for (int i = 0; i < n; ++i) x[i] = (x[i] + alpha * ph[i]) + omega * sh[i];
+        for (int i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+        r_true = 0;
+        rho0 = rho;
+        rn = nrm2(n, r);
+        if (omega == 0.0 && !(rn <= lim)) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+    }
+}
+
+/* ---- GMRES(m), right-preconditioned, modified Gram-Schmidt Arnoldi and
+ *      Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning) -- */
+static or_result solve_gmres(const or_mat *A, const double *d, const double *b, double *x,
+                             double bn, double tol, int max_iter, int m, double *ws)
+{
+    int n = A->n, k = 0;
+    double *r = ws, *t = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    double *V = ws + 4 * n;                          /* (m+1) x n            */
+    double *H = V + (size_t)(m + 1) * n;             /* (m+1) x m, H[i*m+j]  */
+    double *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *y = g + m + 1;
+    double lim = tol * bn;
+
+    for (;;) {
+        double beta = true_residual(A, b, x, r, t);
+        if (!isfinite(beta)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (beta <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+        for (int i = 0; i < n; ++i) V[i] = r[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int jend = -1;
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * n;
+            for (int i = 0; i < n; ++i) z[i] = d[i] * vj[i];
+            spmv(A, z, w);                               /* w = A M v_j      */
+            for (int i = 0; i <= j; ++i) {               /* MGS              */
+                double *vi = V + (size_t)i * n;
+                double h = dot(n, w, vi);
+                H[(size_t)i * m + j] = h;
+                for (int l = 0; l < n; ++l) w[l] = w[l] - h * vi[l];
+            }
+            double hn = nrm2(n, w);
+            H[(size_t)(j + 1) * m + j] = hn;
+            k += 1;
+            if (!isfinite(hn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+            for (int i = 0; i < j; ++i) {                /* old rotations    */
+                double h0 = H[(size_t)i * m + j], h1 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * h0 + sn[i] * h1;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
+            }
+            double hjj = H[(size_t)j * m + j];
+            double dd = sqrt(hjj * hjj + hn * hn);
+            if (dd == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+            cs[j] = hjj / dd;
+            sn[j] = hn / dd;
+            H[(size_t)j * m + j] = dd;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            jend = j;
+            if (fabs(g[j + 1]) <= lim || hn == 0.0 || k >= max_iter) break;
+            double *vn = V + (size_t)(j + 1) * n;
+            for (int i = 0; i < n; ++i) vn[i] = w[i] / hn;
+        }
+        for (int i = jend; i >= 0; --i) {                /* back substitution */
+            double acc = g[i];
+            for (int l = i + 1; l <= jend; ++l) acc = acc - H[(size_t)i * m + l] * y[l];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < n; ++i) z[i] = 0.0;
+        for (int j = 0; j <= jend; ++j) {
+            double *vj = V + (size_t)j * n;
+            for (int i = 0; i < n; ++i) z[i] = z[i] + y[j] * vj[i];
+        }
+        for (int i = 0; i < n; ++i) x[i] = x[i] + d[i] * z[i];
+    }
+}
+
+static size_t workspace_doubles(int solver, int n, int m)
+{
+    if (solver == OR_CG) return (size_t)4 * n + n;
+    if (solver == OR_BICGSTAB) return (size_t)8 * n + n;
+    return (size_t)4 * n + (size_t)(m + 1) * n + (size_t)(m + 1) * m + 4 * (size_t)m + 2 + n;
+}
+
+static or_result solve_one(const or_mat *A, int solver, int precond, const double *b,
+                           double *x, double tol, int max_iter, int m, double *ws)
+{
+    int n = A->n;
+    double *d = ws;                         /* the first n doubles hold d */
+    double *work = ws + n;
+    or_result res;
+    double bn = nrm2(n, b);
+    if (!isfinite(bn)) {
+        res.iters = 0; res.status = OR_NONFINITE; res.resid = bn;
+        return res;
+    }
+    if (bn == 0.0) {                        /* b = 0: x = 0 solves it exactly */
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        res.iters = 0; res.status = OR_CONVERGED; res.resid = 0.0;
+        return res;
+    }
+    jacobi_diag(A, precond, d);
+    if (solver == OR_CG) return solve_cg(A, d, b, x, bn, tol, max_iter, work);
+    if (solver == OR_BICGSTAB) return solve_bicgstab(A, d, b, x, bn, tol, max_iter, work);
+    return solve_gmres(A, d, b, x, bn, tol, max_iter, m, work);
+}
+
+static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *col,
+                     int width, const int *ecol, const double *val)
+{
+    A->fmt = fmt; A->n = n; A->width = width;
+    A->row_ptr = row_ptr; A->col = col; A->ecol = ecol; A->val = val;
+}
+
+/* ------------------------------- exports -------------------------------- */
+
+/* Solve every system of the batch; x holds x0 on entry and the result on exit.
+ * values: CSR [n_batch][nnz], ELL [n_batch][width][n].  Returns 0. */
+int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                   int nnz, int width, const int *ell_col, const double *values,
+                   const double *b, double *x, int solver, int precond, double tol,
+                   int max_iter, int restart, int *iters, double *resid, int *status,
+                   int nthreads)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    int m = restart > 0 ? restart : 30;
+    size_t wsz = workspace_doubles(solver, n, m) + n;
+    if (nthreads < 1) nthreads = 1;
+    #pragma omp parallel num_threads(nthreads)
+    {
+        double *ws = (double *)malloc(wsz * sizeof(double));
+        #pragma omp for schedule(dynamic, 8)
+        for (int64_t s = 0; s < n_batch; ++s) {
+            or_mat A;
+            make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+            or_result res = solve_one(&A, solver, precond, b + (size_t)s * n, x + (size_t)s * n,
+                                      tol, max_iter, m, ws);
+            iters[s] = res.iters;
+            status[s] = res.status;
+            resid[s] = res.resid;
+        }
+        free(ws);
+    }
+    return 0;
+}
+
+/* y = A x for every system. */
+void or_batch_spmv(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                   int nnz, int width, const int *ell_col, const double *values,
+                   const double *x, double *y)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    for (int64_t s = 0; s < n_batch; ++s) {
+        or_mat A;
+        make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+        spmv(&A, x + (size_t)s * n, y + (size_t)s * n);
+    }
+}
+
+/* ||b - A x|| / ||b|| per system (||b - A x|| when ||b|| = 0). */
+void or_batch_true_residual(int fmt, int64_t n_batch, int n, const int *row_ptr,
+                            const int *col_idx, int nnz, int width, const int *ell_col,
+                            const double *values, const double *b, const double *x,
+                            double *out, int nthreads)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    if (nthreads < 1) nthreads = 1;
+    #pragma omp parallel num_threads(nthreads)
+    {
+        double *r = (double *)malloc(2 * (size_t)n * sizeof(double));
+        #pragma omp for schedule(static)
+        for (int64_t s = 0; s < n_batch; ++s) {
+            or_mat A;
+            make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+            double rn = true_residual(&A, b + (size_t)s * n, x + (size_t)s * n, r, r + n);
+            double bn = nrm2(n, b + (size_t)s * n);
+            out[s] = bn == 0.0 ? rn : rn / bn;
+        }
+        free(r);
+    }
+}
+
+/* Jacobi diagonal d_i per system (for pinning the preconditioner). */
+void or_batch_jacobi(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                     int nnz, int width, const int *ell_col, const double *values, double *d)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    for (int64_t s = 0; s < n_batch; ++s) {
+        or_mat A;
+        make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+        jacobi_diag(&A, OR_PREC_JACOBI, d + (size_t)s * n);
+    }
+}
+
+double or_dot(int n, const double *a, const double *b) { return dot(n, a, b); }
+
+/* BatchEll from BatchCsr (Sec. 3.1): width = longest row; slot s of row i is
+ * the s-th stored entry of that row in CSR order, -1 where the row is short.
+ * Call with ell_col = NULL to query the width only.  Returns the width. */
+int or_csr_to_ell(int n, const int *row_ptr, const int *col_idx, int *ell_col)
+{
+    int width = 0;
+    for (int i = 0; i < n; ++i)
+        if (row_ptr[i + 1] - row_ptr[i] > width) width = row_ptr[i + 1] - row_ptr[i];
+    if (!ell_col) return width;
+    for (int s = 0; s < width; ++s)
+        for (int i = 0; i < n; ++i) {
+            int k = row_ptr[i] + s;
+            ell_col[(size_t)s * n + i] = k < row_ptr[i + 1] ? col_idx[k] : -1;
+        }
+    return width;
+}
+
+/* Values of every system moved from CSR order to the ELL slot layout
+ * (padding slots set to 0). */
+void or_csr_values_to_ell(int64_t n_batch, int n, const int *row_ptr, int nnz, int width,
+                          const double *csr_vals, double *ell_vals)
+{
+    for (int64_t s = 0; s < n_batch; ++s) {
+        const double *src = csr_vals + (size_t)s * nnz;
+        double *dst = ell_vals + (size_t)s * width * n;
+        for (int sl = 0; sl < width; ++sl)
+            for (int i = 0; i < n; ++i) {
+                int k = row_ptr[i] + sl;
+                dst[(size_t)sl * n + i] = k < row_ptr[i + 1] ? src[k] : 0.0;
+            }
+    }
+}
+
+/* Dense LU with partial pivoting: A (row-major n x n) is overwritten by its
+ * factors, b by the solution.  Returns 0, or 1 if a zero pivot is met. */
+int or_dense_solve(int n, double *A, double *b)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (fabs(A[(size_t)i * n + c]) > fabs(A[(size_t)piv * n + c])) piv = i;
+        if (A[(size_t)piv * n + c] == 0.0) return 1;
+        if (piv != c) {
+            for (int j = 0; j < n; ++j) {
+                double tmp = A[(size_t)c * n + j];
+                A[(size_t)c * n + j] = A[(size_t)piv * n + j];
+                A[(size_t)piv * n + j] = tmp;
+            }
+            double tb = b[c]; b[c] = b[piv]; b[piv] = tb;
+        }
+        for (int i = c + 1; i < n; ++i) {
+            double l = A[(size_t)i * n + c] / A[(size_t)c * n + c];
+            A[(size_t)i * n + c] = l;
+            for (int j = c + 1; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)c * n + j];
+            b[i] -= l * b[c];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double acc = b[i];
+        for (int j = i + 1; j < n; ++j) acc -= A[(size_t)i * n + j] * b[j];
+        b[i] = acc / A[(size_t)i * n + i];
+    }
+    return 0;
+}

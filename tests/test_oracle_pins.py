@@ -1,0 +1,458 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test fixes the oracle to mathematics or to an independent implementation:
+exact integer arithmetic, closed forms, textbook optimality properties checked
+by brute force on tiny systems, dense LU, and scipy's own CG/BiCGSTAB run for a
+fixed number of iterations.  A dropped term, a wrong sign or a transposed
+operand in any solver step fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_2308_08417_amd import workloads as W
+
+EPS = np.finfo(np.float64).eps
+
+
+def rand_pattern(rng, n, fill, diag=True, empty_rows=()):
+    mask = rng.random((n, n)) < fill
+    if diag:
+        np.fill_diagonal(mask, True)
+    for r in empty_rows:
+        mask[r, :] = False
+    rows, cols = np.nonzero(mask)
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32)
+
+
+def csr_dense(n, rp, ci, vals):
+    A = np.zeros((n, n), dtype=vals.dtype)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A[rows, ci] = vals
+    return A
+
+
+def batch_from_dense(As, bs):
+    """Shared pattern = union of nonzeros (plus diagonal); CSR values per system."""
+    n = As.shape[1]
+    mask = np.any(As != 0, axis=0) | np.eye(n, dtype=bool)
+    rows, cols = np.nonzero(mask)
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    vals = As[:, rows, cols]
+    return O.Pattern(n, rp, cols.astype(np.int32)), np.ascontiguousarray(vals), np.ascontiguousarray(bs)
+
+
+# --------------------------------------------------------------- SpMV / ELL
+@pytest.mark.parametrize("n,fill,empty", [(1, 1.0, ()), (7, 0.4, (3,)), (64, 0.3, ()), (97, 0.1, (0, 96))])
+def test_spmv_integer_exact(n, fill, empty):
+    rng = np.random.default_rng(n)
+    rp, ci = rand_pattern(rng, n, fill, empty_rows=empty)
+    P = O.Pattern(n, rp, ci)
+    B = 5
+    vals = rng.integers(-1024, 1025, size=(B, P.nnz)).astype(np.float64)
+    x = rng.integers(-1024, 1025, size=(B, n)).astype(np.float64)
+    y = O.batch_spmv(P, vals, x)
+    for s in range(B):  # every product and sum is exact in FP64 at these sizes
+        A = csr_dense(n, rp, ci, vals[s].astype(np.int64))
+        assert np.array_equal(y[s], (A @ x[s].astype(np.int64)).astype(np.float64))
+    ev = O.csr_values_to_ell(P, vals)
+    assert np.array_equal(O.batch_spmv(P, ev, x, fmt=O.ELL), y)
+
+
+def test_ell_layout_reconstructs_matrix():
+    rng = np.random.default_rng(3)
+    n = 23
+    rp, ci = rand_pattern(rng, n, 0.3, empty_rows=(5,))
+    P = O.Pattern(n, rp, ci)
+    assert P.width == int(np.diff(rp).max())
+    vals = rng.random((2, P.nnz))
+    ev = O.csr_values_to_ell(P, vals).reshape(2, P.width, n)
+    ec = P.ell_col.reshape(P.width, n)
+    for s in range(2):
+        A = np.zeros((n, n))
+        for sl in range(P.width):
+            for i in range(n):
+                if ec[sl, i] >= 0:
+                    A[i, ec[sl, i]] += ev[s, sl, i]
+                else:
+                    assert ev[s, sl, i] == 0.0
+        assert np.array_equal(A, csr_dense(n, rp, ci, vals[s]))
+    # padding only at the end of each row
+    for i in range(n):
+        col = ec[:, i]
+        k = int(np.sum(col >= 0))
+        assert np.all(col[:k] >= 0) and np.all(col[k:] == -1)
+
+
+def test_storage_formulas(golden_dir):
+    """Sec. 3.1 storage list on the Tab. 3 shapes: CSR stores B*nnz values plus
+    (n+1)+nnz indexes; ELL stores B*W*n values (the padded count) plus W*n indexes."""
+    import json, os
+    g = json.load(open(os.path.join(golden_dir, "tab3_shapes.json")))
+    B = g["batch"]
+    for e in g["inputs"]:
+        n, nnz = e["n"], e["nnz"]
+        rng = np.random.default_rng(0)
+        # a pattern with exactly nnz entries, full diagonal
+        off = rng.permutation(n * n - n)[: nnz - n]
+        mask = np.eye(n, dtype=bool)
+        idx = np.flatnonzero(~np.eye(n, dtype=bool).ravel())[off]
+        mask.ravel()[idx] = True
+        rows, cols = np.nonzero(mask)
+        rp = np.zeros(n + 1, np.int32)
+        np.add.at(rp, rows + 1, 1)
+        rp = np.cumsum(rp).astype(np.int32)
+        P = O.Pattern(n, rp, cols.astype(np.int32))
+        assert P.nnz == nnz
+        csr_vals, csr_idx = B * nnz, (n + 1) + nnz
+        ell_vals, ell_idx = B * P.width * n, P.width * n
+        assert csr_vals == B * e["nnz"] and csr_idx == n + 1 + e["nnz"]
+        assert ell_vals >= csr_vals and ell_idx == P.ell_col.size
+
+
+# --------------------------------------------------------------- dot / Jacobi
+def test_dot_against_fsum():
+    rng = np.random.default_rng(1)
+    for n in (1, 10, 1000):
+        a, b = rng.standard_normal(n), rng.standard_normal(n)
+        exact = math.fsum(a * b)  # products of doubles are exact in fsum's sense only up to rounding
+        ref = math.fsum([float(x) * float(y) for x, y in zip(a, b)])
+        bound = n * EPS * float(np.sum(np.abs(a * b))) + 1e-300
+        assert abs(O.dot(a, b) - ref) <= bound
+        assert abs(exact - ref) <= bound
+    ai = rng.integers(-2**20, 2**20, 500).astype(np.float64)
+    bi = rng.integers(-2**20, 2**20, 500).astype(np.float64)
+    assert O.dot(ai, bi) == float(np.dot(ai.astype(np.int64), bi.astype(np.int64)))
+
+
+def test_jacobi_closed_form():
+    n = 6
+    rp = np.array([0, 2, 3, 4, 5, 6, 7], np.int32)
+    ci = np.array([0, 1, 2, 3, 4, 0, 5], np.int32)  # row 1: no diagonal stored; row 5 has col 0
+    P = O.Pattern(n, rp, ci)
+    vals = np.array([[4.0, 1.0, 3.0, 0.0, -8.0, 2.0, 0.5]])
+    d = O.jacobi(P, vals)[0]
+    # row0 a=4, row1 absent->1, row2 col2? row 2 stores col 3 -> absent -> 1
+    assert d[0] == 0.25 and d[1] == 1.0
+    assert d[2] == 1.0 and d[3] == 1.0 and d[4] == 1.0  # rows 2..4 store off-diagonals only
+    assert d[5] == 2.0
+    ev = O.csr_values_to_ell(P, vals)
+    assert np.array_equal(O.jacobi(P, ev, fmt=O.ELL), O.jacobi(P, vals))
+
+
+# --------------------------------------------------------------- dense LU
+def test_dense_lu_matches_lapack():
+    rng = np.random.default_rng(2)
+    for n in (1, 2, 5, 33):
+        A = rng.standard_normal((n, n)) + n * np.eye(n) * 0.1
+        A[0, 0] = 0.0 if n > 1 else 1.0  # forces a row swap
+        b = rng.standard_normal(n)
+        x = O.dense_solve(A, b)
+        xr = scipy.linalg.solve(A, b)
+        k = np.linalg.cond(A)
+        assert np.linalg.norm(x - xr) <= 1e3 * k * EPS * np.linalg.norm(xr)
+    with pytest.raises(np.linalg.LinAlgError):
+        O.dense_solve(np.zeros((3, 3)), np.ones(3))
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_diagonal_system_one_iteration(solver):
+    """With scalar Jacobi a diagonal A gives M A = I: one iteration, x = b / a."""
+    rng = np.random.default_rng(4)
+    n, B = 9, 4
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    P = O.Pattern(n, rp, ci)
+    vals = 1.0 + 9.0 * rng.random((B, n))
+    b = rng.standard_normal((B, n))
+    x, it, res, st = O.batch_solve(P, vals, b, solver=solver)
+    assert np.all(st == O.CONVERGED) and np.all(it == 1)
+    assert np.allclose(x, b / vals, rtol=4 * EPS, atol=0)
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_one_by_one(solver):
+    P = O.Pattern(1, np.array([0, 1], np.int32), np.array([0], np.int32))
+    vals = np.array([[3.0], [-0.5], [7.25]])
+    b = np.array([[1.0], [2.0], [-3.0]])
+    for prec in (O.PREC_NONE, O.PREC_JACOBI):
+        x, it, res, st = O.batch_solve(P, vals, b, solver=solver, precond=prec)
+        assert np.all(it == 1) and np.all(st == O.CONVERGED)
+        assert np.allclose(x, b / vals, rtol=2 * EPS, atol=0)
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_distinct_eigenvalues_bound(solver):
+    """Without preconditioning, Krylov methods on a diagonalisable A with k distinct
+    eigenvalues terminate within k steps (exact arithmetic; k steps + rounding here)."""
+    n = 40
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    P = O.Pattern(n, rp, ci)
+    rng = np.random.default_rng(5)
+    for k, eig in ((2, [1.0, 2.0]), (3, [1.0, 2.5, 4.0])):
+        vals = np.asarray([eig[i % k] for i in range(n)])[None, :]
+        b = rng.standard_normal((1, n))
+        x, it, res, st = O.batch_solve(P, vals, b, solver=solver, precond=O.PREC_NONE)
+        assert st[0] == O.CONVERGED and it[0] <= k
+
+
+def test_cg_laplacian_eigenvector_rhs():
+    """1D Laplacian tridiag(-1,2,-1): eigenvectors sin(j pi i/(n+1)).  A right-hand
+    side in the span of 3 eigenvectors makes CG terminate within 3 iterations."""
+    n = 31
+    rp, ci, vals = [0], [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+                vals.append(2.0 if i == j else -1.0)
+        rp.append(len(ci))
+    P = O.Pattern(n, np.array(rp, np.int32), np.array(ci, np.int32))
+    i = np.arange(1, n + 1)
+    b = sum(c * np.sin(j * np.pi * i / (n + 1)) for c, j in ((1.0, 1), (0.5, 7), (-2.0, 20)))
+    x, it, res, st = O.batch_solve(P, np.array([vals]), b[None, :], solver=O.CG,
+                                   precond=O.PREC_NONE)
+    assert st[0] == O.CONVERGED and it[0] <= 3
+    lam = lambda j: 2 - 2 * np.cos(j * np.pi / (n + 1))
+    xe = sum(c / lam(j) * np.sin(j * np.pi * i / (n + 1)) for c, j in ((1.0, 1), (0.5, 7), (-2.0, 20)))
+    assert np.linalg.norm(x[0] - xe) <= 1e-9 * np.linalg.norm(xe)
+
+
+def test_identity_one_half_step():
+    n = 17
+    rp = np.arange(n + 1, dtype=np.int32)
+    P = O.Pattern(n, rp, rp[:-1].copy())
+    b = np.random.default_rng(6).standard_normal((2, n))
+    x, it, res, st = O.batch_solve(P, np.ones((2, n)), b, solver=O.BICGSTAB,
+                                   precond=O.PREC_NONE)
+    assert np.all(it == 1) and np.array_equal(x, b)
+
+
+# --------------------------------------------------------------- brute force
+def tiny_spd(rng, n):
+    Q = rng.standard_normal((n, n))
+    return Q @ Q.T + n * np.eye(n)
+
+
+def tiny_nonsym(rng, n):
+    return rng.standard_normal((n, n)) + 2.5 * np.sqrt(n) * np.eye(n)
+
+
+def krylov(Mop, v, k):
+    """Orthonormal basis of span{v, Mop v, ..., Mop^(k-1) v} (Gram-Schmidt, twice).
+
+    Same space as the power basis, without its ill-conditioning."""
+    Q = [v / np.linalg.norm(v)]
+    for _ in range(k - 1):
+        w = Mop(Q[-1])
+        for _ in range(2):
+            for q in Q:
+                w = w - (q @ w) * q
+        Q.append(w / np.linalg.norm(w))
+    return np.stack(Q, axis=1)
+
+
+@pytest.mark.parametrize("prec", [O.PREC_NONE, O.PREC_JACOBI])
+def test_cg_is_energy_minimiser(prec):
+    """PCG iterate x_k minimises ||x - x*||_A over x0 + K_k(M A, M r0)."""
+    rng = np.random.default_rng(7)
+    n = 8
+    A = tiny_spd(rng, n)
+    A[np.abs(A) < 0.3] = 0.0  # some sparsity, still SPD (diagonal dominant part)
+    A = (A + A.T) / 2 + n * np.eye(n)
+    b = rng.standard_normal(n)
+    x0 = rng.standard_normal(n) * 0.1
+    P, vals, bb = batch_from_dense(A[None], b[None])
+    M = np.diag(1 / np.diag(A)) if prec == O.PREC_JACOBI else np.eye(n)
+    xs = np.linalg.solve(A, b)
+    r0 = b - A @ x0
+    for k in range(1, n):
+        x, it, res, st = O.batch_solve(P, vals, bb, x0=x0[None], solver=O.CG, precond=prec,
+                                       tol=1e-300, max_iter=k)
+        assert it[0] == k and st[0] == O.MAX_ITER
+        K = krylov(lambda v: M @ (A @ v), M @ r0, k)
+        c = np.linalg.solve(K.T @ A @ K, K.T @ r0)
+        xb = x0 + K @ c
+        assert np.linalg.norm(x[0] - xb) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("prec", [O.PREC_NONE, O.PREC_JACOBI])
+def test_gmres_is_residual_minimiser(prec):
+    """GMRES step k (no restart): x_k minimises ||b - A x|| over x0 + M K_k(A M, r0)."""
+    rng = np.random.default_rng(8)
+    n = 7
+    A = tiny_nonsym(rng, n)
+    b = rng.standard_normal(n)
+    P, vals, bb = batch_from_dense(A[None], b[None])
+    M = np.diag(1 / np.diag(A)) if prec == O.PREC_JACOBI else np.eye(n)
+    for k in range(1, n):
+        x, it, res, st = O.batch_solve(P, vals, bb, solver=O.GMRES, precond=prec,
+                                       tol=1e-300, max_iter=k, restart=30)
+        assert it[0] == k
+        K = M @ krylov(lambda v: A @ (M @ v), b, k)
+        c, *_ = np.linalg.lstsq(A @ K, b, rcond=None)
+        xb = K @ c
+        assert np.linalg.norm(x[0] - xb) <= 1e-9 * np.linalg.norm(xb)
+        assert abs(np.linalg.norm(b - A @ x[0]) / np.linalg.norm(b) - res[0]) <= 1e-12
+
+
+def test_gmres_restart_cycles_are_minimisers():
+    """GMRES(m): each cycle minimises over the Krylov space of that cycle's true residual."""
+    rng = np.random.default_rng(9)
+    n, m = 9, 3
+    A = tiny_nonsym(rng, n)
+    b = rng.standard_normal(n)
+    P, vals, bb = batch_from_dense(A[None], b[None])
+    M = np.diag(1 / np.diag(A))
+    xb = np.zeros(n)
+    done = 0
+    for k in (3, 6, 8):
+        steps = k - done
+        r = b - A @ xb
+        K = M @ krylov(lambda v: A @ (M @ v), r, steps)
+        c, *_ = np.linalg.lstsq(A @ K, r, rcond=None)
+        xb = xb + K @ c
+        done = k
+        x, it, res, st = O.batch_solve(P, vals, bb, solver=O.GMRES, precond=O.PREC_JACOBI,
+                                       tol=1e-300, max_iter=k, restart=m)
+        assert it[0] == k
+        assert np.linalg.norm(x[0] - xb) <= 1e-9 * np.linalg.norm(xb)
+
+
+def test_gmres_full_dimension_converges():
+    rng = np.random.default_rng(10)
+    n = 12
+    A = tiny_nonsym(rng, n)
+    b = rng.standard_normal(n)
+    P, vals, bb = batch_from_dense(A[None], b[None])
+    x, it, res, st = O.batch_solve(P, vals, bb, solver=O.GMRES, restart=30)
+    assert st[0] == O.CONVERGED and it[0] <= n
+
+
+# --------------------------------------------------------------- independent implementations
+def test_cg_matches_scipy_fixed_iterations():
+    rng = np.random.default_rng(11)
+    n = 30
+    A = sp.diags([-1.0 * np.ones(n - 1), 2.5 + rng.random(n), -1.0 * np.ones(n - 1)], [-1, 0, 1]).toarray()
+    b = rng.standard_normal(n)
+    P, vals, bb = batch_from_dense(A[None], b[None])
+    Minv = spla.LinearOperator((n, n), matvec=lambda v: v / np.diag(A))
+    for k in (1, 2, 5, 9):
+        xs, _ = spla.cg(A, b, rtol=0.0, atol=0.0, maxiter=k, M=Minv)
+        x, it, *_ = O.batch_solve(P, vals, bb, solver=O.CG, tol=1e-300, max_iter=k)
+        assert it[0] == k
+        assert np.linalg.norm(x[0] - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_bicgstab_matches_scipy_fixed_iterations():
+    b = W.tridiag_stencil(n_batch=3, n=32, seed=1)
+    P = O.Pattern(b.n, b.row_ptr, b.col_idx)
+    for s in range(3):
+        A = O.to_dense(P, b.values[s])
+        Minv = spla.LinearOperator(A.shape, matvec=lambda v, d=np.diag(A): v / d)
+        for k in (1, 2, 4, 7):
+            xs, _ = spla.bicgstab(A, b.b[s], rtol=0.0, atol=0.0, maxiter=k, M=Minv)
+            x, it, *_ = O.batch_solve(P, b.values[s:s + 1], b.b[s:s + 1], solver=O.BICGSTAB,
+                                      tol=1e-300, max_iter=k)
+            assert it[0] == k
+            assert np.linalg.norm(x[0] - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+# --------------------------------------------------------------- final results
+@pytest.mark.parametrize("solver", [O.BICGSTAB, O.GMRES])
+@pytest.mark.parametrize("gen", ["tridiag", "chem", "collision"])
+def test_solution_matches_dense_lu(solver, gen):
+    if gen == "tridiag":
+        bt = W.tridiag_stencil(n_batch=16)
+    elif gen == "chem":
+        bt = W.chem_jacobian(n_batch=16)
+    else:
+        bt = W.collision_stencil(n_batch=3)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    tol = 1e-10
+    x, it, res, st = O.batch_solve(P, bt.values, bt.b, solver=solver, tol=tol, max_iter=1000)
+    assert np.all(st == O.CONVERGED)
+    assert np.all(res <= tol)
+    for s in range(bt.n_batch):
+        A = O.to_dense(P, bt.values[s])
+        xs = O.dense_solve(A, bt.b[s])
+        kappa = np.linalg.cond(A)
+        rr = np.linalg.norm(bt.b[s] - A @ x[s]) / np.linalg.norm(bt.b[s])
+        assert abs(rr - res[s]) <= 1e-13
+        assert np.linalg.norm(x[s] - xs) <= 1.01 * kappa * tol * np.linalg.norm(xs) + 1e-14
+
+
+def test_cg_spd_batch_matches_dense():
+    bt = W.tridiag_stencil(n_batch=8, n=50, seed=3)
+    # symmetrise: use the lower off-diagonal for both sides
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    vals = bt.values.copy()
+    for s in range(8):
+        A = O.to_dense(P, vals[s])
+        A = np.tril(A) + np.tril(A, -1).T
+        vals[s] = A[np.repeat(np.arange(bt.n), np.diff(bt.row_ptr)), bt.col_idx]
+    x, it, res, st = O.batch_solve(P, vals, bt.b, solver=O.CG)
+    assert np.all(st == O.CONVERGED) and np.all(res <= 1e-10)
+    for s in range(8):
+        A = O.to_dense(P, vals[s])
+        xs = np.linalg.solve(A, bt.b[s])
+        assert np.linalg.norm(x[s] - xs) <= 2 * np.linalg.cond(A) * 1e-10 * np.linalg.norm(xs)
+
+
+def test_csr_and_ell_solves_identical():
+    bt = W.chem_jacobian(n_batch=64)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    ev = O.csr_values_to_ell(P, bt.values)
+    for solver in (O.CG, O.BICGSTAB, O.GMRES):
+        a = O.batch_solve(P, bt.values, bt.b, solver=solver)
+        e = O.batch_solve(P, ev, bt.b, fmt=O.ELL, solver=solver)
+        for u, v in zip(a, e):
+            assert np.array_equal(u, v)
+
+
+# --------------------------------------------------------------- status codes
+def small_batch():
+    bt = W.tridiag_stencil(n_batch=4, n=8)
+    return O.Pattern(bt.n, bt.row_ptr, bt.col_idx), bt
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_status_codes(solver):
+    P, bt = small_batch()
+    # b = 0 -> x = 0, converged, 0 iterations
+    x, it, res, st = O.batch_solve(P, bt.values, np.zeros_like(bt.b), x0=np.ones_like(bt.b),
+                                   solver=solver)
+    assert np.all(x == 0) and np.all(it == 0) and np.all(st == O.CONVERGED) and np.all(res == 0)
+    # max_iter = 0 -> MAX_ITER, x untouched
+    x, it, res, st = O.batch_solve(P, bt.values, bt.b, solver=solver, max_iter=0)
+    assert np.all(st == O.MAX_ITER) and np.all(it == 0) and np.all(x == 0)
+    # unreachable tolerance
+    x, it, res, st = O.batch_solve(P, bt.values, bt.b, solver=solver, tol=1e-30, max_iter=25)
+    assert np.all(st == O.MAX_ITER) and np.all(it == 25)
+    # exact initial guess -> 0 iterations
+    xs = np.stack([np.linalg.solve(O.to_dense(P, bt.values[s]), bt.b[s]) for s in range(4)])
+    x, it, res, st = O.batch_solve(P, bt.values, bt.b, x0=xs, solver=solver, tol=1e-8)
+    assert np.all(it == 0) and np.all(st == O.CONVERGED)
+    # NaN in one system only affects that system
+    v = bt.values.copy()
+    v[1, 3] = np.nan
+    x, it, res, st = O.batch_solve(P, v, bt.b, solver=solver)
+    assert st[1] == O.NONFINITE and np.all(st[[0, 2, 3]] == O.CONVERGED)
+    bb = bt.b.copy()
+    bb[2, 0] = np.inf
+    x, it, res, st = O.batch_solve(P, bt.values, bb, solver=solver)
+    assert st[2] == O.NONFINITE and it[2] == 0
+    # zero matrix -> breakdown
+    x, it, res, st = O.batch_solve(P, np.zeros_like(bt.values), bt.b, solver=solver)
+    assert np.all(st == O.BREAKDOWN)
