@@ -1,0 +1,179 @@
+/*
+ * batchsolve -- batched sparse Krylov solvers for AMD Instinct MI355X (gfx950).
+ *
+ * Solves A_i x_i = b_i for very many small sparse systems i that share one
+ * sparsity pattern (paper Sec. 1 and Sec. 3: "batched iterative solvers" with a
+ * shared pattern, each system monitored individually).  One fused kernel runs
+ * the whole solve of every system: SpMV, scalar Jacobi, dot products, vector
+ * updates and the stop test (Sec. 3.2, Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *   - Return value: BS_OK (0) or a negative bs_error code.  A negative code means
+ *     nothing was launched and no output was written.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library never
+ *     frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Solves are
+ *     asynchronous on that stream; results are valid after the stream is
+ *     synchronised.  The library performs no host synchronisation in a solve.
+ *   - Matrix values, right-hand sides and solutions are FP64.  Indexes are int32.
+ */
+#ifndef BATCHSOLVE_H
+#define BATCHSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Matrix formats of Sec. 3.1.  BS_CSR: shared row_ptr[n+1] and col_idx[nnz];
+ * values [n_batch][nnz] in CSR order.  BS_ELL: rows padded to the width W of
+ * the longest row, shared slot-major column array [W][n] (the paper's
+ * "column-major" layout; slot s of row i at s*n + i, padding = -1); values
+ * [n_batch][W][n] in the same layout, padding values ignored. */
+typedef enum { BS_CSR = 0, BS_ELL = 1 } bs_format;
+
+/* Solvers of Tab. 2.  BS_CG follows Sec. 3.5, Alg. 1 (stop test replaced by the
+ * relative residual); BS_BICGSTAB is right-preconditioned BiCGSTAB; BS_GMRES is
+ * right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and Givens
+ * rotations. */
+typedef enum { BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2 } bs_solver;
+
+/* Preconditioners of Tab. 2: none, or scalar Jacobi d_i = 1/a_ii (1 where the
+ * diagonal entry is zero or not stored). */
+typedef enum { BS_PREC_NONE = 0, BS_PREC_JACOBI = 1 } bs_precond;
+
+/* BS_FP64: everything in FP64.  BS_MIXED: iterative refinement whose outer loop
+ * (true residual b - A x, its norm, the update of x) is FP64 and whose inner
+ * Krylov solve (SpMV, Krylov vectors, inner reductions) is FP32. */
+typedef enum { BS_FP64 = 0, BS_MIXED = 1 } bs_precision;
+
+/* Per-system outcome written to status[]. */
+enum {
+  BS_CONVERGED = 0, /* true relative residual <= tol                          */
+  BS_MAX_ITER = 1,  /* iteration budget used up                               */
+  BS_BREAKDOWN = 2, /* an exact zero divisor (rho, sigma, omega, p.Ap, Givens) */
+  BS_NONFINITE = 3  /* a NaN or Inf appeared (input or arithmetic)             */
+};
+
+typedef enum {
+  BS_OK = 0,
+  BS_ERR_INVALID_ARG = -1, /* bad size, tolerance, enum, or NULL pointer          */
+  BS_ERR_PATTERN = -2,     /* malformed pattern (see bs_pattern_create_csr)       */
+  BS_ERR_UNSUPPORTED = -3, /* shape outside the fused kernels' limits             */
+  BS_ERR_HIP = -4,         /* a HIP runtime call failed (message in last error)   */
+  BS_ERR_NO_DEVICE = -5    /* no HIP device is present                            */
+} bs_error;
+
+/* Flags for bs_options.flags. */
+#define BS_FLAG_X0_ZERO 1 /* ignore x on entry and start from x0 = 0 (x is not read) */
+
+/* Largest system the fused kernels take: one row per lane, up to 1024 lanes per
+ * system, and 2 or 4 rows per lane beyond that; longest row held in registers.
+ * GMRES takes one row per lane (up to 1024 rows). */
+#define BS_MAX_ROWS 2048
+#define BS_MAX_ROW_NNZ 64
+#define BS_MAX_RESTART 30
+
+typedef struct bs_pattern_s *bs_pattern;
+
+/* Create a shared pattern from CSR arrays in HOST memory (Sec. 3.1: one copy of
+ * the pattern for the whole batch).  The library validates it once, derives the
+ * ELL slot layout, the diagonal position of every row and the per-wave row
+ * lengths, and uploads them to the current device (it owns that copy).
+ * row_ptr[n_rows+1] must start at 0, be nondecreasing and end at nnz; every
+ * col_idx must lie in [0, n_rows) with no duplicate column within a row.
+ * Errors: BS_ERR_INVALID_ARG (n_rows < 1, nnz < 0, NULL pointer),
+ * BS_ERR_PATTERN (the rules above), BS_ERR_NO_DEVICE / BS_ERR_HIP on upload. */
+int bs_pattern_create_csr(int32_t n_rows, int32_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, bs_pattern *out);
+
+/* Same, from an ELL slot-major column array [ell_width][n_rows] in HOST memory;
+ * padding slots are -1 and must follow a row's stored entries. */
+int bs_pattern_create_ell(int32_t n_rows, int32_t ell_width, const int32_t *ell_col,
+                          bs_pattern *out);
+
+/* Release the pattern's device copy.  NULL is accepted. */
+int bs_pattern_destroy(bs_pattern pattern);
+
+/* Shape of a pattern (any output pointer may be NULL). */
+int bs_pattern_query(bs_pattern pattern, int32_t *n_rows, int32_t *nnz, int32_t *ell_width,
+                     int32_t *max_row_nnz);
+
+/* Copy the ELL slot-major column array [ell_width][n_rows] to HOST memory. */
+int bs_pattern_ell_cols(bs_pattern pattern, int32_t *ell_col_out);
+
+/* Rewrite CSR-ordered values [n_batch][nnz] (device) into the ELL layout
+ * [n_batch][W][n] (device), zeros in padding slots.  Asynchronous on stream. */
+int bs_values_csr_to_ell(bs_pattern pattern, int64_t n_batch, const double *csr_values,
+                         double *ell_values, void *stream);
+
+/* Number of stored values and indexes of a batched matrix (Sec. 3.1 storage
+ * list): CSR n_batch*nnz values + (n_rows+1)+nnz indexes; ELL n_batch*W*n values
+ * + W*n indexes.  Pure host function. */
+int bs_matrix_storage(bs_format fmt, int64_t n_batch, int32_t n_rows, int32_t nnz,
+                      int32_t ell_width, int64_t *value_count, int64_t *index_count);
+
+typedef struct {
+  int32_t restart;      /* GMRES restart length m in [1, 30]; 0 selects 30       */
+  int32_t precision;    /* bs_precision; 0 = BS_FP64                             */
+  double inner_tol;     /* BS_MIXED inner relative tolerance; 0 selects 1e-6     */
+  int32_t flags;        /* BS_FLAG_*                                             */
+  int32_t team;         /* lanes per system (16..1024, power of two); 0 = planner */
+  int32_t rows_per_lane;/* 1, 2 or 4; 0 = planner                                */
+  int32_t *outer_iters; /* BS_MIXED: optional device int32[n_batch] of refinement
+                           steps; NULL = not written                              */
+} bs_options;
+
+/* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch
+ * systems, each by one team of lanes (a sub-wave, a wave or a workgroup).
+ *   fmt, pattern   format of `values` and the shared pattern (its n must equal n_rows)
+ *   values         device, CSR [n_batch][nnz] or ELL [n_batch][W][n_rows]
+ *   b              device [n_batch][n_rows]
+ *   x              device [n_batch][n_rows]; in: initial guess (unless
+ *                  BS_FLAG_X0_ZERO), out: the last iterate
+ *   tol            relative tolerance: stop when ||b - A x||_2 <= tol ||b||_2,
+ *                  confirmed on the true residual; tol > 0 and finite
+ *   max_iter       >= 0; CG/BiCGSTAB iterations, GMRES Arnoldi steps (BS_MIXED:
+ *                  inner iterations summed over refinement steps)
+ *   iters, resid,  device int32/FP64/int32 [n_batch]: iterations, true relative
+ *   status         residual of the returned x (absolute when ||b|| = 0), and the
+ *                  bs status code; status may be NULL
+ *   opts           NULL for defaults
+ * Errors: BS_ERR_INVALID_ARG (n_batch < 0, n_rows mismatch, bad enum, tol <= 0 or
+ * non-finite, max_iter < 0, bad restart/team, NULL required pointer),
+ * BS_ERR_UNSUPPORTED (n_rows > BS_MAX_ROWS, longest row > BS_MAX_ROW_NNZ, or no
+ * kernel shape for the request), BS_ERR_HIP (launch failure).  n_batch = 0 is a
+ * no-op. */
+int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
+                   const double *values, const double *b, double *x, bs_solver solver,
+                   bs_precond precond, double tol, int32_t max_iter, int32_t *iters,
+                   double *resid, int32_t *status, const bs_options *opts, void *stream);
+
+/* The kernel shape bs_batch_solve would use (Sec. 3.6: work-group size from the
+ * row count; Sec. 3.5: what is kept on chip).  Pure host function.
+ *   team           lanes per system;  rows_per_lane  rows held by each lane
+ *   slots          register slots per row (>= longest row)
+ *   group_size     threads per workgroup; systems_per_group
+ *   lds_bytes      dynamic LDS per workgroup
+ *   stage_values   1 if CSR values are staged through LDS for coalesced loads */
+typedef struct {
+  int32_t team, rows_per_lane, slots, group_size, systems_per_group, lds_bytes, stage_values;
+} bs_plan_info;
+
+int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_solver solver,
+            const bs_options *opts, bs_plan_info *out);
+
+/* Text for a bs_error code; never NULL. */
+const char *bs_error_string(int code);
+
+/* Last HIP error text recorded by the library (thread-local); never NULL. */
+const char *bs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BATCHSOLVE_H */

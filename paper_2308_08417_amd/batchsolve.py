@@ -1,0 +1,249 @@
+"""Thin Python binding of the C ABI in ``include/batchsolve.h``.
+
+Each ``bs_*`` function here marshals its arguments (torch device tensors, numpy
+host arrays, the current HIP stream) into the call of the same name in
+``libbatchsolve.so``; every step of the solve runs in the HIP kernels.  There
+is no CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbatchsolve.so")
+
+# enums of batchsolve.h
+CSR, ELL = 0, 1
+CG, BICGSTAB, GMRES = 0, 1, 2
+PREC_NONE, PREC_JACOBI = 0, 1
+FP64, MIXED = 0, 1
+CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+OK, ERR_INVALID_ARG, ERR_PATTERN, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_DEVICE = 0, -1, -2, -3, -4, -5
+FLAG_X0_ZERO = 1
+MAX_ROWS, MAX_ROW_NNZ, MAX_RESTART = 2048, 64, 30
+
+
+class BatchSolveError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = bs_error_string(code)
+        extra = bs_last_error() if code == ERR_HIP else ""
+        super().__init__(f"{where}: {msg} ({code}){' - ' + extra if extra else ''}")
+
+
+class bs_options(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("precision", C.c_int32), ("inner_tol", C.c_double),
+                ("flags", C.c_int32), ("team", C.c_int32), ("rows_per_lane", C.c_int32),
+                ("outer_iters", C.c_void_p)]
+
+
+class bs_plan_info(C.Structure):
+    _fields_ = [("team", C.c_int32), ("rows_per_lane", C.c_int32), ("slots", C.c_int32),
+                ("group_size", C.c_int32), ("systems_per_group", C.c_int32),
+                ("lds_bytes", C.c_int32), ("stage_values", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load ``libbatchsolve.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2308_08417_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.bs_pattern_create_csr.argtypes = [i32, i32, vp, vp, C.POINTER(vp)]
+    L.bs_pattern_create_ell.argtypes = [i32, i32, vp, C.POINTER(vp)]
+    L.bs_pattern_destroy.argtypes = [vp]
+    L.bs_pattern_query.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.bs_pattern_ell_cols.argtypes = [vp, vp]
+    L.bs_values_csr_to_ell.argtypes = [vp, i64, vp, vp, vp]
+    L.bs_matrix_storage.argtypes = [C.c_int, i64, i32, i32, i32, C.POINTER(i64), C.POINTER(i64)]
+    L.bs_batch_solve.argtypes = [C.c_int, i64, i32, vp, vp, vp, vp, C.c_int, C.c_int, dbl, i32,
+                                 vp, vp, vp, C.POINTER(bs_options), vp]
+    L.bs_plan.argtypes = [C.c_int, i32, i32, i32, C.c_int, C.POINTER(bs_options),
+                          C.POINTER(bs_plan_info)]
+    L.bs_error_string.argtypes = [C.c_int]
+    L.bs_error_string.restype = C.c_char_p
+    L.bs_last_error.argtypes = []
+    L.bs_last_error.restype = C.c_char_p
+    for name in ("bs_pattern_create_csr", "bs_pattern_create_ell", "bs_pattern_destroy",
+                 "bs_pattern_query", "bs_pattern_ell_cols", "bs_values_csr_to_ell",
+                 "bs_matrix_storage", "bs_batch_solve", "bs_plan"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise BatchSolveError(code, where)
+
+
+def bs_error_string(code: int) -> str:
+    return lib().bs_error_string(code).decode()
+
+
+def bs_last_error() -> str:
+    return lib().bs_last_error().decode()
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (None stays NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ------------------------------------------------------------------ patterns
+def bs_pattern_create_csr(row_ptr, col_idx) -> int:
+    rp, ci = _host_i32(row_ptr), _host_i32(col_idx)
+    h = C.c_void_p()
+    _check(lib().bs_pattern_create_csr(rp.size - 1, ci.size, rp.ctypes.data,
+                                       ci.ctypes.data if ci.size else None, C.byref(h)),
+           "bs_pattern_create_csr")
+    return h.value
+
+
+def bs_pattern_create_ell(n_rows: int, ell_col) -> int:
+    ec = _host_i32(ell_col)
+    width = ec.size // n_rows
+    h = C.c_void_p()
+    _check(lib().bs_pattern_create_ell(n_rows, width, ec.ctypes.data if ec.size else None,
+                                       C.byref(h)), "bs_pattern_create_ell")
+    return h.value
+
+
+def bs_pattern_destroy(handle: int) -> None:
+    _check(lib().bs_pattern_destroy(handle), "bs_pattern_destroy")
+
+
+def bs_pattern_query(handle: int) -> dict:
+    v = [C.c_int32() for _ in range(4)]
+    _check(lib().bs_pattern_query(handle, *[C.byref(x) for x in v]), "bs_pattern_query")
+    return dict(zip(("n_rows", "nnz", "ell_width", "max_row_nnz"), (x.value for x in v)))
+
+
+def bs_pattern_ell_cols(handle: int) -> np.ndarray:
+    q = bs_pattern_query(handle)
+    out = np.empty(max(q["ell_width"] * q["n_rows"], 1), np.int32)
+    _check(lib().bs_pattern_ell_cols(handle, out.ctypes.data), "bs_pattern_ell_cols")
+    return out[: q["ell_width"] * q["n_rows"]]
+
+
+def bs_values_csr_to_ell(handle: int, csr_values, ell_values, stream=None) -> None:
+    _check(lib().bs_values_csr_to_ell(handle, csr_values.shape[0], _ptr(csr_values),
+                                      _ptr(ell_values), _stream(stream)), "bs_values_csr_to_ell")
+
+
+def bs_matrix_storage(fmt: int, n_batch: int, n_rows: int, nnz: int, ell_width: int):
+    vc, ic = C.c_int64(), C.c_int64()
+    _check(lib().bs_matrix_storage(fmt, n_batch, n_rows, nnz, ell_width, C.byref(vc), C.byref(ic)),
+           "bs_matrix_storage")
+    return vc.value, ic.value
+
+
+def make_options(restart: int = 0, precision: int = FP64, inner_tol: float = 0.0, flags: int = 0,
+                 team: int = 0, rows_per_lane: int = 0, outer_iters=None) -> bs_options:
+    return bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters))
+
+
+def bs_plan(fmt: int, n_rows: int, nnz: int, max_row_nnz: int, solver: int,
+            opts: Optional[bs_options] = None) -> dict:
+    out = bs_plan_info()
+    _check(lib().bs_plan(fmt, n_rows, nnz, max_row_nnz, solver,
+                         C.byref(opts) if opts is not None else None, C.byref(out)), "bs_plan")
+    return out.as_dict()
+
+
+# ------------------------------------------------------------------ solve
+def bs_batch_solve(fmt: int, pattern: int, values, b, x, solver: int, precond: int, tol: float,
+                   max_iter: int, iters, resid, status=None, opts: Optional[bs_options] = None,
+                   stream=None) -> None:
+    """Launch the fused solve on ``stream`` (default: torch's current stream).
+
+    ``values``/``b``/``x``: float64 device tensors ``[B, nnz]`` (CSR) or ``[B, W*n]``
+    (ELL), ``[B, n]``, ``[B, n]``; ``iters``/``status`` int32 ``[B]``; ``resid``
+    float64 ``[B]``.  Asynchronous: synchronise the stream before reading results.
+    """
+    n_batch, n_rows = b.shape
+    _check(lib().bs_batch_solve(fmt, n_batch, n_rows, pattern, _ptr(values), _ptr(b), _ptr(x),
+                                solver, precond, float(tol), int(max_iter), _ptr(iters),
+                                _ptr(resid), _ptr(status),
+                                C.byref(opts) if opts is not None else None, _stream(stream)),
+           "bs_batch_solve")
+
+
+@dataclass
+class Pattern:
+    """Owns a pattern handle; releases its device copy when collected."""
+
+    handle: int
+    n_rows: int
+    nnz: int
+    ell_width: int
+    max_row_nnz: int
+
+    @classmethod
+    def from_csr(cls, row_ptr, col_idx) -> "Pattern":
+        h = bs_pattern_create_csr(row_ptr, col_idx)
+        return cls(h, **bs_pattern_query(h))
+
+    @classmethod
+    def from_ell(cls, n_rows: int, ell_col) -> "Pattern":
+        h = bs_pattern_create_ell(n_rows, ell_col)
+        return cls(h, **bs_pattern_query(h))
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.bs_pattern_destroy(self.handle)
+            self.handle = 0
+
+
+def solve(pattern: Pattern, values, b, x=None, fmt: int = CSR, solver: int = BICGSTAB,
+          precond: int = PREC_JACOBI, tol: float = 1e-10, max_iter: int = 500,
+          opts: Optional[bs_options] = None, stream=None):
+    """Allocate the outputs with torch and call :func:`bs_batch_solve`.
+
+    Returns ``(x, iters, resid, status)`` as device tensors (not synchronised).
+    If ``x`` is None the solve starts from zero (``BS_FLAG_X0_ZERO``).
+    """
+    import torch
+    B = b.shape[0]
+    dev = b.device
+    if x is None:
+        x = torch.empty_like(b)
+        opts = opts if opts is not None else make_options()
+        opts.flags |= FLAG_X0_ZERO
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    bs_batch_solve(fmt, pattern.handle, values, b, x, solver, precond, tol, max_iter, iters, resid,
+                   status, opts, stream)
+    return x, iters, resid, status

@@ -1,0 +1,408 @@
+// Host side of the C ABI declared in include/batchsolve.h: argument and pattern
+// validation, one-time pattern preprocessing (Sec. 3.1: one pattern copy for the
+// whole batch), the kernel-shape planner (Sec. 3.3 multi-level dispatch,
+// Sec. 3.5 on-chip placement, Sec. 3.6 size-dependent work-group choice) and the
+// launch of the fused solver kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/batchsolve.h"
+#include "bs_registry.hpp"
+#include "bs_shape.hpp"
+
+struct bs_pattern_s {
+  int n = 0, nnz = 0, width = 0, max_row = 0, device = -1;
+  std::vector<int> row_ptr, col, slot_col, row_len, diag_slot;
+  int* d_base = nullptr;  // one allocation: row_ptr | slot_col | row_len | diag_slot
+  int *d_row_ptr = nullptr, *d_slot_col = nullptr, *d_row_len = nullptr, *d_diag = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return BS_ERR_HIP;
+}
+
+// Derived per-row data shared by the CSR and ELL forms.
+void derive(bs_pattern_s& p) {
+  const int n = p.n;
+  p.row_len.resize(n);
+  p.diag_slot.assign(n, -1);
+  p.max_row = 0;
+  for (int i = 0; i < n; ++i) {
+    const int len = p.row_ptr[i + 1] - p.row_ptr[i];
+    p.row_len[i] = len;
+    p.max_row = std::max(p.max_row, len);
+    for (int k = 0; k < len; ++k)
+      if (p.col[p.row_ptr[i] + k] == i && p.diag_slot[i] < 0) p.diag_slot[i] = k;
+  }
+  p.width = p.max_row;
+  p.slot_col.assign((size_t)p.width * n, -1);
+  for (int s = 0; s < p.width; ++s)
+    for (int i = 0; i < n; ++i)
+      if (s < p.row_len[i]) p.slot_col[(size_t)s * n + i] = p.col[p.row_ptr[i] + s];
+}
+
+int upload(bs_pattern_s& p) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    g_last_error = "no HIP device";
+    return BS_ERR_NO_DEVICE;
+  }
+  hipError_t e = hipGetDevice(&p.device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const size_t n_rp = p.n + 1, n_sc = std::max<size_t>((size_t)p.width * p.n, 1), n_rl = p.n;
+  const size_t total = n_rp + n_sc + 2 * n_rl;
+  e = hipMalloc(&p.d_base, total * sizeof(int));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(pattern)");
+  p.d_row_ptr = p.d_base;
+  p.d_slot_col = p.d_row_ptr + n_rp;
+  p.d_row_len = p.d_slot_col + n_sc;
+  p.d_diag = p.d_row_len + n_rl;
+  std::vector<int> h(total, -1);
+  std::copy(p.row_ptr.begin(), p.row_ptr.end(), h.begin());
+  std::copy(p.slot_col.begin(), p.slot_col.end(), h.begin() + n_rp);
+  std::copy(p.row_len.begin(), p.row_len.end(), h.begin() + n_rp + n_sc);
+  std::copy(p.diag_slot.begin(), p.diag_slot.end(), h.begin() + n_rp + n_sc + n_rl);
+  e = hipMemcpy(p.d_base, h.data(), total * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p.d_base);
+    p.d_base = nullptr;
+    return hip_fail(e, "hipMemcpy(pattern)");
+  }
+  return BS_OK;
+}
+
+// Columns of one row must be in range and distinct.
+bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) {
+  for (int k = 0; k < len; ++k) {
+    const int c = cols[k];
+    if (c < 0 || c >= n || mark[c] == stamp) return false;
+    mark[c] = stamp;
+  }
+  return true;
+}
+
+int variant_of(bs_solver solver, int precision) {
+  if (solver == BS_CG) return precision == BS_MIXED ? -1 : bs::V_CG;
+  if (solver == BS_BICGSTAB) return precision == BS_MIXED ? bs::V_BICGSTAB_MIXED : bs::V_BICGSTAB;
+  if (solver == BS_GMRES) return precision == BS_MIXED ? -1 : bs::V_GMRES;
+  return -1;
+}
+
+bs::KernelTable table_of(int variant) {
+  switch (variant) {
+    case bs::V_CG: return bs::kernels_cg();
+    case bs::V_BICGSTAB: return bs::kernels_bicgstab();
+    case bs::V_BICGSTAB_MIXED: return bs::kernels_bicgstab_mixed();
+    case bs::V_GMRES: return bs::kernels_gmres();
+    default: return {nullptr, 0};
+  }
+}
+
+const bs::KernelEntry* find_kernel(int variant, int team, int r, int nz_min) {
+  const bs::KernelTable t = table_of(variant);
+  const bs::KernelEntry* best = nullptr;
+  for (int i = 0; i < t.count; ++i) {
+    const bs::KernelEntry& e = t.entries[i];
+    if (e.team == team && e.r == r && e.nz >= nz_min && (!best || e.nz < best->nz)) best = &e;
+  }
+  return best;
+}
+
+bool pow2_team(int t) { return t >= 16 && t <= 1024 && (t & (t - 1)) == 0; }
+
+// Staging of CSR values through LDS is used while a workgroup's staging area
+// stays within this budget.
+constexpr int kStageBudget = 48 * 1024;
+
+struct Plan {
+  bs_plan_info info;
+  const bs::KernelEntry* k;
+};
+
+int make_plan(bs_format fmt, int n, int nnz, int max_row, bs_solver solver, const bs_options* o,
+              Plan* out) {
+  const int precision = o ? o->precision : BS_FP64;
+  const int variant = variant_of(solver, precision);
+  if (variant < 0) return BS_ERR_UNSUPPORTED;
+  if (n > BS_MAX_ROWS || max_row > BS_MAX_ROW_NNZ) return BS_ERR_UNSUPPORTED;
+  const int force_team = o ? o->team : 0, force_r = o ? o->rows_per_lane : 0;
+  if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
+  if (force_r != 0 && force_r != 1 && force_r != 2 && force_r != 4) return BS_ERR_INVALID_ARG;
+  // Sec. 3.6: at least one lane per row, rounded up to a power of two no
+  // smaller than the 16-lane DPP row; systems beyond one workgroup of lanes take
+  // 2 or 4 rows per lane.  Shapes are tried from the fewest rows per lane and the
+  // narrowest team upwards; the first compiled shape whose register slots cover
+  // the longest row is taken.
+  const bs::KernelEntry* k = nullptr;
+  int team = 0, r = 0;
+  for (int rr = 1; rr <= 4 && !k; rr *= 2) {
+    if (force_r && rr != force_r) continue;
+    int t = 16;
+    while (t * rr < n && t < 1024) t *= 2;
+    if (force_team) t = force_team;
+    for (; t <= 1024 && !k; t *= 2) {
+      if (t * rr < n) break;
+      k = find_kernel(variant, t, rr, std::max(max_row, 1));
+      team = t;
+      r = rr;
+      if (force_team) break;
+    }
+  }
+  if (!k) return BS_ERR_UNSUPPORTED;
+  const int rows = team * r;
+  const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
+  const bool gm = variant == bs::V_GMRES;
+  int stage = 0;
+  if (fmt == BS_CSR && team <= bs::kWave &&
+      teams * bs::team_lds_bytes(rows, gm, nnz) <= kStageBudget)
+    stage = 1;
+  const int tb = bs::team_lds_bytes(rows, gm, stage ? nnz : 0);
+  out->k = k;
+  out->info.team = team;
+  out->info.rows_per_lane = r;
+  out->info.slots = k->nz;
+  out->info.group_size = wg;
+  out->info.systems_per_group = teams;
+  out->info.lds_bytes = teams * tb + bs::red_lds_bytes(waves);
+  out->info.stage_values = stage;
+  return BS_OK;
+}
+
+__global__ void k_csr_to_ell(int64_t n_batch, int n, int nnz, int width, const int* row_ptr,
+                             const int* row_len, const double* src, double* dst) {
+  const int64_t per = (int64_t)width * n;
+  const int64_t total = n_batch * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / per;
+    const int rem = (int)(e - s * per);
+    const int slot = rem / n, i = rem - slot * n;
+    dst[e] = slot < row_len[i] ? src[s * nnz + row_ptr[i] + slot] : 0.0;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bs_error_string(int code) {
+  switch (code) {
+    case BS_OK: return "success";
+    case BS_ERR_INVALID_ARG: return "invalid argument";
+    case BS_ERR_PATTERN: return "malformed sparsity pattern";
+    case BS_ERR_UNSUPPORTED: return "unsupported shape or option";
+    case BS_ERR_HIP: return "HIP runtime error";
+    case BS_ERR_NO_DEVICE: return "no HIP device";
+    default: return "unknown error";
+  }
+}
+
+const char* bs_last_error(void) { return g_last_error.c_str(); }
+
+int bs_pattern_create_csr(int32_t n_rows, int32_t nnz, const int32_t* row_ptr,
+                          const int32_t* col_idx, bs_pattern* out) {
+  if (!out || !row_ptr || (nnz > 0 && !col_idx) || n_rows < 1 || nnz < 0)
+    return BS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (row_ptr[0] != 0 || row_ptr[n_rows] != nnz) return BS_ERR_PATTERN;
+  for (int i = 0; i < n_rows; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return BS_ERR_PATTERN;
+  std::vector<int> mark(n_rows, -1);
+  for (int i = 0; i < n_rows; ++i)
+    if (!row_ok(col_idx + row_ptr[i], row_ptr[i + 1] - row_ptr[i], n_rows, mark, i))
+      return BS_ERR_PATTERN;
+  bs_pattern_s* p = new bs_pattern_s();
+  p->n = n_rows;
+  p->nnz = nnz;
+  p->row_ptr.assign(row_ptr, row_ptr + n_rows + 1);
+  p->col.assign(col_idx, col_idx + nnz);
+  derive(*p);
+  const int rc = upload(*p);
+  if (rc != BS_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return BS_OK;
+}
+
+int bs_pattern_create_ell(int32_t n_rows, int32_t ell_width, const int32_t* ell_col,
+                          bs_pattern* out) {
+  if (!out || n_rows < 1 || ell_width < 0 || (ell_width > 0 && !ell_col))
+    return BS_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::vector<int> rp(n_rows + 1, 0), col;
+  for (int i = 0; i < n_rows; ++i) {
+    int len = 0;
+    bool pad = false;
+    for (int s = 0; s < ell_width; ++s) {
+      const int c = ell_col[(size_t)s * n_rows + i];
+      if (c == -1) {
+        pad = true;
+      } else {
+        if (pad || c < -1 || c >= n_rows) return BS_ERR_PATTERN;
+        ++len;
+      }
+    }
+    rp[i + 1] = rp[i] + len;
+  }
+  col.resize(rp[n_rows]);
+  for (int i = 0; i < n_rows; ++i)
+    for (int s = 0; s < rp[i + 1] - rp[i]; ++s) col[rp[i] + s] = ell_col[(size_t)s * n_rows + i];
+  std::vector<int> mark(n_rows, -1);
+  for (int i = 0; i < n_rows; ++i)
+    if (!row_ok(col.data() + rp[i], rp[i + 1] - rp[i], n_rows, mark, i)) return BS_ERR_PATTERN;
+  bs_pattern_s* p = new bs_pattern_s();
+  p->n = n_rows;
+  p->nnz = rp[n_rows];
+  p->row_ptr = std::move(rp);
+  p->col = std::move(col);
+  derive(*p);
+  // Keep the caller's width (it may include all-padding slots).
+  if (ell_width > p->width) {
+    p->slot_col.resize((size_t)ell_width * n_rows, -1);
+    p->width = ell_width;
+  }
+  const int rc = upload(*p);
+  if (rc != BS_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return BS_OK;
+}
+
+int bs_pattern_destroy(bs_pattern p) {
+  if (!p) return BS_OK;
+  if (p->d_base) (void)hipFree(p->d_base);
+  delete p;
+  return BS_OK;
+}
+
+int bs_pattern_query(bs_pattern p, int32_t* n_rows, int32_t* nnz, int32_t* ell_width,
+                     int32_t* max_row_nnz) {
+  if (!p) return BS_ERR_INVALID_ARG;
+  if (n_rows) *n_rows = p->n;
+  if (nnz) *nnz = p->nnz;
+  if (ell_width) *ell_width = p->width;
+  if (max_row_nnz) *max_row_nnz = p->max_row;
+  return BS_OK;
+}
+
+int bs_pattern_ell_cols(bs_pattern p, int32_t* out) {
+  if (!p || (!out && p->width > 0)) return BS_ERR_INVALID_ARG;
+  std::copy(p->slot_col.begin(), p->slot_col.end(), out);
+  return BS_OK;
+}
+
+int bs_values_csr_to_ell(bs_pattern p, int64_t n_batch, const double* csr, double* ell,
+                         void* stream) {
+  if (!p || n_batch < 0) return BS_ERR_INVALID_ARG;
+  if (n_batch == 0 || p->width == 0) return BS_OK;
+  if (!csr || !ell) return BS_ERR_INVALID_ARG;
+  const int64_t total = n_batch * (int64_t)p->width * p->n;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_csr_to_ell, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     n_batch, p->n, p->nnz, p->width, p->d_row_ptr, p->d_row_len, csr, ell);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BS_OK : hip_fail(e, "k_csr_to_ell");
+}
+
+int bs_matrix_storage(bs_format fmt, int64_t n_batch, int32_t n_rows, int32_t nnz,
+                      int32_t ell_width, int64_t* value_count, int64_t* index_count) {
+  if (n_batch < 0 || n_rows < 1 || nnz < 0 || ell_width < 0 || !value_count || !index_count)
+    return BS_ERR_INVALID_ARG;
+  if (fmt == BS_CSR) {
+    *value_count = n_batch * (int64_t)nnz;
+    *index_count = (int64_t)n_rows + 1 + nnz;
+  } else if (fmt == BS_ELL) {
+    *value_count = n_batch * (int64_t)ell_width * n_rows;
+    *index_count = (int64_t)ell_width * n_rows;
+  } else {
+    return BS_ERR_INVALID_ARG;
+  }
+  return BS_OK;
+}
+
+int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_solver solver,
+            const bs_options* opts, bs_plan_info* out) {
+  if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 || (fmt != BS_CSR && fmt != BS_ELL) ||
+      (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES))
+    return BS_ERR_INVALID_ARG;
+  Plan pl;
+  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, solver, opts, &pl);
+  if (rc == BS_OK) *out = pl.info;
+  return rc;
+}
+
+int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
+                   const double* values, const double* b, double* x, bs_solver solver,
+                   bs_precond precond, double tol, int32_t max_iter, int32_t* iters,
+                   double* resid, int32_t* status, const bs_options* opts, void* stream) {
+  if (!pattern || n_batch < 0 || n_rows != pattern->n) return BS_ERR_INVALID_ARG;
+  if (fmt != BS_CSR && fmt != BS_ELL) return BS_ERR_INVALID_ARG;
+  if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_INVALID_ARG;
+  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI) return BS_ERR_INVALID_ARG;
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;
+  int restart = bs::kMaxRestart;
+  double inner_tol = 1e-6;
+  int flags = 0;
+  if (opts) {
+    if (opts->restart < 0 || opts->restart > bs::kMaxRestart) return BS_ERR_INVALID_ARG;
+    if (opts->restart > 0) restart = opts->restart;
+    if (opts->precision != BS_FP64 && opts->precision != BS_MIXED) return BS_ERR_INVALID_ARG;
+    if (opts->inner_tol < 0.0 || !std::isfinite(opts->inner_tol)) return BS_ERR_INVALID_ARG;
+    if (opts->inner_tol > 0.0) inner_tol = opts->inner_tol;
+    flags = opts->flags;
+  }
+  if (n_batch == 0) return BS_OK;
+  if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
+  Plan pl;
+  const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, solver, opts, &pl);
+  if (rc != BS_OK) return rc;
+  bs::KArgs a;
+  a.n_batch = n_batch;
+  a.n = pattern->n;
+  a.nnz = pattern->nnz;
+  a.width = pattern->width;
+  a.fmt = fmt == BS_CSR ? 0 : 1;
+  a.precond = precond == BS_PREC_JACOBI ? 1 : 0;
+  a.flags = flags;
+  a.max_iter = max_iter;
+  a.restart = restart;
+  a.stage = pl.info.stage_values;
+  a.team_bytes = bs::team_lds_bytes(pl.info.team * pl.info.rows_per_lane, solver == BS_GMRES,
+                                    pl.info.stage_values ? pattern->nnz : 0);
+  a.tol = tol;
+  a.inner_tol = inner_tol;
+  a.row_ptr = pattern->d_row_ptr;
+  a.slot_col = pattern->d_slot_col;
+  a.row_len = pattern->d_row_len;
+  a.diag_slot = pattern->d_diag;
+  a.values = values;
+  a.b = b;
+  a.x = x;
+  a.iters = iters;
+  a.resid = resid;
+  a.status = status;
+  a.outer = opts ? opts->outer_iters : nullptr;
+  const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;
+  if (groups > 0x7fffffff) return BS_ERR_UNSUPPORTED;
+  const hipError_t e = pl.k->launch(a, (unsigned)groups, (unsigned)pl.info.lds_bytes,
+                                    (hipStream_t)stream);
+  return e == hipSuccess ? BS_OK : hip_fail(e, "solver launch");
+}
+
+}  // extern "C"

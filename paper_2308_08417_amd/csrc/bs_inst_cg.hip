@@ -1,0 +1,22 @@
+// Kernel instances of the cg solver for every compiled shape.
+#include "bs_registry.hpp"
+#include "bs_solvers.hpp"
+
+namespace bs {
+namespace {
+
+template <class S>
+hipError_t launch(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream) {
+  hipLaunchKernelGGL((k_cg<S>), dim3(grid), dim3(S::WG), lds, stream, a);
+  return hipGetLastError();
+}
+
+#define ENTRY(T, R, NZ) {V_CG, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>>},
+const KernelEntry kTable[] = {BS_SHAPES_R1(ENTRY) BS_SHAPES_RN(ENTRY)};
+#undef ENTRY
+
+}  // namespace
+
+KernelTable kernels_cg() { return {kTable, (int)(sizeof(kTable) / sizeof(kTable[0]))}; }
+
+}  // namespace bs

@@ -1,0 +1,43 @@
+// Registry of the compiled kernel instances: the host planner looks a request
+// up here by (variant, team, rows per lane, slots per row).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bs_shape.hpp"
+
+namespace bs {
+
+enum Variant { V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_COUNT = 4 };
+
+typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
+
+struct KernelEntry {
+  int variant, team, r, nz, wg;
+  LaunchFn launch;
+};
+
+struct KernelTable {
+  const KernelEntry* entries;
+  int count;
+};
+
+KernelTable kernels_cg();
+KernelTable kernels_bicgstab();
+KernelTable kernels_bicgstab_mixed();
+KernelTable kernels_gmres();
+
+// Shapes compiled for every solver: one row per lane for teams of 16..1024
+// lanes, and 2 or 4 rows per lane for the largest systems.  Slots per row are
+// capped where the registers of a full workgroup would overflow.
+#define BS_SHAPES_R1(X)                                                                   \
+  X(16, 1, 4) X(16, 1, 8) X(16, 1, 16)                                                    \
+  X(32, 1, 4) X(32, 1, 8) X(32, 1, 16) X(32, 1, 32)                                       \
+  X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 32) X(64, 1, 64)                          \
+  X(128, 1, 4) X(128, 1, 8) X(128, 1, 16) X(128, 1, 32) X(128, 1, 64)                     \
+  X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 64)                     \
+  X(512, 1, 4) X(512, 1, 8) X(512, 1, 16) X(512, 1, 32)                                   \
+  X(1024, 1, 4) X(1024, 1, 8) X(1024, 1, 12) X(1024, 1, 16)
+#define BS_SHAPES_RN(X)                                                                   \
+  X(512, 2, 8) X(512, 2, 16) X(1024, 2, 8) X(256, 4, 8) X(512, 4, 8)
+
+}  // namespace bs

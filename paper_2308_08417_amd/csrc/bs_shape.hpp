@@ -1,0 +1,67 @@
+// Kernel shapes and launch arguments shared by the host planner and the HIP
+// kernels of the fused batched solver.
+#pragma once
+#include <stdint.h>
+
+namespace bs {
+
+constexpr int kWave = 64;
+constexpr int kMaxRestart = 30;  // GMRES basis held in registers: m+1 vectors
+
+// Per-team LDS scalars of GMRES: current Hessenberg column (m+2), rotated
+// upper-triangular R packed by columns (m(m+1)/2), Givens c and s (m each),
+// right-hand side g (m+1) and the least-squares solution y (m).  Each entry is
+// written once per cycle with the same bits by every lane of the team.
+constexpr int kGmresScalars = (kMaxRestart + 2) + kMaxRestart * (kMaxRestart + 1) / 2 +
+                              2 * kMaxRestart + (kMaxRestart + 1) + kMaxRestart;
+
+// Largest number of values reduced together (the LDS slot stride of the
+// cross-wave stage).
+constexpr int kMaxFused = 4;
+
+// Arguments of every solver kernel (passed by value).
+struct KArgs {
+  int64_t n_batch;
+  int n, nnz, width, fmt;      // fmt: 0 CSR, 1 ELL
+  int precond, flags, max_iter, restart;
+  int stage;                   // CSR values staged through LDS
+  int team_bytes;              // LDS bytes per team (>= the team's needs)
+  double tol, inner_tol;
+  const int* row_ptr;          // [n+1]
+  const int* slot_col;         // [width][n], -1 padding
+  const int* row_len;          // [n]
+  const int* diag_slot;        // [n], -1 if no stored diagonal
+  const double* values;
+  const double* b;
+  double* x;
+  int* iters;
+  double* resid;
+  int* status;
+  int* outer;
+};
+
+// team: lanes per system; R: rows per lane; NZ: register slots per row.
+template <int TEAM_, int R_, int NZ_>
+struct Shape {
+  static constexpr int TEAM = TEAM_, R = R_, NZ = NZ_;
+  static constexpr int WG = TEAM < kWave ? kWave : TEAM;
+  static constexpr int TEAMS = WG / TEAM;  // systems per workgroup
+  static constexpr int WAVES = WG / kWave;
+  static constexpr int ROWS = TEAM * R;    // largest system a team holds
+};
+
+// Vector buffers per team (SpMV source vectors, double-buffered).
+constexpr int kVecBuffers = 2;
+
+inline int round16(int b) { return (b + 15) & ~15; }
+
+// LDS bytes a team needs for its vectors and solver scalars.
+inline int team_lds_bytes(int rows, int solver_is_gmres, int stage_nnz) {
+  int vec = kVecBuffers * rows * 8 + (solver_is_gmres ? kGmresScalars * 8 : 0);
+  int stg = stage_nnz * 8;
+  return round16(vec > stg ? vec : stg);
+}
+
+inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }
+
+}  // namespace bs

@@ -1,0 +1,630 @@
+// The fused batched Krylov solvers (paper Sec. 3.2-3.6): one kernel launch, one
+// team of lanes per system, the whole solve of each system inside the kernel.
+//
+// Control flow.  Teams that share a wave (16- or 32-lane teams) run in lockstep
+// through the same instruction stream: every cross-lane operation is executed by
+// all lanes, and per-team state changes are committed under per-team
+// predicates.  A team that has finished keeps executing (its results are
+// discarded) until every team of its wave has finished.  Multi-wave teams make
+// identical decisions in every wave because every wave reads the same reduced
+// bits, so all their barriers match.
+//
+// Stop test.  ||r||_2 <= tol*||b||_2 on the recurrence residual, confirmed on the
+// true residual b - A x; if the confirmation fails and iterations remain, the
+// method restarts from the true residual.  (The paper's Alg. 1 tests |r.z|
+// against a threshold; its Tab. 2 lists a relative criterion, which is used.)
+#pragma once
+#include <type_traits>
+
+#include "bs_device.hpp"
+
+namespace bs {
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// Shared epilogue: true residual for teams that do not have it, then outputs.
+template <class S>
+__device__ __forceinline__ void finish(Team<S>& tm, const Rows<S>& A, const KArgs& g,
+                                       const double (&b)[S::R], const double (&x)[S::R], int st,
+                                       int k, int outer, double bn, double rn, bool have_rn) {
+  const bool need = tm.live && !have_rn;
+  if (tm.any(need)) {
+    double t[S::R], q[1];
+    A.template spmv<0>(tm, A.a, x, t, S::ROWS);
+    double p[S::R];
+#pragma unroll
+    for (int r = 0; r < S::R; ++r) { const double e = b[r] - t[r]; p[r] = e * e; }
+    q[0] = sum_rows(p);
+    tm.sum(q);
+    if (need) rn = sqrt(q[0]);
+  }
+  if (!tm.live) return;
+#pragma unroll
+  for (int r = 0; r < S::R; ++r)
+    if (A.ok[r]) g.x[tm.sys * g.n + A.row[r]] = x[r];
+  if (tm.lane == 0) {
+    g.iters[tm.sys] = k;
+    g.resid[tm.sys] = !finite(bn) ? bn : (bn == 0.0 ? rn : rn / bn);
+    if (g.status) g.status[tm.sys] = st;
+    if (g.outer) g.outer[tm.sys] = outer;
+  }
+}
+
+// Shared prologue: load the system, its Jacobi diagonal, b, x0 and the initial
+// residual r0 = b - A x0 (r0 = b when x0 = 0 is promised).
+template <class S>
+struct Prologue {
+  double b[S::R], x[S::R], r[S::R], d[S::R];
+};
+
+template <class S>
+__device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g, Prologue<S>& P) {
+  A.load(tm, g);
+  A.jacobi(g.precond, P.d);
+  const bool x0zero = (g.flags & 1) != 0;
+#pragma unroll
+  for (int r = 0; r < S::R; ++r) {
+    const bool ok = tm.live && A.ok[r];
+    const size_t off = ok ? (size_t)tm.sys * g.n + A.row[r] : 0;
+    P.b[r] = ok ? g.b[off] : 0.0;
+    P.x[r] = (ok && !x0zero) ? g.x[off] : 0.0;
+  }
+  if (!x0zero) {
+    double t[S::R];
+    A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+#pragma unroll
+    for (int r = 0; r < S::R; ++r) P.r[r] = P.b[r] - t[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < S::R; ++r) P.r[r] = P.b[r];
+  }
+}
+
+// =================================================================== BiCGSTAB
+// Right-preconditioned BiCGSTAB (van der Vorst 1992), the solver the paper
+// evaluates on all application inputs (Sec. 4.3).  Per iteration: two SpMVs and
+// three fused reductions (r^.v; s.s, t.t, t.s; r.r, r^.r).  The second SpMV is
+// issued before the half-step test so that ||s|| joins the t-reduction; it is
+// discarded when the half step already converges.
+//
+// MIXED: the Krylov vectors, the FP32 copy of A and the inner reductions are
+// FP32 and solve for a correction to the FP64 x, scaled by 1/||r||; the "true
+// residual confirmation" becomes the FP64 outer refinement step r = b - A x,
+// which also ends the inner solve when it meets inner_tol or breaks down.
+template <class S, bool MIXED>
+__global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  extern __shared__ __align__(16) char smem[];
+  Team<S> tm(smem, g);
+  if constexpr (S::TEAMS == 1) {
+    if (!tm.live) return;  // whole workgroup idle
+  }
+  Rows<S> A;
+  Prologue<S> P;
+  prologue(tm, A, g, P);
+  constexpr int R = S::R;
+
+  // FP32 copy of the rows and of the Jacobi diagonal for the inner solve.
+  using AT = typename std::conditional<MIXED, float, double>::type;
+  AT a_in[R][S::NZ];
+  T d_in[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    d_in[r] = (T)P.d[r];
+#pragma unroll
+    for (int k = 0; k < S::NZ; ++k) a_in[r][k] = (AT)A.a[r][k];
+  }
+
+  double q2[2];
+  {
+    double p0[R], p1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { p0[r] = P.b[r] * P.b[r]; p1[r] = P.r[r] * P.r[r]; }
+    q2[0] = sum_rows(p0);
+    q2[1] = sum_rows(p1);
+    tm.sum(q2);
+  }
+  const double bn = sqrt(q2[0]);
+  double rn = sqrt(q2[1]);  // FP64 norm of the outer (or only) residual
+  const double lim = g.tol * bn;
+  int st = tm.live ? ST_RUNNING : ST_IDLE;
+  bool rtrue = true;
+  if (st == ST_RUNNING) {
+    if (!finite(bn)) st = ST_NONFINITE;
+    else if (bn == 0.0) {
+      st = ST_CONVERGED;
+#pragma unroll
+      for (int r = 0; r < R; ++r) P.x[r] = 0.0;
+      rn = 0.0;
+    }
+  }
+  int k = 0, outer = 0;
+
+  // Krylov state.
+  T r[R], rh[R], p[R], v[R];
+  T rho, rho0, alpha, omega, rn_in;
+  double scale;  // x += scale * (inner update)
+  double rn_prev = rn;
+  auto restart = [&](double rtrue_norm) {
+    // r_in = r / scale; r^ = r_in; p = v = 0; rho0 = alpha = omega = 1
+    scale = MIXED ? rtrue_norm : 1.0;
+    const double inv = MIXED ? (rtrue_norm > 0.0 ? 1.0 / rtrue_norm : 0.0) : 1.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      r[i] = (T)(MIXED ? P.r[i] * inv : P.r[i]);
+      rh[i] = r[i];
+      p[i] = 0;
+      v[i] = 0;
+    }
+    rho0 = alpha = omega = (T)1;
+  };
+  restart(rn);
+  if constexpr (MIXED) {
+    T q[1];
+    T pr[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) pr[i] = r[i] * r[i];
+    q[0] = sum_rows(pr);
+    tm.sum(q);
+    rho = q[0];
+    rn_in = sqrt(q[0]);
+  } else {
+    rho = (T)q2[1];  // r^ = r, so r^.r is the same sum as r.r
+    rn_in = (T)rn;
+  }
+  // Inner stop level: absolute on the same scale as r_in.
+  auto inner_lim = [&]() -> T {
+    if constexpr (MIXED) {
+      const double want = 0.5 * lim / (rn > 0.0 ? rn : 1.0);
+      return (T)(want > g.inner_tol ? want : g.inner_tol);
+    } else {
+      return (T)lim;
+    }
+  };
+  T ilim = inner_lim();
+  bool inner_end = false;  // MIXED: inner solve ended (met inner tol or broke down)
+
+  for (;;) {
+    // ---- top: convergence / budget checks, per team
+    bool need_chk = false;
+    if (st == ST_RUNNING) {
+      if (MIXED ? !finite(rn) : !finite((double)rn_in)) {
+        st = ST_NONFINITE;
+      } else if (MIXED ? (rn <= lim || inner_end || rn_in <= ilim) : (rn_in <= ilim)) {
+        if (!MIXED && rtrue) st = ST_CONVERGED;
+        else if (MIXED && rtrue && rn <= lim) st = ST_CONVERGED;
+        else need_chk = true;
+      } else if (k >= g.max_iter) {
+        st = ST_MAX_ITER;
+      }
+    }
+    if (tm.any(need_chk)) {
+      // ---- true residual (plain) / outer refinement step (mixed), FP64
+      double t[R], pr[R], q[1];
+      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double e = P.b[i] - t[i];
+        if (need_chk) P.r[i] = e;
+        pr[i] = e * e;
+      }
+      q[0] = sum_rows(pr);
+      tm.sum(q);
+      if (need_chk) {
+        const double rnc = sqrt(q[0]);
+        rtrue = true;
+        if constexpr (MIXED) outer += 1;
+        const bool stagnant = MIXED && !(rnc < rn_prev);
+        rn = rnc;
+        rn_prev = rnc;
+        if (!finite(rnc)) st = ST_NONFINITE;
+        else if (rnc <= lim) st = ST_CONVERGED;
+        else if (k >= g.max_iter) st = ST_MAX_ITER;
+        else if (stagnant) st = ST_BREAKDOWN;
+        else {
+          restart(rnc);
+          inner_end = false;
+          ilim = inner_lim();
+        }
+      }
+      if constexpr (MIXED) {
+        // new inner residual norm and rho for restarted teams
+        T qq[1], pp[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) pp[i] = r[i] * r[i];
+        qq[0] = sum_rows(pp);
+        tm.sum(qq);
+        if (need_chk && st == ST_RUNNING) { rho = qq[0]; rn_in = sqrt(qq[0]); }
+      } else {
+        if (need_chk && st == ST_RUNNING) { rho = (T)q[0]; rn_in = (T)rn; }
+      }
+      continue;
+    }
+    if (!tm.any(st == ST_RUNNING)) break;
+
+    // ---- one BiCGSTAB iteration; committed for teams still running
+    bool go = st == ST_RUNNING;
+    if (go) {
+      k += 1;
+      if (!finite((double)rho)) {
+        if (MIXED) inner_end = true; else st = ST_NONFINITE;
+        go = false;
+      } else if (rho == (T)0) {
+        if (MIXED) inner_end = true; else st = ST_BREAKDOWN;
+        go = false;
+      }
+    }
+    const T beta = (rho / rho0) * (alpha / omega);
+    T ph[R], s[R], sh[R], t[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      ph[i] = d_in[i] * p[i];
+    }
+    A.template spmv<0>(tm, a_in, ph, v, S::ROWS);
+    T q1[1];
+    {
+      T pr[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) pr[i] = rh[i] * v[i];
+      q1[0] = sum_rows(pr);
+    }
+    tm.sum(q1);
+    const T sigma = q1[0];
+    if (go) {
+      if (!finite((double)sigma)) { if (MIXED) inner_end = true; else st = ST_NONFINITE; go = false; }
+      else if (sigma == (T)0) { if (MIXED) inner_end = true; else st = ST_BREAKDOWN; go = false; }
+    }
+    const T al = rho / sigma;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      s[i] = r[i] - al * v[i];
+      sh[i] = d_in[i] * s[i];
+    }
+    A.template spmv<1>(tm, a_in, sh, t, S::ROWS);
+    T q3[3];
+    {
+      T p0[R], p1[R], p2[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) { p0[i] = s[i] * s[i]; p1[i] = t[i] * t[i]; p2[i] = t[i] * s[i]; }
+      q3[0] = sum_rows(p0);
+      q3[1] = sum_rows(p1);
+      q3[2] = sum_rows(p2);
+    }
+    tm.sum(q3);
+    const T sn = sqrt(q3[0]), tt = q3[1], ts = q3[2];
+    bool half = false;
+    if (go) {
+      if (!finite((double)sn)) { if (MIXED) inner_end = true; else st = ST_NONFINITE; go = false; }
+      else if (sn <= ilim) half = true;
+      else if (!finite((double)tt) || !finite((double)ts)) {
+        if (MIXED) inner_end = true; else st = ST_NONFINITE;
+        go = false;
+      }
+    }
+    const double sal = scale * (double)al;
+    if (half) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        P.x[i] = fma(sal, (double)ph[i], P.x[i]);
+        r[i] = s[i];
+      }
+      rtrue = false;
+      rn_in = sn;
+      go = false;
+    }
+    const T om = (tt == (T)0) ? (T)0 : ts / tt;
+    if (go) {
+      const double som = scale * (double)om;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        P.x[i] = fma(som, (double)sh[i], fma(sal, (double)ph[i], P.x[i]));
+        r[i] = s[i] - om * t[i];
+      }
+      rtrue = false;
+      rho0 = rho;
+      alpha = al;
+      omega = om;
+    }
+    T q4[2];
+    {
+      T p0[R], p1[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) { p0[i] = r[i] * r[i]; p1[i] = rh[i] * r[i]; }
+      q4[0] = sum_rows(p0);
+      q4[1] = sum_rows(p1);
+    }
+    tm.sum(q4);
+    if (go) {
+      rn_in = sqrt(q4[0]);
+      rho = q4[1];
+      if (om == (T)0 && !(rn_in <= ilim)) {
+        if (MIXED) inner_end = true; else st = ST_BREAKDOWN;
+      }
+    }
+  }
+  finish(tm, A, g, P.b, P.x, st, k, outer, bn, rn, st == ST_CONVERGED || st == ST_IDLE);
+}
+
+// =================================================================== CG
+// Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
+// stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
+template <class S>
+__global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
+  extern __shared__ __align__(16) char smem[];
+  Team<S> tm(smem, g);
+  if constexpr (S::TEAMS == 1) {
+    if (!tm.live) return;
+  }
+  Rows<S> A;
+  Prologue<S> P;
+  prologue(tm, A, g, P);
+  constexpr int R = S::R;
+  double z[R], p[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) { z[i] = P.d[i] * P.r[i]; p[i] = z[i]; }
+  double q3[3];
+  {
+    double p0[R], p1[R], p2[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) { p0[i] = P.b[i] * P.b[i]; p1[i] = P.r[i] * P.r[i]; p2[i] = P.r[i] * z[i]; }
+    q3[0] = sum_rows(p0); q3[1] = sum_rows(p1); q3[2] = sum_rows(p2);
+  }
+  tm.sum(q3);
+  const double bn = sqrt(q3[0]);
+  double rn = sqrt(q3[1]), rho = q3[2];
+  const double lim = g.tol * bn;
+  int st = tm.live ? ST_RUNNING : ST_IDLE;
+  if (st == ST_RUNNING) {
+    if (!finite(bn)) st = ST_NONFINITE;
+    else if (bn == 0.0) {
+      st = ST_CONVERGED;
+#pragma unroll
+      for (int i = 0; i < R; ++i) P.x[i] = 0.0;
+      rn = 0.0;
+    }
+  }
+  bool rtrue = true;
+  int k = 0;
+  for (;;) {
+    bool need_chk = false;
+    if (st == ST_RUNNING) {
+      if (!finite(rn) || !finite(rho)) st = ST_NONFINITE;
+      else if (rn <= lim) { if (rtrue) st = ST_CONVERGED; else need_chk = true; }
+      else if (k >= g.max_iter) st = ST_MAX_ITER;
+    }
+    if (tm.any(need_chk)) {
+      double t[R], rc[R], zc[R], p0[R], p1[R], q[2];
+      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        rc[i] = P.b[i] - t[i];
+        zc[i] = P.d[i] * rc[i];
+        p0[i] = rc[i] * rc[i];
+        p1[i] = rc[i] * zc[i];
+      }
+      q[0] = sum_rows(p0); q[1] = sum_rows(p1);
+      tm.sum(q);
+      if (need_chk) {
+        rn = sqrt(q[0]);
+        rtrue = true;
+        if (!finite(rn)) st = ST_NONFINITE;
+        else if (rn <= lim) st = ST_CONVERGED;
+        else if (k >= g.max_iter) st = ST_MAX_ITER;
+        else {
+#pragma unroll
+          for (int i = 0; i < R; ++i) { P.r[i] = rc[i]; z[i] = zc[i]; p[i] = zc[i]; }
+          rho = q[1];
+        }
+      }
+      continue;
+    }
+    if (!tm.any(st == ST_RUNNING)) break;
+    bool go = st == ST_RUNNING;
+    if (go && rho == 0.0) { st = ST_BREAKDOWN; go = false; }
+    double t[R];
+    A.template spmv<0>(tm, A.a, p, t, S::ROWS);
+    double q1[1];
+    {
+      double pr[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) pr[i] = p[i] * t[i];
+      q1[0] = sum_rows(pr);
+    }
+    tm.sum(q1);
+    const double pt = q1[0];
+    if (go) {
+      if (!finite(pt)) { st = ST_NONFINITE; go = false; }
+      else if (pt == 0.0) { st = ST_BREAKDOWN; go = false; }
+    }
+    const double alpha = rho / pt;
+    double rr[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      rr[i] = go ? fma(-alpha, t[i], P.r[i]) : P.r[i];
+      if (go) P.x[i] = fma(alpha, p[i], P.x[i]);
+      z[i] = P.d[i] * rr[i];
+    }
+    double q2[2];
+    {
+      double p0[R], p1[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) { p0[i] = rr[i] * z[i]; p1[i] = rr[i] * rr[i]; }
+      q2[0] = sum_rows(p0); q2[1] = sum_rows(p1);
+    }
+    tm.sum(q2);
+    if (go) {
+      const double beta = q2[0] / rho;
+#pragma unroll
+      for (int i = 0; i < R; ++i) { P.r[i] = rr[i]; p[i] = fma(beta, p[i], z[i]); }
+      rho = q2[0];
+      rn = sqrt(q2[1]);
+      rtrue = false;
+      k += 1;
+    }
+  }
+  finish(tm, A, g, P.b, P.x, st, k, 0, bn, rn, st == ST_CONVERGED || st == ST_IDLE);
+}
+
+// =================================================================== GMRES(m)
+// Right-preconditioned restarted GMRES with modified Gram-Schmidt Arnoldi and
+// Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning).  The m+1
+// basis vectors stay in registers (one element per row per lane), so a cycle
+// never touches HBM.  The Hessenberg column, the rotated triangle R, the
+// rotations, g and y are per-team LDS scalars written once per cycle: every lane
+// of the team computes the same bits and writes them, and reads only entries it
+// has written itself, so no barrier is needed around them.  The last entry of g
+// changes at every step and is kept in a register.  At the end of a cycle
+// y = R^{-1} g by back substitution and x += M V y.
+template <class S>
+__global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
+  static_assert(S::R == 1, "GMRES keeps one row per lane");
+  constexpr int M = kMaxRestart;
+  extern __shared__ __align__(16) char smem[];
+  Team<S> tm(smem, g);
+  if constexpr (S::TEAMS == 1) {
+    if (!tm.live) return;
+  }
+  Rows<S> A;
+  Prologue<S> P;
+  prologue(tm, A, g, P);
+  const int m = g.restart;
+  // LDS scalars of this team
+  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * S::ROWS * 8);
+  double* Rt = hcol + (M + 2);               // packed by columns: R[i][j] at j(j+1)/2 + i
+  double* cs = Rt + M * (M + 1) / 2;
+  double* sn = cs + M;
+  double* gv = sn + M;
+  double* yv = gv + (M + 1);
+
+  double q1[1];
+  {
+    double pr[1] = {P.b[0] * P.b[0]};
+    q1[0] = pr[0];
+  }
+  tm.sum(q1);
+  const double bn = sqrt(q1[0]);
+  const double lim = g.tol * bn;
+  int st = tm.live ? ST_RUNNING : ST_IDLE;
+  double rn = 0.0;
+  if (st == ST_RUNNING) {
+    if (!finite(bn)) st = ST_NONFINITE;
+    else if (bn == 0.0) { st = ST_CONVERGED; P.x[0] = 0.0; }
+  }
+  double V[M + 1];
+#pragma unroll
+  for (int i = 0; i <= M; ++i) V[i] = 0.0;
+  int k = 0, j = 0;
+  double gcur = 0.0;   // g_j, the entry the next rotation acts on
+  bool start = true;   // at a cycle start (true residual due)
+  const double d = P.d[0];
+  for (;;) {
+    // ---- cycle start: true residual, convergence, V0 = r/beta
+    if (tm.any(st == ST_RUNNING && start)) {
+      const bool me = st == ST_RUNNING && start;
+      double t[1];
+      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+      const double rc = P.b[0] - t[0];
+      double q[1] = {rc * rc};
+      tm.sum(q);
+      if (me) {
+        const double beta = sqrt(q[0]);
+        rn = beta;
+        if (!finite(beta)) st = ST_NONFINITE;
+        else if (beta <= lim) st = ST_CONVERGED;
+        else if (k >= g.max_iter) st = ST_MAX_ITER;
+        else {
+          V[0] = rc / beta;
+          gcur = beta;
+          j = 0;
+          start = false;
+        }
+      }
+    }
+    if (!tm.any(st == ST_RUNNING)) break;
+    // ---- one Arnoldi step for every running team (all of them are mid-cycle)
+    const bool act = st == ST_RUNNING;
+    double vj = V[0];
+#pragma unroll
+    for (int i = 1; i < M; ++i)
+      if (j == i) vj = V[i];
+    double z[1] = {d * vj}, w[1];
+    A.template spmv<0>(tm, A.a, z, w, S::ROWS);
+    const int jmax = wave_max(act ? j : -1);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      if (i <= jmax) {
+        double q[1] = {w[0] * V[i]};
+        tm.sum(q);
+        if (act && i <= j) {
+          w[0] = fma(-q[0], V[i], w[0]);
+          hcol[i] = q[0];
+        }
+      }
+    }
+    double qn[1] = {w[0] * w[0]};
+    tm.sum(qn);
+    bool end = false;
+    if (act) {
+      const double hn = sqrt(qn[0]);
+      k += 1;
+      if (!finite(hn)) {
+        st = ST_NONFINITE;
+      } else {
+        // apply the previous rotations to column j
+        double hp = hcol[0];
+        const int cj = j * (j + 1) / 2;
+        for (int i = 0; i < j; ++i) {
+          const double hnx = hcol[i + 1];
+          const double c = cs[i], s = sn[i];
+          Rt[cj + i] = c * hp + s * hnx;
+          hp = -s * hp + c * hnx;
+        }
+        const double dd = sqrt(hp * hp + hn * hn);
+        if (dd == 0.0) {
+          st = ST_BREAKDOWN;
+        } else {
+          const double c = hp / dd, s = hn / dd;
+          cs[j] = c;
+          sn[j] = s;
+          Rt[cj + j] = dd;
+          gv[j] = c * gcur;
+          gcur = -s * gcur;
+          end = fabs(gcur) <= lim || hn == 0.0 || k >= g.max_iter || j == m - 1;
+          if (!end) {
+            const double vn = w[0] / hn;
+#pragma unroll
+            for (int i = 1; i <= M; ++i)
+              if (j + 1 == i) V[i] = vn;
+            j += 1;
+          }
+        }
+      }
+    }
+    // ---- cycle end: y = R^{-1} g (back substitution), x += M V y
+    if (tm.any(end)) {
+      const int jend = wave_max(end ? j : -1);
+      double zacc = 0.0;
+#pragma unroll
+      for (int i = M - 1; i >= 0; --i) {
+        if (i <= jend) {
+          if (end && i <= j) {
+            double acc = gv[i];
+            for (int l = i + 1; l <= j; ++l) acc = fma(-Rt[l * (l + 1) / 2 + i], yv[l], acc);
+            const double yi = acc / Rt[i * (i + 1) / 2 + i];
+            yv[i] = yi;
+            zacc = fma(yi, V[i], zacc);
+          }
+        }
+      }
+      if (end) {
+        P.x[0] = fma(d, zacc, P.x[0]);
+        start = true;
+      }
+    }
+  }
+  finish(tm, A, g, P.b, P.x, st, k, 0, bn, rn,
+         st == ST_CONVERGED || st == ST_IDLE || (st == ST_MAX_ITER && start));
+}
+
+}  // namespace bs

@@ -1,0 +1,151 @@
+"""Host-side tests of the C ABI: the library loads, exports every declared entry
+point, and its pure host logic (pattern validation, storage counts, planner,
+error strings) behaves as documented.  No kernel is launched."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2308_08417_amd import batchsolve as bs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(bs_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(bs.LIB_PATH):
+        pytest.fail("libbatchsolve.so is not built (run __graft_entry__.build())")
+    return bs.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_error_strings(L):
+    for code in (bs.OK, bs.ERR_INVALID_ARG, bs.ERR_PATTERN, bs.ERR_UNSUPPORTED, bs.ERR_HIP,
+                 bs.ERR_NO_DEVICE, -99):
+        assert isinstance(bs.bs_error_string(code), str) and bs.bs_error_string(code)
+
+
+def test_storage_counts_tab3(L, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "tab3_shapes.json")))
+    B = g["batch"]
+    for e in g["inputs"]:
+        n, nnz = e["n"], e["nnz"]
+        assert bs.bs_matrix_storage(bs.CSR, B, n, nnz, 0) == (B * nnz, n + 1 + nnz)
+        w = 40
+        assert bs.bs_matrix_storage(bs.ELL, B, n, nnz, w) == (B * w * n, w * n)
+    with pytest.raises(bs.BatchSolveError):
+        bs.bs_matrix_storage(7, 1, 1, 1, 1)
+
+
+def tri(n):
+    rp, ci = [0], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32)
+
+
+def create_code(fn, *args):
+    try:
+        fn(*args)
+        return bs.OK
+    except bs.BatchSolveError as e:
+        return e.code
+
+
+def test_pattern_validation(L):
+    rp, ci = tri(8)
+    bad_start = rp.copy(); bad_start[0] = 1
+    assert create_code(bs.bs_pattern_create_csr, bad_start, ci) == bs.ERR_PATTERN
+    bad_mono = rp.copy(); bad_mono[3] = bad_mono[4] + 1
+    assert create_code(bs.bs_pattern_create_csr, bad_mono, ci) == bs.ERR_PATTERN
+    bad_col = ci.copy(); bad_col[2] = 8
+    assert create_code(bs.bs_pattern_create_csr, rp, bad_col) == bs.ERR_PATTERN
+    neg_col = ci.copy(); neg_col[2] = -1
+    assert create_code(bs.bs_pattern_create_csr, rp, neg_col) == bs.ERR_PATTERN
+    dup = ci.copy(); dup[3] = dup[2]   # row 1 = (0,1,2) -> (0,0,2)
+    assert create_code(bs.bs_pattern_create_csr, rp, dup) == bs.ERR_PATTERN
+    # ELL: padding before a stored entry
+    n = 4
+    ell = np.array([[0, 1, 2, 3], [-1, 0, 1, 2], [1, -1, -1, -1]], np.int32).ravel()
+    assert create_code(bs.bs_pattern_create_ell, n, ell) == bs.ERR_PATTERN
+    ell_oob = np.array([[0, 1, 2, 4]], np.int32).ravel()
+    assert create_code(bs.bs_pattern_create_ell, n, ell_oob) == bs.ERR_PATTERN
+    # invalid arguments
+    assert L.bs_pattern_create_csr(0, 0, None, None, None) == bs.ERR_INVALID_ARG
+    assert L.bs_batch_solve(0, 1, 4, None, None, None, None, 1, 1, 1e-10, 10, None, None, None,
+                            None, None) == bs.ERR_INVALID_ARG
+
+
+def test_valid_pattern_needs_device(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; covered by the GPU tests")
+    rp, ci = tri(5)
+    assert create_code(bs.bs_pattern_create_csr, rp, ci) == bs.ERR_NO_DEVICE
+
+
+@pytest.mark.parametrize("n", [1, 16, 17, 32, 33, 54, 64, 65, 128, 300, 992, 1024, 1025, 2048, 4096])
+def test_plan_covers_rows(L, n):
+    """Sec. 3.6 work-group rule: at least one lane per row, a power of two that
+    is a multiple of the 16-lane DPP row (or the whole wave), slots >= longest row."""
+    for solver in (bs.CG, bs.BICGSTAB, bs.GMRES):
+        maxrow = min(n, 9 if n <= 1024 else 5)
+        try:
+            p = bs.bs_plan(bs.ELL, n, n * maxrow, maxrow, solver)
+        except bs.BatchSolveError as e:
+            assert e.code == bs.ERR_UNSUPPORTED
+            assert n > bs.MAX_ROWS or (solver == bs.GMRES and n > 1024)
+            continue
+        assert p["team"] * p["rows_per_lane"] >= n
+        assert p["team"] in (16, 32, 64, 128, 256, 512, 1024)
+        assert p["slots"] >= maxrow
+        assert p["group_size"] % 64 == 0 and p["group_size"] == max(p["team"], 64)
+        assert p["systems_per_group"] * p["team"] == p["group_size"]
+        # smallest team for one row per lane
+        if n <= 1024:
+            assert p["rows_per_lane"] == 1 and (p["team"] == 16 or p["team"] // 2 < n)
+        assert p["lds_bytes"] <= 64 * 1024
+
+
+def test_plan_stage_and_limits(L):
+    p = bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB)
+    assert p["team"] == 64 and p["slots"] == 32 and p["stage_values"] == 1
+    assert p["lds_bytes"] >= 1042 * 8
+    p = bs.bs_plan(bs.ELL, 54, 1042, 28, bs.BICGSTAB)
+    assert p["stage_values"] == 0
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_plan(bs.CSR, 54, 1042, 65, bs.BICGSTAB)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_plan(bs.CSR, 5000, 15000, 3, bs.BICGSTAB)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB, bs.make_options(team=48))
+    assert e.value.code == bs.ERR_INVALID_ARG
+    p = bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB, bs.make_options(team=128))
+    assert p["team"] == 128 and p["systems_per_group"] == 1
+    p = bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB, bs.make_options(precision=bs.MIXED))
+    assert p["team"] == 64
+    with pytest.raises(bs.BatchSolveError):
+        bs.bs_plan(bs.CSR, 54, 1042, 28, bs.CG, bs.make_options(precision=bs.MIXED))

@@ -1,0 +1,308 @@
+"""GPU parity: the fused HIP solver against the FP64 CPU oracle, through the C ABI.
+
+Bar (per system): status equal; for converged systems the true relative residual
+of the GPU's x, recomputed by the oracle, is <= tol; ||x - x_oracle|| /
+||x_oracle|| <= 1e-8; |iters - iters_oracle| <= 2.  Layout work (ELL pattern and
+value conversion) must match the oracle bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_08417_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2308_08417_amd import batchsolve as bs  # noqa: E402
+
+SOLVER_O = {bs.CG: O.CG, bs.BICGSTAB: O.BICGSTAB, bs.GMRES: O.GMRES}
+XTOL, ITOL = 1e-8, 2
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bs.lib()
+    return torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+class Case:
+    def __init__(self, batch: W.Batch):
+        self.batch = batch
+        self.P = bs.Pattern.from_csr(batch.row_ptr, batch.col_idx)
+        self.OP = O.Pattern(batch.n, batch.row_ptr, batch.col_idx)
+        self.vals = dev(batch.values)
+        self._ell = None
+
+    def values(self, fmt):
+        if fmt == bs.CSR:
+            return self.vals
+        if self._ell is None:
+            B = self.batch.n_batch
+            self._ell = torch.empty((B, self.P.ell_width * self.batch.n), dtype=torch.float64,
+                                    device="cuda:0")
+            bs.bs_values_csr_to_ell(self.P.handle, self.vals, self._ell)
+        return self._ell
+
+    def oracle_values(self, fmt):
+        return self.batch.values if fmt == bs.CSR else O.csr_values_to_ell(self.OP, self.batch.values)
+
+    def gpu(self, fmt, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=500, x0=None,
+            b=None, values=None, **opt):
+        say(f"  gpu: {self.batch.name} n={self.batch.n} B={self.batch.n_batch} fmt={fmt} "
+            f"solver={solver} prec={precond} opt={opt}")
+        bb = dev(self.batch.b if b is None else b)
+        flags = 0
+        if x0 is None:
+            x = torch.zeros_like(bb)
+            flags = bs.FLAG_X0_ZERO
+        else:
+            x = dev(x0)
+        opts = bs.make_options(flags=flags, **opt)
+        B = bb.shape[0]
+        iters = torch.full((B,), -7, dtype=torch.int32, device="cuda:0")
+        resid = torch.full((B,), -7.0, dtype=torch.float64, device="cuda:0")
+        status = torch.full((B,), -7, dtype=torch.int32, device="cuda:0")
+        v = self.values(fmt) if values is None else values
+        bs.bs_batch_solve(fmt, self.P.handle, v, bb, x, solver, precond, tol, max_iter, iters,
+                          resid, status, opts)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), iters.cpu().numpy(), resid.cpu().numpy(), status.cpu().numpy()
+
+    def oracle(self, fmt, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=500, x0=None,
+               b=None, values=None, restart=30):
+        v = self.oracle_values(fmt) if values is None else values
+        return O.batch_solve(self.OP, v, self.batch.b if b is None else b, x0=x0,
+                             fmt=O.CSR if fmt == bs.CSR else O.ELL, solver=SOLVER_O[solver],
+                             precond=precond, tol=tol, max_iter=max_iter, restart=restart)
+
+
+def check(case, g, o, tol=1e-10, fmt=bs.CSR, b=None, values=None, xtol=XTOL, itol=ITOL):
+    xg, ig, rg, sg = g
+    xo, io, ro, so = o
+    assert np.array_equal(sg, so), f"status mismatch at {np.flatnonzero(sg != so)[:10]}"
+    conv = so == O.CONVERGED
+    v = case.oracle_values(fmt) if values is None else values
+    bb = case.batch.b if b is None else b
+    rt = O.true_residual(case.OP, v, bb, xg, fmt=O.CSR if fmt == bs.CSR else O.ELL)
+    assert np.all(rt[conv] <= tol), f"true residual {rt[conv].max()}"
+    assert np.all(rg[conv] <= tol)
+    # the GPU-reported residual is the true residual of its x
+    fin = np.isfinite(rt)
+    assert np.allclose(rg[fin], rt[fin], rtol=1e-6, atol=1e-300)
+    nx = np.linalg.norm(xo, axis=1)
+    err = np.linalg.norm(xg - xo, axis=1) / np.where(nx > 0, nx, 1.0)
+    assert np.all(err[conv] <= xtol), f"x error {err[conv].max()}"
+    d = np.abs(ig.astype(np.int64) - io)
+    assert np.all(d <= itol), f"iteration mismatch {d.max()} at {np.argmax(d)}: {ig[np.argmax(d)]} vs {io[np.argmax(d)]}"
+    return err, d
+
+
+# ------------------------------------------------------------------ layout
+def test_ell_layout_bit_exact():
+    bt = W.chem_jacobian(n_batch=37)
+    c = Case(bt)
+    assert np.array_equal(bs.bs_pattern_ell_cols(c.P.handle), c.OP.ell_col)
+    assert c.P.ell_width == c.OP.width
+    ev = c.values(bs.ELL).cpu().numpy()
+    assert np.array_equal(ev, O.csr_values_to_ell(c.OP, bt.values))
+
+
+# ------------------------------------------------------------------ configurations
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+def test_tridiag_stencil(fmt, solver):
+    c = Case(W.tridiag_stencil(n_batch=64, n=32, seed=0))
+    g = c.gpu(fmt, solver, max_iter=200)
+    o = c.oracle(fmt, solver, max_iter=200)
+    check(c, g, o, fmt=fmt)
+    assert np.all(g[3] == bs.CONVERGED)
+
+
+def symmetric_tridiag(B, n, seed):
+    bt = W.tridiag_stencil(n_batch=B, n=n, seed=seed)
+    rows = np.repeat(np.arange(n), np.diff(bt.row_ptr))
+    lower = {}
+    for k, (i, j) in enumerate(zip(rows, bt.col_idx)):
+        if j < i:
+            lower[(i, j)] = k
+    v = bt.values.copy()
+    for k, (i, j) in enumerate(zip(rows, bt.col_idx)):
+        if j > i:
+            v[:, k] = bt.values[:, lower[(j, i)]]
+    bt.values = v
+    return bt
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("n", [32, 100, 700])
+def test_cg_spd(fmt, n):
+    c = Case(symmetric_tridiag(48, n, seed=n))
+    g = c.gpu(fmt, bs.CG, max_iter=1000)
+    o = c.oracle(fmt, bs.CG, max_iter=1000)
+    check(c, g, o, fmt=fmt)
+    assert np.all(g[3] == bs.CONVERGED)
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES, bs.CG])
+def test_chem_jacobian_small(fmt, solver):
+    c = Case(W.chem_jacobian(n_batch=3000))  # ragged against any team count
+    g = c.gpu(fmt, solver)
+    o = c.oracle(fmt, solver)
+    check(c, g, o, fmt=fmt)
+    assert np.all(g[3] == bs.CONVERGED)
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+def test_collision_stencil(fmt, solver):
+    c = Case(W.collision_stencil(n_batch=40))
+    g = c.gpu(fmt, solver, max_iter=1000)
+    o = c.oracle(fmt, solver, max_iter=1000)
+    check(c, g, o, fmt=fmt)
+    assert np.all(g[3] == bs.CONVERGED)
+
+
+@pytest.mark.parametrize("team", [128, 256, 512])
+def test_forced_wider_teams(team):
+    """A system spread over more lanes (several waves) gives the same result."""
+    c = Case(W.chem_jacobian(n_batch=257))
+    g = c.gpu(bs.CSR, bs.BICGSTAB, team=team)
+    o = c.oracle(bs.CSR, bs.BICGSTAB)
+    check(c, g, o)
+
+
+@pytest.mark.parametrize("n,r", [(300, 2), (1000, 1), (1500, 2), (2048, 2), (2000, 4)])
+def test_large_systems_rows_per_lane(n, r):
+    bt = W.tridiag_stencil(n_batch=6, n=n, seed=n)
+    c = Case(bt)
+    for solver in (bs.BICGSTAB, bs.CG):
+        if solver == bs.CG:
+            c = Case(symmetric_tridiag(6, n, seed=n))
+        g = c.gpu(bs.ELL, solver, max_iter=2000, rows_per_lane=r)
+        o = c.oracle(bs.ELL, solver, max_iter=2000)
+        check(c, g, o, fmt=bs.ELL)
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 31, 33, 63, 65, 129])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES, bs.CG])
+def test_odd_sizes_and_ragged_batches(n, solver):
+    B = 61
+    bt = symmetric_tridiag(B, n, seed=3 * n + 1) if solver == bs.CG else W.tridiag_stencil(B, n, seed=n)
+    c = Case(bt)
+    g = c.gpu(bs.CSR, solver)
+    o = c.oracle(bs.CSR, solver)
+    check(c, g, o)
+
+
+# ------------------------------------------------------------------ options and edge cases
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES, bs.CG])
+def test_edge_cases(solver):
+    base = symmetric_tridiag(8, 24, seed=5) if solver == bs.CG else W.tridiag_stencil(8, 24, seed=5)
+    c = Case(base)
+    bt = base
+    # nonzero initial guess, exact initial guess, b = 0, NaN values, Inf in b
+    x0 = np.random.default_rng(1).standard_normal(bt.b.shape)
+    xs = np.stack([np.linalg.solve(O.to_dense(c.OP, bt.values[s]), bt.b[s]) for s in range(8)])
+    x0[1] = xs[1]
+    b = bt.b.copy()
+    b[2] = 0.0
+    b[3, 4] = np.inf
+    vals = bt.values.copy()
+    vals[4, 7] = np.nan
+    vd = dev(vals)
+    g = c.gpu(bs.CSR, solver, x0=x0, b=b, values=vd, tol=1e-8)
+    o = c.oracle(bs.CSR, solver, x0=x0, b=b, values=vals, tol=1e-8)
+    check(c, g, o, tol=1e-8, b=b, values=vals)
+    assert g[3][2] == bs.CONVERGED and g[1][2] == 0 and np.all(g[0][2] == 0.0)
+    assert g[3][3] == bs.NONFINITE and g[3][4] == bs.NONFINITE
+    assert g[1][1] == 0
+    # no iterations allowed
+    g = c.gpu(bs.CSR, solver, max_iter=0)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 0) and np.all(g[0] == 0)
+    # unreachable tolerance: exactly max_iter iterations
+    g = c.gpu(bs.CSR, solver, tol=1e-30, max_iter=13)
+    o = c.oracle(bs.CSR, solver, tol=1e-30, max_iter=13)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 13) and np.array_equal(g[1], o[1])
+    # zero matrix: breakdown
+    z = np.zeros_like(bt.values)
+    g = c.gpu(bs.CSR, solver, values=dev(z))
+    o = c.oracle(bs.CSR, solver, values=z)
+    assert np.all(g[3] == bs.BREAKDOWN) and np.array_equal(g[1], o[1])
+    # no preconditioner
+    g = c.gpu(bs.CSR, solver, precond=bs.PREC_NONE)
+    o = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE)
+    check(c, g, o)
+
+
+def test_gmres_restart_lengths():
+    c = Case(W.collision_stencil(n_batch=12, nx=12, ny=10))
+    for m in (1, 4, 11, 30):
+        g = c.gpu(bs.CSR, bs.GMRES, max_iter=2000, restart=m)
+        o = c.oracle(bs.CSR, bs.GMRES, max_iter=2000, restart=m)
+        check(c, g, o)
+
+
+def test_deterministic():
+    c = Case(W.chem_jacobian(n_batch=2000))
+    a = c.gpu(bs.ELL, bs.BICGSTAB)
+    b = c.gpu(bs.ELL, bs.BICGSTAB)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+# ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("gen", ["tridiag", "chem", "collision"])
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+def test_mixed_precision_meets_fp64_tolerance(gen, fmt):
+    bt = {"tridiag": lambda: W.tridiag_stencil(64),
+          "chem": lambda: W.chem_jacobian(2048),
+          "collision": lambda: W.collision_stencil(24)}[gen]()
+    c = Case(bt)
+    outer = torch.zeros(bt.n_batch, dtype=torch.int32, device="cuda:0")
+    g = c.gpu(fmt, bs.BICGSTAB, max_iter=2000, precision=bs.MIXED, outer_iters=outer)
+    o = c.oracle(fmt, bs.BICGSTAB, max_iter=2000)
+    assert np.all(g[3] == bs.CONVERGED)
+    # iteration counts of the mixed form are not those of the FP64 method
+    err, _ = check(c, g, o, fmt=fmt, itol=10**9)
+    say(f"  mixed {gen}: max x error vs FP64 oracle {err.max():.2e}, "
+        f"inner iters mean {g[1].mean():.2f} (fp64 {o[1].mean():.2f}), "
+        f"outer mean {outer.float().mean().item():.2f}")
+    assert outer.min().item() >= 1
+
+
+# ------------------------------------------------------------------ full size
+def test_chem_jacobian_full_size_sampled():
+    """2^17 systems in the benchmark's launch shape: every system's residual is
+    checked by the oracle, and a random sample is re-solved by the oracle."""
+    bt = W.chem_jacobian(n_batch=1 << 17)
+    c = Case(bt)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(bt.n_batch, 1024, replace=False))
+    for fmt in (bs.CSR, bs.ELL):
+        g = c.gpu(fmt, bs.BICGSTAB)
+        assert np.all(g[3] == bs.CONVERGED)
+        v = c.oracle_values(fmt)
+        rt = O.true_residual(c.OP, v, bt.b, g[0], fmt=O.CSR if fmt == bs.CSR else O.ELL)
+        assert np.all(rt <= 1e-10)
+        sub = bt.subset(idx)
+        o = O.batch_solve(c.OP, v[idx], sub.b, fmt=O.CSR if fmt == bs.CSR else O.ELL,
+                          solver=O.BICGSTAB, tol=1e-10, max_iter=500)
+        xg = g[0][idx]
+        err = np.linalg.norm(xg - o[0], axis=1) / np.linalg.norm(o[0], axis=1)
+        assert np.all(err <= XTOL)
+        assert np.all(np.abs(g[1][idx] - o[1]) <= ITOL)
