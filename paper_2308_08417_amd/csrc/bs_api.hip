@@ -120,6 +120,20 @@ const bs::KernelEntry* find_kernel(int variant, int team, int r, int nz_min) {
   return best;
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
 bool pow2_team(int t) { return t >= 16 && t <= 1024 && (t & (t - 1)) == 0; }
 
 // Staging of CSR values through LDS is used while a workgroup's staging area
@@ -383,6 +397,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.max_iter = max_iter;
   a.restart = restart;
   a.stage = pl.info.stage_values;
+  a.gmres = solver == BS_GMRES ? 1 : 0;
   a.team_bytes = bs::team_lds_bytes(pl.info.team * pl.info.rows_per_lane, solver == BS_GMRES,
                                     pl.info.stage_values ? pattern->nnz : 0);
   a.tol = tol;
@@ -398,9 +413,14 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.resid = resid;
   a.status = status;
   a.outer = opts ? opts->outer_iters : nullptr;
+  // Persistent grid: as many workgroups as can be resident at once, each
+  // walking over the batch (never more than there are systems).
   const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;
-  if (groups > 0x7fffffff) return BS_ERR_UNSUPPORTED;
-  const hipError_t e = pl.k->launch(a, (unsigned)groups, (unsigned)pl.info.lds_bytes,
+  const int cus = device_cus();
+  if (cus < 1) return BS_ERR_HIP;
+  const int64_t resident = (int64_t)pl.k->occupancy((unsigned)pl.info.lds_bytes) * cus;
+  const int64_t grid = std::min(groups, resident);
+  const hipError_t e = pl.k->launch(a, (unsigned)grid, (unsigned)pl.info.lds_bytes,
                                     (hipStream_t)stream);
   return e == hipSuccess ? BS_OK : hip_fail(e, "solver launch");
 }

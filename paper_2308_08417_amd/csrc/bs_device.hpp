@@ -78,6 +78,21 @@ __device__ __forceinline__ int wave_max(int v) {
   return max(max(a, b), max(c, d));
 }
 
+// 32-bit LDS addresses: gathers go through address-space-3 pointers so that a
+// buffer's constant offset folds into the ds_read immediate.
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return (unsigned)(uintptr_t)(const lds_char*)p;
+}
+template <class T>
+__device__ __forceinline__ T lds_load(unsigned addr) {
+  return *(const __attribute__((address_space(3))) T*)(lds_char*)(uintptr_t)addr;
+}
+template <class T>
+__device__ __forceinline__ void lds_store(unsigned addr, T v) {
+  *(__attribute__((address_space(3))) T*)(lds_char*)(uintptr_t)addr = v;
+}
+
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
@@ -87,9 +102,10 @@ template <class S>
 struct Team {
   int lane;         // lane within the team
   int tix;          // team index within the workgroup
-  int64_t sys;      // system index
+  int64_t sys;      // system being solved
   bool live;        // sys < n_batch
-  char* lds;        // this team's LDS region
+  char* lds;        // this team's LDS region (vector buffers, solver scalars)
+  char* stage;      // this team's staging area for CSR values
   double* red;      // cross-wave reduction slots (multi-wave teams)
   int phase;        // which half of `red` the next reduction uses
 
@@ -97,9 +113,10 @@ struct Team {
     const int t = threadIdx.x;
     lane = S::TEAM < kWave ? (t & (S::TEAM - 1)) : t;
     tix = S::TEAM < kWave ? (t / S::TEAM) : 0;
-    sys = (int64_t)blockIdx.x * S::TEAMS + tix;
-    live = sys < a.n_batch;
+    sys = -1;
+    live = false;
     lds = smem + (size_t)tix * a.team_bytes;
+    stage = lds + team_vec_bytes(S::ROWS, a.gmres);
     red = reinterpret_cast<double*>(smem + (size_t)S::TEAMS * a.team_bytes);
     phase = 0;
   }
@@ -156,62 +173,109 @@ struct Team {
 
 // ---------------------------------------------------------------- sparse rows
 // The rows a lane owns, held in registers: values a[r][k] of slot k of row
-// (lane + r*TEAM), and the LDS byte offset of that slot's column inside a
-// vector buffer (8 bytes per element).  `nzw` is the wave's longest row.
+// (lane + r*TEAM), and the LDS address of that slot's column in the team's
+// first vector buffer (8 bytes per element).  Slots past a row's end hold a
+// zero value and column 0, so every SpMV runs over all NZ slots without
+// branches.
 template <class S>
 struct Rows {
   double a[S::R][S::NZ];
-  int c[S::R][S::NZ];
+  unsigned c[S::R][S::NZ];
+  unsigned vrow[S::R];  // LDS address of the lane's own rows in buffer 0
   int row[S::R];
   bool ok[S::R];   // row < n
+  int len[S::R];
   int dslot[S::R];
-  int nzw;
+  int rp[S::R];    // CSR offset of the row's first entry
+  double dval[S::R];  // the row's stored diagonal value (0 if none)
 
-  // Load this team's system.  CSR values are either staged through the team's
-  // LDS (one coalesced copy of the contiguous value block, then row reads) or
-  // read straight from HBM; ELL values are read slot by slot, which is
-  // coalesced across the lanes.  Syncs: the caller's whole workgroup must call.
-  __device__ void load(Team<S>& tm, const KArgs& g) {
-    int len[S::R];
-    int lmax = 0;
+  // The shared pattern, once per kernel: it is the same for every system.
+  __device__ void load_pattern(const Team<S>& tm, const KArgs& g) {
+    const unsigned base = lds_addr(tm.lds);
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
       row[r] = tm.lane + r * S::TEAM;
+      vrow[r] = base + row[r] * 8;
       ok[r] = row[r] < g.n;
-      len[r] = ok[r] ? g.row_len[row[r]] : 0;
-      dslot[r] = ok[r] ? g.diag_slot[row[r]] : -1;
-      lmax = max(lmax, len[r]);
+      const int rr = ok[r] ? row[r] : 0;
+      len[r] = ok[r] ? g.row_len[rr] : 0;
+      dslot[r] = ok[r] ? g.diag_slot[rr] : -1;
+      rp[r] = g.row_ptr[rr];
+#pragma unroll
+      for (int k = 0; k < S::NZ; ++k) {
+        const bool has = k < len[r];
+        const int col = g.slot_col[has ? (size_t)k * g.n + rr : 0];
+        c[r][k] = base + (has ? col * 8 : 0);
+      }
     }
-    nzw = wave_max(lmax);
-    const int64_t vbase = tm.sys * (g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n);
-    const double* vals = g.values + (tm.live ? vbase : 0);
-    const double* stage = reinterpret_cast<const double*>(tm.lds);
+  }
+
+  // This team's values.  CSR values are staged through LDS (one coalesced copy
+  // of the system's contiguous value block, then row reads) or read straight
+  // from HBM; ELL values are read slot by slot, coalesced across the lanes.
+  // Every lane of the workgroup must call it (it syncs when staging).
+  __device__ void load_values(Team<S>& tm, const KArgs& g) {
+    const int64_t per = g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n;
+    const double* vals = g.values + (tm.live ? tm.sys * per : 0);
+    // Per-lane offsets are passed through an empty asm once per system so the
+    // compiler recomputes the per-slot addresses here instead of hoisting them
+    // out of the batch loop, where they would pin registers for the whole kernel.
+    int off[S::R], ln[S::R], ds[S::R];
+#pragma unroll
+    for (int r = 0; r < S::R; ++r) {
+      off[r] = g.fmt == 0 ? rp[r] : row[r];
+      ln[r] = tm.live ? len[r] : 0;
+      ds[r] = tm.live ? dslot[r] : -1;
+      __asm__ volatile("" : "+v"(off[r]), "+v"(ln[r]), "+v"(ds[r]));
+    }
     if (g.fmt == 0 && g.stage) {
-      double* st = reinterpret_cast<double*>(tm.lds);
+      double* st = reinterpret_cast<double*>(tm.stage);
       if (tm.live)
         for (int e = tm.lane; e < g.nnz; e += S::TEAM) st[e] = __builtin_nontemporal_load(vals + e);
       tm.sync();
-    }
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) {
-      const int rp = (ok[r] && g.fmt == 0) ? g.row_ptr[row[r]] : 0;
+      for (int r = 0; r < S::R; ++r)
 #pragma unroll
-      for (int k = 0; k < S::NZ; ++k) {
-        a[r][k] = 0.0;
-        c[r][k] = 0;
-        if (k < nzw) {
-          const bool has = tm.live && k < len[r];
-          if (has) {
-            c[r][k] = g.slot_col[(size_t)k * g.n + row[r]] * 8;
-            if (g.fmt == 0)
-              a[r][k] = g.stage ? stage[rp + k] : __builtin_nontemporal_load(vals + rp + k);
-            else
-              a[r][k] = __builtin_nontemporal_load(vals + (size_t)k * g.n + row[r]);
-          }
+        for (int k = 0; k < S::NZ; ++k) {
+          const bool has = k < ln[r];
+          const double v = st[has ? off[r] + k : 0];
+          a[r][k] = has ? v : 0.0;
         }
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        const double v = st[ds[r] >= 0 ? off[r] + ds[r] : 0];
+        dval[r] = ds[r] >= 0 ? v : 0.0;
+      }
+      tm.sync();  // the staging area is refilled for the next system
+    } else if (g.fmt == 0) {
+#pragma unroll
+      for (int r = 0; r < S::R; ++r)
+#pragma unroll
+        for (int k = 0; k < S::NZ; ++k) {
+          const bool has = k < ln[r];
+          const double v = __builtin_nontemporal_load(vals + (has ? off[r] + k : 0));
+          a[r][k] = has ? v : 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        const double v = vals[ds[r] >= 0 ? off[r] + ds[r] : 0];
+        dval[r] = ds[r] >= 0 ? v : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < S::R; ++r)
+#pragma unroll
+        for (int k = 0; k < S::NZ; ++k) {
+          const bool has = k < ln[r];
+          const double v = __builtin_nontemporal_load(vals + (has ? k * g.n + off[r] : 0));
+          a[r][k] = has ? v : 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        const double v = vals[ds[r] >= 0 ? ds[r] * g.n + off[r] : 0];
+        dval[r] = ds[r] >= 0 ? v : 0.0;
       }
     }
-    if (g.fmt == 0 && g.stage) tm.sync();  // staging area is reused for vectors
   }
 
   // Scalar Jacobi: d = 1/a_ii, 1 where the diagonal is zero or absent; 0 for
@@ -219,32 +283,48 @@ struct Rows {
   __device__ void jacobi(int precond, double (&d)[S::R]) const {
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
-      double dv = 0.0;
-#pragma unroll
-      for (int k = 0; k < S::NZ; ++k)
-        if (k == dslot[r]) dv = a[r][k];
+      const double dv = dval[r];
       d[r] = !ok[r] ? 0.0 : (precond == 1 && dslot[r] >= 0 && dv != 0.0) ? 1.0 / dv : 1.0;
     }
   }
 
   // y = A v.  v is written to the team's vector buffer BUF, the team syncs, and
   // each lane gathers its rows' columns from LDS.  T is the arithmetic type;
-  // the buffer always spaces elements 8 bytes apart.
+  // the buffer always spaces elements 8 bytes apart.  The gathers go out in
+  // groups of kGather (a scheduling barrier between groups bounds the
+  // registers held by loads in flight); four partial sums per row keep the
+  // FMA chains short.
   template <int BUF, class T, class AT>
   __device__ __forceinline__ void spmv(Team<S>& tm, const AT (&av)[S::R][S::NZ],
-                                       const T (&v)[S::R], T (&y)[S::R], int rows) const {
-    char* buf = tm.lds + BUF * rows * 8;
+                                       const T (&v)[S::R], T (&y)[S::R]) const {
+    constexpr int kGather = 8;
+    constexpr unsigned off = BUF * S::ROWS * 8;
 #pragma unroll
     for (int r = 0; r < S::R; ++r)
-      if (ok[r]) *reinterpret_cast<T*>(buf + row[r] * 8) = v[r];
+      if (ok[r]) lds_store<T>(vrow[r] + off, v[r]);
     tm.sync();
+    constexpr int NA = S::NZ >= 4 ? 4 : S::NZ;
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
-      T acc = 0;
+      T acc[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int k = 0; k < S::NZ; ++k)
-        if (k < nzw) acc = fma((T)av[r][k], *reinterpret_cast<const T*>(buf + c[r][k]), acc);
-      y[r] = acc;
+      for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
+        T xv[kGather];
+#pragma unroll
+        for (int k = k0; k < k0 + kGather && k < S::NZ; ++k) xv[k - k0] = lds_load<T>(c[r][k] + off);
+#pragma unroll
+        for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
+          acc[k % NA] = fma((T)av[r][k], xv[k - k0], acc[k % NA]);
+        // finish this group's FMAs before the next group's gathers are issued
+        __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+      }
+      T s = acc[0];
+      if constexpr (NA == 4) s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      else {
+#pragma unroll
+        for (int i = 1; i < NA; ++i) s += acc[i];
+      }
+      y[r] = s;
     }
   }
 };

@@ -11,7 +11,16 @@ hipError_t launch(const KArgs& a, unsigned grid, unsigned lds, hipStream_t strea
   return hipGetLastError();
 }
 
-#define ENTRY(T, R, NZ) {V_BICGSTAB_MIXED, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>>},
+template <class S>
+int occupancy(unsigned lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_bicgstab<S, true>), S::WG,
+                                                   lds) != hipSuccess || n < 1)
+    n = 1;
+  return n;
+}
+
+#define ENTRY(T, R, NZ) {V_BICGSTAB_MIXED, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>>, &occupancy<Shape<T, R, NZ>>},
 const KernelEntry kTable[] = {BS_SHAPES_R1(ENTRY) BS_SHAPES_RN(ENTRY)};
 #undef ENTRY
 

@@ -10,10 +10,13 @@ namespace bs {
 enum Variant { V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_COUNT = 4 };
 
 typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
+// Resident workgroups per compute unit for a given dynamic LDS size.
+typedef int (*OccupancyFn)(unsigned lds);
 
 struct KernelEntry {
   int variant, team, r, nz, wg;
   LaunchFn launch;
+  OccupancyFn occupancy;
 };
 
 struct KernelTable {

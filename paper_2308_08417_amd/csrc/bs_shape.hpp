@@ -1,6 +1,7 @@
 // Kernel shapes and launch arguments shared by the host planner and the HIP
 // kernels of the fused batched solver.
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace bs {
@@ -25,6 +26,7 @@ struct KArgs {
   int n, nnz, width, fmt;      // fmt: 0 CSR, 1 ELL
   int precond, flags, max_iter, restart;
   int stage;                   // CSR values staged through LDS
+  int gmres;                   // GMRES scalars live behind the vector buffers
   int team_bytes;              // LDS bytes per team (>= the team's needs)
   double tol, inner_tol;
   const int* row_ptr;          // [n+1]
@@ -53,13 +55,16 @@ struct Shape {
 // Vector buffers per team (SpMV source vectors, double-buffered).
 constexpr int kVecBuffers = 2;
 
-inline int round16(int b) { return (b + 15) & ~15; }
+__host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
 
-// LDS bytes a team needs for its vectors and solver scalars.
+// LDS bytes of a team's vector buffers and solver scalars; the CSR staging
+// area (if any) follows them.
+__host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres) {
+  return round16(kVecBuffers * rows * 8 + (solver_is_gmres ? kGmresScalars * 8 : 0));
+}
+
 inline int team_lds_bytes(int rows, int solver_is_gmres, int stage_nnz) {
-  int vec = kVecBuffers * rows * 8 + (solver_is_gmres ? kGmresScalars * 8 : 0);
-  int stg = stage_nnz * 8;
-  return round16(vec > stg ? vec : stg);
+  return team_vec_bytes(rows, solver_is_gmres) + round16(stage_nnz * 8);
 }
 
 inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }

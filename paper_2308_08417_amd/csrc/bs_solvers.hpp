@@ -30,7 +30,7 @@ __device__ __forceinline__ void finish(Team<S>& tm, const Rows<S>& A, const KArg
   const bool need = tm.live && !have_rn;
   if (tm.any(need)) {
     double t[S::R], q[1];
-    A.template spmv<0>(tm, A.a, x, t, S::ROWS);
+    A.template spmv<0>(tm, A.a, x, t);
     double p[S::R];
 #pragma unroll
     for (int r = 0; r < S::R; ++r) { const double e = b[r] - t[r]; p[r] = e * e; }
@@ -59,7 +59,6 @@ struct Prologue {
 
 template <class S>
 __device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g, Prologue<S>& P) {
-  A.load(tm, g);
   A.jacobi(g.precond, P.d);
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
@@ -71,7 +70,7 @@ __device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g
   }
   if (!x0zero) {
     double t[S::R];
-    A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+    A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
     for (int r = 0; r < S::R; ++r) P.r[r] = P.b[r] - t[r];
   } else {
@@ -92,14 +91,8 @@ __device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g
 // residual confirmation" becomes the FP64 outer refinement step r = b - A x,
 // which also ends the inner solve when it meets inner_tol or breaks down.
 template <class S, bool MIXED>
-__global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
+__device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
   using T = typename std::conditional<MIXED, float, double>::type;
-  extern __shared__ __align__(16) char smem[];
-  Team<S> tm(smem, g);
-  if constexpr (S::TEAMS == 1) {
-    if (!tm.live) return;  // whole workgroup idle
-  }
-  Rows<S> A;
   Prologue<S> P;
   prologue(tm, A, g, P);
   constexpr int R = S::R;
@@ -201,7 +194,7 @@ __global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
     if (tm.any(need_chk)) {
       // ---- true residual (plain) / outer refinement step (mixed), FP64
       double t[R], pr[R], q[1];
-      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+      A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const double e = P.b[i] - t[i];
@@ -261,7 +254,7 @@ __global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
       p[i] = r[i] + beta * (p[i] - omega * v[i]);
       ph[i] = d_in[i] * p[i];
     }
-    A.template spmv<0>(tm, a_in, ph, v, S::ROWS);
+    A.template spmv<0>(tm, a_in, ph, v);
     T q1[1];
     {
       T pr[R];
@@ -281,7 +274,7 @@ __global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
       s[i] = r[i] - al * v[i];
       sh[i] = d_in[i] * s[i];
     }
-    A.template spmv<1>(tm, a_in, sh, t, S::ROWS);
+    A.template spmv<1>(tm, a_in, sh, t);
     T q3[3];
     {
       T p0[R], p1[R], p2[R];
@@ -350,13 +343,7 @@ __global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
 // Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
 // stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
 template <class S>
-__global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
-  extern __shared__ __align__(16) char smem[];
-  Team<S> tm(smem, g);
-  if constexpr (S::TEAMS == 1) {
-    if (!tm.live) return;
-  }
-  Rows<S> A;
+__device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
   Prologue<S> P;
   prologue(tm, A, g, P);
   constexpr int R = S::R;
@@ -395,7 +382,7 @@ __global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
     }
     if (tm.any(need_chk)) {
       double t[R], rc[R], zc[R], p0[R], p1[R], q[2];
-      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+      A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         rc[i] = P.b[i] - t[i];
@@ -423,7 +410,7 @@ __global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
     bool go = st == ST_RUNNING;
     if (go && rho == 0.0) { st = ST_BREAKDOWN; go = false; }
     double t[R];
-    A.template spmv<0>(tm, A.a, p, t, S::ROWS);
+    A.template spmv<0>(tm, A.a, p, t);
     double q1[1];
     {
       double pr[R];
@@ -477,15 +464,9 @@ __global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
 // changes at every step and is kept in a register.  At the end of a cycle
 // y = R^{-1} g by back substitution and x += M V y.
 template <class S>
-__global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
+__device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
   static_assert(S::R == 1, "GMRES keeps one row per lane");
   constexpr int M = kMaxRestart;
-  extern __shared__ __align__(16) char smem[];
-  Team<S> tm(smem, g);
-  if constexpr (S::TEAMS == 1) {
-    if (!tm.live) return;
-  }
-  Rows<S> A;
   Prologue<S> P;
   prologue(tm, A, g, P);
   const int m = g.restart;
@@ -523,7 +504,7 @@ __global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
     if (tm.any(st == ST_RUNNING && start)) {
       const bool me = st == ST_RUNNING && start;
       double t[1];
-      A.template spmv<0>(tm, A.a, P.x, t, S::ROWS);
+      A.template spmv<0>(tm, A.a, P.x, t);
       const double rc = P.b[0] - t[0];
       double q[1] = {rc * rc};
       tm.sum(q);
@@ -549,7 +530,7 @@ __global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
     for (int i = 1; i < M; ++i)
       if (j == i) vj = V[i];
     double z[1] = {d * vj}, w[1];
-    A.template spmv<0>(tm, A.a, z, w, S::ROWS);
+    A.template spmv<0>(tm, A.a, z, w);
     const int jmax = wave_max(act ? j : -1);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
@@ -626,5 +607,38 @@ __global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
   finish(tm, A, g, P.b, P.x, st, k, 0, bn, rn,
          st == ST_CONVERGED || st == ST_IDLE || (st == ST_MAX_ITER && start));
 }
+
+// =================================================================== kernels
+// Each workgroup loads the shared pattern into registers once and then walks
+// over the batch: teams take systems blockIdx*TEAMS + tix, stepping by the grid.
+#define BS_PERSISTENT_LOOP(CALL)                                                    \
+  extern __shared__ __align__(16) char smem[];                                     \
+  Team<S> tm(smem, g);                                                             \
+  Rows<S> A;                                                                       \
+  A.load_pattern(tm, g);                                                           \
+  const int64_t stride = (int64_t)gridDim.x * S::TEAMS;                            \
+  for (int64_t base = (int64_t)blockIdx.x * S::TEAMS; base < g.n_batch; base += stride) { \
+    tm.sys = base + tm.tix;                                                        \
+    tm.live = tm.sys < g.n_batch;                                                  \
+    A.load_values(tm, g);                                                          \
+    CALL;                                                                          \
+  }
+
+template <class S, bool MIXED>
+__global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
+  BS_PERSISTENT_LOOP((bicgstab_system<S, MIXED>(tm, A, g)))
+}
+
+template <class S>
+__global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
+  BS_PERSISTENT_LOOP((cg_system<S>(tm, A, g)))
+}
+
+template <class S>
+__global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
+  BS_PERSISTENT_LOOP((gmres_system<S>(tm, A, g)))
+}
+
+#undef BS_PERSISTENT_LOOP
 
 }  // namespace bs
