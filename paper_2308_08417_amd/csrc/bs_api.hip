@@ -145,8 +145,8 @@ struct Plan {
   const bs::KernelEntry* k;
 };
 
-int make_plan(bs_format fmt, int n, int nnz, int max_row, bs_solver solver, const bs_options* o,
-              Plan* out) {
+int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver solver,
+              const bs_options* o, Plan* out) {
   const int precision = o ? o->precision : BS_FP64;
   const int variant = variant_of(solver, precision);
   if (variant < 0) return BS_ERR_UNSUPPORTED;
@@ -178,18 +178,17 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, bs_solver solver, cons
   const int rows = team * r;
   const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
   const bool gm = variant == bs::V_GMRES;
+  const int stored = fmt == BS_CSR ? nnz : width * n;
+  const int vec = teams * bs::team_vec_bytes(rows, gm) + bs::red_lds_bytes(waves);
   int stage = 0;
-  if (fmt == BS_CSR && team <= bs::kWave &&
-      teams * bs::team_lds_bytes(rows, gm, nnz) <= kStageBudget)
-    stage = 1;
-  const int tb = bs::team_lds_bytes(rows, gm, stage ? nnz : 0);
+  if (waves == 1 && bs::stage_total_bytes(teams, stored, n) <= kStageBudget) stage = 1;
   out->k = k;
   out->info.team = team;
   out->info.rows_per_lane = r;
   out->info.slots = k->nz;
   out->info.group_size = wg;
   out->info.systems_per_group = teams;
-  out->info.lds_bytes = teams * tb + bs::red_lds_bytes(waves);
+  out->info.lds_bytes = vec + (stage ? bs::stage_total_bytes(teams, stored, n) : 0);
   out->info.stage_values = stage;
   return BS_OK;
 }
@@ -356,7 +355,7 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
       (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES))
     return BS_ERR_INVALID_ARG;
   Plan pl;
-  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, solver, opts, &pl);
+  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, &pl);
   if (rc == BS_OK) *out = pl.info;
   return rc;
 }
@@ -384,7 +383,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (n_batch == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   Plan pl;
-  const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, solver, opts, &pl);
+  const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, pattern->width, solver,
+                           opts, &pl);
   if (rc != BS_OK) return rc;
   bs::KArgs a;
   a.n_batch = n_batch;
@@ -398,8 +398,14 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.restart = restart;
   a.stage = pl.info.stage_values;
   a.gmres = solver == BS_GMRES ? 1 : 0;
-  a.team_bytes = bs::team_lds_bytes(pl.info.team * pl.info.rows_per_lane, solver == BS_GMRES,
-                                    pl.info.stage_values ? pattern->nnz : 0);
+  {
+    const int rows = pl.info.team * pl.info.rows_per_lane;
+    const int teams = pl.info.systems_per_group, waves = pl.info.group_size / bs::kWave;
+    const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
+    a.team_bytes = bs::team_vec_bytes(rows, a.gmres);
+    a.stage_team_bytes = bs::stage_team_bytes(stored, pattern->n);
+    a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
+  }
   a.tol = tol;
   a.inner_tol = inner_tol;
   a.row_ptr = pattern->d_row_ptr;

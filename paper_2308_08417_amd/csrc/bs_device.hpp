@@ -105,7 +105,8 @@ struct Team {
   int64_t sys;      // system being solved
   bool live;        // sys < n_batch
   char* lds;        // this team's LDS region (vector buffers, solver scalars)
-  char* stage;      // this team's staging area for CSR values
+  char* stage_all;  // the group's staging area (single-wave groups)
+  char* stage;      // this team's part of it: values, then b
   double* red;      // cross-wave reduction slots (multi-wave teams)
   int phase;        // which half of `red` the next reduction uses
 
@@ -116,13 +117,25 @@ struct Team {
     sys = -1;
     live = false;
     lds = smem + (size_t)tix * a.team_bytes;
-    stage = lds + team_vec_bytes(S::ROWS, a.gmres);
+    stage_all = smem + a.stage_offset;
+    stage = stage_all + (size_t)tix * a.stage_team_bytes;
     red = reinterpret_cast<double*>(smem + (size_t)S::TEAMS * a.team_bytes);
     phase = 0;
   }
 
-  // Make this team's LDS writes visible to all of its lanes.
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+  // Make this team's LDS writes visible to all of its lanes.  A single-wave
+  // group needs no barrier: a wave's LDS operations complete in issue order,
+  // so only the compiler must keep them in order (wavefront-scope LDS fence).
+  // That also keeps the wait off the direct-to-LDS prefetch in flight, which a
+  // workgroup-scope fence would have to drain.
+  __device__ __forceinline__ void sync() {
+    if constexpr (S::WAVES == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      __syncthreads();
+    }
+  }
 
   // In-place sum of K per-lane partials over the team; every lane of the team
   // receives the same bits.  All lanes of the workgroup must call it together.
@@ -188,6 +201,8 @@ struct Rows {
   int dslot[S::R];
   int rp[S::R];    // CSR offset of the row's first entry
   double dval[S::R];  // the row's stored diagonal value (0 if none)
+  double bval[S::R];  // right-hand side of the row (0 past the last row)
+  double xval[S::R];  // initial guess of the row (0 when x0 = 0 is promised)
 
   // The shared pattern, once per kernel: it is the same for every system.
   __device__ void load_pattern(const Team<S>& tm, const KArgs& g) {
@@ -206,75 +221,124 @@ struct Rows {
         const bool has = k < len[r];
         const int col = g.slot_col[has ? (size_t)k * g.n + rr : 0];
         c[r][k] = base + (has ? col * 8 : 0);
+        // keep the full address in the register: otherwise the compiler keeps
+        // col*8 and re-adds the (link-time) LDS base before every gather
+        __asm__ volatile("" : "+v"(c[r][k]));
       }
+      __asm__ volatile("" : "+v"(vrow[r]));
     }
   }
 
-  // This team's values.  CSR values are staged through LDS (one coalesced copy
-  // of the system's contiguous value block, then row reads) or read straight
-  // from HBM; ELL values are read slot by slot, coalesced across the lanes.
-  // Every lane of the workgroup must call it (it syncs when staging).
+  // Prefetch the values and right-hand sides of the systems base..base+TEAMS-1
+  // into the group's staging area with direct global-to-LDS dword loads: each
+  // instruction of the wave fills 256 contiguous bytes, lane l its 4 bytes at
+  // offset 4l, from a source address chosen per lane.  Nothing is read past a
+  // block's end; bytes beyond the teams' blocks receive a harmless copy of the
+  // first value.  Single-wave groups only.
+  __device__ __forceinline__ void prefetch(const Team<S>& tm, const KArgs& g, int64_t base) const {
+    static_assert(S::WAVES == 1, "prefetch is for single-wave groups");
+    const int per = g.fmt == 0 ? g.nnz : g.width * g.n;
+    const unsigned vs = (unsigned)per * 8, ts = (unsigned)g.stage_team_bytes;
+    const unsigned bsz = (unsigned)g.n * 8;
+    const unsigned region = ts * S::TEAMS;
+    const unsigned l4 = 4u * (unsigned)lane_id();
+    const char* dflt = reinterpret_cast<const char*>(g.values);
+    for (unsigned d0 = 0; d0 < region; d0 += 256) {
+      unsigned o = d0 + l4;
+      int t = 0;
+#pragma unroll
+      for (int i = 1; i < S::TEAMS; ++i)
+        if (o >= ts) { o -= ts; ++t; }
+      const int64_t sy = base + t;
+      const char* src = dflt;
+      if (d0 + l4 < region && sy < g.n_batch) {
+        if (o < vs) src = reinterpret_cast<const char*>(g.values + sy * per) + o;
+        else if (o < vs + bsz) src = reinterpret_cast<const char*>(g.b + sy * g.n) + (o - vs);
+      }
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(tm.stage_all + d0),
+                                       4, 0, 0);
+    }
+  }
+
+  // This team's values and right-hand side.  Staged groups read them from the
+  // prefetched LDS block (CSR: row offset + slot; ELL: slot*n + row); other
+  // groups read HBM directly, coalesced across lanes for ELL.
   __device__ void load_values(Team<S>& tm, const KArgs& g) {
     const int64_t per = g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n;
     const double* vals = g.values + (tm.live ? tm.sys * per : 0);
     // Per-lane offsets are passed through an empty asm once per system so the
     // compiler recomputes the per-slot addresses here instead of hoisting them
     // out of the batch loop, where they would pin registers for the whole kernel.
-    int off[S::R], ln[S::R], ds[S::R];
+    int off[S::R], ln[S::R], ds[S::R], rw[S::R];
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
       off[r] = g.fmt == 0 ? rp[r] : row[r];
       ln[r] = tm.live ? len[r] : 0;
       ds[r] = tm.live ? dslot[r] : -1;
-      __asm__ volatile("" : "+v"(off[r]), "+v"(ln[r]), "+v"(ds[r]));
+      rw[r] = (tm.live && ok[r]) ? row[r] : -1;
+      __asm__ volatile("" : "+v"(off[r]), "+v"(ln[r]), "+v"(ds[r]), "+v"(rw[r]));
     }
-    if (g.fmt == 0 && g.stage) {
-      double* st = reinterpret_cast<double*>(tm.stage);
-      if (tm.live)
-        for (int e = tm.lane; e < g.nnz; e += S::TEAM) st[e] = __builtin_nontemporal_load(vals + e);
-      tm.sync();
+    const int step = g.fmt == 0 ? 1 : g.n;
+    if constexpr (S::WAVES == 1) {
+      if (g.stage) {
+        const double* st = reinterpret_cast<const double*>(tm.stage);
 #pragma unroll
-      for (int r = 0; r < S::R; ++r)
+        for (int r = 0; r < S::R; ++r) {
 #pragma unroll
-        for (int k = 0; k < S::NZ; ++k) {
-          const bool has = k < ln[r];
-          const double v = st[has ? off[r] + k : 0];
-          a[r][k] = has ? v : 0.0;
+          for (int k = 0; k < S::NZ; ++k) {
+            const bool has = k < ln[r];
+            const double v = st[has ? off[r] + k * step : 0];
+            a[r][k] = has ? v : 0.0;
+          }
+          const double dv = st[ds[r] >= 0 ? off[r] + ds[r] * step : 0];
+          dval[r] = ds[r] >= 0 ? dv : 0.0;
+          const double bv = st[per + (rw[r] >= 0 ? rw[r] : 0)];
+          bval[r] = rw[r] >= 0 ? bv : 0.0;
         }
-#pragma unroll
-      for (int r = 0; r < S::R; ++r) {
-        const double v = st[ds[r] >= 0 ? off[r] + ds[r] : 0];
-        dval[r] = ds[r] >= 0 ? v : 0.0;
+        load_x0(tm, g, rw);
+        return;
       }
-      tm.sync();  // the staging area is refilled for the next system
-    } else if (g.fmt == 0) {
+    }
+    const double* bb = g.b + (tm.live ? tm.sys * g.n : 0);
 #pragma unroll
-      for (int r = 0; r < S::R; ++r)
+    for (int r = 0; r < S::R; ++r) {
 #pragma unroll
-        for (int k = 0; k < S::NZ; ++k) {
-          const bool has = k < ln[r];
-          const double v = __builtin_nontemporal_load(vals + (has ? off[r] + k : 0));
-          a[r][k] = has ? v : 0.0;
-        }
-#pragma unroll
-      for (int r = 0; r < S::R; ++r) {
-        const double v = vals[ds[r] >= 0 ? off[r] + ds[r] : 0];
-        dval[r] = ds[r] >= 0 ? v : 0.0;
+      for (int k = 0; k < S::NZ; ++k) {
+        const bool has = k < ln[r];
+        const double v = __builtin_nontemporal_load(vals + (has ? off[r] + k * step : 0));
+        a[r][k] = has ? v : 0.0;
       }
-    } else {
+      const double dv = vals[ds[r] >= 0 ? off[r] + ds[r] * step : 0];
+      dval[r] = ds[r] >= 0 ? dv : 0.0;
+      const double bv = bb[rw[r] >= 0 ? rw[r] : 0];
+      bval[r] = rw[r] >= 0 ? bv : 0.0;
+    }
+    // Complete these loads here: the registers are shared with the staged path,
+    // and a load left pending would make the compiler wait on the in-order
+    // memory counter later, which would also drain the prefetch in flight.
 #pragma unroll
-      for (int r = 0; r < S::R; ++r)
+    for (int r = 0; r < S::R; ++r) {
 #pragma unroll
-        for (int k = 0; k < S::NZ; ++k) {
-          const bool has = k < ln[r];
-          const double v = __builtin_nontemporal_load(vals + (has ? k * g.n + off[r] : 0));
-          a[r][k] = has ? v : 0.0;
-        }
+      for (int k = 0; k < S::NZ; ++k) settle(a[r][k]);
+      settle(dval[r]);
+      settle(bval[r]);
+    }
+    load_x0(tm, g, rw);
+  }
+
+  static __device__ __forceinline__ void settle(double& v) { __asm__ volatile("" : "+v"(v)); }
+
+  // The initial guess is read here, before the next prefetch is issued, so a
+  // wait for it never waits behind that prefetch.
+  __device__ __forceinline__ void load_x0(const Team<S>& tm, const KArgs& g, const int (&rw)[S::R]) {
+    const bool zero = (g.flags & 1) != 0;
+    const double* xx = g.x + (tm.live ? tm.sys * g.n : 0);
 #pragma unroll
-      for (int r = 0; r < S::R; ++r) {
-        const double v = vals[ds[r] >= 0 ? ds[r] * g.n + off[r] : 0];
-        dval[r] = ds[r] >= 0 ? v : 0.0;
-      }
+    for (int r = 0; r < S::R; ++r) {
+      double xv = 0.0;
+      if (!zero && rw[r] >= 0) xv = xx[rw[r]];
+      settle(xv);  // completed before the next prefetch is issued
+      xval[r] = xv;
     }
   }
 
@@ -297,7 +361,7 @@ struct Rows {
   template <int BUF, class T, class AT>
   __device__ __forceinline__ void spmv(Team<S>& tm, const AT (&av)[S::R][S::NZ],
                                        const T (&v)[S::R], T (&y)[S::R]) const {
-    constexpr int kGather = 8;
+    constexpr int kGather = 4;
     constexpr unsigned off = BUF * S::ROWS * 8;
 #pragma unroll
     for (int r = 0; r < S::R; ++r)

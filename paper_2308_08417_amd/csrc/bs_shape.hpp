@@ -25,9 +25,11 @@ struct KArgs {
   int64_t n_batch;
   int n, nnz, width, fmt;      // fmt: 0 CSR, 1 ELL
   int precond, flags, max_iter, restart;
-  int stage;                   // CSR values staged through LDS
+  int stage;                   // values and b prefetched into LDS (single-wave groups)
   int gmres;                   // GMRES scalars live behind the vector buffers
-  int team_bytes;              // LDS bytes per team (>= the team's needs)
+  int team_bytes;              // LDS bytes per team for vectors and scalars
+  int stage_team_bytes;        // LDS staging bytes per team (values then b)
+  int stage_offset;            // byte offset of the staging area in LDS
   double tol, inner_tol;
   const int* row_ptr;          // [n+1]
   const int* slot_col;         // [width][n], -1 padding
@@ -50,6 +52,10 @@ struct Shape {
   static constexpr int TEAMS = WG / TEAM;  // systems per workgroup
   static constexpr int WAVES = WG / kWave;
   static constexpr int ROWS = TEAM * R;    // largest system a team holds
+  // Waves per SIMD the register allocator is asked to fit: single-wave groups
+  // with up to 32 slots per row are held to 3 (at most 168 VGPRs), which keeps
+  // enough waves resident to hide the reductions' latency.
+  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ == 32) ? 3 : 1;
 };
 
 // Vector buffers per team (SpMV source vectors, double-buffered).
@@ -63,10 +69,14 @@ __host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres) {
   return round16(kVecBuffers * rows * 8 + (solver_is_gmres ? kGmresScalars * 8 : 0));
 }
 
-inline int team_lds_bytes(int rows, int solver_is_gmres, int stage_nnz) {
-  return team_vec_bytes(rows, solver_is_gmres) + round16(stage_nnz * 8);
-}
-
 inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }
+
+// Staging of one team: its system's values (`stored` doubles) then its b (n
+// doubles); the whole staging area of a group is a multiple of 256 bytes, the
+// span of one direct-to-LDS load instruction of a wave.
+inline int stage_team_bytes(int stored, int n) { return round16((stored + n) * 8); }
+inline int stage_total_bytes(int teams, int stored, int n) {
+  return (teams * stage_team_bytes(stored, n) + 255) & ~255;
+}
 
 }  // namespace bs

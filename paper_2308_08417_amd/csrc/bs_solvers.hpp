@@ -63,10 +63,8 @@ __device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
   for (int r = 0; r < S::R; ++r) {
-    const bool ok = tm.live && A.ok[r];
-    const size_t off = ok ? (size_t)tm.sys * g.n + A.row[r] : 0;
-    P.b[r] = ok ? g.b[off] : 0.0;
-    P.x[r] = (ok && !x0zero) ? g.x[off] : 0.0;
+    P.b[r] = A.bval[r];
+    P.x[r] = A.xval[r];
   }
   if (!x0zero) {
     double t[S::R];
@@ -135,7 +133,7 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
 
   // Krylov state.
   T r[R], rh[R], p[R], v[R];
-  T rho, rho0, alpha, omega, rn_in;
+  T rho, rho0, alpha, omega, rr_in;  // rr_in: squared norm of the inner residual
   double scale;  // x += scale * (inner update)
   double rn_prev = rn;
   auto restart = [&](double rtrue_norm) {
@@ -160,10 +158,10 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
     q[0] = sum_rows(pr);
     tm.sum(q);
     rho = q[0];
-    rn_in = sqrt(q[0]);
+    rr_in = q[0];
   } else {
     rho = (T)q2[1];  // r^ = r, so r^.r is the same sum as r.r
-    rn_in = (T)rn;
+    rr_in = (T)q2[1];
   }
   // Inner stop level: absolute on the same scale as r_in.
   auto inner_lim = [&]() -> T {
@@ -174,16 +172,19 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
       return (T)lim;
     }
   };
+  // The recurrence tests compare squared norms (no square root per test);
+  // the true-residual confirmation below compares the norm itself.
   T ilim = inner_lim();
+  T ilim2 = ilim * ilim;
   bool inner_end = false;  // MIXED: inner solve ended (met inner tol or broke down)
 
   for (;;) {
     // ---- top: convergence / budget checks, per team
     bool need_chk = false;
     if (st == ST_RUNNING) {
-      if (MIXED ? !finite(rn) : !finite((double)rn_in)) {
+      if (MIXED ? !finite(rn) : !finite((double)rr_in)) {
         st = ST_NONFINITE;
-      } else if (MIXED ? (rn <= lim || inner_end || rn_in <= ilim) : (rn_in <= ilim)) {
+      } else if (MIXED ? (rn <= lim || inner_end || rr_in <= ilim2) : (rr_in <= ilim2)) {
         if (!MIXED && rtrue) st = ST_CONVERGED;
         else if (MIXED && rtrue && rn <= lim) st = ST_CONVERGED;
         else need_chk = true;
@@ -218,6 +219,7 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
           restart(rnc);
           inner_end = false;
           ilim = inner_lim();
+          ilim2 = ilim * ilim;
         }
       }
       if constexpr (MIXED) {
@@ -227,9 +229,9 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
         for (int i = 0; i < R; ++i) pp[i] = r[i] * r[i];
         qq[0] = sum_rows(pp);
         tm.sum(qq);
-        if (need_chk && st == ST_RUNNING) { rho = qq[0]; rn_in = sqrt(qq[0]); }
+        if (need_chk && st == ST_RUNNING) { rho = qq[0]; rr_in = qq[0]; }
       } else {
-        if (need_chk && st == ST_RUNNING) { rho = (T)q[0]; rn_in = (T)rn; }
+        if (need_chk && st == ST_RUNNING) { rho = (T)q[0]; rr_in = (T)q[0]; }
       }
       continue;
     }
@@ -247,7 +249,7 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
         go = false;
       }
     }
-    const T beta = (rho / rho0) * (alpha / omega);
+    const T beta = (rho * alpha) / (rho0 * omega);
     T ph[R], s[R], sh[R], t[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
@@ -285,11 +287,11 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
       q3[2] = sum_rows(p2);
     }
     tm.sum(q3);
-    const T sn = sqrt(q3[0]), tt = q3[1], ts = q3[2];
+    const T ss = q3[0], tt = q3[1], ts = q3[2];
     bool half = false;
     if (go) {
-      if (!finite((double)sn)) { if (MIXED) inner_end = true; else st = ST_NONFINITE; go = false; }
-      else if (sn <= ilim) half = true;
+      if (!finite((double)ss)) { if (MIXED) inner_end = true; else st = ST_NONFINITE; go = false; }
+      else if (ss <= ilim2) half = true;
       else if (!finite((double)tt) || !finite((double)ts)) {
         if (MIXED) inner_end = true; else st = ST_NONFINITE;
         go = false;
@@ -303,7 +305,7 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
         r[i] = s[i];
       }
       rtrue = false;
-      rn_in = sn;
+      rr_in = ss;
       go = false;
     }
     const T om = (tt == (T)0) ? (T)0 : ts / tt;
@@ -329,9 +331,9 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
     }
     tm.sum(q4);
     if (go) {
-      rn_in = sqrt(q4[0]);
+      rr_in = q4[0];
       rho = q4[1];
-      if (om == (T)0 && !(rn_in <= ilim)) {
+      if (om == (T)0 && !(rr_in <= ilim2)) {
         if (MIXED) inner_end = true; else st = ST_BREAKDOWN;
       }
     }
@@ -360,7 +362,8 @@ __device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& 
   tm.sum(q3);
   const double bn = sqrt(q3[0]);
   double rn = sqrt(q3[1]), rho = q3[2];
-  const double lim = g.tol * bn;
+  double rsq = q3[1];  // squared recurrence residual (the loop compares squares)
+  const double lim = g.tol * bn, lim2 = lim * lim;
   int st = tm.live ? ST_RUNNING : ST_IDLE;
   if (st == ST_RUNNING) {
     if (!finite(bn)) st = ST_NONFINITE;
@@ -376,8 +379,8 @@ __device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& 
   for (;;) {
     bool need_chk = false;
     if (st == ST_RUNNING) {
-      if (!finite(rn) || !finite(rho)) st = ST_NONFINITE;
-      else if (rn <= lim) { if (rtrue) st = ST_CONVERGED; else need_chk = true; }
+      if (!finite(rsq) || !finite(rho)) st = ST_NONFINITE;
+      else if (rsq <= lim2) { if (rtrue) st = ST_CONVERGED; else need_chk = true; }
       else if (k >= g.max_iter) st = ST_MAX_ITER;
     }
     if (tm.any(need_chk)) {
@@ -394,6 +397,7 @@ __device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& 
       tm.sum(q);
       if (need_chk) {
         rn = sqrt(q[0]);
+        rsq = q[0];
         rtrue = true;
         if (!finite(rn)) st = ST_NONFINITE;
         else if (rn <= lim) st = ST_CONVERGED;
@@ -445,7 +449,7 @@ __device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& 
 #pragma unroll
       for (int i = 0; i < R; ++i) { P.r[i] = rr[i]; p[i] = fma(beta, p[i], z[i]); }
       rho = q2[0];
-      rn = sqrt(q2[1]);
+      rsq = q2[1];
       rtrue = false;
       k += 1;
     }
@@ -611,31 +615,50 @@ __device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArg
 // =================================================================== kernels
 // Each workgroup loads the shared pattern into registers once and then walks
 // over the batch: teams take systems blockIdx*TEAMS + tix, stepping by the grid.
+// Single-wave groups prefetch the next round's systems into LDS while the
+// current round is solved: wait for the prefetch, copy the block into registers,
+// wait for those LDS reads, start the next prefetch, solve.
 #define BS_PERSISTENT_LOOP(CALL)                                                    \
   extern __shared__ __align__(16) char smem[];                                     \
   Team<S> tm(smem, g);                                                             \
   Rows<S> A;                                                                       \
   A.load_pattern(tm, g);                                                           \
   const int64_t stride = (int64_t)gridDim.x * S::TEAMS;                            \
+  bool staged = false;                                                             \
+  if constexpr (S::WAVES == 1) {                                                   \
+    staged = g.stage != 0;                                                         \
+    if (staged) A.prefetch(tm, g, (int64_t)blockIdx.x * S::TEAMS);                 \
+  }                                                                                \
   for (int64_t base = (int64_t)blockIdx.x * S::TEAMS; base < g.n_batch; base += stride) { \
     tm.sys = base + tm.tix;                                                        \
     tm.live = tm.sys < g.n_batch;                                                  \
+    if (staged) { /* the prefetch of this round has landed */                      \
+      __builtin_amdgcn_s_waitcnt(0);                                               \
+      __asm__ volatile("" ::: "memory");                                           \
+    }                                                                              \
     A.load_values(tm, g);                                                          \
+    if constexpr (S::WAVES == 1) {                                                 \
+      if (staged && base + stride < g.n_batch) {                                   \
+        __builtin_amdgcn_s_waitcnt(0xC07F); /* staging reads done (lgkmcnt 0) */   \
+        __asm__ volatile("" ::: "memory");                                         \
+        A.prefetch(tm, g, base + stride);                                          \
+      }                                                                            \
+    }                                                                              \
     CALL;                                                                          \
   }
 
 template <class S, bool MIXED>
-__global__ __launch_bounds__(S::WG) void k_bicgstab(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_bicgstab(const KArgs g) {
   BS_PERSISTENT_LOOP((bicgstab_system<S, MIXED>(tm, A, g)))
 }
 
 template <class S>
-__global__ __launch_bounds__(S::WG) void k_cg(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
   BS_PERSISTENT_LOOP((cg_system<S>(tm, A, g)))
 }
 
 template <class S>
-__global__ __launch_bounds__(S::WG) void k_gmres(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_gmres(const KArgs g) {
   BS_PERSISTENT_LOOP((gmres_system<S>(tm, A, g)))
 }
 

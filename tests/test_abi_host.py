@@ -132,8 +132,12 @@ def test_plan_stage_and_limits(L):
     p = bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB)
     assert p["team"] == 64 and p["slots"] == 32 and p["stage_values"] == 1
     assert p["lds_bytes"] >= 1042 * 8
+    # single-wave groups prefetch each system's values and b into LDS
     p = bs.bs_plan(bs.ELL, 54, 1042, 28, bs.BICGSTAB)
-    assert p["stage_values"] == 0
+    assert p["stage_values"] == 1 and p["lds_bytes"] >= (28 * 54 + 54) * 8
+    # multi-wave teams read HBM directly
+    p = bs.bs_plan(bs.ELL, 992, 8554, 9, bs.BICGSTAB)
+    assert p["group_size"] == 1024 and p["stage_values"] == 0
     with pytest.raises(bs.BatchSolveError) as e:
         bs.bs_plan(bs.CSR, 54, 1042, 65, bs.BICGSTAB)
     assert e.value.code == bs.ERR_UNSUPPORTED
