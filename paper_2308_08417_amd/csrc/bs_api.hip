@@ -181,14 +181,14 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const int vec = teams * bs::team_vec_bytes(rows, gm) + bs::red_lds_bytes(waves);
   int stage = 0;
-  if (waves == 1 && bs::stage_total_bytes(teams, stored, n) <= kStageBudget) stage = 1;
+  if (waves == 1 && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget) stage = 1;
   out->k = k;
   out->info.team = team;
   out->info.rows_per_lane = r;
   out->info.slots = k->nz;
   out->info.group_size = wg;
   out->info.systems_per_group = teams;
-  out->info.lds_bytes = vec + (stage ? bs::stage_total_bytes(teams, stored, n) : 0);
+  out->info.lds_bytes = vec + (stage ? bs::stage_total_bytes(teams, stored, n, k->nz) : 0);
   out->info.stage_values = stage;
   return BS_OK;
 }
@@ -403,8 +403,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     const int teams = pl.info.systems_per_group, waves = pl.info.group_size / bs::kWave;
     const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
     a.team_bytes = bs::team_vec_bytes(rows, a.gmres);
-    a.stage_team_bytes = bs::stage_team_bytes(stored, pattern->n);
+    a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
+    a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
+    // CSR rows go through a fixed window when the block holds a full window
+    a.window = (fmt == BS_CSR && pattern->nnz >= pl.info.slots) ? 1 : 0;
   }
   a.tol = tol;
   a.inner_tol = inner_tol;

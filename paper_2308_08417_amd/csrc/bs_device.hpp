@@ -24,19 +24,21 @@ enum : int {
 };
 
 // ---------------------------------------------------------------- cross-lane
+// DPP moves with bound control: lanes whose source is outside the pattern read
+// zero, so no old value has to be materialised.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ int dpp(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ double rdlane(double v, int l) {
@@ -52,7 +54,7 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 // value to its mirror partner's (quad_perm [1,0,3,2], [2,3,0,1], half-row
 // mirror, row mirror).  Each pairwise sum is formed as a+b in one lane and b+a in
 // the other, which IEEE addition makes bit-identical, so all 16 lanes end with
-// the same bits -- the scalars of a team never diverge between its lanes.
+// the same bits.
 template <class T>
 __device__ __forceinline__ T row16_sum(T v) {
   v = v + dpp<0xB1>(v);
@@ -60,6 +62,17 @@ __device__ __forceinline__ T row16_sum(T v) {
   v = v + dpp<0x141>(v);
   v = v + dpp<0x140>(v);
   return v;
+}
+
+// Combine the four row sums S0..S3 (all lanes of row r hold S_r): row_bcast:15
+// adds the previous row's sum (row 1 then holds S1+S0, row 3 holds S3+S2);
+// row_bcast:31 adds lane 31 to row 3, so lane 63 holds (S3+S2)+(S1+S0).
+template <class T>
+__device__ __forceinline__ T rows_pairs(T v) { return v + dpp<0x142>(v); }
+template <class T>
+__device__ __forceinline__ T rows_total(T v) {
+  v = rows_pairs(v);
+  return v + dpp<0x143>(v);
 }
 
 __device__ __forceinline__ int row16_max(int v) {
@@ -144,20 +157,17 @@ struct Team {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = row16_sum(v[k]);
     if constexpr (S::TEAM == 32) {
+      // teams are rows {0,1} and {2,3}: their sums end in lanes 31 and 63
       const bool hi = lane_id() >= 32;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const T s0 = rdlane(v[k], 0), s1 = rdlane(v[k], 16);
-        const T s2 = rdlane(v[k], 32), s3 = rdlane(v[k], 48);
-        v[k] = hi ? (s2 + s3) : (s0 + s1);
+        const T p = rows_pairs(v[k]);
+        const T s01 = rdlane(p, 31), s23 = rdlane(p, 63);
+        v[k] = hi ? s23 : s01;
       }
     } else if constexpr (S::TEAM >= 64) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const T s0 = rdlane(v[k], 0), s1 = rdlane(v[k], 16);
-        const T s2 = rdlane(v[k], 32), s3 = rdlane(v[k], 48);
-        v[k] = (s0 + s1) + (s2 + s3);
-      }
+      for (int k = 0; k < K; ++k) v[k] = rdlane(rows_total(v[k]), 63);
       if constexpr (S::WAVES > 1) {
         static_assert(K <= kMaxFused, "too many fused values");
         double* buf = red + phase * (kMaxFused * S::WAVES);
@@ -185,11 +195,18 @@ struct Team {
 };
 
 // ---------------------------------------------------------------- sparse rows
-// The rows a lane owns, held in registers: values a[r][k] of slot k of row
-// (lane + r*TEAM), and the LDS address of that slot's column in the team's
-// first vector buffer (8 bytes per element).  Slots past a row's end hold a
-// zero value and column 0, so every SpMV runs over all NZ slots without
-// branches.
+// The rows a lane owns, held in registers: values a[r][k] of register slot k
+// of row (lane + r*TEAM), and the LDS address that slot gathers from in the
+// team's first vector buffer (8 bytes per element).  Slots that hold no entry
+// of the row gather from the buffer's zero cell, so every SpMV runs over all NZ
+// slots without branches.
+//
+// CSR rows are read through a window: slot k holds the value at CSR position
+// w + k, where w = min(row start, nnz - NZ) keeps the window inside the
+// system's block.  The row's own entries sit in slots shift .. shift+len-1
+// (shift = row start - w); the other slots hold neighbouring rows' values,
+// which meet the zero cell.  Each slot is then one LDS read at a constant
+// offset.  ELL rows use slot k for the row's k-th stored entry.
 template <class S>
 struct Rows {
   double a[S::R][S::NZ];
@@ -198,15 +215,23 @@ struct Rows {
   int row[S::R];
   bool ok[S::R];   // row < n
   int len[S::R];
-  int dslot[S::R];
-  int rp[S::R];    // CSR offset of the row's first entry
+  int dslot[S::R];  // slot of the stored diagonal, -1 if none
+  int w[S::R];      // CSR: first position of the read window; ELL: the row
   double dval[S::R];  // the row's stored diagonal value (0 if none)
   double bval[S::R];  // right-hand side of the row (0 past the last row)
   double xval[S::R];  // initial guess of the row (0 when x0 = 0 is promised)
 
+  static constexpr unsigned kBuf = vec_buf_bytes(S::ROWS);  // bytes per vector buffer
+
   // The shared pattern, once per kernel: it is the same for every system.
+  // Also clears the team's zero cells.
   __device__ void load_pattern(const Team<S>& tm, const KArgs& g) {
     const unsigned base = lds_addr(tm.lds);
+    const unsigned zero = base + S::ROWS * 8;
+    if (tm.lane == 0) {
+#pragma unroll
+      for (int b = 0; b < kVecBuffers; ++b) lds_store<double>(zero + b * kBuf, 0.0);
+    }
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
       row[r] = tm.lane + r * S::TEAM;
@@ -214,13 +239,22 @@ struct Rows {
       ok[r] = row[r] < g.n;
       const int rr = ok[r] ? row[r] : 0;
       len[r] = ok[r] ? g.row_len[rr] : 0;
-      dslot[r] = ok[r] ? g.diag_slot[rr] : -1;
-      rp[r] = g.row_ptr[rr];
+      const int ds = ok[r] ? g.diag_slot[rr] : -1;
+      const int rp = g.row_ptr[rr];
+      int shift = 0;
+      if (g.fmt == 0) {
+        w[r] = g.window ? max(0, min(rp, g.nnz - S::NZ)) : rp;
+        shift = rp - w[r];
+      } else {
+        w[r] = rr;
+      }
+      dslot[r] = ds >= 0 ? ds + shift : -1;
 #pragma unroll
       for (int k = 0; k < S::NZ; ++k) {
-        const bool has = k < len[r];
-        const int col = g.slot_col[has ? (size_t)k * g.n + rr : 0];
-        c[r][k] = base + (has ? col * 8 : 0);
+        const int j = k - shift;  // entry of the row held by slot k
+        const bool has = j >= 0 && j < len[r];
+        const int col = g.slot_col[has ? (size_t)j * g.n + rr : 0];
+        c[r][k] = has ? base + col * 8 : zero;
         // keep the full address in the register: otherwise the compiler keeps
         // col*8 and re-adds the (link-time) LDS base before every gather
         __asm__ volatile("" : "+v"(c[r][k]));
@@ -230,83 +264,129 @@ struct Rows {
   }
 
   // Prefetch the values and right-hand sides of the systems base..base+TEAMS-1
-  // into the group's staging area with direct global-to-LDS dword loads: each
-  // instruction of the wave fills 256 contiguous bytes, lane l its 4 bytes at
-  // offset 4l, from a source address chosen per lane.  Nothing is read past a
-  // block's end; bytes beyond the teams' blocks receive a harmless copy of the
-  // first value.  Single-wave groups only.
+  // into the group's staging area with direct global-to-LDS loads of 16 bytes
+  // per lane: each instruction of the wave fills 1 KiB of LDS, lane l the 16
+  // bytes at offset 16l, from a source chosen per lane.  Every block is copied
+  // as the 16-byte-aligned chunks that overlap it; such a chunk never crosses a
+  // page, so reading all of it is safe, and its bytes outside the block land
+  // outside the block's LDS range.  Single-wave groups only.
   __device__ __forceinline__ void prefetch(const Team<S>& tm, const KArgs& g, int64_t base) const {
     static_assert(S::WAVES == 1, "prefetch is for single-wave groups");
     const int per = g.fmt == 0 ? g.nnz : g.width * g.n;
-    const unsigned vs = (unsigned)per * 8, ts = (unsigned)g.stage_team_bytes;
-    const unsigned bsz = (unsigned)g.n * 8;
-    const unsigned region = ts * S::TEAMS;
-    const unsigned l4 = 4u * (unsigned)lane_id();
-    const char* dflt = reinterpret_cast<const char*>(g.values);
-    for (unsigned d0 = 0; d0 < region; d0 += 256) {
-      unsigned o = d0 + l4;
-      int t = 0;
+    const unsigned l16 = 16u * (unsigned)lane_id();
+    const unsigned vr = (unsigned)g.stage_vals_bytes;
+    typedef __attribute__((address_space(3))) void lds_void;
+    if constexpr (S::TEAMS == 1) {
+      // one system per wave: each region is a run of whole KiB; lanes past the
+      // block's last chunk fetch that chunk again
+      const uintptr_t v0 = (uintptr_t)(g.values + base * per);
+      const uintptr_t va = v0 & ~(uintptr_t)15;
+      const unsigned vlast = (unsigned)(((v0 + (uintptr_t)per * 8 - 1) & ~(uintptr_t)15) - va);
+      for (unsigned d0 = 0; d0 < vr; d0 += 1024)
+        __builtin_amdgcn_global_load_lds((const void*)(va + min(d0 + l16, vlast)),
+                                         (lds_void*)(tm.stage_all + d0), 16, 0, 0);
+      const uintptr_t b0 = (uintptr_t)(g.b + base * g.n);
+      const uintptr_t ba = b0 & ~(uintptr_t)15;
+      const unsigned blast = (unsigned)(((b0 + (uintptr_t)g.n * 8 - 1) & ~(uintptr_t)15) - ba);
+      const unsigned br = (unsigned)g.stage_team_bytes - vr;
+      for (unsigned d0 = 0; d0 < br; d0 += 1024)
+        __builtin_amdgcn_global_load_lds((const void*)(ba + min(d0 + l16, blast)),
+                                         (lds_void*)(tm.stage_all + vr + d0), 16, 0, 0);
+    } else {
+      // several teams per wave: map every lane's 16 destination bytes to its
+      // team, region and chunk; lanes with nothing to fetch re-read the values
+      // array's first chunk
+      const unsigned ts = (unsigned)g.stage_team_bytes;
+      const unsigned region = ts * S::TEAMS;
+      const uintptr_t dflt = (uintptr_t)g.values & ~(uintptr_t)15;
+      for (unsigned d0 = 0; d0 < region; d0 += 1024) {
+        unsigned o = d0 + l16;
+        int t = 0;
 #pragma unroll
-      for (int i = 1; i < S::TEAMS; ++i)
-        if (o >= ts) { o -= ts; ++t; }
-      const int64_t sy = base + t;
-      const char* src = dflt;
-      if (d0 + l4 < region && sy < g.n_batch) {
-        if (o < vs) src = reinterpret_cast<const char*>(g.values + sy * per) + o;
-        else if (o < vs + bsz) src = reinterpret_cast<const char*>(g.b + sy * g.n) + (o - vs);
+        for (int i = 1; i < S::TEAMS; ++i)
+          if (o >= ts) { o -= ts; ++t; }
+        const int64_t sy = base + t;
+        uintptr_t src = dflt;
+        if (d0 + l16 < region && sy < g.n_batch) {
+          uintptr_t start, end;
+          if (o < vr) {
+            start = (uintptr_t)(g.values + sy * per);
+            end = start + (uintptr_t)per * 8;
+          } else {
+            o -= vr;
+            start = (uintptr_t)(g.b + sy * g.n);
+            end = start + (uintptr_t)g.n * 8;
+          }
+          const uintptr_t chunk = (start & ~(uintptr_t)15) + o;
+          if (chunk < end) src = chunk;
+        }
+        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(tm.stage_all + d0), 16, 0, 0);
       }
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(tm.stage_all + d0),
-                                       4, 0, 0);
     }
   }
 
+  static __device__ __forceinline__ void settle(double& v) { __asm__ volatile("" : "+v"(v)); }
+
   // This team's values and right-hand side.  Staged groups read them from the
-  // prefetched LDS block (CSR: row offset + slot; ELL: slot*n + row); other
-  // groups read HBM directly, coalesced across lanes for ELL.
+  // prefetched LDS block; other groups read HBM directly.
   __device__ void load_values(Team<S>& tm, const KArgs& g) {
     const int64_t per = g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n;
     const double* vals = g.values + (tm.live ? tm.sys * per : 0);
+    const double* bb = g.b + (tm.live ? tm.sys * g.n : 0);
     // Per-lane offsets are passed through an empty asm once per system so the
     // compiler recomputes the per-slot addresses here instead of hoisting them
     // out of the batch loop, where they would pin registers for the whole kernel.
     int off[S::R], ln[S::R], ds[S::R], rw[S::R];
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
-      off[r] = g.fmt == 0 ? rp[r] : row[r];
+      off[r] = w[r];
       ln[r] = tm.live ? len[r] : 0;
       ds[r] = tm.live ? dslot[r] : -1;
       rw[r] = (tm.live && ok[r]) ? row[r] : -1;
       __asm__ volatile("" : "+v"(off[r]), "+v"(ln[r]), "+v"(ds[r]), "+v"(rw[r]));
     }
+    const bool win = g.fmt == 0 && g.window;
     const int step = g.fmt == 0 ? 1 : g.n;
     if constexpr (S::WAVES == 1) {
       if (g.stage) {
-        const double* st = reinterpret_cast<const double*>(tm.stage);
+        // the blocks sit in LDS at their address modulo 16 (see prefetch)
+        const unsigned st = lds_addr(tm.stage) + ((uintptr_t)vals & 15);
+        const unsigned sb = lds_addr(tm.stage) + g.stage_vals_bytes + ((uintptr_t)bb & 15);
 #pragma unroll
         for (int r = 0; r < S::R; ++r) {
+          if (win) {
+            const unsigned wa = st + off[r] * 8;
 #pragma unroll
-          for (int k = 0; k < S::NZ; ++k) {
-            const bool has = k < ln[r];
-            const double v = st[has ? off[r] + k * step : 0];
-            a[r][k] = has ? v : 0.0;
+            for (int k = 0; k < S::NZ; ++k) a[r][k] = lds_load<double>(wa + k * 8);
+          } else {
+#pragma unroll
+            for (int k = 0; k < S::NZ; ++k) {
+              const bool has = k < ln[r];
+              const double v = lds_load<double>(st + (has ? off[r] + k * step : 0) * 8);
+              a[r][k] = has ? v : 0.0;
+            }
           }
-          const double dv = st[ds[r] >= 0 ? off[r] + ds[r] * step : 0];
+          const double dv = lds_load<double>(st + (ds[r] >= 0 ? off[r] + ds[r] * step : 0) * 8);
           dval[r] = ds[r] >= 0 ? dv : 0.0;
-          const double bv = st[per + (rw[r] >= 0 ? rw[r] : 0)];
+          const double bv = lds_load<double>(sb + (rw[r] >= 0 ? rw[r] : 0) * 8);
           bval[r] = rw[r] >= 0 ? bv : 0.0;
         }
         load_x0(tm, g, rw);
         return;
       }
     }
-    const double* bb = g.b + (tm.live ? tm.sys * g.n : 0);
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
+      if (win) {
 #pragma unroll
-      for (int k = 0; k < S::NZ; ++k) {
-        const bool has = k < ln[r];
-        const double v = __builtin_nontemporal_load(vals + (has ? off[r] + k * step : 0));
-        a[r][k] = has ? v : 0.0;
+        for (int k = 0; k < S::NZ; ++k) a[r][k] = __builtin_nontemporal_load(vals + off[r] + k);
+      } else {
+#pragma unroll
+        for (int k = 0; k < S::NZ; ++k) {
+          const bool has = k < ln[r];
+          const double v = __builtin_nontemporal_load(vals + (has ? off[r] + k * step : 0));
+          a[r][k] = has ? v : 0.0;
+        }
       }
       const double dv = vals[ds[r] >= 0 ? off[r] + ds[r] * step : 0];
       dval[r] = ds[r] >= 0 ? dv : 0.0;
@@ -326,8 +406,6 @@ struct Rows {
     load_x0(tm, g, rw);
   }
 
-  static __device__ __forceinline__ void settle(double& v) { __asm__ volatile("" : "+v"(v)); }
-
   // The initial guess is read here, before the next prefetch is issued, so a
   // wait for it never waits behind that prefetch.
   __device__ __forceinline__ void load_x0(const Team<S>& tm, const KArgs& g, const int (&rw)[S::R]) {
@@ -340,6 +418,11 @@ struct Rows {
       settle(xv);  // completed before the next prefetch is issued
       xval[r] = xv;
     }
+  }
+
+  // Whether slot k of row r holds one of the row's entries (not the zero cell).
+  __device__ __forceinline__ bool real(int r, int k) const {
+    return c[r][k] != vrow[0] - row[0] * 8 + S::ROWS * 8;
   }
 
   // Scalar Jacobi: d = 1/a_ii, 1 where the diagonal is zero or absent; 0 for
@@ -355,14 +438,14 @@ struct Rows {
   // y = A v.  v is written to the team's vector buffer BUF, the team syncs, and
   // each lane gathers its rows' columns from LDS.  T is the arithmetic type;
   // the buffer always spaces elements 8 bytes apart.  The gathers go out in
-  // groups of kGather (a scheduling barrier between groups bounds the
-  // registers held by loads in flight); four partial sums per row keep the
-  // FMA chains short.
+  // groups of kGather (an empty asm that the group's FMAs feed keeps the next
+  // group's gathers behind them, bounding the registers held by loads in
+  // flight); four partial sums per row keep the FMA chains short.
   template <int BUF, class T, class AT>
   __device__ __forceinline__ void spmv(Team<S>& tm, const AT (&av)[S::R][S::NZ],
                                        const T (&v)[S::R], T (&y)[S::R]) const {
     constexpr int kGather = 4;
-    constexpr unsigned off = BUF * S::ROWS * 8;
+    constexpr unsigned off = BUF * kBuf;
 #pragma unroll
     for (int r = 0; r < S::R; ++r)
       if (ok[r]) lds_store<T>(vrow[r] + off, v[r]);

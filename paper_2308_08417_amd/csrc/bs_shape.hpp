@@ -29,7 +29,9 @@ struct KArgs {
   int gmres;                   // GMRES scalars live behind the vector buffers
   int team_bytes;              // LDS bytes per team for vectors and scalars
   int stage_team_bytes;        // LDS staging bytes per team (values then b)
+  int stage_vals_bytes;        // of which the values region
   int stage_offset;            // byte offset of the staging area in LDS
+  int window;                  // CSR rows read through a fixed window of NZ slots
   double tol, inner_tol;
   const int* row_ptr;          // [n+1]
   const int* slot_col;         // [width][n], -1 padding
@@ -58,25 +60,38 @@ struct Shape {
   static constexpr int OCC = (WAVES == 1 && R == 1 && NZ == 32) ? 3 : 1;
 };
 
-// Vector buffers per team (SpMV source vectors, double-buffered).
+// Vector buffers per team (SpMV source vectors, double-buffered).  Each buffer
+// holds ROWS elements plus one cell that stays zero: register slots that hold
+// no entry of the lane's row gather from it.
 constexpr int kVecBuffers = 2;
 
-__host__ __device__ inline int round16(int b) { return (b + 15) & ~15; }
+__host__ __device__ constexpr int round16(int b) { return (b + 15) & ~15; }
+__host__ __device__ constexpr int round1k(int b) { return (b + 1023) & ~1023; }
+__host__ __device__ constexpr int vec_buf_bytes(int rows) { return (rows + 1) * 8; }
 
-// LDS bytes of a team's vector buffers and solver scalars; the CSR staging
-// area (if any) follows them.
+// LDS bytes of a team's vector buffers and solver scalars.
 __host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres) {
-  return round16(kVecBuffers * rows * 8 + (solver_is_gmres ? kGmresScalars * 8 : 0));
+  return round16(kVecBuffers * vec_buf_bytes(rows) + (solver_is_gmres ? kGmresScalars * 8 : 0));
 }
 
 inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }
 
-// Staging of one team: its system's values (`stored` doubles) then its b (n
-// doubles); the whole staging area of a group is a multiple of 256 bytes, the
-// span of one direct-to-LDS load instruction of a wave.
-inline int stage_team_bytes(int stored, int n) { return round16((stored + n) * 8); }
-inline int stage_total_bytes(int teams, int stored, int n) {
-  return (teams * stage_team_bytes(stored, n) + 255) & ~255;
+// Staging of one team (single-wave groups): its system's values then its b,
+// each copied as the 16-byte-aligned chunks that cover it, so each region
+// holds up to 16 bytes more than its block; the values region also covers a
+// full window of NZ slots.  With one team per wave the two regions are whole
+// KiB, the span of one 16-byte-per-lane direct-to-LDS load of a wave; the
+// whole staging area is always a multiple of 1 KiB.
+inline int stage_vals_bytes(int teams, int stored, int nz) {
+  const int b = round16((stored > nz ? stored : nz) * 8) + 16;
+  return teams == 1 ? round1k(b) : b;
+}
+inline int stage_b_bytes(int teams, int n) {
+  const int b = round16(n * 8) + 16;
+  return teams == 1 ? round1k(b) : b;
+}
+inline int stage_total_bytes(int teams, int stored, int n, int nz) {
+  return round1k(teams * (stage_vals_bytes(teams, stored, nz) + stage_b_bytes(teams, n)));
 }
 
 }  // namespace bs

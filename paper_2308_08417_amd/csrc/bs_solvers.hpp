@@ -103,7 +103,12 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
   for (int r = 0; r < R; ++r) {
     d_in[r] = (T)P.d[r];
 #pragma unroll
-    for (int k = 0; k < S::NZ; ++k) a_in[r][k] = (AT)A.a[r][k];
+    for (int k = 0; k < S::NZ; ++k) {
+      // slots without an entry of the row may hold other rows' values: zero
+      // them so that a value beyond FP32 range cannot meet the zero cell as Inf
+      if constexpr (MIXED) a_in[r][k] = A.real(r, k) ? (AT)A.a[r][k] : (AT)0;
+      else a_in[r][k] = (AT)A.a[r][k];
+    }
   }
 
   double q2[2];
@@ -475,7 +480,7 @@ __device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArg
   prologue(tm, A, g, P);
   const int m = g.restart;
   // LDS scalars of this team
-  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * S::ROWS * 8);
+  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(S::ROWS));
   double* Rt = hcol + (M + 2);               // packed by columns: R[i][j] at j(j+1)/2 + i
   double* cs = Rt + M * (M + 1) / 2;
   double* sn = cs + M;
