@@ -166,6 +166,76 @@ typedef struct {
 int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_solver solver,
             const bs_options *opts, bs_plan_info *out);
 
+/* ---------------------------------------------------------------------------
+ * Uneven batches: systems of different sizes and patterns solved by ONE
+ * persistent kernel launch (the paper's batched solvers take one shared
+ * pattern, Sec. 3.1; its per-device size thresholds, Sec. 3.6, become an
+ * autotuned choice here).  Systems are grouped by size class into tasks of one
+ * to sixteen systems, ordered largest first, and taken from an atomic work
+ * queue by 1024-lane workgroups; each system is solved by a team of
+ * 64..1024 lanes (one row per lane, n_rows <= 1024, longest row <= 16).
+ * ------------------------------------------------------------------------- */
+typedef struct bs_varbatch_s *bs_varbatch;
+
+/* Describe an uneven batch from HOST arrays (copied; the library owns the
+ * device copy and a work counter).  Patterns are CSR: pattern p has
+ * pat_rows[p] rows, row_ptr at rowptr_all[pat_rowptr_off[p] ..] (pat_rows[p]+1
+ * entries) and columns at col_all[pat_col_off[p] ..]; system s uses pattern
+ * sys_pat[s].  Values of system s are its pattern's nnz doubles in CSR order,
+ * stored after those of system s-1; b and x likewise with n_rows doubles.
+ * Errors: BS_ERR_INVALID_ARG, BS_ERR_PATTERN (as for bs_pattern_create_csr, or
+ * sys_pat out of range), BS_ERR_UNSUPPORTED (a pattern with more than 1024
+ * rows or a row longer than 16), BS_ERR_NO_DEVICE / BS_ERR_HIP. */
+int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t *pat_rows,
+                       const int64_t *pat_rowptr_off, const int32_t *rowptr_all,
+                       const int64_t *pat_col_off, const int32_t *col_all, const int32_t *sys_pat,
+                       bs_varbatch *out);
+
+int bs_varbatch_destroy(bs_varbatch vb);
+
+/* Totals: rows (= length of b and x), values, queue tasks, current policy. */
+int bs_varbatch_query(bs_varbatch vb, int64_t *total_rows, int64_t *total_values, int32_t *n_tasks,
+                      int32_t *policy);
+
+/* Queue policies: 0 = team of the next power of two >= n (at least 64),
+ * largest tasks first; 1 = teams twice that size (fewer systems per task);
+ * 2 = as 0 with the systems of a class kept in batch order. */
+int bs_varbatch_set_policy(bs_varbatch vb, int32_t policy);
+
+/* Solve all systems (BS_CG or BS_BICGSTAB; BS_MIXED for BiCGSTAB), arguments
+ * as in bs_batch_solve with the concatenated layouts above.  One launch of
+ * the counter reset and one of the persistent solver, asynchronous. */
+int bs_varbatch_solve(bs_varbatch vb, const double *values, const double *b, double *x,
+                      bs_solver solver, bs_precond precond, double tol, int32_t max_iter,
+                      int32_t *iters, double *resid, int32_t *status, const bs_options *opts,
+                      void *stream);
+
+/* Autotuner: time every queue policy on these inputs (1 warm-up and `reps`
+ * timed solves each, synchronising `stream`), keep the fastest, and write a
+ * one-line report "policy=<p> times_ms=<t0>,<t1>,<t2>" into report (may be
+ * NULL).  If cache_path is not NULL the choice is looked up in / appended to
+ * that text file, keyed by the size-class histogram, solver and precision; a
+ * cached choice is applied without timing or solving.  Each timed solve
+ * starts from the caller's x (kept in a temporary device copy) unless
+ * opts->flags has BS_FLAG_X0_ZERO; after timing, one more solve with the
+ * chosen policy leaves x/iters/resid/status as bs_varbatch_solve would. */
+int bs_varbatch_tune(bs_varbatch vb, const double *values, const double *b, double *x,
+                     bs_solver solver, bs_precond precond, double tol, int32_t max_iter,
+                     int32_t *iters, double *resid, int32_t *status, const bs_options *opts,
+                     int32_t reps, const char *cache_path, char *report, size_t report_len,
+                     void *stream);
+
+/* Capture the counter reset and the solve (with these arguments) into a HIP
+ * graph owned by the handle, replacing any previous one; bs_varbatch_replay
+ * launches it on `stream`.  The graph holds no memset nodes.  A change of
+ * queue policy (bs_varbatch_set_policy, bs_varbatch_tune) drops the graph;
+ * bs_varbatch_replay then fails with BS_ERR_INVALID_ARG until the next
+ * capture. */
+int bs_varbatch_capture(bs_varbatch vb, const double *values, const double *b, double *x,
+                        bs_solver solver, bs_precond precond, double tol, int32_t max_iter,
+                        int32_t *iters, double *resid, int32_t *status, const bs_options *opts);
+int bs_varbatch_replay(bs_varbatch vb, void *stream);
+
 /* Text for a bs_error code; never NULL. */
 const char *bs_error_string(int code);
 

@@ -74,13 +74,27 @@ def lib() -> C.CDLL:
                                  vp, vp, vp, C.POINTER(bs_options), vp]
     L.bs_plan.argtypes = [C.c_int, i32, i32, i32, C.c_int, C.POINTER(bs_options),
                           C.POINTER(bs_plan_info)]
+    sz = C.c_size_t
+    L.bs_varbatch_create.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
+    L.bs_varbatch_destroy.argtypes = [vp]
+    L.bs_varbatch_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
+                                    C.POINTER(i32)]
+    L.bs_varbatch_set_policy.argtypes = [vp, i32]
+    _vsolve = [vp, vp, vp, vp, C.c_int, C.c_int, dbl, i32, vp, vp, vp, C.POINTER(bs_options)]
+    L.bs_varbatch_solve.argtypes = _vsolve + [vp]
+    L.bs_varbatch_tune.argtypes = _vsolve + [i32, C.c_char_p, C.c_char_p, sz, vp]
+    L.bs_varbatch_capture.argtypes = _vsolve
+    L.bs_varbatch_replay.argtypes = [vp, vp]
     L.bs_error_string.argtypes = [C.c_int]
     L.bs_error_string.restype = C.c_char_p
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = C.c_char_p
     for name in ("bs_pattern_create_csr", "bs_pattern_create_ell", "bs_pattern_destroy",
                  "bs_pattern_query", "bs_pattern_ell_cols", "bs_values_csr_to_ell",
-                 "bs_matrix_storage", "bs_batch_solve", "bs_plan"):
+                 "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_varbatch_create",
+                 "bs_varbatch_destroy", "bs_varbatch_query", "bs_varbatch_set_policy",
+                 "bs_varbatch_solve", "bs_varbatch_tune", "bs_varbatch_capture",
+                 "bs_varbatch_replay"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -247,3 +261,93 @@ def solve(pattern: Pattern, values, b, x=None, fmt: int = CSR, solver: int = BIC
     bs_batch_solve(fmt, pattern.handle, values, b, x, solver, precond, tol, max_iter, iters, resid,
                    status, opts, stream)
     return x, iters, resid, status
+
+
+# ------------------------------------------------------------------ uneven batches
+def _host(a, dt) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=dt)
+
+
+def bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_all, sys_pat) -> int:
+    pr, pro, rpa = _host(pat_rows, np.int32), _host(pat_rowptr_off, np.int64), _host(rowptr_all, np.int32)
+    pco, ca, sp = _host(pat_col_off, np.int64), _host(col_all, np.int32), _host(sys_pat, np.int32)
+    h = C.c_void_p()
+    _check(lib().bs_varbatch_create(sp.size, pr.size, pr.ctypes.data, pro.ctypes.data,
+                                    rpa.ctypes.data, pco.ctypes.data,
+                                    ca.ctypes.data if ca.size else None,
+                                    sp.ctypes.data if sp.size else None, C.byref(h)),
+           "bs_varbatch_create")
+    return h.value
+
+
+def bs_varbatch_destroy(handle: int) -> None:
+    _check(lib().bs_varbatch_destroy(handle), "bs_varbatch_destroy")
+
+
+def bs_varbatch_query(handle: int) -> dict:
+    r, v = C.c_int64(), C.c_int64()
+    t, p = C.c_int32(), C.c_int32()
+    _check(lib().bs_varbatch_query(handle, C.byref(r), C.byref(v), C.byref(t), C.byref(p)),
+           "bs_varbatch_query")
+    return {"total_rows": r.value, "total_values": v.value, "n_tasks": t.value, "policy": p.value}
+
+
+def bs_varbatch_set_policy(handle: int, policy: int) -> None:
+    _check(lib().bs_varbatch_set_policy(handle, policy), "bs_varbatch_set_policy")
+
+
+def _vargs(handle, values, b, x, solver, precond, tol, max_iter, iters, resid, status, opts):
+    return (handle, _ptr(values), _ptr(b), _ptr(x), solver, precond, float(tol), int(max_iter),
+            _ptr(iters), _ptr(resid), _ptr(status), C.byref(opts) if opts is not None else None)
+
+
+def bs_varbatch_solve(handle: int, values, b, x, solver: int, precond: int, tol: float,
+                      max_iter: int, iters, resid, status=None, opts: Optional[bs_options] = None,
+                      stream=None) -> None:
+    """Solve an uneven batch: ``values``/``b``/``x`` are the concatenated float64
+    device vectors, ``iters``/``status`` int32 and ``resid`` float64 per system."""
+    _check(lib().bs_varbatch_solve(*_vargs(handle, values, b, x, solver, precond, tol, max_iter,
+                                           iters, resid, status, opts), _stream(stream)),
+           "bs_varbatch_solve")
+
+
+def bs_varbatch_tune(handle: int, values, b, x, solver: int, precond: int, tol: float,
+                     max_iter: int, iters, resid, status=None, opts: Optional[bs_options] = None,
+                     reps: int = 3, cache_path: Optional[str] = None, stream=None) -> str:
+    """Time the queue policies, keep the fastest; returns the report line."""
+    buf = C.create_string_buffer(512)
+    _check(lib().bs_varbatch_tune(*_vargs(handle, values, b, x, solver, precond, tol, max_iter,
+                                          iters, resid, status, opts), int(reps),
+                                  cache_path.encode() if cache_path else None, buf, len(buf),
+                                  _stream(stream)), "bs_varbatch_tune")
+    return buf.value.decode()
+
+
+def bs_varbatch_capture(handle: int, values, b, x, solver: int, precond: int, tol: float,
+                        max_iter: int, iters, resid, status=None,
+                        opts: Optional[bs_options] = None) -> None:
+    _check(lib().bs_varbatch_capture(*_vargs(handle, values, b, x, solver, precond, tol, max_iter,
+                                             iters, resid, status, opts)), "bs_varbatch_capture")
+
+
+def bs_varbatch_replay(handle: int, stream=None) -> None:
+    _check(lib().bs_varbatch_replay(handle, _stream(stream)), "bs_varbatch_replay")
+
+
+class VarBatch:
+    """Owns an uneven-batch handle (see ``bs_varbatch_create``)."""
+
+    def __init__(self, pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_all, sys_pat):
+        self.handle = bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off,
+                                         col_all, sys_pat)
+        self.n_batch = int(np.asarray(sys_pat).size)
+        q = bs_varbatch_query(self.handle)
+        self.total_rows, self.total_values = q["total_rows"], q["total_values"]
+
+    def query(self) -> dict:
+        return bs_varbatch_query(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", 0) and _lib is not None:
+            _lib.bs_varbatch_destroy(self.handle)
+            self.handle = 0

@@ -24,8 +24,15 @@ struct bs_pattern_s {
 };
 
 namespace {
-
 thread_local std::string g_last_error = "";
+}  // namespace
+
+namespace bs {
+// Shared by every translation unit of the library (bs_last_error reads it).
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace bs
+
+namespace {
 
 int hip_fail(hipError_t e, const char* what) {
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);

@@ -116,6 +116,7 @@ struct Team {
   int lane;         // lane within the team
   int tix;          // team index within the workgroup
   int64_t sys;      // system being solved
+  int64_t row0;     // offset of its first row in b and x
   bool live;        // sys < n_batch
   char* lds;        // this team's LDS region (vector buffers, solver scalars)
   char* stage_all;  // the group's staging area (single-wave groups)
@@ -128,6 +129,7 @@ struct Team {
     lane = S::TEAM < kWave ? (t & (S::TEAM - 1)) : t;
     tix = S::TEAM < kWave ? (t / S::TEAM) : 0;
     sys = -1;
+    row0 = 0;
     live = false;
     lds = smem + (size_t)tix * a.team_bytes;
     stage_all = smem + a.stage_offset;
@@ -209,6 +211,7 @@ struct Team {
 // offset.  ELL rows use slot k for the row's k-th stored entry.
 template <class S>
 struct Rows {
+  static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS;
   double a[S::R][S::NZ];
   unsigned c[S::R][S::NZ];
   unsigned vrow[S::R];  // LDS address of the lane's own rows in buffer 0

@@ -23,25 +23,25 @@ namespace bs {
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Shared epilogue: true residual for teams that do not have it, then outputs.
-template <class S>
-__device__ __forceinline__ void finish(Team<S>& tm, const Rows<S>& A, const KArgs& g,
-                                       const double (&b)[S::R], const double (&x)[S::R], int st,
+template <class TM, class RW>
+__device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
+                                       const double (&b)[RW::R], const double (&x)[RW::R], int st,
                                        int k, int outer, double bn, double rn, bool have_rn) {
   const bool need = tm.live && !have_rn;
   if (tm.any(need)) {
-    double t[S::R], q[1];
+    double t[RW::R], q[1];
     A.template spmv<0>(tm, A.a, x, t);
-    double p[S::R];
+    double p[RW::R];
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) { const double e = b[r] - t[r]; p[r] = e * e; }
+    for (int r = 0; r < RW::R; ++r) { const double e = b[r] - t[r]; p[r] = e * e; }
     q[0] = sum_rows(p);
     tm.sum(q);
     if (need) rn = sqrt(q[0]);
   }
   if (!tm.live) return;
 #pragma unroll
-  for (int r = 0; r < S::R; ++r)
-    if (A.ok[r]) g.x[tm.sys * g.n + A.row[r]] = x[r];
+  for (int r = 0; r < RW::R; ++r)
+    if (A.ok[r]) g.x[tm.row0 + A.row[r]] = x[r];
   if (tm.lane == 0) {
     g.iters[tm.sys] = k;
     g.resid[tm.sys] = !finite(bn) ? bn : (bn == 0.0 ? rn : rn / bn);
@@ -52,28 +52,28 @@ __device__ __forceinline__ void finish(Team<S>& tm, const Rows<S>& A, const KArg
 
 // Shared prologue: load the system, its Jacobi diagonal, b, x0 and the initial
 // residual r0 = b - A x0 (r0 = b when x0 = 0 is promised).
-template <class S>
+template <int R>
 struct Prologue {
-  double b[S::R], x[S::R], r[S::R], d[S::R];
+  double b[R], x[R], r[R], d[R];
 };
 
-template <class S>
-__device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g, Prologue<S>& P) {
+template <class TM, class RW>
+__device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue<RW::R>& P) {
   A.jacobi(g.precond, P.d);
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
-  for (int r = 0; r < S::R; ++r) {
+  for (int r = 0; r < RW::R; ++r) {
     P.b[r] = A.bval[r];
     P.x[r] = A.xval[r];
   }
   if (!x0zero) {
-    double t[S::R];
+    double t[RW::R];
     A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) P.r[r] = P.b[r] - t[r];
+    for (int r = 0; r < RW::R; ++r) P.r[r] = P.b[r] - t[r];
   } else {
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) P.r[r] = P.b[r];
+    for (int r = 0; r < RW::R; ++r) P.r[r] = P.b[r];
   }
 }
 
@@ -88,22 +88,22 @@ __device__ __forceinline__ void prologue(Team<S>& tm, Rows<S>& A, const KArgs& g
 // FP32 and solve for a correction to the FP64 x, scaled by 1/||r||; the "true
 // residual confirmation" becomes the FP64 outer refinement step r = b - A x,
 // which also ends the inner solve when it meets inner_tol or breaks down.
-template <class S, bool MIXED>
-__device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
+template <bool MIXED, class TM, class RW>
+__device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
   using T = typename std::conditional<MIXED, float, double>::type;
-  Prologue<S> P;
+  Prologue<RW::R> P;
   prologue(tm, A, g, P);
-  constexpr int R = S::R;
+  constexpr int R = RW::R;
 
   // FP32 copy of the rows and of the Jacobi diagonal for the inner solve.
   using AT = typename std::conditional<MIXED, float, double>::type;
-  AT a_in[R][S::NZ];
+  AT a_in[R][RW::NZ];
   T d_in[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     d_in[r] = (T)P.d[r];
 #pragma unroll
-    for (int k = 0; k < S::NZ; ++k) {
+    for (int k = 0; k < RW::NZ; ++k) {
       // slots without an entry of the row may hold other rows' values: zero
       // them so that a value beyond FP32 range cannot meet the zero cell as Inf
       if constexpr (MIXED) a_in[r][k] = A.real(r, k) ? (AT)A.a[r][k] : (AT)0;
@@ -349,11 +349,11 @@ __device__ __forceinline__ void bicgstab_system(Team<S>& tm, Rows<S>& A, const K
 // =================================================================== CG
 // Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
 // stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
-template <class S>
-__device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
-  Prologue<S> P;
+template <class TM, class RW>
+__device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
+  Prologue<RW::R> P;
   prologue(tm, A, g, P);
-  constexpr int R = S::R;
+  constexpr int R = RW::R;
   double z[R], p[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) { z[i] = P.d[i] * P.r[i]; p[i] = z[i]; }
@@ -472,15 +472,15 @@ __device__ __forceinline__ void cg_system(Team<S>& tm, Rows<S>& A, const KArgs& 
 // has written itself, so no barrier is needed around them.  The last entry of g
 // changes at every step and is kept in a register.  At the end of a cycle
 // y = R^{-1} g by back substitution and x += M V y.
-template <class S>
-__device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArgs& g) {
-  static_assert(S::R == 1, "GMRES keeps one row per lane");
+template <class TM, class RW>
+__device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
+  static_assert(RW::R == 1, "GMRES keeps one row per lane");
   constexpr int M = kMaxRestart;
-  Prologue<S> P;
+  Prologue<RW::R> P;
   prologue(tm, A, g, P);
   const int m = g.restart;
   // LDS scalars of this team
-  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(S::ROWS));
+  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(RW::ROWS));
   double* Rt = hcol + (M + 2);               // packed by columns: R[i][j] at j(j+1)/2 + i
   double* cs = Rt + M * (M + 1) / 2;
   double* sn = cs + M;
@@ -637,6 +637,7 @@ __device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArg
   for (int64_t base = (int64_t)blockIdx.x * S::TEAMS; base < g.n_batch; base += stride) { \
     tm.sys = base + tm.tix;                                                        \
     tm.live = tm.sys < g.n_batch;                                                  \
+    tm.row0 = tm.live ? tm.sys * g.n : 0;                                          \
     if (staged) { /* the prefetch of this round has landed */                      \
       __builtin_amdgcn_s_waitcnt(0);                                               \
       __asm__ volatile("" ::: "memory");                                           \
@@ -654,17 +655,17 @@ __device__ __forceinline__ void gmres_system(Team<S>& tm, Rows<S>& A, const KArg
 
 template <class S, bool MIXED>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_bicgstab(const KArgs g) {
-  BS_PERSISTENT_LOOP((bicgstab_system<S, MIXED>(tm, A, g)))
+  BS_PERSISTENT_LOOP((bicgstab_system<MIXED>(tm, A, g)))
 }
 
 template <class S>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
-  BS_PERSISTENT_LOOP((cg_system<S>(tm, A, g)))
+  BS_PERSISTENT_LOOP((cg_system(tm, A, g)))
 }
 
 template <class S>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system<S>(tm, A, g)))
+  BS_PERSISTENT_LOOP((gmres_system(tm, A, g)))
 }
 
 #undef BS_PERSISTENT_LOOP

@@ -153,3 +153,56 @@ def test_plan_stage_and_limits(L):
     assert p["team"] == 64
     with pytest.raises(bs.BatchSolveError):
         bs.bs_plan(bs.CSR, 54, 1042, 28, bs.CG, bs.make_options(precision=bs.MIXED))
+
+
+def varbatch_parts(pats, sys_pat):
+    """Concatenate CSR patterns the way bs_varbatch_create takes them."""
+    rows, rpo, cpo, rpa, ca = [], [], [], [], []
+    for rp, ci in pats:
+        rows.append(len(rp) - 1)
+        rpo.append(sum(len(x) for x in rpa))
+        cpo.append(sum(len(x) for x in ca))
+        rpa.append(np.asarray(rp, np.int32))
+        ca.append(np.asarray(ci, np.int32))
+    return (rows, rpo, np.concatenate(rpa), cpo, np.concatenate(ca), np.asarray(sys_pat, np.int32))
+
+
+def test_varbatch_validation(L):
+    rp, ci = tri(8)
+    good = varbatch_parts([(rp, ci), tri(3)], [0, 1, 1, 0])
+    # pattern checks as for a single CSR pattern
+    bad_col = ci.copy(); bad_col[4] = 9
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, bad_col)], [0])) == bs.ERR_PATTERN
+    dup = ci.copy(); dup[3] = dup[2]
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, dup)], [0])) == bs.ERR_PATTERN
+    # a system naming a pattern that does not exist
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, ci)], [0, 1])) == bs.ERR_PATTERN
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, ci)], [-1])) == bs.ERR_PATTERN
+    # beyond the kernel's limits: more than 1024 rows, or a row longer than 16
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([tri(1025)], [0])) == bs.ERR_UNSUPPORTED
+    n = 20
+    dense = (np.arange(n + 1, dtype=np.int32) * n, np.tile(np.arange(n, dtype=np.int32), n))
+    assert create_code(bs.bs_varbatch_create, *varbatch_parts([dense], [0])) == bs.ERR_UNSUPPORTED
+    assert L.bs_varbatch_create(-1, 0, None, None, None, None, None, None, None) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_query(None, None, None, None, None) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_set_policy(None, 0) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_replay(None, None) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_destroy(None) == bs.OK
+    import torch
+    if not torch.cuda.is_available():
+        assert create_code(bs.bs_varbatch_create, *good) == bs.ERR_NO_DEVICE
+
+
+def test_varbatch_generator_layout():
+    """The uneven generator's concatenated layout is what bs_varbatch_create reads."""
+    from paper_2308_08417_amd import workloads as w
+    vb = w.uneven_banded(200, 16, 300, seed=3)
+    assert vb.row_off[-1] == vb.b.size == vb.x0.size
+    assert vb.val_off[-1] == vb.values.size
+    for s in (0, 57, 199):
+        p = vb.pat_id[s]
+        n = vb.pat_rows[p]
+        assert vb.sys_rows[s] == n and 16 <= n <= 300
+        rp = vb.rowptr_all[vb.pat_rowptr_off[p]: vb.pat_rowptr_off[p] + n + 1]
+        assert vb.val_off[s + 1] - vb.val_off[s] == rp[-1]
+        assert np.diff(rp).max() <= 9

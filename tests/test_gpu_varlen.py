@@ -1,0 +1,291 @@
+"""GPU parity of the uneven-batch path (systems of different sizes and patterns
+in one persistent launch) against the FP64 CPU oracle, through the C ABI.
+
+The oracle solves each pattern's systems as one fixed-size batch; the bar per
+system is that of the fixed-size parity tests (status equal, true residual of
+the GPU's x <= tol, x within 1e-8 of the oracle's, iterations within 2).
+"""
+import os
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_08417_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2308_08417_amd import batchsolve as bs  # noqa: E402
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from test_gpu_parity import check, dev, say  # noqa: E402
+
+SOLVER_O = {bs.CG: O.CG, bs.BICGSTAB: O.BICGSTAB}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bs.lib()
+
+
+def symmetric_values(vb: W.VarBatch, seed: int) -> np.ndarray:
+    """SPD values on symmetric band patterns: a_ij = a_ji = -(1 + 0.5 u) with u
+    drawn per unordered pair, a_ii = 1.1 sum_j |a_ij| + 0.1 (strictly dominant)."""
+    rng = np.random.default_rng(seed)
+    vals = np.empty_like(vb.values)
+    for s in range(vb.n_batch):
+        rp, ci, _, _, _ = vb.system(s)
+        n = rp.size - 1
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        lo, hi = np.minimum(rows, ci), np.maximum(rows, ci)
+        u = rng.random(n * 8).reshape(n, 8)
+        w = -(1.0 + 0.5 * u[lo, np.minimum(hi - lo, 7)])
+        diag = rows == ci
+        w[diag] = 0.0
+        w[diag] = 1.1 * np.bincount(rows, weights=np.abs(w), minlength=n) + 0.1
+        vals[vb.val_off[s]:vb.val_off[s + 1]] = w
+    return vals
+
+
+class VCase:
+    """An uneven batch on the device plus its per-pattern oracle groups."""
+
+    def __init__(self, vb: W.VarBatch, values=None):
+        self.vb = vb
+        self.values = vb.values if values is None else values
+        self.h = bs.VarBatch(vb.pat_rows, vb.pat_rowptr_off, vb.rowptr_all, vb.pat_col_off,
+                             vb.col_all, vb.pat_id)
+        self.dv = dev(self.values)
+        self.db = dev(vb.b)
+
+    def outputs(self):
+        B = self.vb.n_batch
+        x = torch.full((self.vb.b.size,), np.nan, dtype=torch.float64, device="cuda:0")
+        it = torch.full((B,), -7, dtype=torch.int32, device="cuda:0")
+        rs = torch.full((B,), -7.0, dtype=torch.float64, device="cuda:0")
+        st = torch.full((B,), -7, dtype=torch.int32, device="cuda:0")
+        return x, it, rs, st
+
+    def gpu(self, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=1000, values=None, b=None,
+            x0=None, **opt):
+        say(f"  varlen gpu: B={self.vb.n_batch} rows={self.vb.b.size} solver={solver} "
+            f"prec={precond} tol={tol} max_iter={max_iter} opt={opt}")
+        x, it, rs, st = self.outputs()
+        flags = bs.FLAG_X0_ZERO
+        if x0 is not None:
+            x.copy_(dev(x0))
+            flags = 0
+        opts = bs.make_options(flags=flags, **opt)
+        bs.bs_varbatch_solve(self.h.handle, self.dv if values is None else values,
+                             self.db if b is None else b, x, solver, precond, tol, max_iter, it,
+                             rs, st, opts)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
+
+    def groups(self):
+        vb = self.vb
+        for p in range(len(vb.pat_rows)):
+            sys_ = np.flatnonzero(vb.pat_id == p)
+            if sys_.size == 0:
+                continue
+            n = int(vb.pat_rows[p])
+            rp = vb.rowptr_all[vb.pat_rowptr_off[p]: vb.pat_rowptr_off[p] + n + 1]
+            ci = vb.col_all[vb.pat_col_off[p]: vb.pat_col_off[p] + rp[-1]]
+            rows = (vb.row_off[sys_][:, None] + np.arange(n)).ravel()
+            vals = (vb.val_off[sys_][:, None] + np.arange(rp[-1])).ravel()
+            yield sys_, n, rp, ci, rows, vals
+
+    def check(self, g, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=1000, values=None,
+              b=None, x0=None, itol=2):
+        xg, ig, rg, sg = g
+        V = self.values if values is None else values
+        Bv = self.vb.b if b is None else b
+        for sys_, n, rp, ci, rows, vals in self.groups():
+            OP = O.Pattern(n, rp, ci)
+            v = V[vals].reshape(sys_.size, -1)
+            bb = Bv[rows].reshape(sys_.size, n)
+            xx = None if x0 is None else x0[rows].reshape(sys_.size, n)
+            o = O.batch_solve(OP, v, bb, x0=xx, solver=SOLVER_O[solver], precond=precond,
+                              tol=tol, max_iter=max_iter)
+            case = SimpleNamespace(batch=SimpleNamespace(b=bb, row_ptr=rp), OP=OP,
+                                   oracle_values=lambda fmt, v=v: v)
+            gg = (xg[rows].reshape(sys_.size, n), ig[sys_], rg[sys_], sg[sys_])
+            check(case, gg, o, tol=tol, itol=itol)
+
+
+def test_bicgstab_mixed_sizes():
+    """Every team size 64..1024 in one launch (n from 16 to 1024)."""
+    c = VCase(W.uneven_banded(400, 16, 1024, seed=1))
+    g = c.gpu(bs.BICGSTAB)
+    assert np.all(g[3] == bs.CONVERGED)
+    c.check(g, bs.BICGSTAB)
+
+
+def test_cg_spd_mixed_sizes():
+    vb = W.uneven_banded(300, 16, 1024, w_min=5, w_max=5, seed=2)   # symmetric bands
+    c = VCase(vb, symmetric_values(vb, seed=2))
+    g = c.gpu(bs.CG)
+    assert np.all(g[3] == bs.CONVERGED)
+    c.check(g, bs.CG)
+
+
+def test_small_systems_many_per_task():
+    """Teams of one wave: 16 systems per task; a ragged last task."""
+    c = VCase(W.uneven_banded(1000 + 13, 16, 64, seed=3))
+    g = c.gpu(bs.BICGSTAB, precond=bs.PREC_NONE)
+    c.check(g, bs.BICGSTAB, precond=bs.PREC_NONE)
+
+
+def test_policies_give_identical_results():
+    """The queue order and the team width change who solves a system, not the
+    arithmetic: every policy gives the same bits."""
+    c = VCase(W.uneven_banded(500, 16, 700, seed=4))
+    ref = None
+    for p in (0, 1, 2):
+        bs.bs_varbatch_set_policy(c.h.handle, p)
+        q = c.h.query()
+        assert q["policy"] == p and q["n_tasks"] >= 1
+        g = c.gpu(bs.BICGSTAB)
+        if ref is None:
+            ref = g
+            c.check(g, bs.BICGSTAB)
+        else:
+            for u, v in zip(ref, g):
+                assert np.array_equal(u, v), f"policy {p} differs"
+
+
+def test_mixed_precision_uneven():
+    c = VCase(W.uneven_banded(300, 16, 1024, seed=5))
+    outer = torch.zeros(c.vb.n_batch, dtype=torch.int32, device="cuda:0")
+    g = c.gpu(bs.BICGSTAB, max_iter=2000, precision=bs.MIXED, outer_iters=outer)
+    assert np.all(g[3] == bs.CONVERGED)
+    c.check(g, bs.BICGSTAB, max_iter=2000, itol=10**9)
+    assert outer.min().item() >= 1
+
+
+def test_edge_cases_uneven():
+    vb = W.uneven_banded(40, 16, 200, seed=6)
+    c = VCase(vb)
+    x0 = np.random.default_rng(1).standard_normal(vb.b.shape)
+    b = vb.b.copy()
+    b[vb.row_off[2]:vb.row_off[3]] = 0.0        # b = 0: converged, x = 0
+    b[vb.row_off[5] + 3] = np.inf               # Inf in b
+    vals = vb.values.copy()
+    vals[vb.val_off[7] + 4] = np.nan            # NaN in A
+    g = c.gpu(bs.BICGSTAB, values=dev(vals), b=dev(b), x0=x0, tol=1e-8)
+    c.check(g, bs.BICGSTAB, values=vals, b=b, x0=x0, tol=1e-8)
+    assert g[3][2] == bs.CONVERGED and g[1][2] == 0
+    assert np.all(g[0][vb.row_off[2]:vb.row_off[3]] == 0.0)
+    assert g[3][5] == bs.NONFINITE and g[3][7] == bs.NONFINITE
+    g = c.gpu(bs.BICGSTAB, max_iter=0)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 0) and np.all(g[0] == 0)
+    g = c.gpu(bs.BICGSTAB, tol=1e-30, max_iter=9)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 9)
+
+
+def test_single_row_systems():
+    """n = 1 (x = b / a exactly for these values) in a batch of three."""
+    one = (np.array([0, 1], np.int32), np.array([0], np.int32))
+    h = bs.VarBatch([1], [0], one[0], [0], one[1], [0, 0, 0])
+    vals = dev(np.array([2.0, -4.0, 0.5]))
+    b = dev(np.array([1.0, 2.0, 3.0]))
+    x = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    it = torch.empty(3, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(3, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(3, dtype=torch.int32, device="cuda:0")
+    for solver in (bs.BICGSTAB, bs.CG):
+        say(f"  n=1 solver={solver}")
+        bs.bs_varbatch_solve(h.handle, vals, b, x, solver, bs.PREC_JACOBI, 1e-10, 10, it, rs, st,
+                             bs.make_options(flags=bs.FLAG_X0_ZERO))
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), [0.5, -0.5, 6.0])
+        assert np.all(st.cpu().numpy() == bs.CONVERGED)
+
+
+def test_graph_replay_matches_eager():
+    """The captured graph (counter reset kernel + solve) replayed several times,
+    with eager work and synchronisation between replays, equals the eager solve
+    bit for bit each time."""
+    c = VCase(W.uneven_banded(300, 16, 1024, seed=7))
+    eager = c.gpu(bs.BICGSTAB)
+    x, it, rs, st = c.outputs()
+    bs.bs_varbatch_capture(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10, 1000,
+                           it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO))
+    for rep in range(4):
+        x.fill_(np.nan)
+        it.fill_(-7)
+        rs.fill_(-7.0)
+        st.fill_(-7)
+        torch.cuda.synchronize()
+        say(f"  replay {rep}")
+        bs.bs_varbatch_replay(c.h.handle)
+        torch.cuda.synchronize()
+        for u, v in zip(eager, (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(),
+                                st.cpu().numpy())):
+            assert np.array_equal(u, v), f"replay {rep} differs from the eager solve"
+    # a policy change drops the graph
+    bs.bs_varbatch_set_policy(c.h.handle, 1)
+    with pytest.raises(bs.BatchSolveError):
+        bs.bs_varbatch_replay(c.h.handle)
+
+
+def test_tune_and_cache(tmp_path):
+    c = VCase(W.uneven_banded(600, 16, 1024, seed=8))
+    eager = c.gpu(bs.BICGSTAB)
+    x, it, rs, st = c.outputs()
+    cache = str(tmp_path / "tune.txt")
+    rep = bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
+                              1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO), reps=2,
+                              cache_path=cache)
+    torch.cuda.synchronize()
+    say(f"  tune: {rep}")
+    assert rep.startswith("policy=") and "times_ms=" in rep
+    pol = int(rep.split()[0].split("=")[1])
+    assert c.h.query()["policy"] == pol
+    assert np.array_equal(x.cpu().numpy(), eager[0])
+    assert open(cache).read().count("\n") == 1
+    rep2 = bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
+                               1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO), reps=2,
+                               cache_path=cache)
+    assert "cached" in rep2 and rep2.startswith(f"policy={pol}")
+    # tuning from a nonzero x0 restarts every timed solve from it
+    x0 = np.random.default_rng(2).standard_normal(c.vb.b.shape)
+    ref = c.gpu(bs.BICGSTAB, x0=x0)
+    x.copy_(dev(x0))
+    bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10, 1000, it,
+                        rs, st, bs.make_options(), reps=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), ref[0]) and np.array_equal(it.cpu().numpy(), ref[1])
+
+
+def test_uneven_full_size_sampled():
+    """100k systems, n in [16, 1024], bands of width 5..9, in the benchmark's
+    launch shape: every system converges with a true residual <= 1e-10 (checked
+    by the oracle per pattern), and a random sample is re-solved by the oracle."""
+    vb = W.uneven_banded(100_000, 16, 1024, seed=0)
+    c = VCase(vb)
+    g = c.gpu(bs.BICGSTAB)
+    assert np.all(g[3] == bs.CONVERGED)
+    rng = np.random.default_rng(0)
+    pick = set(rng.choice(vb.n_batch, 300, replace=False).tolist())
+    worst = 0.0
+    for sys_, n, rp, ci, rows, vals in c.groups():
+        OP = O.Pattern(n, rp, ci)
+        v = vb.values[vals].reshape(sys_.size, -1)
+        bb = vb.b[rows].reshape(sys_.size, n)
+        xg = g[0][rows].reshape(sys_.size, n)
+        rt = O.true_residual(OP, v, bb, xg)
+        worst = max(worst, float(rt.max()))
+        sel = np.array([i for i, s in enumerate(sys_) if s in pick], dtype=np.int64)
+        if sel.size:
+            o = O.batch_solve(OP, v[sel], bb[sel], solver=O.BICGSTAB, tol=1e-10, max_iter=1000)
+            err = np.linalg.norm(xg[sel] - o[0], axis=1) / np.linalg.norm(o[0], axis=1)
+            assert np.all(err <= 1e-8)
+            assert np.all(np.abs(g[1][sys_[sel]] - o[1]) <= 2)
+    say(f"  uneven full size: worst true residual {worst:.2e}")
+    assert worst <= 1e-10
