@@ -7,8 +7,10 @@ stored entries at seed 0), A = I - 1e-6 J with J = +-10^U(-3,3), b ~ U(-1,1),
 x0 = 0 -- solved by FP64 BiCGSTAB with scalar Jacobi in BatchCsr to relative
 residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
-forms of the same batch, the HBM roofline of the solver kernel, and the CPU
-oracle's throughput on the host cores.
+forms of the same batch, the uneven batch (100k banded systems with n in
+[16, 1024] in one persistent launch, eager and graph-replayed), the HBM
+roofline of the solver kernel, and the CPU oracle's throughput on the host
+cores.
 """
 from __future__ import annotations
 
@@ -48,6 +50,66 @@ def load_traffic(name: str):
     return t
 
 
+def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """Uneven batch in one persistent launch: ``args.uneven_batch`` banded
+    nonsymmetric systems, n ~ U{16..1024}, band width ~ U{5..9}, BiCGSTAB +
+    Jacobi to 1e-10, queue policy picked by the library's tuner, then timed as
+    eager launches and as replays of the captured graph (FP64 and mixed)."""
+    t0 = time.time()
+    vb = W.uneven_banded(args.uneven_batch, 16, 1024, seed=0)
+    gen_s = time.time() - t0
+    h = bs.VarBatch(vb.pat_rows, vb.pat_rowptr_off, vb.rowptr_all, vb.pat_col_off, vb.col_all,
+                    vb.pat_id)
+    B = vb.n_batch
+    vals = torch.from_numpy(vb.values).to(dev)
+    b = torch.from_numpy(vb.b).to(dev)
+    x = torch.empty_like(b)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    out = {"workload": f"uneven_banded_b{B}_n16-1024_w5-9_bicgstab_jacobi",
+           "n_batch": B, "total_rows": int(vb.b.size), "total_values": int(vb.values.size),
+           "gen_seconds": gen_s}
+    steps = max(3, args.steps // 4)
+    for name, prec in (("fp64", bs.FP64), ("mixed", bs.MIXED)):
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec)
+        args_ = (h.handle, vals, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter, iters, resid,
+                 status, opts)
+        report = bs.bs_varbatch_tune(*args_, reps=2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bs.bs_varbatch_solve(*args_)
+        e1.record()
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1) / steps
+        bs.bs_varbatch_capture(*args_)
+        bs.bs_varbatch_replay(h.handle)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            bs.bs_varbatch_replay(h.handle)
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+        # algorithmic bytes: every system's values, b and x once, the outputs,
+        # and each distinct pattern once
+        alg = (8 * vb.values.size + 16 * vb.b.size + 16 * B + 4 * vb.rowptr_all.size
+               + 8 * vb.col_all.size)
+        ms = min(eager_ms, graph_ms)
+        out[name] = {"tune": report, "eager_ms": eager_ms, "graph_ms": graph_ms,
+                     "systems_per_s": B / (ms * 1e-3),
+                     "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": int(alg),
+                     "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+                     "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                     "max_resid": float(rs.max())}
+    del vals, b, x
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +122,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="time only the headline form (for profiler runs)")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-batch leg (100k systems, n in [16, 1024])")
+    ap.add_argument("--uneven-batch", type=int, default=100_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -141,6 +206,10 @@ def main() -> int:
             r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
             variants[name] = r
 
+    uneven = None
+    if not args.no_uneven:
+        uneven = uneven_leg(args, bs, W, torch, np, dev, tol, max_iter)
+
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
@@ -208,6 +277,7 @@ def main() -> int:
         "check": {"all_converged": head["all_converged"], "iters_mean": head["iters_mean"],
                   "iters_max": head["iters_max"], "max_resid": head["max_resid"]},
         "variants": variants,
+        "uneven": uneven,
         "gen_seconds": gen_s,
         "kernel_source_sha": kernel_source_sha(),
     }

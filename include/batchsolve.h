@@ -172,8 +172,9 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
  * pattern, Sec. 3.1; its per-device size thresholds, Sec. 3.6, become an
  * autotuned choice here).  Systems are grouped by size class into tasks of one
  * to sixteen systems, ordered largest first, and taken from an atomic work
- * queue by 1024-lane workgroups; each system is solved by a team of
- * 64..1024 lanes (one row per lane, n_rows <= 1024, longest row <= 16).
+ * queue by the workgroups of one persistent launch; each system is solved by a
+ * team of 64 or more lanes that own R rows each (n_rows <= 1024, longest row
+ * <= 16).  Workgroup shapes: 1024 lanes x 1 row, 512 x 2, 256 x 4.
  * ------------------------------------------------------------------------- */
 typedef struct bs_varbatch_s *bs_varbatch;
 
@@ -197,9 +198,12 @@ int bs_varbatch_destroy(bs_varbatch vb);
 int bs_varbatch_query(bs_varbatch vb, int64_t *total_rows, int64_t *total_values, int32_t *n_tasks,
                       int32_t *policy);
 
-/* Queue policies: 0 = team of the next power of two >= n (at least 64),
- * largest tasks first; 1 = teams twice that size (fewer systems per task);
- * 2 = as 0 with the systems of a class kept in batch order. */
+/* Policy p (0..8) = workgroup shape p / 3 (0: 1024 lanes x 1 row per lane,
+ * 1: 512 x 2, 2: 256 x 4) and queue order p % 3: 0 = team of the next power
+ * of two >= n / R lanes (at least 64), largest tasks first; 1 = teams twice
+ * that size (fewer systems per task); 2 = as 0 with the systems of a class
+ * kept in batch order.  Policy 0 after bs_varbatch_create.
+ * BS_ERR_INVALID_ARG for p outside 0..8. */
 int bs_varbatch_set_policy(bs_varbatch vb, int32_t policy);
 
 /* Solve all systems (BS_CG or BS_BICGSTAB; BS_MIXED for BiCGSTAB), arguments
@@ -212,7 +216,7 @@ int bs_varbatch_solve(bs_varbatch vb, const double *values, const double *b, dou
 
 /* Autotuner: time every queue policy on these inputs (1 warm-up and `reps`
  * timed solves each, synchronising `stream`), keep the fastest, and write a
- * one-line report "policy=<p> times_ms=<t0>,<t1>,<t2>" into report (may be
+ * one-line report "policy=<p> times_ms=<t0>,..,<t8>" into report (may be
  * NULL).  If cache_path is not NULL the choice is looked up in / appended to
  * that text file, keyed by the size-class histogram, solver and precision; a
  * cached choice is applied without timing or solving.  Each timed solve

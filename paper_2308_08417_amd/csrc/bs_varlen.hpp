@@ -1,24 +1,35 @@
 // Uneven batches in one persistent launch: systems of different sizes (and
-// patterns) share one kernel.  A workgroup of kVarWG lanes takes tasks from an
-// atomic queue; a task is up to kVarWG/T systems of one size class, each
-// solved by a team of T lanes (T a power of two in [64, kVarWG], one row per
-// lane).  The teams of a workgroup advance in lockstep: every barrier and
-// every branch around a barrier is decided for the whole workgroup (any() is a
-// workgroup-wide OR), so a team that has finished idles until the task ends.
+// patterns) share one kernel.  A workgroup of WG lanes takes tasks from an
+// atomic queue; a task is up to WG/T systems of one size class, each solved by
+// a team of T lanes (T a power of two in [64, WG]) that owns R rows per lane,
+// rows lane, lane+T, .., lane+(R-1)T.  The largest system has WG*R rows.
+//
+// Teams of one wave need no workgroup barrier: when a task's teams are single
+// waves, each advances on its own (wave-level fences, ballots and DPP sums)
+// and the waves meet only at the next task.  Teams of several waves share the
+// workgroup's barriers, so the teams of such a task advance in lockstep: any()
+// is then a workgroup-wide OR and a finished team idles until the task ends.
 // The solver bodies are the ones of the fixed-size kernels.
 #pragma once
 #include "bs_solvers.hpp"
 
 namespace bs {
 
-constexpr int kVarWG = 1024;
-constexpr int kVarWaves = kVarWG / kWave;
-constexpr int kVarMaxTeams = kVarWG / kWave;  // teams of at least one wave
+template <int WG_, int R_>
+struct VarShape {
+  static constexpr int WG = WG_, R = R_;
+  static constexpr int WAVES = WG / kWave;
+  static constexpr int MAXT = WG / kWave;  // teams per task at most (T >= 64)
+  static constexpr int ROWS = WG * R;      // largest system
+  // waves per SIMD that one group places (the register budget per lane);
+  // asking the narrow shapes for more spills their rows to scratch
+  static constexpr int OCC = WG / 256;
+};
 
 struct VTask {
   int team;   // lanes per system
   int first;  // index of the first system in the queue order
-  int count;  // systems in this task (<= kVarWG / team)
+  int count;  // systems in this task (<= WG / team)
   int pad;
 };
 
@@ -41,14 +52,25 @@ struct VArgs {
   int* counter;           // task counter, zero at launch
 };
 
-// Team of runtime size inside a kVarWG-lane workgroup.
+// Vector buffers: team t's rows at elements [t*T*R, (t+1)*T*R), then one zero
+// cell per team after the ROWS elements, so the stride is a constant.
+template <class VS>
+constexpr unsigned var_buf_bytes() { return round16((unsigned)(VS::ROWS + VS::MAXT) * 8); }
+
+template <class VS>
+constexpr int var_lds_bytes() {
+  return 2 * (int)var_buf_bytes<VS>() + 2 * kMaxFused * VS::WAVES * 8;
+}
+
+// Team of runtime size T (uniform across the workgroup for a task).
+template <class VS>
 struct VarTeam {
-  int T;               // lanes per team (uniform across the workgroup)
+  int T;               // lanes per team
   int lane, tix;       // lane within the team, team within the workgroup
   int wpt;             // waves per team
   int64_t sys, row0;
   bool live;
-  char* lds;           // vector buffers (shared layout, see VarRows)
+  char* lds;
   double* red;         // cross-wave reduction slots
   int phase;
 
@@ -58,33 +80,57 @@ struct VarTeam {
     tix = threadIdx.x / t;
     wpt = t / kWave;
     lds = smem;
-    red = reinterpret_cast<double*>(smem + 2 * (kVarWG + kVarMaxTeams) * 8);
+    red = reinterpret_cast<double*>(smem + 2 * var_buf_bytes<VS>());
   }
 
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+  // Single-wave teams: a wave's LDS operations complete in issue order, so a
+  // wavefront-scope fence (for the compiler) is enough.
+  __device__ __forceinline__ void sync() {
+    if (wpt == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      __syncthreads();
+    }
+  }
 
-  // Workgroup-wide: teams run in lockstep, so every branch that contains a
-  // barrier must be taken by all of them.
-  __device__ __forceinline__ bool any(bool p) const { return __syncthreads_or(p ? 1 : 0) != 0; }
+  __device__ __forceinline__ bool any(bool p) const {
+    if (wpt == 1) return wave_any(p);
+    return __syncthreads_or(p ? 1 : 0) != 0;
+  }
 
   template <class V, int K>
   __device__ __forceinline__ void sum(V (&v)[K]) {
     static_assert(K <= kMaxFused, "too many fused values");
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = rdlane(rows_total(row16_sum(v[k])), 63);
-    if (wpt > 1) {  // uniform: every team of the task has the same size
-      double* buf = red + phase * (kMaxFused * kVarWaves);
+    if (wpt > 1) {
+      double* buf = red + phase * (kMaxFused * VS::WAVES);
       const int w = threadIdx.x >> 6;
       if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) buf[k * kVarWaves + w] = (double)v[k];
+        for (int k = 0; k < K; ++k) buf[k * VS::WAVES + w] = (double)v[k];
       }
       __syncthreads();
+      // the team's wave partials in order, four loads in flight at a time
+      // (wpt is a power of two >= 2, uniform over the workgroup)
+      constexpr int kG = VS::WAVES < 4 ? VS::WAVES : 4;
       const int w0 = tix * wpt;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        double s = buf[k * kVarWaves + w0];
-        for (int i = 1; i < wpt; ++i) s += buf[k * kVarWaves + w0 + i];
+        const double* q = buf + k * VS::WAVES + w0;
+        double s = q[0];
+#pragma unroll
+        for (int i0 = 0; i0 < VS::WAVES; i0 += kG) {
+          if (i0 < wpt) {
+            double part[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) part[j] = q[min(i0 + j, wpt - 1)];
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+              if (i0 + j > 0 && i0 + j < wpt) s += part[j];
+          }
+        }
         v[k] = (V)s;
       }
       phase ^= 1;
@@ -92,121 +138,139 @@ struct VarTeam {
   }
 };
 
-// The row a lane owns (one per lane).  Vector buffer b holds team t's row i at
-// element t*T + i, and the teams' zero cells after the kVarWG rows, so the
-// buffer stride is a constant whatever the team size.
-template <int NZ_>
+// The R rows a lane owns, their values and LDS gather addresses in registers.
+template <class VS, int NZ_>
 struct VarRows {
-  static constexpr int R = 1, NZ = NZ_, ROWS = kVarWG;
-  static constexpr unsigned kBuf = (kVarWG + kVarMaxTeams) * 8;
-  double a[1][NZ];
-  unsigned c[1][NZ];
-  unsigned vrow[1];
-  int row[1];
-  bool ok[1];
-  int dslot[1];
+  static constexpr int R = VS::R, NZ = NZ_, ROWS = VS::ROWS;
+  static constexpr unsigned kBuf = var_buf_bytes<VS>();
+  double a[R][NZ];
+  unsigned c[R][NZ];
+  unsigned vrow[R];
+  int row[R];
+  bool ok[R];
+  int dslot[R];
   unsigned zero;
-  double dval[1], bval[1], xval[1];
+  double dval[R], bval[R], xval[R];
 
-  // Pattern and values of this team's system, straight from HBM.
-  __device__ void load(const VarTeam& tm, const VArgs& va, unsigned lds_base) {
+  // Pattern and values of this team's system, straight from HBM.  Every load
+  // is guarded: an idle lane, row or slot reads nothing.
+  __device__ void load(const VarTeam<VS>& tm, const VArgs& va, unsigned lds_base) {
     const KArgs& g = va.base;
     const int s = tm.live ? (int)tm.sys : 0;
     const int n = tm.live ? va.sys_rows[s] : 0;
     const int p = va.sys_pat[s];
-    row[0] = tm.lane;
-    ok[0] = tm.lane < n;
-    vrow[0] = lds_base + (unsigned)(tm.tix * tm.T + tm.lane) * 8;
-    zero = lds_base + (unsigned)(kVarWG + tm.tix) * 8;
-    const int rr = ok[0] ? row[0] : 0;
+    const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
+    zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
     const int64_t pr = va.pat_row[p];
-    const int len = ok[0] ? va.prow_len[pr + rr] : 0;
-    const int ds = ok[0] ? va.pdiag[pr + rr] : -1;
-    const int rp = ok[0] ? va.prow_ptr[va.pat_rp[p] + rr] : 0;
+    const int* rps = va.prow_ptr + va.pat_rp[p];
     const int* sc = va.pslot_col + va.pat_sc[p];
     const double* vals = g.values + va.val_off[s];
-    const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T) * 8;
-    // every load is guarded: an idle lane or slot reads nothing
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) {
-      const bool has = k < len;
-      int col = 0;
-      double v = 0.0;
-      if (has) {
-        col = sc[(size_t)k * n + rr];
-        v = __builtin_nontemporal_load(vals + rp + k);
+    for (int r = 0; r < R; ++r) {
+      row[r] = tm.lane + r * tm.T;
+      ok[r] = row[r] < n;
+      vrow[r] = tb + (unsigned)row[r] * 8;
+      const int rr = row[r];
+      int len = 0, ds = -1, rp = 0;
+      if (ok[r]) {
+        len = va.prow_len[pr + rr];
+        ds = va.pdiag[pr + rr];
+        rp = rps[rr];
       }
-      c[0][k] = has ? tb + col * 8 : zero;
-      a[0][k] = v;
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) {
+        const bool has = k < len;
+        int col = 0;
+        double v = 0.0;
+        if (has) {
+          col = sc[(size_t)k * n + rr];
+          v = __builtin_nontemporal_load(vals + rp + k);
+        }
+        c[r][k] = has ? tb + col * 8 : zero;
+        a[r][k] = v;
+      }
+      dslot[r] = ds;
+      dval[r] = ds >= 0 ? vals[rp + ds] : 0.0;
+      bval[r] = ok[r] ? g.b[tm.row0 + rr] : 0.0;
+      double xv = 0.0;
+      if ((g.flags & 1) == 0 && ok[r]) xv = g.x[tm.row0 + rr];
+      xval[r] = xv;
     }
-    dslot[0] = ds;
-    dval[0] = ds >= 0 ? vals[rp + ds] : 0.0;
-    bval[0] = ok[0] ? g.b[tm.row0 + rr] : 0.0;
-    double xv = 0.0;
-    if ((g.flags & 1) == 0 && ok[0]) xv = g.x[tm.row0 + rr];
-    xval[0] = xv;
   }
 
-  __device__ __forceinline__ bool real(int, int k) const { return c[0][k] != zero; }
+  __device__ __forceinline__ bool real(int r, int k) const { return c[r][k] != zero; }
 
-  __device__ void jacobi(int precond, double (&d)[1]) const {
-    const double dv = dval[0];
-    d[0] = !ok[0] ? 0.0 : (precond == 1 && dslot[0] >= 0 && dv != 0.0) ? 1.0 / dv : 1.0;
+  __device__ void jacobi(int precond, double (&d)[R]) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dv = dval[r];
+      d[r] = !ok[r] ? 0.0 : (precond == 1 && dslot[r] >= 0 && dv != 0.0) ? 1.0 / dv : 1.0;
+    }
   }
 
   template <int BUF, class V, class AT>
-  __device__ __forceinline__ void spmv(VarTeam& tm, const AT (&av)[1][NZ], const V (&v)[1],
-                                       V (&y)[1]) const {
+  __device__ __forceinline__ void spmv(VarTeam<VS>& tm, const AT (&av)[R][NZ], const V (&v)[R],
+                                       V (&y)[R]) const {
     constexpr int kGather = 4;
     constexpr unsigned off = BUF * kBuf;
-    if (ok[0]) lds_store<V>(vrow[0] + off, v[0]);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (ok[r]) lds_store<V>(vrow[r] + off, v[r]);
     tm.sync();
-    V acc[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k0 = 0; k0 < NZ; k0 += kGather) {
-      V xv[kGather];
+    for (int r = 0; r < R; ++r) {
+      V acc[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int k = k0; k < k0 + kGather && k < NZ; ++k) xv[k - k0] = lds_load<V>(c[0][k] + off);
+      for (int k0 = 0; k0 < NZ; k0 += kGather) {
+        V xv[kGather];
 #pragma unroll
-      for (int k = k0; k < k0 + kGather && k < NZ; ++k)
-        acc[k % 4] = fma((V)av[0][k], xv[k - k0], acc[k % 4]);
-      __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+        for (int k = k0; k < k0 + kGather && k < NZ; ++k) xv[k - k0] = lds_load<V>(c[r][k] + off);
+#pragma unroll
+        for (int k = k0; k < k0 + kGather && k < NZ; ++k)
+          acc[k % 4] = fma((V)av[r][k], xv[k - k0], acc[k % 4]);
+        __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+      }
+      y[r] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
-    y[0] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
 };
 
-// LDS of the uneven-batch kernel: two vector buffers, then the reduction slots.
-constexpr int kVarLdsBytes = 2 * (kVarWG + kVarMaxTeams) * 8 + 2 * kMaxFused * kVarWaves * 8;
-
 __global__ void k_varlen_reset(int* counter) { *counter = 0; }
 
-template <int NZ, int SOLVER, bool MIXED>
-__global__ __launch_bounds__(kVarWG) void k_varlen(const VArgs va) {
-  __shared__ __align__(16) char smem[kVarLdsBytes];
+template <class VS, int NZ, int SOLVER, bool MIXED>
+__global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(VS::OCC)))
+void k_varlen(const VArgs va) {
+  __shared__ __align__(16) char smem[var_lds_bytes<VS>()];
   __shared__ int task_sh;
   const unsigned lds_base = lds_addr(smem);
-  if (threadIdx.x < kVarMaxTeams * kVecBuffers) {  // zero cells of both buffers
-    const int b = threadIdx.x / kVarMaxTeams, t = threadIdx.x % kVarMaxTeams;
-    lds_store<double>(lds_base + b * VarRows<NZ>::kBuf + (kVarWG + t) * 8, 0.0);
+  constexpr unsigned kBuf = var_buf_bytes<VS>();
+  if (threadIdx.x < VS::MAXT * kVecBuffers) {  // zero cells of both buffers
+    const int b = threadIdx.x / VS::MAXT, t = threadIdx.x % VS::MAXT;
+    lds_store<double>(lds_base + b * kBuf + (VS::ROWS + t) * 8, 0.0);
   }
-  VarTeam tm;
+  VarTeam<VS> tm;
   tm.phase = 0;
   for (;;) {
     if (threadIdx.x == 0) task_sh = atomicAdd(va.counter, 1);
     __syncthreads();
-    const int t = task_sh;
+    const int t = __builtin_amdgcn_readfirstlane(task_sh);
     __syncthreads();  // every lane has read the task before it is overwritten
-    if (t >= va.n_tasks) break;
-    const VTask task = va.tasks[t];
+    // Read the arguments at an address that depends on the task index (the
+    // offset is zero: task indices are never negative).  Otherwise the compiler
+    // hoists every argument load out of this loop and the ones that only the
+    // loading phase needs stay live in scalar registers through the whole
+    // solve, where they spill.
+    const VArgs& a = (&va)[(unsigned)t >> 31];
+    if (t >= a.n_tasks) break;
+    const VTask task = a.tasks[t];
     tm.set_team(task.team, smem);
     tm.live = tm.tix < task.count;
-    tm.sys = tm.live ? va.order[task.first + tm.tix] : 0;
-    tm.row0 = tm.live ? va.row_off[tm.sys] : 0;
-    VarRows<NZ> A;
-    A.load(tm, va, lds_base);
-    if constexpr (SOLVER == 0) cg_system(tm, A, va.base);
-    else bicgstab_system<MIXED>(tm, A, va.base);
+    tm.sys = tm.live ? a.order[task.first + tm.tix] : 0;
+    tm.row0 = tm.live ? a.row_off[tm.sys] : 0;
+    VarRows<VS, NZ> A;
+    A.load(tm, a, lds_base);
+    if constexpr (SOLVER == 0) cg_system(tm, A, a.base);
+    else bicgstab_system<MIXED>(tm, A, a.base);
   }
 }
 

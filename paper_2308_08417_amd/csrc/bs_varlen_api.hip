@@ -35,35 +35,49 @@ int next_pow2(int v) {
 typedef hipError_t (*VLaunch)(const bs::VArgs&, unsigned grid, hipStream_t);
 typedef hipError_t (*VOccupancy)(int*);
 
-template <int NZ, int SOLVER, bool MIXED>
+template <class VS, int NZ, int SOLVER, bool MIXED>
 hipError_t vlaunch(const bs::VArgs& a, unsigned grid, hipStream_t s) {
-  hipLaunchKernelGGL((bs::k_varlen<NZ, SOLVER, MIXED>), dim3(grid), dim3(bs::kVarWG), 0, s, a);
+  hipLaunchKernelGGL((bs::k_varlen<VS, NZ, SOLVER, MIXED>), dim3(grid), dim3(VS::WG), 0, s, a);
   return hipGetLastError();
 }
 
-template <int NZ, int SOLVER, bool MIXED>
+template <class VS, int NZ, int SOLVER, bool MIXED>
 hipError_t voccupancy(int* blocks) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, reinterpret_cast<const void*>(&bs::k_varlen<NZ, SOLVER, MIXED>), bs::kVarWG, 0);
+      blocks, reinterpret_cast<const void*>(&bs::k_varlen<VS, NZ, SOLVER, MIXED>), VS::WG, 0);
 }
 
-// Compiled instances: slots per row x (CG, BiCGSTAB, BiCGSTAB mixed).
+// Workgroup shapes (lanes, rows per lane); each holds systems of up to 1024 rows.
+struct VShapeInfo {
+  int wg, r;
+};
+constexpr VShapeInfo kVShapes[] = {{1024, 1}, {512, 2}, {256, 4}};
+constexpr int kNumShapes = 3;
+constexpr int kNumOrders = 3;
+constexpr int kNumPolicies = kNumShapes * kNumOrders;
+constexpr int kMaxVarRows = 1024;
+
+// Compiled instances: shape x slots per row x (CG, BiCGSTAB, BiCGSTAB mixed).
 struct VEntry {
-  int nz, solver, mixed;
+  int wg, r, nz, solver, mixed;
   VLaunch fn;
   VOccupancy occ;
 };
-#define VE(NZ)                                                                         \
-  {NZ, 0, 0, &vlaunch<NZ, 0, false>, &voccupancy<NZ, 0, false>},                       \
-      {NZ, 1, 0, &vlaunch<NZ, 1, false>, &voccupancy<NZ, 1, false>},                   \
-      {NZ, 1, 1, &vlaunch<NZ, 1, true>, &voccupancy<NZ, 1, true>},
-const VEntry kVTable[] = {VE(8) VE(12) VE(16)};
+#define VE1(W, R, NZ, SO, MX)                                                         \
+  {W, R, NZ, SO, MX, &vlaunch<bs::VarShape<W, R>, NZ, SO, MX>,                         \
+   &voccupancy<bs::VarShape<W, R>, NZ, SO, MX>},
+#define VE(W, R, NZ) VE1(W, R, NZ, 0, false) VE1(W, R, NZ, 1, false) VE1(W, R, NZ, 1, true)
+#define VES(W, R) VE(W, R, 8) VE(W, R, 10) VE(W, R, 12) VE(W, R, 16)
+const VEntry kVTable[] = {VES(1024, 1) VES(512, 2) VES(256, 4)};
+#undef VES
 #undef VE
+#undef VE1
 
-const VEntry* find_v(int nz, int solver, int mixed) {
+const VEntry* find_v(int wg, int r, int nz, int solver, int mixed) {
   const VEntry* best = nullptr;
   for (const VEntry& e : kVTable)
-    if (e.solver == solver && e.mixed == mixed && e.nz >= nz && (!best || e.nz < best->nz))
+    if (e.wg == wg && e.r == r && e.solver == solver && e.mixed == mixed && e.nz >= nz &&
+        (!best || e.nz < best->nz))
       best = &e;
   return best;
 }
@@ -73,6 +87,7 @@ const VEntry* find_v(int nz, int solver, int mixed) {
 struct bs_varbatch_s {
   int64_t B = 0;
   int P = 0, max_row = 0, device = -1, policy = 0;
+  int policy_next = 0;  // policy of the tasks being uploaded
   std::vector<int> sys_rows, sys_pat, pat_n, pat_nnz;
   std::vector<int64_t> row_off, val_off, pat_rp, pat_row, pat_sc;
   std::vector<int> prow_ptr, prow_len, pdiag, pslot_col;
@@ -91,27 +106,30 @@ struct bs_varbatch_s {
 
 namespace {
 
-// Tasks for a queue policy (see bs_varbatch_set_policy).
+// Tasks for a policy (see bs_varbatch_set_policy): workgroup shape
+// policy / 3, queue order policy % 3.
 void build_tasks(bs_varbatch_s& v, int policy) {
+  const VShapeInfo sh = kVShapes[policy / kNumOrders];
+  const int order = policy % kNumOrders;
   std::vector<int> team(v.B);
   for (int64_t s = 0; s < v.B; ++s) {
-    int t = std::max(bs::kWave, next_pow2(v.sys_rows[s]));
-    if (policy == 1) t = std::min(bs::kVarWG, 2 * t);
+    int t = std::max(bs::kWave, next_pow2((v.sys_rows[s] + sh.r - 1) / sh.r));
+    if (order == 1) t = std::min(sh.wg, 2 * t);
     team[s] = t;
   }
   std::vector<int> idx(v.B);
   for (int64_t s = 0; s < v.B; ++s) idx[s] = (int)s;
   // group by team size (largest first); inside a class, largest systems first
-  // (similar sizes share a task) unless the policy keeps batch order
+  // (similar sizes share a task) unless the order keeps the batch order
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
     if (team[a] != team[b]) return team[a] > team[b];
-    if (policy == 2) return false;
+    if (order == 2) return false;
     return v.val_off[a + 1] - v.val_off[a] > v.val_off[b + 1] - v.val_off[b];
   });
   v.order = idx;
   v.tasks.clear();
   for (int64_t i = 0; i < v.B;) {
-    const int t = team[idx[i]], cap = bs::kVarWG / t;
+    const int t = team[idx[i]], cap = sh.wg / t;
     int c = 0;
     while (i + c < v.B && c < cap && team[idx[i + c]] == t) ++c;
     v.tasks.push_back({t, (int)i, c, 0});
@@ -122,13 +140,14 @@ void build_tasks(bs_varbatch_s& v, int policy) {
 int upload_tasks(bs_varbatch_s& v) {
   // what the kernel assumes of every task: a power-of-two team of at least a
   // wave that holds each of its systems, and teams that fit one workgroup
+  const VShapeInfo sh = kVShapes[v.policy_next / kNumOrders];
   int64_t covered = 0;
   for (const bs::VTask& t : v.tasks) {
-    if (t.team < bs::kWave || t.team > bs::kVarWG || (t.team & (t.team - 1)) || t.count < 1 ||
-        (int64_t)t.count * t.team > bs::kVarWG || t.first != covered)
+    if (t.team < bs::kWave || t.team > sh.wg || (t.team & (t.team - 1)) || t.count < 1 ||
+        (int64_t)t.count * t.team > sh.wg || t.first != covered)
       return BS_ERR_INVALID_ARG;
     for (int i = 0; i < t.count; ++i)
-      if (v.sys_rows[v.order[t.first + i]] > t.team) return BS_ERR_INVALID_ARG;
+      if (v.sys_rows[v.order[t.first + i]] > t.team * sh.r) return BS_ERR_INVALID_ARG;
     covered += t.count;
   }
   if (covered != v.B) return BS_ERR_INVALID_ARG;
@@ -153,7 +172,8 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   if (o && (o->inner_tol < 0.0 || !std::isfinite(o->inner_tol))) return BS_ERR_INVALID_ARG;
   if (v.B == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
-  const VEntry* k = find_v(std::max(v.max_row, 1), solver == BS_CG ? 0 : 1, mixed);
+  const VShapeInfo sh = kVShapes[v.policy / kNumOrders];
+  const VEntry* k = find_v(sh.wg, sh.r, std::max(v.max_row, 1), solver == BS_CG ? 0 : 1, mixed);
   if (!k) return BS_ERR_UNSUPPORTED;
   bs::VArgs a = v.args;
   bs::KArgs& g = a.base;
@@ -237,7 +257,7 @@ int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t* pat_r
   for (int p = 0; p < n_patterns && rc == BS_OK; ++p) {
     const int n = pat_rows[p];
     if (n < 1) { rc = BS_ERR_INVALID_ARG; break; }
-    if (n > bs::kVarWG) { rc = BS_ERR_UNSUPPORTED; break; }
+    if (n > kMaxVarRows) { rc = BS_ERR_UNSUPPORTED; break; }
     const int32_t* rp = rowptr_all + pat_rowptr_off[p];
     const int32_t* ci = col_all + pat_col_off[p];
     if (rp[0] != 0) { rc = BS_ERR_PATTERN; break; }
@@ -355,6 +375,7 @@ int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t* pat_r
       v->args.counter = v->d_counter;
     }
     if (rc == BS_OK) {
+      v->policy_next = 0;
       build_tasks(*v, 0);
       rc = upload_tasks(*v);
     }
@@ -391,14 +412,21 @@ int bs_varbatch_query(bs_varbatch v, int64_t* total_rows, int64_t* total_values,
 }
 
 int bs_varbatch_set_policy(bs_varbatch v, int32_t policy) {
-  if (!v || policy < 0 || policy > 2) return BS_ERR_INVALID_ARG;
+  if (!v || policy < 0 || policy >= kNumPolicies) return BS_ERR_INVALID_ARG;
   if (policy == v->policy) return BS_OK;
   // a captured graph holds the old task count: drop it
   if (v->gexec) { (void)hipGraphExecDestroy(v->gexec); v->gexec = nullptr; }
   if (v->graph) { (void)hipGraphDestroy(v->graph); v->graph = nullptr; }
+  v->policy_next = policy;
   build_tasks(*v, policy);
   const int rc = upload_tasks(*v);
-  if (rc == BS_OK) v->policy = policy;
+  if (rc == BS_OK) {
+    v->policy = policy;
+  } else {  // restore the previous tasks
+    v->policy_next = v->policy;
+    build_tasks(*v, v->policy);
+    (void)upload_tasks(*v);
+  }
   return rc;
 }
 
@@ -428,7 +456,7 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
       double t = 0;
       int found = -1;
       while (std::fscanf(f, "%511s %d %lf", k, &p, &t) == 3)
-        if (key == k && p >= 0 && p <= 2) found = p;
+        if (key == k && p >= 0 && p < kNumPolicies) found = p;
       std::fclose(f);
       if (found >= 0) {
         const int rc = bs_varbatch_set_policy(v, found);
@@ -438,7 +466,7 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
       }
     }
   }
-  double times[3] = {0, 0, 0};
+  double times[kNumPolicies] = {0};
   int best = 0;
   // every timed solve starts from the caller's x0 (kept in a copy) unless the
   // flags say x0 = 0; the copy back is timed for every policy alike
@@ -464,7 +492,7 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
   int rc = BS_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = hip_err(hipGetLastError(), "tune events");
-  for (int p = 0; p < 3 && rc == BS_OK; ++p) {
+  for (int p = 0; p < kNumPolicies && rc == BS_OK; ++p) {
     rc = bs_varbatch_set_policy(v, p);
     if (rc != BS_OK) break;
     rc = run();
@@ -488,9 +516,16 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
     (void)hipFree(x0);
   }
   if (rc != BS_OK) return rc;
-  if (report && report_len)
-    std::snprintf(report, report_len, "policy=%d times_ms=%.4f,%.4f,%.4f key=%s", best, times[0],
-                  times[1], times[2], key.c_str());
+  if (report && report_len) {
+    std::string t;
+    for (int p = 0; p < kNumPolicies; ++p) {
+      char buf[32];
+      std::snprintf(buf, sizeof buf, "%s%.4f", p ? "," : "", times[p]);
+      t += buf;
+    }
+    std::snprintf(report, report_len, "policy=%d times_ms=%s key=%s", best, t.c_str(),
+                  key.c_str());
+  }
   if (rc == BS_OK && cache_path) {
     FILE* f = std::fopen(cache_path, "a");
     if (f) {

@@ -141,12 +141,17 @@ def test_small_systems_many_per_task():
     c.check(g, bs.BICGSTAB, precond=bs.PREC_NONE)
 
 
-def test_policies_give_identical_results():
-    """The queue order and the team width change who solves a system, not the
-    arithmetic: every policy gives the same bits."""
-    c = VCase(W.uneven_banded(500, 16, 700, seed=4))
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_policies(shape):
+    """Every workgroup shape (1024 x 1, 512 x 2, 256 x 4 rows per lane) and
+    queue order meets the oracle.  The queue order changes who solves a system,
+    not the arithmetic: orders 0 and 2 give the same bits, and so does order 1
+    (teams twice as wide) with one row per lane; with R rows per lane a wider
+    team moves rows between lanes, which reorders the sums."""
+    c = VCase(W.uneven_banded(500, 16, 1024, seed=4))
     ref = None
-    for p in (0, 1, 2):
+    for order in (0, 2, 1):
+        p = 3 * shape + order
         bs.bs_varbatch_set_policy(c.h.handle, p)
         q = c.h.query()
         assert q["policy"] == p and q["n_tasks"] >= 1
@@ -154,9 +159,13 @@ def test_policies_give_identical_results():
         if ref is None:
             ref = g
             c.check(g, bs.BICGSTAB)
-        else:
+        elif order == 2 or shape == 0:
             for u, v in zip(ref, g):
                 assert np.array_equal(u, v), f"policy {p} differs"
+        else:
+            c.check(g, bs.BICGSTAB)
+    with pytest.raises(bs.BatchSolveError):
+        bs.bs_varbatch_set_policy(c.h.handle, 9)
 
 
 def test_mixed_precision_uneven():
@@ -207,11 +216,13 @@ def test_single_row_systems():
         assert np.all(st.cpu().numpy() == bs.CONVERGED)
 
 
-def test_graph_replay_matches_eager():
+@pytest.mark.parametrize("policy", [0, 4, 8])
+def test_graph_replay_matches_eager(policy):
     """The captured graph (counter reset kernel + solve) replayed several times,
     with eager work and synchronisation between replays, equals the eager solve
     bit for bit each time."""
     c = VCase(W.uneven_banded(300, 16, 1024, seed=7))
+    bs.bs_varbatch_set_policy(c.h.handle, policy)
     eager = c.gpu(bs.BICGSTAB)
     x, it, rs, st = c.outputs()
     bs.bs_varbatch_capture(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10, 1000,
@@ -229,14 +240,13 @@ def test_graph_replay_matches_eager():
                                 st.cpu().numpy())):
             assert np.array_equal(u, v), f"replay {rep} differs from the eager solve"
     # a policy change drops the graph
-    bs.bs_varbatch_set_policy(c.h.handle, 1)
+    bs.bs_varbatch_set_policy(c.h.handle, (policy + 1) % 9)
     with pytest.raises(bs.BatchSolveError):
         bs.bs_varbatch_replay(c.h.handle)
 
 
 def test_tune_and_cache(tmp_path):
     c = VCase(W.uneven_banded(600, 16, 1024, seed=8))
-    eager = c.gpu(bs.BICGSTAB)
     x, it, rs, st = c.outputs()
     cache = str(tmp_path / "tune.txt")
     rep = bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
@@ -247,7 +257,11 @@ def test_tune_and_cache(tmp_path):
     assert rep.startswith("policy=") and "times_ms=" in rep
     pol = int(rep.split()[0].split("=")[1])
     assert c.h.query()["policy"] == pol
-    assert np.array_equal(x.cpu().numpy(), eager[0])
+    assert len(rep.split()[1].split("=")[1].split(",")) == 9
+    # the outputs are those of an eager solve with the chosen policy
+    chosen = c.gpu(bs.BICGSTAB)
+    assert np.array_equal(x.cpu().numpy(), chosen[0])
+    c.check(chosen, bs.BICGSTAB)
     assert open(cache).read().count("\n") == 1
     rep2 = bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
                                1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO), reps=2,
