@@ -125,6 +125,13 @@ typedef struct {
   int32_t rows_per_lane;/* 1, 2 or 4; 0 = planner                                */
   int32_t *outer_iters; /* BS_MIXED: optional device int32[n_batch] of refinement
                            steps; NULL = not written                              */
+  const double *x_alt;  /* optional device [n_batch][n_rows]: a second initial
+                           guess.  Each system starts from whichever of x and
+                           x_alt has the smaller ||b - A x||_2 (x on a tie; x_alt
+                           also when only x's norm is NaN), one extra SpMV.  Not
+                           with BS_FLAG_X0_ZERO (BS_ERR_INVALID_ARG)              */
+  int32_t *alt_used;    /* optional device int32[n_batch]: 1 where x_alt was
+                           taken, 0 where x was; written only with x_alt          */
 } bs_options;
 
 /* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch
@@ -239,6 +246,71 @@ int bs_varbatch_capture(bs_varbatch vb, const double *values, const double *b, d
                         bs_solver solver, bs_precond precond, double tol, int32_t max_iter,
                         int32_t *iters, double *resid, int32_t *status, const bs_options *opts);
 int bs_varbatch_replay(bs_varbatch vb, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned initial guess for sequences of related batches (systems that drift
+ * from one time step to the next, as along an integration in time; the paper
+ * solves such sequences, Sec. 4.3).  A three-layer perceptron maps the
+ * features f = [diag(A_t), b_t, x_{t-1}] of a system (3n values, normalised by
+ * training-set means and standard deviations) through two hidden ReLU layers
+ * of width 256 to y (n values); the guess is x0 = x_{t-1} + sigma_d * y, with
+ * sigma_d the per-component standard deviation of x_t - x_{t-1} over the
+ * training data.  Training minimises the mean squared error between y and
+ * (x_t - x_{t-1}) / sigma_d with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Products run on BF16 matrix cores with FP32 accumulation; the master
+ * weights, Adam moments, biases and losses are FP32, the scaling FP64.
+ *
+ * Parameter vector (FP32, this order, row-major): W1 [3n][256], b1 [256],
+ * W2 [256][256], b2 [256], W3 [256][n], b3 [n].
+ * Device arrays: feat [rows][3n] and delta [rows][n] FP32; rows (optional)
+ * selects the samples of a minibatch; values/b/x FP64 as in bs_batch_solve
+ * (CSR values of the model's pattern).  Calls taking a stream are
+ * asynchronous on it; the others synchronise the device.
+ * ------------------------------------------------------------------------- */
+typedef struct bs_ws_model_s *bs_ws_model;
+
+/* Model for systems with the given CSR pattern (host arrays; n <= 64).
+ * Weights start at zero and the scaling at mean 0 / deviation 1.
+ * Errors: BS_ERR_INVALID_ARG, BS_ERR_PATTERN, BS_ERR_UNSUPPORTED (n > 64),
+ * BS_ERR_NO_DEVICE, BS_ERR_HIP. */
+int bs_ws_create(int32_t n, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                 bs_ws_model *out);
+int bs_ws_destroy(bs_ws_model m);
+int bs_ws_param_count(bs_ws_model m, int64_t *count);
+
+/* Copy the FP32 parameter vector in (and reset Adam) or out (host arrays). */
+int bs_ws_set_params(bs_ws_model m, const float *host_params);
+int bs_ws_get_params(bs_ws_model m, float *host_params);
+
+/* Raw features of n_batch systems and, if x_next is not NULL, their change
+ * delta = x_next - x_prev (FP32). */
+int bs_ws_features(bs_ws_model m, int64_t n_batch, const double *values, const double *b,
+                   const double *x_prev, const double *x_next, float *feat, float *delta,
+                   void *stream);
+
+/* Fit the scaling (feature means and deviations, and sigma_d) to n_samples
+ * training rows; get/set copy it from/to host arrays (F = 3n, n, n values). */
+int bs_ws_fit_scaling(bs_ws_model m, int64_t n_samples, const float *feat, const float *delta,
+                      void *stream);
+int bs_ws_get_scaling(bs_ws_model m, double *mu_f, double *sd_f, double *sd_d);
+int bs_ws_set_scaling(bs_ws_model m, const double *mu_f, const double *sd_f, const double *sd_d);
+
+/* Network output y [n_samples][n] for raw feature rows. */
+int bs_ws_forward(bs_ws_model m, int64_t n_samples, const float *feat, const int32_t *rows,
+                  float *y, void *stream);
+
+/* Loss (device scalar) and gradient (device [param_count]) of a batch,
+ * without changing the model; bs_ws_train_step takes one Adam step with
+ * learning rate lr on it (loss may be NULL). */
+int bs_ws_grad(bs_ws_model m, int64_t n_samples, const float *feat, const float *delta,
+               const int32_t *rows, float *grad, float *loss, void *stream);
+int bs_ws_train_step(bs_ws_model m, int64_t n_samples, const float *feat, const float *delta,
+                     const int32_t *rows, float lr, float *loss, void *stream);
+
+/* x0 = x_prev + sigma_d * y(f) for n_batch systems, features built from the
+ * batch itself (one fused kernel). */
+int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double *values, const double *b,
+                const double *x_prev, double *x0, void *stream);
 
 /* Text for a bs_error code; never NULL. */
 const char *bs_error_string(int code);

@@ -39,7 +39,7 @@ class BatchSolveError(RuntimeError):
 class bs_options(C.Structure):
     _fields_ = [("restart", C.c_int32), ("precision", C.c_int32), ("inner_tol", C.c_double),
                 ("flags", C.c_int32), ("team", C.c_int32), ("rows_per_lane", C.c_int32),
-                ("outer_iters", C.c_void_p)]
+                ("outer_iters", C.c_void_p), ("x_alt", C.c_void_p), ("alt_used", C.c_void_p)]
 
 
 class bs_plan_info(C.Structure):
@@ -85,6 +85,20 @@ def lib() -> C.CDLL:
     L.bs_varbatch_tune.argtypes = _vsolve + [i32, C.c_char_p, C.c_char_p, sz, vp]
     L.bs_varbatch_capture.argtypes = _vsolve
     L.bs_varbatch_replay.argtypes = [vp, vp]
+    f32p = vp
+    L.bs_ws_create.argtypes = [i32, i32, vp, vp, C.POINTER(vp)]
+    L.bs_ws_destroy.argtypes = [vp]
+    L.bs_ws_param_count.argtypes = [vp, C.POINTER(i64)]
+    L.bs_ws_set_params.argtypes = [vp, vp]
+    L.bs_ws_get_params.argtypes = [vp, vp]
+    L.bs_ws_features.argtypes = [vp, i64, vp, vp, vp, vp, f32p, f32p, vp]
+    L.bs_ws_fit_scaling.argtypes = [vp, i64, vp, vp, vp]
+    L.bs_ws_get_scaling.argtypes = [vp, vp, vp, vp]
+    L.bs_ws_set_scaling.argtypes = [vp, vp, vp, vp]
+    L.bs_ws_forward.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.bs_ws_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.bs_ws_train_step.argtypes = [vp, i64, vp, vp, vp, C.c_float, vp, vp]
+    L.bs_ws_infer.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.bs_error_string.argtypes = [C.c_int]
     L.bs_error_string.restype = C.c_char_p
     L.bs_last_error.argtypes = []
@@ -94,7 +108,10 @@ def lib() -> C.CDLL:
                  "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_varbatch_create",
                  "bs_varbatch_destroy", "bs_varbatch_query", "bs_varbatch_set_policy",
                  "bs_varbatch_solve", "bs_varbatch_tune", "bs_varbatch_capture",
-                 "bs_varbatch_replay"):
+                 "bs_varbatch_replay", "bs_ws_create", "bs_ws_destroy", "bs_ws_param_count",
+                 "bs_ws_set_params", "bs_ws_get_params", "bs_ws_features", "bs_ws_fit_scaling",
+                 "bs_ws_get_scaling", "bs_ws_set_scaling", "bs_ws_forward", "bs_ws_grad",
+                 "bs_ws_train_step", "bs_ws_infer"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -184,8 +201,13 @@ def bs_matrix_storage(fmt: int, n_batch: int, n_rows: int, nnz: int, ell_width: 
 
 
 def make_options(restart: int = 0, precision: int = FP64, inner_tol: float = 0.0, flags: int = 0,
-                 team: int = 0, rows_per_lane: int = 0, outer_iters=None) -> bs_options:
-    return bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters))
+                 team: int = 0, rows_per_lane: int = 0, outer_iters=None, x_alt=None,
+                 alt_used=None) -> bs_options:
+    o = bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters),
+                   _ptr(x_alt), _ptr(alt_used))
+    # the structure holds raw device pointers: keep their tensors alive with it
+    o._keep = (outer_iters, x_alt, alt_used)
+    return o
 
 
 def bs_plan(fmt: int, n_rows: int, nnz: int, max_row_nnz: int, solver: int,
@@ -350,4 +372,107 @@ class VarBatch:
     def __del__(self):
         if getattr(self, "handle", 0) and _lib is not None:
             _lib.bs_varbatch_destroy(self.handle)
+            self.handle = 0
+
+
+# ------------------------------------------------------------------ learned initial guess
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float32)
+
+
+def _f64h(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+
+
+def bs_ws_create(n: int, row_ptr, col_idx) -> int:
+    rp, ci = _host_i32(row_ptr), _host_i32(col_idx)
+    h = C.c_void_p()
+    _check(lib().bs_ws_create(n, ci.size, rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                              C.byref(h)), "bs_ws_create")
+    return h.value
+
+
+def bs_ws_destroy(handle: int) -> None:
+    _check(lib().bs_ws_destroy(handle), "bs_ws_destroy")
+
+
+def bs_ws_param_count(handle: int) -> int:
+    c = C.c_int64()
+    _check(lib().bs_ws_param_count(handle, C.byref(c)), "bs_ws_param_count")
+    return c.value
+
+
+def bs_ws_set_params(handle: int, params) -> None:
+    p = _f32(params)
+    if p.size != bs_ws_param_count(handle):
+        raise ValueError("parameter vector has the wrong length")
+    _check(lib().bs_ws_set_params(handle, p.ctypes.data), "bs_ws_set_params")
+
+
+def bs_ws_get_params(handle: int) -> np.ndarray:
+    p = np.empty(bs_ws_param_count(handle), np.float32)
+    _check(lib().bs_ws_get_params(handle, p.ctypes.data), "bs_ws_get_params")
+    return p
+
+
+def bs_ws_features(handle: int, values, b, x_prev, feat, x_next=None, delta=None,
+                   stream=None) -> None:
+    _check(lib().bs_ws_features(handle, b.shape[0], _ptr(values), _ptr(b), _ptr(x_prev),
+                                _ptr(x_next), _ptr(feat), _ptr(delta), _stream(stream)),
+           "bs_ws_features")
+
+
+def bs_ws_fit_scaling(handle: int, feat, delta, stream=None) -> None:
+    _check(lib().bs_ws_fit_scaling(handle, feat.shape[0], _ptr(feat), _ptr(delta),
+                                   _stream(stream)), "bs_ws_fit_scaling")
+
+
+def bs_ws_get_scaling(handle: int, n: int):
+    mu, sd, sdd = np.empty(3 * n), np.empty(3 * n), np.empty(n)
+    _check(lib().bs_ws_get_scaling(handle, mu.ctypes.data, sd.ctypes.data, sdd.ctypes.data),
+           "bs_ws_get_scaling")
+    return mu, sd, sdd
+
+
+def bs_ws_set_scaling(handle: int, mu_f, sd_f, sd_d) -> None:
+    mu, sd, sdd = _f64h(mu_f), _f64h(sd_f), _f64h(sd_d)
+    _check(lib().bs_ws_set_scaling(handle, mu.ctypes.data, sd.ctypes.data, sdd.ctypes.data),
+           "bs_ws_set_scaling")
+
+
+def bs_ws_forward(handle: int, feat, y, rows=None, stream=None) -> None:
+    _check(lib().bs_ws_forward(handle, y.shape[0], _ptr(feat), _ptr(rows), _ptr(y),
+                               _stream(stream)), "bs_ws_forward")
+
+
+def bs_ws_grad(handle: int, feat, delta, grad, loss, rows=None, n_samples=None,
+               stream=None) -> None:
+    M = n_samples if n_samples is not None else (rows.shape[0] if rows is not None else feat.shape[0])
+    _check(lib().bs_ws_grad(handle, M, _ptr(feat), _ptr(delta), _ptr(rows), _ptr(grad), _ptr(loss),
+                            _stream(stream)), "bs_ws_grad")
+
+
+def bs_ws_train_step(handle: int, feat, delta, lr: float, loss=None, rows=None, n_samples=None,
+                     stream=None) -> None:
+    M = n_samples if n_samples is not None else (rows.shape[0] if rows is not None else feat.shape[0])
+    _check(lib().bs_ws_train_step(handle, M, _ptr(feat), _ptr(delta), _ptr(rows), float(lr),
+                                  _ptr(loss), _stream(stream)), "bs_ws_train_step")
+
+
+def bs_ws_infer(handle: int, values, b, x_prev, x0, stream=None) -> None:
+    _check(lib().bs_ws_infer(handle, b.shape[0], _ptr(values), _ptr(b), _ptr(x_prev), _ptr(x0),
+                             _stream(stream)), "bs_ws_infer")
+
+
+class WarmStartModel:
+    """Owns a learned-initial-guess model (see ``bs_ws_create``)."""
+
+    def __init__(self, n: int, row_ptr, col_idx):
+        self.n = n
+        self.handle = bs_ws_create(n, row_ptr, col_idx)
+        self.param_count = bs_ws_param_count(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", 0) and _lib is not None:
+            _lib.bs_ws_destroy(self.handle)
             self.handle = 0

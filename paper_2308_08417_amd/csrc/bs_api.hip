@@ -429,6 +429,9 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.resid = resid;
   a.status = status;
   a.outer = opts ? opts->outer_iters : nullptr;
+  a.x_alt = opts ? opts->x_alt : nullptr;
+  a.alt_used = opts ? opts->alt_used : nullptr;
+  if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
   // Persistent grid: as many workgroups as can be resident at once, each
   // walking over the batch (never more than there are systems).
   const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;

@@ -223,6 +223,7 @@ struct Rows {
   double dval[S::R];  // the row's stored diagonal value (0 if none)
   double bval[S::R];  // right-hand side of the row (0 past the last row)
   double xval[S::R];  // initial guess of the row (0 when x0 = 0 is promised)
+  double xalt[S::R];  // the second candidate start (when one is given)
 
   static constexpr unsigned kBuf = vec_buf_bytes(S::ROWS);  // bytes per vector buffer
 
@@ -420,6 +421,16 @@ struct Rows {
       if (!zero && rw[r] >= 0) xv = xx[rw[r]];
       settle(xv);  // completed before the next prefetch is issued
       xval[r] = xv;
+    }
+    if (g.x_alt) {
+      const double* xa = g.x_alt + (tm.live ? tm.sys * g.n : 0);
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        double xv = 0.0;
+        if (rw[r] >= 0) xv = xa[rw[r]];
+        settle(xv);
+        xalt[r] = xv;
+      }
     }
   }
 

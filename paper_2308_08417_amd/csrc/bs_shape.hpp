@@ -44,6 +44,8 @@ struct KArgs {
   double* resid;
   int* status;
   int* outer;
+  const double* x_alt;         // optional second initial guess [n_batch][n]
+  int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
 };
 
 // team: lanes per system; R: rows per lane; NZ: register slots per row.

@@ -71,6 +71,28 @@ __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue
     A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
     for (int r = 0; r < RW::R; ++r) P.r[r] = P.b[r] - t[r];
+    if (g.x_alt) {
+      // Second candidate start: keep whichever has the smaller residual
+      // norm (x on a tie; x_alt also when only x's norm is not a number).
+      // The other buffer: lanes may still gather from buffer 0.
+      double ta[RW::R], ra[RW::R], p0[RW::R], p1[RW::R];
+      A.template spmv<1>(tm, A.a, A.xalt, ta);
+#pragma unroll
+      for (int r = 0; r < RW::R; ++r) {
+        ra[r] = P.b[r] - ta[r];
+        p0[r] = P.r[r] * P.r[r];
+        p1[r] = ra[r] * ra[r];
+      }
+      double q[2] = {sum_rows(p0), sum_rows(p1)};
+      tm.sum(q);
+      const bool alt = q[1] < q[0] || (q[0] != q[0] && q[1] == q[1]);
+#pragma unroll
+      for (int r = 0; r < RW::R; ++r) {
+        P.x[r] = alt ? A.xalt[r] : P.x[r];
+        P.r[r] = alt ? ra[r] : P.r[r];
+      }
+      if (g.alt_used && tm.live && tm.lane == 0) g.alt_used[tm.sys] = alt ? 1 : 0;
+    }
   } else {
 #pragma unroll
     for (int r = 0; r < RW::R; ++r) P.r[r] = P.b[r];

@@ -150,7 +150,7 @@ struct VarRows {
   bool ok[R];
   int dslot[R];
   unsigned zero;
-  double dval[R], bval[R], xval[R];
+  double dval[R], bval[R], xval[R], xalt[R];
 
   // Pattern and values of this team's system, straight from HBM.  Every load
   // is guarded: an idle lane, row or slot reads nothing.
@@ -195,6 +195,9 @@ struct VarRows {
       double xv = 0.0;
       if ((g.flags & 1) == 0 && ok[r]) xv = g.x[tm.row0 + rr];
       xval[r] = xv;
+      double xa = 0.0;
+      if (g.x_alt && ok[r]) xa = g.x_alt[tm.row0 + rr];
+      xalt[r] = xa;
     }
   }
 

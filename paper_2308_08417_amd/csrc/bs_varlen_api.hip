@@ -192,6 +192,9 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   g.resid = resid;
   g.status = status;
   g.outer = o ? o->outer_iters : nullptr;
+  g.x_alt = o ? o->x_alt : nullptr;
+  g.alt_used = o ? o->alt_used : nullptr;
+  if (g.x_alt && (g.flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v.device);
   if (e != hipSuccess) return hip_err(e, "device attribute");

@@ -371,3 +371,19 @@ def chem_trajectory(n_batch: int = 1 << 16, n: int = 54, steps: int = 64,
         values[:, is_diag] += 1.0
         yield Batch("chem_trajectory", n, row_ptr, col_idx, values, b.copy(),
                     np.zeros((n_batch, n)), {"seed": seed, "t": t})
+
+
+# --------------------------------------------------------------------------
+# Initial weights of the learned-initial-guess network.
+# --------------------------------------------------------------------------
+def mlp_init(n: int, hidden: int = 256, seed: int = 0, gain: float = 1.0) -> np.ndarray:
+    """Flat FP32 parameter vector (W1 [3n][h], b1, W2 [h][h], b2, W3 [h][n], b3):
+    weights ``gain * N(0, 2 / fan_in)`` (He normal), biases zero.  Draw order:
+    W1, W2, W3, each as one ``rng.standard_normal`` call."""
+    rng = np.random.default_rng(seed)
+    F = 3 * n
+    parts = []
+    for fan_in, fan_out in ((F, hidden), (hidden, hidden), (hidden, n)):
+        w = rng.standard_normal((fan_in, fan_out)) * (gain * np.sqrt(2.0 / fan_in))
+        parts += [w.ravel(), np.zeros(fan_out)]
+    return np.concatenate(parts).astype(np.float32)
