@@ -8,9 +8,10 @@ x0 = 0 -- solved by FP64 BiCGSTAB with scalar Jacobi in BatchCsr to relative
 residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
 forms of the same batch, the uneven batch (100k banded systems with n in
-[16, 1024] in one persistent launch, eager and graph-replayed), the HBM
-roofline of the solver kernel, and the CPU oracle's throughput on the host
-cores.
+[16, 1024] in one persistent launch, eager and graph-replayed), the learned
+warm start along a drifting sequence (mixed precision from the network's
+guess vs the plain FP64 solve), the HBM roofline of the solver kernel, and
+the CPU oracle's throughput on the host cores.
 """
 from __future__ import annotations
 
@@ -110,11 +111,148 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
     return out
 
 
+def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """Learned warm start along a drifting sequence of 2^16 chemistry-like
+    systems (n = 54, A_t = I - gamma_t J_t, 1% drift per step): the network is
+    trained on the plain solver's solutions of steps t < ws_train_steps; on
+    the next ws_eval_steps steps the plain FP64 solve from x0 = 0 is timed
+    against inference + mixed-precision BiCGSTAB started from the network's
+    guess with x_{t-1} as the fallback (and against FP64 from x_{t-1})."""
+    B, n = args.ws_batch, 54
+    T0, Te = args.ws_train_steps, args.ws_eval_steps
+    t_gen = time.time()
+    gen = W.chem_trajectory(n_batch=B, n=n, steps=T0 + Te, seed=0)
+    first = next(gen)
+    P = bs.Pattern.from_csr(first.row_ptr, first.col_idx)
+    m = bs.WarmStartModel(n, first.row_ptr, first.col_idx)
+    bs.bs_ws_set_params(m.handle, W.mlp_init(n, seed=0))
+    bb = torch.from_numpy(first.b).to(dev)
+    it = torch.empty(B, dtype=torch.int32, device=dev)
+    rs = torch.empty(B, dtype=torch.float64, device=dev)
+    st = torch.empty(B, dtype=torch.int32, device=dev)
+    used = torch.empty(B, dtype=torch.int32, device=dev)
+    M = (T0 - 1) * B
+    feat = torch.empty((M, 3 * n), dtype=torch.float32, device=dev)
+    delta = torch.empty((M, n), dtype=torch.float32, device=dev)
+    plain = bs.make_options(flags=bs.FLAG_X0_ZERO)
+
+    def solve(v, x, opts):
+        bs.bs_batch_solve(bs.CSR, P.handle, v, bb, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter,
+                          it, rs, st, opts)
+
+    # training data: the plain solver's solutions, one step at a time
+    x_prev = None
+    vals_t = None
+    batch = first
+    for t in range(T0):
+        if t > 0:
+            batch = next(gen)
+        vals_t = torch.from_numpy(batch.values).to(dev)
+        x_t = torch.empty((B, n), dtype=torch.float64, device=dev)
+        solve(vals_t, x_t, plain)
+        if t > 0:
+            sl = slice((t - 1) * B, t * B)
+            bs.bs_ws_features(m.handle, vals_t, bb, x_prev, feat[sl], x_next=x_t, delta=delta[sl])
+        x_prev = x_t
+    torch.cuda.synchronize()
+    gen_s = time.time() - t_gen
+    # training (timed on its own)
+    bs.bs_ws_fit_scaling(m.handle, feat, delta)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(0)
+    mb = 8192
+    losses = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    n_steps = 0
+    for _ in range(args.ws_epochs):
+        perm = torch.from_numpy(rng.permutation(M).astype(np.int32)).to(dev)
+        for i in range(0, M - mb + 1, mb):
+            bs.bs_ws_train_step(m.handle, feat, delta, 1e-3, loss=loss, rows=perm[i:i + mb])
+            n_steps += 1
+        losses.append(float(loss.item()))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    del feat, delta
+
+    # held-out steps: time each start on the same inputs
+    reps = max(3, args.steps // 4)
+    timing = {"plain_fp64_x0_zero": [], "fp64_from_prev": [], "mixed_learned": []}
+    iters = {k: [] for k in timing}
+    alt_frac, infer_ms = [], []
+    ok = True
+    x = torch.empty((B, n), dtype=torch.float64, device=dev)
+    x_guess = torch.empty_like(x)
+    for _ in range(Te):
+        batch = next(gen)
+        v = torch.from_numpy(batch.values).to(dev)
+        torch.cuda.synchronize()
+        for kind in timing:
+            if kind == "plain_fp64_x0_zero":
+                opts = plain
+            elif kind == "fp64_from_prev":
+                opts = bs.make_options()
+            else:
+                opts = bs.make_options(precision=bs.MIXED, x_alt=x_prev, alt_used=used)
+
+            def once():
+                if kind == "fp64_from_prev":
+                    x.copy_(x_prev)
+                elif kind == "mixed_learned":
+                    bs.bs_ws_infer(m.handle, v, bb, x_prev, x)
+                solve(v, x, opts)
+
+            once()
+            torch.cuda.synchronize()
+            ok = ok and bool((st == 0).all().item()) and bool((rs <= tol).all().item())
+            iters[kind].append(float(it.float().mean().item()))
+            if kind == "mixed_learned":
+                alt_frac.append(float(used.float().mean().item()))
+            e0.record()
+            for _ in range(reps):
+                once()
+            e1.record()
+            torch.cuda.synchronize()
+            timing[kind].append(e0.elapsed_time(e1) / reps)
+            # the copy of x_{t-1} is setup, not part of the method: time it alone
+            if kind == "fp64_from_prev":
+                e0.record()
+                for _ in range(reps):
+                    x.copy_(x_prev)
+                e1.record()
+                torch.cuda.synchronize()
+                timing[kind][-1] -= e0.elapsed_time(e1) / reps
+        e0.record()
+        for _ in range(reps):
+            bs.bs_ws_infer(m.handle, v, bb, x_prev, x_guess)
+        e1.record()
+        torch.cuda.synchronize()
+        infer_ms.append(e0.elapsed_time(e1) / reps)
+        # the next step starts from this step's plain solution
+        xn = torch.empty_like(x)
+        solve(v, xn, plain)
+        x_prev = xn
+    ms = {k: float(np.mean(v_)) for k, v_ in timing.items()}
+    sps = {k: B / (v_ * 1e-3) for k, v_ in ms.items()}
+    return {"workload": f"chem_trajectory_b{B}_n{n}_t{T0 + Te}_train{T0}_eval{Te}",
+            "ms_per_step": ms, "systems_per_s": sps,
+            "ratio_mixed_learned_vs_plain": sps["mixed_learned"] / sps["plain_fp64_x0_zero"],
+            "ratio_mixed_learned_vs_fp64_from_prev": sps["mixed_learned"] / sps["fp64_from_prev"],
+            "iters_mean": {k: float(np.mean(v_)) for k, v_ in iters.items()},
+            "fallback_taken_frac": float(np.mean(alt_frac)), "infer_ms": float(np.mean(infer_ms)),
+            "train": {"samples": M, "epochs": args.ws_epochs, "minibatch": mb,
+                      "adam_steps": n_steps, "ms": train_ms, "loss_by_epoch": losses},
+            "all_converged": ok, "setup_seconds": gen_s}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # the GPU raises its clocks only after some tens of milliseconds of load:
+    # the default warmup (about 70 ms of launches) reaches the steady state
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--batch", type=int, default=1 << 17)
     ap.add_argument("--fmt", choices=["csr", "ell"], default="csr")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -125,6 +263,14 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch leg (100k systems, n in [16, 1024])")
     ap.add_argument("--uneven-batch", type=int, default=100_000)
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the learned-warm-start leg (2^16 systems along a drifting sequence)")
+    ap.add_argument("--ws-batch", type=int, default=1 << 16)
+    ap.add_argument("--ws-train-steps", type=int, default=32,
+                    help="time steps whose solutions train the network (t < this)")
+    ap.add_argument("--ws-eval-steps", type=int, default=4,
+                    help="held-out time steps timed after the training steps")
+    ap.add_argument("--ws-epochs", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -202,13 +348,17 @@ def main() -> int:
                                 ("csr_mixed", bs.CSR, bs.MIXED), ("ell_mixed", bs.ELL, bs.MIXED)):
             if fmt == headline_fmt and prec == bs.FP64:
                 continue
-            r = timed(fmt, prec, max(5, args.steps // 2), 2)
+            r = timed(fmt, prec, max(10, args.steps // 2), args.warmup)
             r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
             variants[name] = r
 
     uneven = None
     if not args.no_uneven:
         uneven = uneven_leg(args, bs, W, torch, np, dev, tol, max_iter)
+
+    warm = None
+    if not args.no_warmstart:
+        warm = warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter)
 
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
@@ -278,6 +428,7 @@ def main() -> int:
                   "iters_max": head["iters_max"], "max_resid": head["max_resid"]},
         "variants": variants,
         "uneven": uneven,
+        "warm_start": warm,
         "gen_seconds": gen_s,
         "kernel_source_sha": kernel_source_sha(),
     }

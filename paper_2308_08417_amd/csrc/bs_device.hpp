@@ -12,6 +12,11 @@
 
 #include "bs_shape.hpp"
 
+// LDS gathers issued back to back in the fixed-size SpMV before their FMAs.
+#ifndef BS_GATHER
+#define BS_GATHER 4
+#endif
+
 namespace bs {
 
 enum : int {
@@ -458,7 +463,7 @@ struct Rows {
   template <int BUF, class T, class AT>
   __device__ __forceinline__ void spmv(Team<S>& tm, const AT (&av)[S::R][S::NZ],
                                        const T (&v)[S::R], T (&y)[S::R]) const {
-    constexpr int kGather = 4;
+    constexpr int kGather = BS_GATHER;
     constexpr unsigned off = BUF * kBuf;
 #pragma unroll
     for (int r = 0; r < S::R; ++r)

@@ -59,7 +59,7 @@ struct Shape {
   // Waves per SIMD the register allocator is asked to fit: single-wave groups
   // with up to 32 slots per row are held to 3 (at most 168 VGPRs), which keeps
   // enough waves resident to hide the reductions' latency.
-  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ == 32) ? 3 : 1;
+  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? 3 : 1;
 };
 
 // Vector buffers per team (SpMV source vectors, double-buffered).  Each buffer

@@ -130,7 +130,8 @@ def test_plan_covers_rows(L, n):
 
 def test_plan_stage_and_limits(L):
     p = bs.bs_plan(bs.CSR, 54, 1042, 28, bs.BICGSTAB)
-    assert p["team"] == 64 and p["slots"] == 32 and p["stage_values"] == 1
+    # the narrowest compiled slot count that holds the longest row (28)
+    assert p["team"] == 64 and p["slots"] == 28 and p["stage_values"] == 1
     assert p["lds_bytes"] >= 1042 * 8
     # single-wave groups prefetch each system's values and b into LDS
     p = bs.bs_plan(bs.ELL, 54, 1042, 28, bs.BICGSTAB)
