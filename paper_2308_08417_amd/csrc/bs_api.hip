@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/batchsolve.h"
@@ -30,6 +31,26 @@ thread_local std::string g_last_error = "";
 namespace bs {
 // Shared by every translation unit of the library (bs_last_error reads it).
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// A device word per device that kernels may write instead of an output the
+// caller did not ask for (allocated once, kept until the process ends).
+int* device_sink() {
+  static std::mutex mu;
+  static std::vector<int*> sinks;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)sinks.size() <= dev) sinks.resize(dev + 1, nullptr);
+  if (!sinks[dev]) {
+    void* p = nullptr;
+    if (hipMalloc(&p, 256) != hipSuccess) {
+      g_last_error = "sink allocation failed";
+      return nullptr;
+    }
+    sinks[dev] = static_cast<int*>(p);
+  }
+  return sinks[dev];
+}
 }  // namespace bs
 
 namespace {
@@ -429,6 +450,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.resid = resid;
   a.status = status;
   a.outer = opts ? opts->outer_iters : nullptr;
+  a.sink = bs::device_sink();
+  if (!a.sink) return BS_ERR_HIP;
   a.x_alt = opts ? opts->x_alt : nullptr;
   a.alt_used = opts ? opts->alt_used : nullptr;
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;

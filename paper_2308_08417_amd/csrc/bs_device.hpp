@@ -418,14 +418,20 @@ struct Rows {
   // The initial guess is read here, before the next prefetch is issued, so a
   // wait for it never waits behind that prefetch.
   __device__ __forceinline__ void load_x0(const Team<S>& tm, const KArgs& g, const int (&rw)[S::R]) {
+    // Only when an initial guess is read does this wait on memory (a wait
+    // here would also wait for the previous system's output stores).
     const bool zero = (g.flags & 1) != 0;
-    const double* xx = g.x + (tm.live ? tm.sys * g.n : 0);
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) {
-      double xv = 0.0;
-      if (!zero && rw[r] >= 0) xv = xx[rw[r]];
-      settle(xv);  // completed before the next prefetch is issued
-      xval[r] = xv;
+    for (int r = 0; r < S::R; ++r) xval[r] = 0.0;
+    if (!zero) {
+      const double* xx = g.x + (tm.live ? tm.sys * g.n : 0);
+#pragma unroll
+      for (int r = 0; r < S::R; ++r) {
+        double xv = 0.0;
+        if (rw[r] >= 0) xv = xx[rw[r]];
+        settle(xv);  // completed before the next prefetch is issued
+        xval[r] = xv;
+      }
     }
     if (g.x_alt) {
       const double* xa = g.x_alt + (tm.live ? tm.sys * g.n : 0);

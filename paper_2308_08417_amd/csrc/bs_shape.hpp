@@ -44,6 +44,7 @@ struct KArgs {
   double* resid;
   int* status;
   int* outer;
+  int* sink;                   // a device word written instead of a missing status
   const double* x_alt;         // optional second initial guess [n_batch][n]
   int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
 };
@@ -59,7 +60,10 @@ struct Shape {
   // Waves per SIMD the register allocator is asked to fit: single-wave groups
   // with up to 32 slots per row are held to 3 (at most 168 VGPRs), which keeps
   // enough waves resident to hide the reductions' latency.
-  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? 3 : 1;
+#ifndef BS_OCC_ONE_WAVE
+#define BS_OCC_ONE_WAVE 3
+#endif
+  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE : 1;
 };
 
 // Vector buffers per team (SpMV source vectors, double-buffered).  Each buffer

@@ -45,7 +45,9 @@ __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
   if (tm.lane == 0) {
     g.iters[tm.sys] = k;
     g.resid[tm.sys] = !finite(bn) ? bn : (bn == 0.0 ? rn : rn / bn);
-    if (g.status) g.status[tm.sys] = st;
+    // always one store (to the sink when no status is wanted): the persistent
+    // loop counts on a fixed number of stores after each prefetch
+    *(g.status ? g.status + tm.sys : g.sink) = st;
     if (g.outer) g.outer[tm.sys] = outer;
   }
 }
@@ -645,6 +647,18 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
 // Single-wave groups prefetch the next round's systems into LDS while the
 // current round is solved: wait for the prefetch, copy the block into registers,
 // wait for those LDS reads, start the next prefetch, solve.
+// Vector memory operations retire in issue order.  After the first round the
+// last ones a wave issued are the previous system's four output stores (x,
+// iters, resid, status), all after this round's prefetch: waiting until at most
+// four are outstanding (and for LDS) means the prefetch has landed, without
+// waiting for the stores to be acknowledged.  s_waitcnt vmcnt(4) expcnt(7)
+// lgkmcnt(0).
+constexpr int kWaitPrefetch = 0x0074;
+
+// The loop body reads the arguments through ga, at an address offset by a
+// zero the compiler cannot see through: otherwise it hoists every argument
+// load out of the loop and keeps them all in scalar registers through the
+// solve, where they spill into vector-register lanes.
 #define BS_PERSISTENT_LOOP(CALL)                                                    \
   extern __shared__ __align__(16) char smem[];                                     \
   Team<S> tm(smem, g);                                                             \
@@ -656,20 +670,26 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     staged = g.stage != 0;                                                         \
     if (staged) A.prefetch(tm, g, (int64_t)blockIdx.x * S::TEAMS);                 \
   }                                                                                \
+  bool first_round = true;                                                         \
   for (int64_t base = (int64_t)blockIdx.x * S::TEAMS; base < g.n_batch; base += stride) { \
+    int opaque_zero;                                                               \
+    __asm__ volatile("s_mov_b32 %0, 0" : "=s"(opaque_zero));                       \
+    const KArgs& ga = (&g)[opaque_zero];                                           \
     tm.sys = base + tm.tix;                                                        \
-    tm.live = tm.sys < g.n_batch;                                                  \
-    tm.row0 = tm.live ? tm.sys * g.n : 0;                                          \
+    tm.live = tm.sys < ga.n_batch;                                                 \
+    tm.row0 = tm.live ? tm.sys * ga.n : 0;                                         \
     if (staged) { /* the prefetch of this round has landed */                      \
-      __builtin_amdgcn_s_waitcnt(0);                                               \
+      if (first_round) __builtin_amdgcn_s_waitcnt(0);                              \
+      else __builtin_amdgcn_s_waitcnt(kWaitPrefetch);                              \
+      first_round = false;                                                         \
       __asm__ volatile("" ::: "memory");                                           \
     }                                                                              \
-    A.load_values(tm, g);                                                          \
+    A.load_values(tm, ga);                                                         \
     if constexpr (S::WAVES == 1) {                                                 \
-      if (staged && base + stride < g.n_batch) {                                   \
+      if (staged && base + stride < ga.n_batch) {                                  \
         __builtin_amdgcn_s_waitcnt(0xC07F); /* staging reads done (lgkmcnt 0) */   \
         __asm__ volatile("" ::: "memory");                                         \
-        A.prefetch(tm, g, base + stride);                                          \
+        A.prefetch(tm, ga, base + stride);                                         \
       }                                                                            \
     }                                                                              \
     CALL;                                                                          \
@@ -677,17 +697,17 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
 
 template <class S, bool MIXED>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_bicgstab(const KArgs g) {
-  BS_PERSISTENT_LOOP((bicgstab_system<MIXED>(tm, A, g)))
+  BS_PERSISTENT_LOOP((bicgstab_system<MIXED>(tm, A, ga)))
 }
 
 template <class S>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
-  BS_PERSISTENT_LOOP((cg_system(tm, A, g)))
+  BS_PERSISTENT_LOOP((cg_system(tm, A, ga)))
 }
 
 template <class S>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system(tm, A, g)))
+  BS_PERSISTENT_LOOP((gmres_system(tm, A, ga)))
 }
 
 #undef BS_PERSISTENT_LOOP

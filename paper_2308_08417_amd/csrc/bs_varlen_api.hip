@@ -17,6 +17,7 @@
 
 namespace bs {
 void set_last_error(const std::string& msg);
+int* device_sink();
 }
 
 namespace {
@@ -192,6 +193,8 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   g.resid = resid;
   g.status = status;
   g.outer = o ? o->outer_iters : nullptr;
+  g.sink = bs::device_sink();
+  if (!g.sink) return BS_ERR_HIP;
   g.x_alt = o ? o->x_alt : nullptr;
   g.alt_used = o ? o->alt_used : nullptr;
   if (g.x_alt && (g.flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
