@@ -47,7 +47,9 @@ typedef enum { BS_PREC_NONE = 0, BS_PREC_JACOBI = 1 } bs_precond;
 
 /* BS_FP64: everything in FP64.  BS_MIXED: iterative refinement whose outer loop
  * (true residual b - A x, its norm, the update of x) is FP64 and whose inner
- * Krylov solve (SpMV, Krylov vectors, inner reductions) is FP32. */
+ * Krylov solve (SpMV, Krylov vectors, inner reductions) is FP32: BiCGSTAB, or
+ * one GMRES(m) cycle per refinement step (its rotations and triangular solve
+ * in FP64).  Not for CG (BS_ERR_UNSUPPORTED). */
 typedef enum { BS_FP64 = 0, BS_MIXED = 1 } bs_precision;
 
 /* Per-system outcome written to status[]. */

@@ -124,7 +124,7 @@ bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) 
 int variant_of(bs_solver solver, int precision) {
   if (solver == BS_CG) return precision == BS_MIXED ? -1 : bs::V_CG;
   if (solver == BS_BICGSTAB) return precision == BS_MIXED ? bs::V_BICGSTAB_MIXED : bs::V_BICGSTAB;
-  if (solver == BS_GMRES) return precision == BS_MIXED ? -1 : bs::V_GMRES;
+  if (solver == BS_GMRES) return precision == BS_MIXED ? bs::V_GMRES_MIXED : bs::V_GMRES;
   return -1;
 }
 
@@ -134,6 +134,7 @@ bs::KernelTable table_of(int variant) {
     case bs::V_BICGSTAB: return bs::kernels_bicgstab();
     case bs::V_BICGSTAB_MIXED: return bs::kernels_bicgstab_mixed();
     case bs::V_GMRES: return bs::kernels_gmres();
+    case bs::V_GMRES_MIXED: return bs::kernels_gmres_mixed();
     default: return {nullptr, 0};
   }
 }
@@ -205,7 +206,7 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   if (!k) return BS_ERR_UNSUPPORTED;
   const int rows = team * r;
   const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
-  const bool gm = variant == bs::V_GMRES;
+  const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED;
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const int vec = teams * bs::team_vec_bytes(rows, gm) + bs::red_lds_bytes(waves);
   int stage = 0;

@@ -1,4 +1,4 @@
-// Kernel instances of the gmres solver for every compiled shape.
+// Kernel instances of the GMRES solver (FP64) for every compiled shape.
 #include "bs_registry.hpp"
 #include "bs_solvers.hpp"
 
@@ -7,14 +7,14 @@ namespace {
 
 template <class S>
 hipError_t launch(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_gmres<S>), dim3(grid), dim3(S::WG), lds, stream, a);
+  hipLaunchKernelGGL((k_gmres<S, false>), dim3(grid), dim3(S::WG), lds, stream, a);
   return hipGetLastError();
 }
 
 template <class S>
 int occupancy(unsigned lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_gmres<S>), S::WG,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_gmres<S, false>), S::WG,
                                                    lds) != hipSuccess || n < 1)
     n = 1;
   return n;

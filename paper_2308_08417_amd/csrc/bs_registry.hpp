@@ -7,7 +7,9 @@
 
 namespace bs {
 
-enum Variant { V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_COUNT = 4 };
+enum Variant {
+  V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4, V_COUNT = 5
+};
 
 typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
 // Resident workgroups per compute unit for a given dynamic LDS size.
@@ -28,6 +30,7 @@ KernelTable kernels_cg();
 KernelTable kernels_bicgstab();
 KernelTable kernels_bicgstab_mixed();
 KernelTable kernels_gmres();
+KernelTable kernels_gmres_mixed();
 
 // Shapes compiled for every solver: one row per lane for teams of 16..1024
 // lanes, and 2 or 4 rows per lane for the largest systems.  Slots per row are

@@ -496,9 +496,18 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 // has written itself, so no barrier is needed around them.  The last entry of g
 // changes at every step and is kept in a register.  At the end of a cycle
 // y = R^{-1} g by back substitution and x += M V y.
-template <class TM, class RW>
+//
+// MIXED: every cycle is an iterative-refinement step.  The cycle start forms
+// the FP64 true residual r = b - A x (as the plain method does at a restart);
+// the cycle's Arnoldi steps run in FP32 (basis, SpMV with an FP32 copy of A,
+// dots and norms), ending when |g| <= max(inner_tol * beta, tol ||b|| / 2) or
+// after m steps; the rotations and the triangular solve stay FP64 and x is
+// updated in FP64.  A cycle that does not lower the FP64 residual ends the
+// solve with BREAKDOWN.
+template <bool MIXED, class TM, class RW>
 __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   static_assert(RW::R == 1, "GMRES keeps one row per lane");
+  using T = typename std::conditional<MIXED, float, double>::type;
   constexpr int M = kMaxRestart;
   Prologue<RW::R> P;
   prologue(tm, A, g, P);
@@ -510,6 +519,15 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   double* sn = cs + M;
   double* gv = sn + M;
   double* yv = gv + (M + 1);
+
+  // the arithmetic copy of the rows (FP32 for MIXED; slots without an entry
+  // zeroed so that no value beyond FP32 range meets the zero cell)
+  T a_in[1][RW::NZ];
+#pragma unroll
+  for (int k = 0; k < RW::NZ; ++k) {
+    if constexpr (MIXED) a_in[0][k] = A.real(0, k) ? (T)A.a[0][k] : (T)0;
+    else a_in[0][k] = A.a[0][k];
+  }
 
   double q1[1];
   {
@@ -525,13 +543,16 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!finite(bn)) st = ST_NONFINITE;
     else if (bn == 0.0) { st = ST_CONVERGED; P.x[0] = 0.0; }
   }
-  double V[M + 1];
+  T V[M + 1];
 #pragma unroll
-  for (int i = 0; i <= M; ++i) V[i] = 0.0;
-  int k = 0, j = 0;
+  for (int i = 0; i <= M; ++i) V[i] = (T)0;
+  int k = 0, j = 0, cycles = 0;
   double gcur = 0.0;   // g_j, the entry the next rotation acts on
+  double ilim = lim;   // the cycle's stopping level for |g|
+  double beta_prev = INFINITY;
   bool start = true;   // at a cycle start (true residual due)
   const double d = P.d[0];
+  const T dT = (T)d;
   for (;;) {
     // ---- cycle start: true residual, convergence, V0 = r/beta
     if (tm.any(st == ST_RUNNING && start)) {
@@ -547,9 +568,13 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
         if (!finite(beta)) st = ST_NONFINITE;
         else if (beta <= lim) st = ST_CONVERGED;
         else if (k >= g.max_iter) st = ST_MAX_ITER;
+        else if (MIXED && !(beta < beta_prev)) st = ST_BREAKDOWN;
         else {
-          V[0] = rc / beta;
+          V[0] = (T)(rc / beta);
           gcur = beta;
+          if constexpr (MIXED) ilim = fmax(g.inner_tol * beta, 0.5 * lim);
+          beta_prev = beta;
+          cycles += 1;
           j = 0;
           start = false;
         }
@@ -558,29 +583,29 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!tm.any(st == ST_RUNNING)) break;
     // ---- one Arnoldi step for every running team (all of them are mid-cycle)
     const bool act = st == ST_RUNNING;
-    double vj = V[0];
+    T vj = V[0];
 #pragma unroll
     for (int i = 1; i < M; ++i)
       if (j == i) vj = V[i];
-    double z[1] = {d * vj}, w[1];
-    A.template spmv<0>(tm, A.a, z, w);
+    T z[1] = {dT * vj}, w[1];
+    A.template spmv<0>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (i <= jmax) {
-        double q[1] = {w[0] * V[i]};
+        T q[1] = {w[0] * V[i]};
         tm.sum(q);
         if (act && i <= j) {
           w[0] = fma(-q[0], V[i], w[0]);
-          hcol[i] = q[0];
+          hcol[i] = (double)q[0];
         }
       }
     }
-    double qn[1] = {w[0] * w[0]};
+    T qn[1] = {w[0] * w[0]};
     tm.sum(qn);
     bool end = false;
     if (act) {
-      const double hn = sqrt(qn[0]);
+      const double hn = sqrt((double)qn[0]);
       k += 1;
       if (!finite(hn)) {
         st = ST_NONFINITE;
@@ -604,9 +629,9 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
           Rt[cj + j] = dd;
           gv[j] = c * gcur;
           gcur = -s * gcur;
-          end = fabs(gcur) <= lim || hn == 0.0 || k >= g.max_iter || j == m - 1;
+          end = fabs(gcur) <= ilim || hn == 0.0 || k >= g.max_iter || j == m - 1;
           if (!end) {
-            const double vn = w[0] / hn;
+            const T vn = (T)((double)w[0] / hn);
 #pragma unroll
             for (int i = 1; i <= M; ++i)
               if (j + 1 == i) V[i] = vn;
@@ -627,7 +652,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
             for (int l = i + 1; l <= j; ++l) acc = fma(-Rt[l * (l + 1) / 2 + i], yv[l], acc);
             const double yi = acc / Rt[i * (i + 1) / 2 + i];
             yv[i] = yi;
-            zacc = fma(yi, V[i], zacc);
+            zacc = fma(yi, (double)V[i], zacc);
           }
         }
       }
@@ -637,8 +662,9 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
       }
     }
   }
-  finish(tm, A, g, P.b, P.x, st, k, 0, bn, rn,
-         st == ST_CONVERGED || st == ST_IDLE || (st == ST_MAX_ITER && start));
+  finish(tm, A, g, P.b, P.x, st, k, MIXED ? cycles : 0, bn, rn,
+         st == ST_CONVERGED || st == ST_IDLE || (st == ST_MAX_ITER && start) ||
+             (MIXED && st == ST_BREAKDOWN && start));
 }
 
 // =================================================================== kernels
@@ -705,9 +731,9 @@ __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC)))
   BS_PERSISTENT_LOOP((cg_system(tm, A, ga)))
 }
 
-template <class S>
+template <class S, bool MIXED>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system(tm, A, ga)))
+  BS_PERSISTENT_LOOP((gmres_system<MIXED>(tm, A, ga)))
 }
 
 #undef BS_PERSISTENT_LOOP

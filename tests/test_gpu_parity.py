@@ -275,23 +275,51 @@ def test_deterministic():
 
 
 # ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
 @pytest.mark.parametrize("gen", ["tridiag", "chem", "collision"])
 @pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
-def test_mixed_precision_meets_fp64_tolerance(gen, fmt):
+def test_mixed_precision_meets_fp64_tolerance(gen, fmt, solver):
     bt = {"tridiag": lambda: W.tridiag_stencil(64),
           "chem": lambda: W.chem_jacobian(2048),
           "collision": lambda: W.collision_stencil(24)}[gen]()
     c = Case(bt)
     outer = torch.zeros(bt.n_batch, dtype=torch.int32, device="cuda:0")
-    g = c.gpu(fmt, bs.BICGSTAB, max_iter=2000, precision=bs.MIXED, outer_iters=outer)
-    o = c.oracle(fmt, bs.BICGSTAB, max_iter=2000)
+    g = c.gpu(fmt, solver, max_iter=2000, precision=bs.MIXED, outer_iters=outer)
+    o = c.oracle(fmt, solver, max_iter=2000)
     assert np.all(g[3] == bs.CONVERGED)
     # iteration counts of the mixed form are not those of the FP64 method
     err, _ = check(c, g, o, fmt=fmt, itol=10**9)
-    say(f"  mixed {gen}: max x error vs FP64 oracle {err.max():.2e}, "
+    say(f"  mixed {solver} {gen}: max x error vs FP64 oracle {err.max():.2e}, "
         f"inner iters mean {g[1].mean():.2f} (fp64 {o[1].mean():.2f}), "
         f"outer mean {outer.float().mean().item():.2f}")
     assert outer.min().item() >= 1
+
+
+def test_mixed_gmres_short_restarts():
+    """Mixed GMRES with short cycles: every cycle is one refinement step, so the
+    outer count grows as the restart length falls, and the answer still meets the
+    FP64 tolerance."""
+    c = Case(W.collision_stencil(n_batch=12, nx=12, ny=10))
+    prev = None
+    for m in (30, 8, 3):
+        outer = torch.zeros(12, dtype=torch.int32, device="cuda:0")
+        g = c.gpu(bs.CSR, bs.GMRES, max_iter=4000, restart=m, precision=bs.MIXED,
+                  outer_iters=outer)
+        o = c.oracle(bs.CSR, bs.GMRES, max_iter=4000, restart=m)
+        assert np.all(g[3] == bs.CONVERGED)
+        check(c, g, o, itol=10**9)
+        mean = outer.float().mean().item()
+        say(f"  restart {m}: outer mean {mean:.2f}, inner mean {g[1].mean():.2f}")
+        if prev is not None:
+            assert mean >= prev
+        prev = mean
+
+
+def test_mixed_cg_unsupported():
+    c = Case(W.tridiag_stencil(8))
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.CSR, bs.CG, precision=bs.MIXED)
+    assert e.value.code == bs.ERR_UNSUPPORTED
 
 
 # ------------------------------------------------------------------ full size
