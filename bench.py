@@ -8,7 +8,8 @@ x0 = 0 -- solved by FP64 BiCGSTAB with scalar Jacobi in BatchCsr to relative
 residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
 forms of the same batch, the uneven batch (100k banded systems with n in
-[16, 1024] in one persistent launch, eager and graph-replayed), the learned
+[16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
+stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the learned
 warm start along a drifting sequence (mixed precision from the network's
 guess vs the plain FP64 solve), the HBM roofline of the solver kernel, and
 the CPU oracle's throughput on the host cores.
@@ -27,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def progress(msg: str) -> None:
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -107,6 +113,60 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                      "max_resid": float(rs.max())}
+    del vals, b, x
+    return out
+
+
+def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """Larger systems, FP64 against mixed precision: ``args.stencil_batch``
+    nonsymmetric 9-point operators on a 32 x 31 grid (n = 992, 8554 stored
+    entries), BiCGSTAB and GMRES(30) with scalar Jacobi to 1e-10 from x0 = 0,
+    BatchCsr.  One workgroup of 1024 lanes per system; the values stay in
+    registers, so the solve is bound by the LDS gathers of the SpMV and the
+    team reductions, not by HBM."""
+    t0 = time.time()
+    bt = W.collision_stencil(n_batch=args.stencil_batch, nx=32, ny=31, seed=0)
+    gen_s = time.time() - t0
+    B, n, nnz = bt.n_batch, bt.n, bt.nnz
+    P = bs.Pattern.from_csr(bt.row_ptr, bt.col_idx)
+    vals = torch.from_numpy(bt.values).to(dev)
+    b = torch.from_numpy(bt.b).to(dev)
+    x = torch.empty_like(b)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    outer = torch.empty(B, dtype=torch.int32, device=dev)
+    out = {"workload": f"collision_stencil_b{B}_n{n}_csr_jacobi", "n_batch": B, "n_rows": n,
+           "nnz": nnz, "gen_seconds": gen_s}
+    steps = max(5, args.steps // 10)
+    alg = B * (8 * nnz + 16 * n + 16) + 4 * (n + 1) + 4 * nnz
+    for sname, solver in (("bicgstab", bs.BICGSTAB), ("gmres30", bs.GMRES)):
+        for pname, prec in (("fp64", bs.FP64), ("mixed", bs.MIXED)):
+            opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec,
+                                   restart=30 if solver == bs.GMRES else 0,
+                                   outer_iters=outer if prec == bs.MIXED else None)
+            a = (bs.CSR, P.handle, vals, b, x, solver, bs.PREC_JACOBI, tol, 2000, iters, resid,
+                 status, opts)
+            for _ in range(max(3, args.warmup // 20)):
+                bs.bs_batch_solve(*a)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                bs.bs_batch_solve(*a)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+            r = {"ms": ms, "systems_per_s": B / (ms * 1e-3),
+                 "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+                 "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                 "max_resid": float(rs.max())}
+            if prec == bs.MIXED:
+                r["outer_mean"] = float(outer.float().mean().item())
+            out[f"{sname}_{pname}"] = r
+    out["algorithmic_bytes_per_launch"] = int(alg)
     del vals, b, x
     return out
 
@@ -263,6 +323,9 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch leg (100k systems, n in [16, 1024])")
     ap.add_argument("--uneven-batch", type=int, default=100_000)
+    ap.add_argument("--no-stencil", action="store_true",
+                    help="skip the 9-point stencil leg (4096 systems, n = 992, FP64 vs mixed)")
+    ap.add_argument("--stencil-batch", type=int, default=4096)
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the learned-warm-start leg (2^16 systems along a drifting sequence)")
     ap.add_argument("--ws-batch", type=int, default=1 << 16)
@@ -341,6 +404,7 @@ def main() -> int:
 
     headline_fmt = bs.CSR if args.fmt == "csr" else bs.ELL
     head = timed(headline_fmt, bs.FP64, args.steps, args.warmup)
+    progress(f"headline: {head['ms_per_step']:.4f} ms per step")
 
     variants = {}
     if not args.no_variants:
@@ -351,14 +415,23 @@ def main() -> int:
             r = timed(fmt, prec, max(10, args.steps // 2), args.warmup)
             r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
             variants[name] = r
+            progress(f"variant {name}: {r['ms_per_step']:.4f} ms")
 
     uneven = None
     if not args.no_uneven:
         uneven = uneven_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress(f"uneven: {uneven['fp64']['eager_ms']:.2f} ms (fp64, eager)")
+
+    stencil = None
+    if not args.no_stencil:
+        stencil = stencil_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress("stencil: " + ", ".join(f"{k} {v['ms']:.3f} ms" for k, v in stencil.items()
+                                         if isinstance(v, dict)))
 
     warm = None
     if not args.no_warmstart:
         warm = warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress(f"warm start: ratio {warm['ratio_mixed_learned_vs_plain']:.3f}")
 
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
@@ -428,6 +501,7 @@ def main() -> int:
                   "iters_max": head["iters_max"], "max_resid": head["max_resid"]},
         "variants": variants,
         "uneven": uneven,
+        "stencil": stencil,
         "warm_start": warm,
         "gen_seconds": gen_s,
         "kernel_source_sha": kernel_source_sha(),

@@ -71,6 +71,9 @@ typedef enum {
 
 /* Flags for bs_options.flags. */
 #define BS_FLAG_X0_ZERO 1 /* ignore x on entry and start from x0 = 0 (x is not read) */
+#define BS_FLAG_PLAIN_LAYOUT 2 /* one-wave teams: lane i owns row i, x_i at buffer
+                                  element i, CSR windows at min(row start, nnz - slots)
+                                  (the pattern's bank-aware layout is not used) */
 
 /* Largest system the fused kernels take: one row per lane, up to 1024 lanes per
  * system, and 2 or 4 rows per lane beyond that; longest row held in registers.
@@ -103,6 +106,39 @@ int bs_pattern_destroy(bs_pattern pattern);
 /* Shape of a pattern (any output pointer may be NULL). */
 int bs_pattern_query(bs_pattern pattern, int32_t *n_rows, int32_t *nnz, int32_t *ell_width,
                      int32_t *max_row_nnz);
+
+/* Bank-aware layout of a one-wave team (one system per 64-lane wave, one row per
+ * lane, CSR rows read through windows of `slots` register slots).  This is the
+ * library's own refinement of the on-chip placement of Sec. 3.5 for the LDS of
+ * gfx950, not a step of the paper: the SpMV gathers x[col] from LDS, a 64-lane
+ * read of 8-byte elements is served as two 32-lane halves, and within a half the
+ * distinct elements on one bank pair ((address / 8) mod 32) are served one after
+ * another.  The layout permutes which lane owns which row, which buffer element
+ * holds which x_j, and where each row's CSR window starts, to lower
+ *   cost = 5 * (gathers + vector writes) + register copy of the values
+ * counted per half and per slot as the largest number of distinct elements on
+ * one bank pair.  Deterministic simulated annealing (`steps` moves) from the
+ * plain layout; the result never costs more than the plain layout's.
+ * Host only (no device is touched).  Outputs, HOST memory:
+ *   lane_row[64]: row owned by lane l, -1 for none (each row exactly once);
+ *   lane_win[64]: CSR position where lane l's window starts: for its row i,
+ *     max(0, row_ptr[i+1] - slots) <= w <= min(row_ptr[i], nnz - slots); an idle
+ *     lane repeats a window of a lane of its own half;
+ *   col_pos[n_rows]: buffer element 0..63 of x_j, all distinct;
+ *   cost[2]: the chosen layout's cost and the plain layout's.
+ * Errors: BS_ERR_INVALID_ARG (NULL pointer, n_rows < 1, nnz < 0, slots < 1,
+ * steps < 0), BS_ERR_PATTERN (as bs_pattern_create_csr), BS_ERR_UNSUPPORTED
+ * (n_rows outside 33..64, nnz < slots, or a row longer than slots). */
+int bs_wave_layout(int32_t n_rows, int32_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                   int32_t slots, int32_t steps, int32_t *lane_row, int32_t *lane_win,
+                   int32_t *col_pos, int64_t *cost);
+
+/* The layout a pattern holds (made at creation for 33..64 rows, with the slot
+ * count the planner takes for one-wave teams; bs_batch_solve uses it whenever
+ * it runs such a shape on CSR values, unless BS_FLAG_PLAIN_LAYOUT is set).
+ * *slots = 0 when the pattern has none; else, when layout is not NULL, it
+ * receives lane_row[64] | lane_win[64] | col_pos[n_rows] (HOST memory). */
+int bs_pattern_layout(bs_pattern pattern, int32_t *slots, int32_t *layout);
 
 /* Copy the ELL slot-major column array [ell_width][n_rows] to HOST memory. */
 int bs_pattern_ell_cols(bs_pattern pattern, int32_t *ell_col_out);

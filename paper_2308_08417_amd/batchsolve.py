@@ -25,6 +25,7 @@ FP64, MIXED = 0, 1
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_PATTERN, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_DEVICE = 0, -1, -2, -3, -4, -5
 FLAG_X0_ZERO = 1
+FLAG_PLAIN_LAYOUT = 2
 MAX_ROWS, MAX_ROW_NNZ, MAX_RESTART = 2048, 64, 30
 
 
@@ -68,6 +69,8 @@ def lib() -> C.CDLL:
     L.bs_pattern_destroy.argtypes = [vp]
     L.bs_pattern_query.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.bs_pattern_ell_cols.argtypes = [vp, vp]
+    L.bs_wave_layout.argtypes = [i32, i32, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.bs_pattern_layout.argtypes = [vp, C.POINTER(i32), vp]
     L.bs_values_csr_to_ell.argtypes = [vp, i64, vp, vp, vp]
     L.bs_matrix_storage.argtypes = [C.c_int, i64, i32, i32, i32, C.POINTER(i64), C.POINTER(i64)]
     L.bs_batch_solve.argtypes = [C.c_int, i64, i32, vp, vp, vp, vp, C.c_int, C.c_int, dbl, i32,
@@ -104,7 +107,8 @@ def lib() -> C.CDLL:
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = C.c_char_p
     for name in ("bs_pattern_create_csr", "bs_pattern_create_ell", "bs_pattern_destroy",
-                 "bs_pattern_query", "bs_pattern_ell_cols", "bs_values_csr_to_ell",
+                 "bs_pattern_query", "bs_pattern_ell_cols", "bs_wave_layout",
+                 "bs_pattern_layout", "bs_values_csr_to_ell",
                  "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_varbatch_create",
                  "bs_varbatch_destroy", "bs_varbatch_query", "bs_varbatch_set_policy",
                  "bs_varbatch_solve", "bs_varbatch_tune", "bs_varbatch_capture",
@@ -186,6 +190,34 @@ def bs_pattern_ell_cols(handle: int) -> np.ndarray:
     out = np.empty(max(q["ell_width"] * q["n_rows"], 1), np.int32)
     _check(lib().bs_pattern_ell_cols(handle, out.ctypes.data), "bs_pattern_ell_cols")
     return out[: q["ell_width"] * q["n_rows"]]
+
+
+def bs_wave_layout(row_ptr, col_idx, slots: int, steps: int = 20000) -> dict:
+    """Bank-aware one-wave layout of a CSR pattern (host only): lane_row[64],
+    lane_win[64], col_pos[n] and the model costs (chosen, plain)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.size - 1
+    lane_row = np.empty(64, np.int32)
+    lane_win = np.empty(64, np.int32)
+    col_pos = np.empty(n, np.int32)
+    cost = np.empty(2, np.int64)
+    _check(lib().bs_wave_layout(n, ci.size, rp.ctypes.data, ci.ctypes.data, slots, steps,
+                                lane_row.ctypes.data, lane_win.ctypes.data, col_pos.ctypes.data,
+                                cost.ctypes.data), "bs_wave_layout")
+    return {"lane_row": lane_row, "lane_win": lane_win, "col_pos": col_pos,
+            "cost": int(cost[0]), "plain_cost": int(cost[1])}
+
+
+def bs_pattern_layout(handle: int):
+    """(slots, lane_row, lane_win, col_pos) of the pattern's layout, or None."""
+    q = bs_pattern_query(handle)
+    slots = C.c_int32()
+    out = np.empty(128 + q["n_rows"], np.int32)
+    _check(lib().bs_pattern_layout(handle, C.byref(slots), out.ctypes.data), "bs_pattern_layout")
+    if slots.value == 0:
+        return None
+    return slots.value, out[:64].copy(), out[64:128].copy(), out[128:].copy()
 
 
 def bs_values_csr_to_ell(handle: int, csr_values, ell_values, stream=None) -> None:

@@ -14,14 +14,20 @@
 #include <vector>
 
 #include "../../include/batchsolve.h"
+#include "bs_layout.hpp"
 #include "bs_registry.hpp"
 #include "bs_shape.hpp"
 
 struct bs_pattern_s {
   int n = 0, nnz = 0, width = 0, max_row = 0, device = -1;
   std::vector<int> row_ptr, col, slot_col, row_len, diag_slot;
-  int* d_base = nullptr;  // one allocation: row_ptr | slot_col | row_len | diag_slot
+  // bank-aware layout for one-wave teams of layout_nz register slots (0: none)
+  std::vector<int> layout;
+  int layout_nz = 0;
+  // one allocation: row_ptr | slot_col | row_len | diag_slot | layout
+  int* d_base = nullptr;
   int *d_row_ptr = nullptr, *d_slot_col = nullptr, *d_row_len = nullptr, *d_diag = nullptr;
+  int* d_layout = nullptr;
 };
 
 namespace {
@@ -90,14 +96,16 @@ int upload(bs_pattern_s& p) {
   hipError_t e = hipGetDevice(&p.device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const size_t n_rp = p.n + 1, n_sc = std::max<size_t>((size_t)p.width * p.n, 1), n_rl = p.n;
-  const size_t total = n_rp + n_sc + 2 * n_rl;
+  const size_t total = n_rp + n_sc + 2 * n_rl + p.layout.size();
   e = hipMalloc(&p.d_base, total * sizeof(int));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(pattern)");
   p.d_row_ptr = p.d_base;
   p.d_slot_col = p.d_row_ptr + n_rp;
   p.d_row_len = p.d_slot_col + n_sc;
   p.d_diag = p.d_row_len + n_rl;
+  p.d_layout = p.layout.empty() ? nullptr : p.d_diag + n_rl;
   std::vector<int> h(total, -1);
+  std::copy(p.layout.begin(), p.layout.end(), h.begin() + n_rp + n_sc + 2 * n_rl);
   std::copy(p.row_ptr.begin(), p.row_ptr.end(), h.begin());
   std::copy(p.slot_col.begin(), p.slot_col.end(), h.begin() + n_rp);
   std::copy(p.row_len.begin(), p.row_len.end(), h.begin() + n_rp + n_sc);
@@ -147,6 +155,27 @@ const bs::KernelEntry* find_kernel(int variant, int team, int r, int nz_min) {
     if (e.team == team && e.r == r && e.nz >= nz_min && (!best || e.nz < best->nz)) best = &e;
   }
   return best;
+}
+
+// Rows of 33..64 entries are solved by one-wave teams (one row per lane); such a
+// pattern gets its bank-aware layout for the register-slot count the planner
+// takes for it.
+constexpr int kLayoutSteps = 20000;
+
+void choose_layout(bs_pattern_s& p) {
+  p.layout.clear();
+  p.layout_nz = 0;
+  if (p.n <= 32 || p.n > bs::kLayoutLanes) return;
+  const bs::KernelEntry* k = find_kernel(bs::V_BICGSTAB, bs::kWave, 1, std::max(p.max_row, 1));
+  if (!k || p.nnz < k->nz) return;
+  const bs::WaveLayout L =
+      bs::choose_wave_layout(p.n, p.nnz, p.row_ptr.data(), p.col.data(), k->nz, kLayoutSteps);
+  if (L.cost >= L.plain_cost) return;
+  p.layout.reserve(2 * bs::kLayoutLanes + p.n);
+  p.layout.insert(p.layout.end(), L.lane_row.begin(), L.lane_row.end());
+  p.layout.insert(p.layout.end(), L.lane_win.begin(), L.lane_win.end());
+  p.layout.insert(p.layout.end(), L.col_pos.begin(), L.col_pos.end());
+  p.layout_nz = k->nz;
 }
 
 // Compute units of the current device (cached per device).
@@ -208,7 +237,8 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
   const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED;
   const int stored = fmt == BS_CSR ? nnz : width * n;
-  const int vec = teams * bs::team_vec_bytes(rows, gm) + bs::red_lds_bytes(waves);
+  const bool mixed = variant == bs::V_GMRES_MIXED;
+  const int vec = teams * bs::team_vec_bytes(rows, gm, wg, mixed) + bs::red_lds_bytes(waves);
   int stage = 0;
   if (waves == 1 && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget) stage = 1;
   out->k = k;
@@ -271,6 +301,7 @@ int bs_pattern_create_csr(int32_t n_rows, int32_t nnz, const int32_t* row_ptr,
   p->row_ptr.assign(row_ptr, row_ptr + n_rows + 1);
   p->col.assign(col_idx, col_idx + nnz);
   derive(*p);
+  choose_layout(*p);
   const int rc = upload(*p);
   if (rc != BS_OK) {
     delete p;
@@ -317,6 +348,7 @@ int bs_pattern_create_ell(int32_t n_rows, int32_t ell_width, const int32_t* ell_
     p->slot_col.resize((size_t)ell_width * n_rows, -1);
     p->width = ell_width;
   }
+  choose_layout(*p);
   const int rc = upload(*p);
   if (rc != BS_OK) {
     delete p;
@@ -330,6 +362,40 @@ int bs_pattern_destroy(bs_pattern p) {
   if (!p) return BS_OK;
   if (p->d_base) (void)hipFree(p->d_base);
   delete p;
+  return BS_OK;
+}
+
+int bs_wave_layout(int32_t n_rows, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                   int32_t slots, int32_t steps, int32_t* lane_row, int32_t* lane_win,
+                   int32_t* col_pos, int64_t* cost) {
+  if (!row_ptr || (nnz > 0 && !col_idx) || !lane_row || !lane_win || !col_pos || !cost ||
+      n_rows < 1 || nnz < 0 || slots < 1 || steps < 0)
+    return BS_ERR_INVALID_ARG;
+  if (row_ptr[0] != 0 || row_ptr[n_rows] != nnz) return BS_ERR_PATTERN;
+  int max_row = 0;
+  for (int i = 0; i < n_rows; ++i) {
+    if (row_ptr[i + 1] < row_ptr[i]) return BS_ERR_PATTERN;
+    max_row = std::max(max_row, row_ptr[i + 1] - row_ptr[i]);
+  }
+  std::vector<int> mark(n_rows, -1);
+  for (int i = 0; i < n_rows; ++i)
+    if (!row_ok(col_idx + row_ptr[i], row_ptr[i + 1] - row_ptr[i], n_rows, mark, i))
+      return BS_ERR_PATTERN;
+  if (n_rows <= 32 || n_rows > bs::kLayoutLanes || nnz < slots || max_row > slots)
+    return BS_ERR_UNSUPPORTED;
+  const bs::WaveLayout L = bs::choose_wave_layout(n_rows, nnz, row_ptr, col_idx, slots, steps);
+  std::copy(L.lane_row.begin(), L.lane_row.end(), lane_row);
+  std::copy(L.lane_win.begin(), L.lane_win.end(), lane_win);
+  std::copy(L.col_pos.begin(), L.col_pos.end(), col_pos);
+  cost[0] = L.cost;
+  cost[1] = L.plain_cost;
+  return BS_OK;
+}
+
+int bs_pattern_layout(bs_pattern p, int32_t* slots, int32_t* layout) {
+  if (!p || !slots) return BS_ERR_INVALID_ARG;
+  *slots = p->layout_nz;
+  if (layout) std::copy(p->layout.begin(), p->layout.end(), layout);
   return BS_OK;
 }
 
@@ -431,7 +497,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     const int rows = pl.info.team * pl.info.rows_per_lane;
     const int teams = pl.info.systems_per_group, waves = pl.info.group_size / bs::kWave;
     const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
-    a.team_bytes = bs::team_vec_bytes(rows, a.gmres);
+    a.team_bytes = bs::team_vec_bytes(rows, a.gmres, pl.info.group_size,
+                                      a.gmres && opts && opts->precision == BS_MIXED);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
@@ -456,6 +523,10 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.x_alt = opts ? opts->x_alt : nullptr;
   a.alt_used = opts ? opts->alt_used : nullptr;
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
+  a.layout = (pattern->d_layout && pl.info.team == bs::kWave && pl.info.rows_per_lane == 1 &&
+              a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT))
+                 ? pattern->d_layout
+                 : nullptr;
   // Persistent grid: as many workgroups as can be resident at once, each
   // walking over the batch (never more than there are systems).
   const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;

@@ -80,6 +80,18 @@ __device__ __forceinline__ T rows_total(T v) {
   return v + dpp<0x143>(v);
 }
 
+// Sum over aligned groups of g lanes (g = 1, 2, 4, 8 or 16, uniform): the first
+// log2(g) steps of the row16_sum butterfly.  Every lane of a group ends with
+// the same bits.
+template <class T>
+__device__ __forceinline__ T group_sum(T v, int g) {
+  if (g >= 2) v = v + dpp<0xB1>(v);
+  if (g >= 4) v = v + dpp<0x4E>(v);
+  if (g >= 8) v = v + dpp<0x141>(v);
+  if (g >= 16) v = v + dpp<0x140>(v);
+  return v;
+}
+
 __device__ __forceinline__ int row16_max(int v) {
   v = max(v, dpp<0xB1>(v));
   v = max(v, dpp<0x4E>(v));
@@ -184,13 +196,13 @@ struct Team {
           for (int k = 0; k < K; ++k) buf[k * S::WAVES + w] = (double)v[k];
         }
         __syncthreads();
+        // lane l reads the partial of wave l mod WAVES; a butterfly over aligned
+        // groups of WAVES lanes leaves the total in every lane, with the same
+        // bits in every wave
+        const int src = threadIdx.x & (S::WAVES - 1);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          double s = buf[k * S::WAVES];
-#pragma unroll
-          for (int i = 1; i < S::WAVES; ++i) s += buf[k * S::WAVES + i];
-          v[k] = (T)s;
-        }
+        for (int k = 0; k < K; ++k)
+          v[k] = (T)rdlane(group_sum(buf[k * S::WAVES + src], S::WAVES), 0);
         phase ^= 1;
       }
     }
@@ -216,10 +228,11 @@ struct Team {
 // offset.  ELL rows use slot k for the row's k-th stored entry.
 template <class S>
 struct Rows {
-  static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS;
+  static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS, WG = S::WG;
   double a[S::R][S::NZ];
   unsigned c[S::R][S::NZ];
   unsigned vrow[S::R];  // LDS address of the lane's own rows in buffer 0
+  unsigned zc;          // LDS address of the zero cell in buffer 0
   int row[S::R];
   bool ok[S::R];   // row < n
   int len[S::R];
@@ -237,22 +250,27 @@ struct Rows {
   __device__ void load_pattern(const Team<S>& tm, const KArgs& g) {
     const unsigned base = lds_addr(tm.lds);
     const unsigned zero = base + S::ROWS * 8;
+    zc = zero;
     if (tm.lane == 0) {
 #pragma unroll
       for (int b = 0; b < kVecBuffers; ++b) lds_store<double>(zero + b * kBuf, 0.0);
     }
+    // A one-wave team may take the pattern's bank-aware layout: the row each
+    // lane owns, its CSR window, and the buffer element of every x_j (64 lanes,
+    // elements 0..63, the zero cell at 64).
+    const int* lay = (S::TEAM == kWave && S::R == 1 && g.fmt == 0 && g.window) ? g.layout : nullptr;
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
-      row[r] = tm.lane + r * S::TEAM;
-      vrow[r] = base + row[r] * 8;
-      ok[r] = row[r] < g.n;
+      row[r] = lay ? lay[tm.lane] : tm.lane + r * S::TEAM;
+      ok[r] = row[r] >= 0 && row[r] < g.n;
       const int rr = ok[r] ? row[r] : 0;
+      vrow[r] = base + (lay ? (ok[r] ? lay[2 * kWave + rr] : S::ROWS) : row[r]) * 8;
       len[r] = ok[r] ? g.row_len[rr] : 0;
       const int ds = ok[r] ? g.diag_slot[rr] : -1;
       const int rp = g.row_ptr[rr];
       int shift = 0;
       if (g.fmt == 0) {
-        w[r] = g.window ? max(0, min(rp, g.nnz - S::NZ)) : rp;
+        w[r] = lay ? lay[kWave + tm.lane] : g.window ? max(0, min(rp, g.nnz - S::NZ)) : rp;
         shift = rp - w[r];
       } else {
         w[r] = rr;
@@ -263,7 +281,8 @@ struct Rows {
         const int j = k - shift;  // entry of the row held by slot k
         const bool has = j >= 0 && j < len[r];
         const int col = g.slot_col[has ? (size_t)j * g.n + rr : 0];
-        c[r][k] = has ? base + col * 8 : zero;
+        const int el = lay ? lay[2 * kWave + col] : col;
+        c[r][k] = has ? base + el * 8 : zero;
         // keep the full address in the register: otherwise the compiler keeps
         // col*8 and re-adds the (link-time) LDS base before every gather
         __asm__ volatile("" : "+v"(c[r][k]));
@@ -446,9 +465,7 @@ struct Rows {
   }
 
   // Whether slot k of row r holds one of the row's entries (not the zero cell).
-  __device__ __forceinline__ bool real(int r, int k) const {
-    return c[r][k] != vrow[0] - row[0] * 8 + S::ROWS * 8;
-  }
+  __device__ __forceinline__ bool real(int r, int k) const { return c[r][k] != zc; }
 
   // Scalar Jacobi: d = 1/a_ii, 1 where the diagonal is zero or absent; 0 for
   // lanes past the last row so padded entries stay zero.

@@ -47,6 +47,7 @@ struct KArgs {
   int* sink;                   // a device word written instead of a missing status
   const double* x_alt;         // optional second initial guess [n_batch][n]
   int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
+  const int* layout;           // one-wave teams: lane_row[64] | lane_win[64] | col_pos[n], or null
 };
 
 // team: lanes per system; R: rows per lane; NZ: register slots per row.
@@ -75,9 +76,26 @@ __host__ __device__ constexpr int round16(int b) { return (b + 15) & ~15; }
 __host__ __device__ constexpr int round1k(int b) { return (b + 1023) & ~1023; }
 __host__ __device__ constexpr int vec_buf_bytes(int rows) { return (rows + 1) * 8; }
 
-// LDS bytes of a team's vector buffers and solver scalars.
-__host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres) {
-  return round16(kVecBuffers * vec_buf_bytes(rows) + (solver_is_gmres ? kGmresScalars * 8 : 0));
+// GMRES basis vectors a team keeps in LDS instead of registers.  A 1024-lane
+// workgroup leaves 128 VGPRs per lane, too few for 31 FP64 basis elements next
+// to the row's values and addresses: such teams keep 16 FP64 (or all 31 FP32)
+// vectors in LDS, one element per lane, each lane reading only its own.
+__host__ __device__ constexpr int gmres_lds_vectors(int wg, bool mixed) {
+  return wg == 1024 ? (mixed ? kMaxRestart + 1 : 16) : 0;
+}
+
+// Offset of the GMRES basis region inside a team's LDS region.
+__host__ __device__ constexpr int gmres_basis_offset(int rows) {
+  return round16(kVecBuffers * vec_buf_bytes(rows) + kGmresScalars * 8);
+}
+
+// LDS bytes of a team's vector buffers and solver scalars (and, for GMRES
+// shapes of `wg` lanes, its basis vectors in LDS).
+__host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres, int wg = 0,
+                                              bool mixed = false) {
+  if (!solver_is_gmres) return round16(kVecBuffers * vec_buf_bytes(rows));
+  return gmres_basis_offset(rows) +
+         round16(gmres_lds_vectors(wg, mixed) * rows * (mixed ? 4 : 8));
 }
 
 inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }

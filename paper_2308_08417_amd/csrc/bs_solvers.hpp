@@ -489,8 +489,8 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 // =================================================================== GMRES(m)
 // Right-preconditioned restarted GMRES with modified Gram-Schmidt Arnoldi and
 // Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning).  The m+1
-// basis vectors stay in registers (one element per row per lane), so a cycle
-// never touches HBM.  The Hessenberg column, the rotated triangle R, the
+// basis vectors stay on chip (one element per row per lane, in registers, or
+// partly in LDS for 1024-lane teams), so a cycle never touches HBM.  The Hessenberg column, the rotated triangle R, the
 // rotations, g and y are per-team LDS scalars written once per cycle: every lane
 // of the team computes the same bits and writes them, and reads only entries it
 // has written itself, so no barrier is needed around them.  The last entry of g
@@ -543,9 +543,21 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!finite(bn)) st = ST_NONFINITE;
     else if (bn == 0.0) { st = ST_CONVERGED; P.x[0] = 0.0; }
   }
-  T V[M + 1];
+  // Basis vectors 0..NL-1 live in LDS (this lane's element of vector i at
+  // vb + i * ROWS * sizeof(T)), vectors NL..M in registers V[i - NL].
+  constexpr int NL = gmres_lds_vectors(RW::WG, MIXED);
+  constexpr int NV = M + 1 - NL;
+  T V[NV > 0 ? NV : 1];
+  const unsigned vb = lds_addr(tm.lds) + gmres_basis_offset(RW::ROWS) + (unsigned)tm.lane * sizeof(T);
+  constexpr unsigned vstride = RW::ROWS * sizeof(T);
 #pragma unroll
-  for (int i = 0; i <= M; ++i) V[i] = (T)0;
+  for (int i = 0; i < NV; ++i) V[i] = (T)0;
+#pragma unroll
+  for (int i = 0; i < NL; ++i) lds_store<T>(vb + i * vstride, (T)0);
+  // basis element i of this lane (i is a compile-time index after unrolling)
+  auto basis = [&](int i) -> T {
+    return i < NL ? lds_load<T>(vb + i * vstride) : V[i >= NL ? i - NL : 0];
+  };
   int k = 0, j = 0, cycles = 0;
   double gcur = 0.0;   // g_j, the entry the next rotation acts on
   double ilim = lim;   // the cycle's stopping level for |g|
@@ -570,7 +582,8 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
         else if (k >= g.max_iter) st = ST_MAX_ITER;
         else if (MIXED && !(beta < beta_prev)) st = ST_BREAKDOWN;
         else {
-          V[0] = (T)(rc / beta);
+          if constexpr (NL > 0) lds_store<T>(vb, (T)(rc / beta));
+          else V[0] = (T)(rc / beta);
           gcur = beta;
           if constexpr (MIXED) ilim = fmax(g.inner_tol * beta, 0.5 * lim);
           beta_prev = beta;
@@ -583,20 +596,24 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!tm.any(st == ST_RUNNING)) break;
     // ---- one Arnoldi step for every running team (all of them are mid-cycle)
     const bool act = st == ST_RUNNING;
-    T vj = V[0];
+    T vj = (T)0;
+    if constexpr (NL > 0) {
+      if (j < NL) vj = lds_load<T>(vb + (unsigned)j * vstride);  // one team per group: j uniform
+    }
 #pragma unroll
-    for (int i = 1; i < M; ++i)
-      if (j == i) vj = V[i];
+    for (int i = NL; i < M; ++i)
+      if (j == i) vj = V[i - NL];
     T z[1] = {dT * vj}, w[1];
     A.template spmv<0>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (i <= jmax) {
-        T q[1] = {w[0] * V[i]};
+        const T vi = basis(i);
+        T q[1] = {w[0] * vi};
         tm.sum(q);
         if (act && i <= j) {
-          w[0] = fma(-q[0], V[i], w[0]);
+          w[0] = fma(-q[0], vi, w[0]);
           hcol[i] = (double)q[0];
         }
       }
@@ -632,9 +649,12 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
           end = fabs(gcur) <= ilim || hn == 0.0 || k >= g.max_iter || j == m - 1;
           if (!end) {
             const T vn = (T)((double)w[0] / hn);
+            if constexpr (NL > 0) {
+              if (j + 1 < NL) lds_store<T>(vb + (unsigned)(j + 1) * vstride, vn);
+            }
 #pragma unroll
-            for (int i = 1; i <= M; ++i)
-              if (j + 1 == i) V[i] = vn;
+            for (int i = (NL > 1 ? NL : 1); i <= M; ++i)
+              if (j + 1 == i) V[i - NL] = vn;
             j += 1;
           }
         }
@@ -652,7 +672,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
             for (int l = i + 1; l <= j; ++l) acc = fma(-Rt[l * (l + 1) / 2 + i], yv[l], acc);
             const double yi = acc / Rt[i * (i + 1) / 2 + i];
             yv[i] = yi;
-            zacc = fma(yi, (double)V[i], zacc);
+            zacc = fma(yi, (double)basis(i), zacc);
           }
         }
       }

@@ -112,27 +112,13 @@ struct VarTeam {
         for (int k = 0; k < K; ++k) buf[k * VS::WAVES + w] = (double)v[k];
       }
       __syncthreads();
-      // the team's wave partials in order, four loads in flight at a time
-      // (wpt is a power of two >= 2, uniform over the workgroup)
-      constexpr int kG = VS::WAVES < 4 ? VS::WAVES : 4;
-      const int w0 = tix * wpt;
+      // lane l reads the partial of its team's wave (l mod wpt); a butterfly
+      // over aligned groups of wpt lanes leaves the team total in every lane
+      // (wpt is a power of two from 2 to 16, uniform over the workgroup)
+      const int src = tix * wpt + (threadIdx.x & (wpt - 1));
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double* q = buf + k * VS::WAVES + w0;
-        double s = q[0];
-#pragma unroll
-        for (int i0 = 0; i0 < VS::WAVES; i0 += kG) {
-          if (i0 < wpt) {
-            double part[kG];
-#pragma unroll
-            for (int j = 0; j < kG; ++j) part[j] = q[min(i0 + j, wpt - 1)];
-#pragma unroll
-            for (int j = 0; j < kG; ++j)
-              if (i0 + j > 0 && i0 + j < wpt) s += part[j];
-          }
-        }
-        v[k] = (V)s;
-      }
+      for (int k = 0; k < K; ++k)
+        v[k] = (V)rdlane(group_sum(buf[k * VS::WAVES + src], wpt), 0);
       phase ^= 1;
     }
   }

@@ -125,7 +125,13 @@ def test_plan_covers_rows(L, n):
         # smallest team for one row per lane
         if n <= 1024:
             assert p["rows_per_lane"] == 1 and (p["team"] == 16 or p["team"] // 2 < n)
-        assert p["lds_bytes"] <= 64 * 1024
+        # 160 KiB of LDS per compute unit; 1024-lane GMRES teams keep 16 FP64
+        # basis vectors there
+        assert p["lds_bytes"] <= 160 * 1024
+        if solver == bs.GMRES and p["group_size"] == 1024:
+            assert p["lds_bytes"] >= 16 * 1024 * 8
+        else:
+            assert p["lds_bytes"] <= 64 * 1024
 
 
 def test_plan_stage_and_limits(L):

@@ -61,7 +61,7 @@ class Case:
         return self.batch.values if fmt == bs.CSR else O.csr_values_to_ell(self.OP, self.batch.values)
 
     def gpu(self, fmt, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=500, x0=None,
-            b=None, values=None, **opt):
+            b=None, values=None, extra_flags=0, **opt):
         say(f"  gpu: {self.batch.name} n={self.batch.n} B={self.batch.n_batch} fmt={fmt} "
             f"solver={solver} prec={precond} opt={opt}")
         bb = dev(self.batch.b if b is None else b)
@@ -71,7 +71,7 @@ class Case:
             flags = bs.FLAG_X0_ZERO
         else:
             x = dev(x0)
-        opts = bs.make_options(flags=flags, **opt)
+        opts = bs.make_options(flags=flags | extra_flags, **opt)
         B = bb.shape[0]
         iters = torch.full((B,), -7, dtype=torch.int32, device="cuda:0")
         resid = torch.full((B,), -7.0, dtype=torch.float64, device="cuda:0")
@@ -320,6 +320,57 @@ def test_mixed_cg_unsupported():
     with pytest.raises(bs.BatchSolveError) as e:
         c.gpu(bs.CSR, bs.CG, precision=bs.MIXED)
     assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ bank-aware layout
+def spd_on_pattern(n, n_batch, seed):
+    """SPD systems on a symmetrised random pattern: symmetric off-diagonal
+    entries U(-1, 1), diagonal = 1 + sum of the row's |off-diagonal|."""
+    rng = np.random.default_rng(seed)
+    mask = rng.random((n, n)) < 0.2
+    mask = mask | mask.T
+    np.fill_diagonal(mask, True)
+    rows, cols = np.nonzero(mask)
+    row_ptr = np.concatenate([[0], np.cumsum(mask.sum(1))]).astype(np.int32)
+    col_idx = cols.astype(np.int32)
+    vals = np.empty((n_batch, col_idx.size))
+    for s in range(n_batch):
+        M = np.triu(2 * rng.random((n, n)) - 1, 1)
+        M = (M + M.T) * mask
+        np.fill_diagonal(M, 1 + np.abs(M).sum(1))
+        vals[s] = M[rows, cols]
+    b = 2 * rng.random((n_batch, n)) - 1
+    return W.Batch("spd_pattern", n, row_ptr, col_idx, vals, b, np.zeros_like(b))
+
+
+@pytest.mark.parametrize("solver,prec", [(bs.BICGSTAB, bs.FP64), (bs.GMRES, bs.FP64),
+                                         (bs.BICGSTAB, bs.MIXED), (bs.GMRES, bs.MIXED)])
+def test_bank_layout_parity(solver, prec):
+    """The pattern's layout (lanes, buffer elements, windows permuted) and the
+    plain layout both meet the oracle; 3001 systems leave a ragged last round."""
+    bt = W.chem_jacobian(n_batch=3001, n=54, seed=0)
+    c = Case(bt)
+    lay = bs.bs_pattern_layout(c.P.handle)
+    assert lay is not None and lay[0] == 28
+    assert sorted(lay[1][lay[1] >= 0].tolist()) == list(range(54))
+    rng = np.random.default_rng(5)
+    x0 = None if prec == bs.MIXED else rng.standard_normal(bt.b.shape)
+    itol = ITOL if prec == bs.FP64 else 10**9
+    o = c.oracle(bs.CSR, solver, x0=x0)
+    for flags in (0, bs.FLAG_PLAIN_LAYOUT):
+        g = c.gpu(bs.CSR, solver, x0=x0, extra_flags=flags, precision=prec)
+        check(c, g, o, itol=itol)
+
+
+def test_bank_layout_cg_spd():
+    bt = spd_on_pattern(48, 700, seed=2)
+    c = Case(bt)
+    lay = bs.bs_pattern_layout(c.P.handle)
+    assert lay is not None
+    o = c.oracle(bs.CSR, bs.CG)
+    for flags in (0, bs.FLAG_PLAIN_LAYOUT):
+        g = c.gpu(bs.CSR, bs.CG, extra_flags=flags)
+        check(c, g, o)
 
 
 # ------------------------------------------------------------------ full size
