@@ -92,6 +92,68 @@ __device__ __forceinline__ T group_sum(T v, int g) {
   return v;
 }
 
+// gfx950 lane swaps between two registers (one instruction per 32-bit word):
+//   swap32(a, b): a <- [a lanes 0-31, b lanes 0-31], b <- [a lanes 32-63, b lanes 32-63]
+//   swap16(a, b): a <- [a row 0, b row 0, a row 2, b row 2],
+//                 b <- [a row 1, b row 1, a row 3, b row 3]   (rows of 16 lanes)
+__device__ __forceinline__ void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sums over the whole wave of K <= 4 values, returned wave-uniform.  Two or
+// more values share the butterfly: swap32 + add leaves value 0's pair sums in
+// lanes 0-31 and value 1's in lanes 32-63; swap16 + add then packs four values
+// into the four rows (rows 0..3 = values 0, 2, 1, 3), and one row butterfly
+// finishes all of them.  Every lane of a row ends with the same bits.
+template <class T, int K>
+__device__ __forceinline__ void wave_sums(T (&v)[K]) {
+  static_assert(K >= 1 && K <= 4, "one to four values");
+  if constexpr (K == 1) {
+    v[0] = rdlane(rows_total(row16_sum(v[0])), 63);
+  } else if constexpr (K == 2) {
+    T a = v[0], b = v[1];
+    swap32(a, b);
+    const T s = rows_pairs(row16_sum(a + b));  // lane 31: rows 0+1, lane 63: rows 2+3
+    v[0] = rdlane(s, 31);
+    v[1] = rdlane(s, 63);
+  } else {
+    T a = v[0], b = v[1], c = v[2], d = (T)0;
+    if constexpr (K == 4) d = v[K - 1];
+    swap32(a, b);
+    swap32(c, d);
+    T s01 = a + b, s23 = c + d;
+    swap16(s01, s23);
+    const T t = row16_sum(s01 + s23);
+    v[0] = rdlane(t, 0);
+    v[1] = rdlane(t, 32);
+    v[2] = rdlane(t, 16);
+    if constexpr (K == 4) v[K - 1] = rdlane(t, 48);
+  }
+}
+
 __device__ __forceinline__ int row16_max(int v) {
   v = max(v, dpp<0xB1>(v));
   v = max(v, dpp<0x4E>(v));
@@ -173,8 +235,10 @@ struct Team {
   // receives the same bits.  All lanes of the workgroup must call it together.
   template <class T, int K>
   __device__ __forceinline__ void sum(T (&v)[K]) {
+    if constexpr (S::TEAM < 64) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = row16_sum(v[k]);
+      for (int k = 0; k < K; ++k) v[k] = row16_sum(v[k]);
+    }
     if constexpr (S::TEAM == 32) {
       // teams are rows {0,1} and {2,3}: their sums end in lanes 31 and 63
       const bool hi = lane_id() >= 32;
@@ -185,10 +249,9 @@ struct Team {
         v[k] = hi ? s23 : s01;
       }
     } else if constexpr (S::TEAM >= 64) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = rdlane(rows_total(v[k]), 63);
+      wave_sums(v);
       if constexpr (S::WAVES > 1) {
-        static_assert(K <= kMaxFused, "too many fused values");
+        static_assert(K <= kMaxFused && K * S::WAVES <= 64, "too many fused values");
         double* buf = red + phase * (kMaxFused * S::WAVES);
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -196,13 +259,14 @@ struct Team {
           for (int k = 0; k < K; ++k) buf[k * S::WAVES + w] = (double)v[k];
         }
         __syncthreads();
-        // lane l reads the partial of wave l mod WAVES; a butterfly over aligned
-        // groups of WAVES lanes leaves the total in every lane, with the same
-        // bits in every wave
-        const int src = threadIdx.x & (S::WAVES - 1);
+        // lane l reads value l / WAVES of wave l mod WAVES; a butterfly over
+        // aligned groups of WAVES lanes leaves value k's total in lanes
+        // k*WAVES .. k*WAVES+WAVES-1, with the same bits in every wave
+        const int l = threadIdx.x & 63;
+        const int vi = l / S::WAVES < K ? l / S::WAVES : 0;
+        const double t = group_sum(buf[vi * S::WAVES + (l & (S::WAVES - 1))], S::WAVES);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-          v[k] = (T)rdlane(group_sum(buf[k * S::WAVES + src], S::WAVES), 0);
+        for (int k = 0; k < K; ++k) v[k] = (T)rdlane(t, k * S::WAVES);
         phase ^= 1;
       }
     }

@@ -65,6 +65,12 @@ struct Shape {
 #define BS_OCC_ONE_WAVE 3
 #endif
   static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE : 1;
+  // The mixed-precision forms hold an FP32 copy of the rows beside the FP64 one.
+#ifndef BS_OCC_ONE_WAVE_MIXED
+#define BS_OCC_ONE_WAVE_MIXED 3
+#endif
+  static constexpr int OCC_MIXED =
+      (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE_MIXED : 1;
 };
 
 // Vector buffers per team (SpMV source vectors, double-buffered).  Each buffer

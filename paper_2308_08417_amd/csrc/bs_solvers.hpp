@@ -742,7 +742,7 @@ constexpr int kWaitPrefetch = 0x0074;
   }
 
 template <class S, bool MIXED>
-__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_bicgstab(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
   BS_PERSISTENT_LOOP((bicgstab_system<MIXED>(tm, A, ga)))
 }
 
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC)))
 }
 
 template <class S, bool MIXED>
-__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_gmres(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_gmres(const KArgs g) {
   BS_PERSISTENT_LOOP((gmres_system<MIXED>(tm, A, ga)))
 }
 

@@ -68,6 +68,7 @@ struct VarTeam {
   int T;               // lanes per team
   int lane, tix;       // lane within the team, team within the workgroup
   int wpt;             // waves per team
+  int lgw;             // log2(wpt)
   int64_t sys, row0;
   bool live;
   char* lds;
@@ -79,6 +80,7 @@ struct VarTeam {
     lane = threadIdx.x & (t - 1);
     tix = threadIdx.x / t;
     wpt = t / kWave;
+    lgw = __builtin_ctz((unsigned)wpt);
     lds = smem;
     red = reinterpret_cast<double*>(smem + 2 * var_buf_bytes<VS>());
   }
@@ -101,9 +103,8 @@ struct VarTeam {
 
   template <class V, int K>
   __device__ __forceinline__ void sum(V (&v)[K]) {
-    static_assert(K <= kMaxFused, "too many fused values");
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = rdlane(rows_total(row16_sum(v[k])), 63);
+    static_assert(K <= kMaxFused && K * 16 <= 64, "too many fused values");
+    wave_sums(v);
     if (wpt > 1) {
       double* buf = red + phase * (kMaxFused * VS::WAVES);
       const int w = threadIdx.x >> 6;
@@ -112,13 +113,15 @@ struct VarTeam {
         for (int k = 0; k < K; ++k) buf[k * VS::WAVES + w] = (double)v[k];
       }
       __syncthreads();
-      // lane l reads the partial of its team's wave (l mod wpt); a butterfly
-      // over aligned groups of wpt lanes leaves the team total in every lane
-      // (wpt is a power of two from 2 to 16, uniform over the workgroup)
-      const int src = tix * wpt + (threadIdx.x & (wpt - 1));
+      // lane l reads value l / wpt of its team's wave (l mod wpt); a butterfly
+      // over aligned groups of wpt lanes leaves value k's team total in lanes
+      // k*wpt .. k*wpt+wpt-1 (wpt is a power of two from 2 to 16, uniform over
+      // the workgroup, and K * wpt <= 64)
+      const int l = threadIdx.x & 63;
+      const int vi = (l >> lgw) < K ? (l >> lgw) : 0;
+      const double t = group_sum(buf[vi * VS::WAVES + tix * wpt + (l & (wpt - 1))], wpt);
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        v[k] = (V)rdlane(group_sum(buf[k * VS::WAVES + src], wpt), 0);
+      for (int k = 0; k < K; ++k) v[k] = (V)rdlane(t, k * wpt);
       phase ^= 1;
     }
   }
