@@ -292,7 +292,7 @@ struct Team {
 // offset.  ELL rows use slot k for the row's k-th stored entry.
 template <class S>
 struct Rows {
-  static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS, WG = S::WG;
+  static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS, WG = S::WG, TEAM = S::TEAM;
   double a[S::R][S::NZ];
   unsigned c[S::R][S::NZ];
   unsigned vrow[S::R];  // LDS address of the lane's own rows in buffer 0

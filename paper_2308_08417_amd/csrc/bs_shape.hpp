@@ -95,13 +95,17 @@ __host__ __device__ constexpr int gmres_basis_offset(int rows) {
   return round16(kVecBuffers * vec_buf_bytes(rows) + kGmresScalars * 8);
 }
 
+// Bytes of a team's GMRES basis region.
+__host__ __device__ constexpr int gmres_basis_bytes(int rows, int wg, bool mixed) {
+  return round16(gmres_lds_vectors(wg, mixed) * rows * (mixed ? 4 : 8));
+}
+
 // LDS bytes of a team's vector buffers and solver scalars (and, for GMRES
 // shapes of `wg` lanes, its basis vectors in LDS).
 __host__ __device__ inline int team_vec_bytes(int rows, int solver_is_gmres, int wg = 0,
                                               bool mixed = false) {
   if (!solver_is_gmres) return round16(kVecBuffers * vec_buf_bytes(rows));
-  return gmres_basis_offset(rows) +
-         round16(gmres_lds_vectors(wg, mixed) * rows * (mixed ? 4 : 8));
+  return gmres_basis_offset(rows) + gmres_basis_bytes(rows, wg, mixed);
 }
 
 inline int red_lds_bytes(int waves) { return waves > 1 ? 2 * kMaxFused * waves * 8 : 0; }

@@ -487,8 +487,11 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 }
 
 // =================================================================== GMRES(m)
-// Right-preconditioned restarted GMRES with modified Gram-Schmidt Arnoldi and
-// Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning).  The m+1
+// Right-preconditioned restarted GMRES with Gram-Schmidt Arnoldi and Givens
+// rotations (Saad 2003, Alg. 6.9 with right preconditioning): modified
+// Gram-Schmidt for teams narrower than a wave, block modified Gram-Schmidt
+// (blocks of four, classical inside a block) for teams of a wave or more, whose
+// reductions then fuse four dots at a time.  The m+1
 // basis vectors stay on chip (one element per row per lane, in registers, or
 // partly in LDS for 1024-lane teams), so a cycle never touches HBM.  The Hessenberg column, the rotated triangle R, the
 // rotations, g and y are per-team LDS scalars written once per cycle: every lane
@@ -558,6 +561,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   auto basis = [&](int i) -> T {
     return i < NL ? lds_load<T>(vb + i * vstride) : V[i >= NL ? i - NL : 0];
   };
+
   int k = 0, j = 0, cycles = 0;
   double gcur = 0.0;   // g_j, the entry the next rotation acts on
   double ilim = lim;   // the cycle's stopping level for |g|
@@ -606,15 +610,43 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     T z[1] = {dT * vj}, w[1];
     A.template spmv<0>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
+    if constexpr (RW::TEAM >= 64) {
+      // Block Gram-Schmidt: blocks of four basis vectors taken in order, as
+      // modified Gram-Schmidt takes single vectors; within a block the four
+      // dots use the same w (classical Gram-Schmidt) and share one fused
+      // reduction, then w -= V_block q.
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (i <= jmax) {
-        const T vi = basis(i);
-        T q[1] = {w[0] * vi};
-        tm.sum(q);
-        if (act && i <= j) {
-          w[0] = fma(-q[0], vi, w[0]);
-          hcol[i] = (double)q[0];
+      for (int g = 0; g < M; g += 4) {
+        if (g <= jmax) {
+          T vq[4], q[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            vq[t] = (g + t < M && g + t <= j) ? basis(g + t) : (T)0;
+            q[t] = w[0] * vq[t];
+          }
+          tm.sum(q);
+          if (act) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              if (g + t < M && g + t <= j) {
+                w[0] = fma(-q[t], vq[t], w[0]);
+                hcol[g + t] = (double)q[t];
+              }
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if (i <= jmax) {
+          const T vi = basis(i);
+          T q[1] = {w[0] * vi};
+          tm.sum(q);
+          if (act && i <= j) {
+            w[0] = fma(-q[0], vi, w[0]);
+            hcol[i] = (double)q[0];
+          }
         }
       }
     }

@@ -295,6 +295,19 @@ def test_mixed_precision_meets_fp64_tolerance(gen, fmt, solver):
     assert outer.min().item() >= 1
 
 
+@pytest.mark.parametrize("dominance", [1.05, 1.02])
+def test_gmres_weaker_dominance(dominance):
+    """Teams of a wave or more orthogonalise by block Gram-Schmidt (blocks of
+    four); the oracle uses modified Gram-Schmidt.  On less dominant stencils
+    (up to 347 steps, a dozen restarts) the two must still agree."""
+    c = Case(W.collision_stencil(n_batch=16, dominance=dominance, seed=3))
+    g = c.gpu(bs.CSR, bs.GMRES, max_iter=5000, restart=30)
+    o = c.oracle(bs.CSR, bs.GMRES, max_iter=5000, restart=30)
+    err, d = check(c, g, o)
+    say(f"  dominance {dominance}: iters {o[1].min()}..{o[1].max()}, max |diff| {d.max()}, "
+        f"x err {err.max():.2e}")
+
+
 def test_mixed_gmres_short_restarts():
     """Mixed GMRES with short cycles: every cycle is one refinement step, so the
     outer count grows as the restart length falls, and the answer still meets the
