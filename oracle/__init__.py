@@ -33,7 +33,7 @@ def lib():
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
         I, I64, D = C.c_int, C.c_int64, C.c_double
         L.or_batch_solve.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p,
-                                     I, I, D, I, I, i32p, f64p, i32p, I]
+                                     I, I, D, I, I, I, i32p, f64p, i32p, I]
         L.or_batch_solve.restype = I
         L.or_batch_spmv.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p]
         L.or_batch_spmv.restype = None
@@ -101,10 +101,13 @@ def csr_values_to_ell(pat: Pattern, values) -> np.ndarray:
 
 def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = BICGSTAB,
                 precond: int = PREC_JACOBI, tol: float = 1e-10, max_iter: int = 500,
-                restart: int = 30, nthreads: Optional[int] = None):
+                restart: int = 30, nthreads: Optional[int] = None, absolute: bool = False):
     """Solve every system; ``values`` in the layout of ``fmt``.
 
-    Returns ``(x, iters, resid, status)``; ``resid`` is the true relative residual.
+    Stop test (Tab. 2): relative ||r|| <= tol ||b|| by default, absolute
+    ||r|| <= tol with ``absolute``.  Returns ``(x, iters, resid, status)``;
+    ``resid`` is the true residual ||b - A x||, divided by ||b|| for the
+    relative criterion.
     """
     v = _f64(values)
     b = _f64(b)
@@ -116,7 +119,8 @@ def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = 
     nt = nthreads if nthreads is not None else (os.cpu_count() or 1)
     rp, ci, nnz, w, ec = pat.args(fmt)
     lib().or_batch_solve(fmt, B, pat.n, rp, ci, nnz, w, ec, v, b, x, solver, precond,
-                         float(tol), int(max_iter), int(restart), iters, resid, status, nt)
+                         float(tol), int(bool(absolute)), int(max_iter), int(restart), iters,
+                         resid, status, nt)
     return x, iters, resid, status
 
 

@@ -14,7 +14,8 @@
  *   - one system at a time; OpenMP only distributes whole systems.
  *
  * Readings of the paper used here (it is silent on them):
- *   - stop test: ||r||_2 <= tol * ||b||_2 on the recurrence residual, then a
+ *   - stop test: ||r||_2 <= tol * ||b||_2 (relative) or ||r||_2 <= tol
+ *     (absolute; Tab. 2 lists both criteria) on the recurrence residual, then a
  *     confirmation on the true residual b - A x; if that fails and iterations
  *     remain, the method restarts from the true residual;
  *   - BiCGSTAB and GMRES are right-preconditioned, so the monitored residual is
@@ -108,24 +109,25 @@ static double true_residual(const or_mat *A, const double *b, const double *x,
 
 typedef struct { int iters, status; double resid; } or_result;
 
-/* Common exit: report the true relative residual of the returned x. */
-static or_result finish(const or_mat *A, const double *b, const double *x, double bn,
+/* Common exit: report the true residual of the returned x divided by rs
+ * (||b||_2 for the relative criterion, 1 for the absolute one). */
+static or_result finish(const or_mat *A, const double *b, const double *x, double rs,
                         int k, int status, double *r, double *t)
 {
     or_result res;
     res.iters = k;
     res.status = status;
-    res.resid = true_residual(A, b, x, r, t) / bn;
+    res.resid = true_residual(A, b, x, r, t) / rs;
     return res;
 }
 
-/* ---- CG: Sec. 3.5, Alg. 1, with the relative-residual stop test -------- */
+/* ---- CG: Sec. 3.5, Alg. 1, with the residual-norm stop test ------------ */
 static or_result solve_cg(const or_mat *A, const double *d, const double *b, double *x,
-                          double bn, double tol, int max_iter, double *ws)
+                          double rs, double lim, int max_iter, double *ws)
 {
     int n = A->n, k = 0, r_true;
     double *r = ws, *z = ws + n, *p = ws + 2 * n, *t = ws + 3 * n;
-    double rho, rn, lim = tol * bn;
+    double rho, rn;
 
     rn = true_residual(A, b, x, r, t);
     r_true = 1;
@@ -134,21 +136,21 @@ restart:
     for (int i = 0; i < n; ++i) p[i] = z[i];
     rho = dot(n, r, z);
     for (;;) {
-        if (!isfinite(rn) || !isfinite(rho)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (!isfinite(rn) || !isfinite(rho)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
         if (rn <= lim) {
-            if (r_true) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            if (r_true) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
             rn = true_residual(A, b, x, r, t);
             r_true = 1;
-            if (rn <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
-            if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+            if (rn <= lim) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
+            if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
             goto restart;
         }
-        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
-        if (rho == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
+        if (rho == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
         spmv(A, p, t);                                   /* t = A p          */
         double pt = dot(n, p, t);
-        if (!isfinite(pt)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
-        if (pt == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        if (!isfinite(pt)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
+        if (pt == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
         double alpha = rho / pt;                         /* alpha = rho/(p.t) */
         for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
         for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * t[i];
@@ -165,12 +167,12 @@ restart:
 
 /* ---- BiCGSTAB, right-preconditioned (van der Vorst 1992) --------------- */
 static or_result solve_bicgstab(const or_mat *A, const double *d, const double *b, double *x,
-                                double bn, double tol, int max_iter, double *ws)
+                                double rs, double lim, int max_iter, double *ws)
 {
     int n = A->n, k = 0, r_true;
     double *r = ws, *rh = ws + n, *p = ws + 2 * n, *v = ws + 3 * n;
     double *ph = ws + 4 * n, *s = ws + 5 * n, *sh = ws + 6 * n, *t = ws + 7 * n;
-    double rho0, alpha, omega, rn, lim = tol * bn;
+    double rho0, alpha, omega, rn;
 
     rn = true_residual(A, b, x, r, t);
     r_true = 1;
@@ -178,31 +180,31 @@ restart:
     for (int i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
     rho0 = alpha = omega = 1.0;
     for (;;) {
-        if (!isfinite(rn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (!isfinite(rn)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
         if (rn <= lim) {
-            if (r_true) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
+            if (r_true) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
             rn = true_residual(A, b, x, r, t);
             r_true = 1;
-            if (rn <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
-            if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+            if (rn <= lim) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
+            if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
             goto restart;
         }
-        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+        if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
         k += 1;
         double rho = dot(n, rh, r);
-        if (!isfinite(rho)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
-        if (rho == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        if (!isfinite(rho)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
+        if (rho == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
         double beta = (rho / rho0) * (alpha / omega);
         for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
         for (int i = 0; i < n; ++i) ph[i] = d[i] * p[i];
         spmv(A, ph, v);                                  /* v = A M p        */
         double sigma = dot(n, rh, v);
-        if (!isfinite(sigma)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
-        if (sigma == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        if (!isfinite(sigma)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
+        if (sigma == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
         alpha = rho / sigma;
         for (int i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
         double sn = nrm2(n, s);
-        if (!isfinite(sn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (!isfinite(sn)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
         if (sn <= lim) {                                 /* half-step exit   */
             for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i];
             for (int i = 0; i < n; ++i) r[i] = s[i];
@@ -213,34 +215,33 @@ restart:
         for (int i = 0; i < n; ++i) sh[i] = d[i] * s[i];
         spmv(A, sh, t);                                  /* t = A M s        */
         double tt = dot(n, t, t), ts = dot(n, t, s);
-        if (!isfinite(tt) || !isfinite(ts)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+        if (!isfinite(tt) || !isfinite(ts)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
         omega = (tt == 0.0) ? 0.0 : ts / tt;
         for (int i = 0; i < n; ++i) x[i] = (x[i] + alpha * ph[i]) + omega * sh[i];
         for (int i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
         r_true = 0;
         rho0 = rho;
         rn = nrm2(n, r);
-        if (omega == 0.0 && !(rn <= lim)) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+        if (omega == 0.0 && !(rn <= lim)) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
     }
 }
 
 /* ---- GMRES(m), right-preconditioned, modified Gram-Schmidt Arnoldi and
  *      Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning) -- */
 static or_result solve_gmres(const or_mat *A, const double *d, const double *b, double *x,
-                             double bn, double tol, int max_iter, int m, double *ws)
+                             double rs, double lim, int max_iter, int m, double *ws)
 {
     int n = A->n, k = 0;
     double *r = ws, *t = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
     double *V = ws + 4 * n;                          /* (m+1) x n            */
     double *H = V + (size_t)(m + 1) * n;             /* (m+1) x m, H[i*m+j]  */
     double *cs = H + (size_t)(m + 1) * m, *sn = cs + m, *g = sn + m, *y = g + m + 1;
-    double lim = tol * bn;
 
     for (;;) {
         double beta = true_residual(A, b, x, r, t);
-        if (!isfinite(beta)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
-        if (beta <= lim) return finish(A, b, x, bn, k, OR_CONVERGED, r, t);
-        if (k >= max_iter) return finish(A, b, x, bn, k, OR_MAX_ITER, r, t);
+        if (!isfinite(beta)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
+        if (beta <= lim) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
+        if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
         for (int i = 0; i < n; ++i) V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i) g[i] = 0.0;
         g[0] = beta;
@@ -258,7 +259,7 @@ static or_result solve_gmres(const or_mat *A, const double *d, const double *b, 
             double hn = nrm2(n, w);
             H[(size_t)(j + 1) * m + j] = hn;
             k += 1;
-            if (!isfinite(hn)) return finish(A, b, x, bn, k, OR_NONFINITE, r, t);
+            if (!isfinite(hn)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
             for (int i = 0; i < j; ++i) {                /* old rotations    */
                 double h0 = H[(size_t)i * m + j], h1 = H[(size_t)(i + 1) * m + j];
                 H[(size_t)i * m + j] = cs[i] * h0 + sn[i] * h1;
@@ -266,7 +267,7 @@ static or_result solve_gmres(const or_mat *A, const double *d, const double *b, 
             }
             double hjj = H[(size_t)j * m + j];
             double dd = sqrt(hjj * hjj + hn * hn);
-            if (dd == 0.0) return finish(A, b, x, bn, k, OR_BREAKDOWN, r, t);
+            if (dd == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
             cs[j] = hjj / dd;
             sn[j] = hn / dd;
             H[(size_t)j * m + j] = dd;
@@ -299,8 +300,11 @@ static size_t workspace_doubles(int solver, int n, int m)
     return (size_t)4 * n + (size_t)(m + 1) * n + (size_t)(m + 1) * m + 4 * (size_t)m + 2 + n;
 }
 
+/* absolute: 0 tests ||r|| <= tol * ||b|| and reports ||b - A x|| / ||b||,
+ * 1 tests ||r|| <= tol and reports ||b - A x||. */
 static or_result solve_one(const or_mat *A, int solver, int precond, const double *b,
-                           double *x, double tol, int max_iter, int m, double *ws)
+                           double *x, double tol, int absolute, int max_iter, int m,
+                           double *ws)
 {
     int n = A->n;
     double *d = ws;                         /* the first n doubles hold d */
@@ -317,9 +321,10 @@ static or_result solve_one(const or_mat *A, int solver, int precond, const doubl
         return res;
     }
     jacobi_diag(A, precond, d);
-    if (solver == OR_CG) return solve_cg(A, d, b, x, bn, tol, max_iter, work);
-    if (solver == OR_BICGSTAB) return solve_bicgstab(A, d, b, x, bn, tol, max_iter, work);
-    return solve_gmres(A, d, b, x, bn, tol, max_iter, m, work);
+    double lim = absolute ? tol : tol * bn, rs = absolute ? 1.0 : bn;
+    if (solver == OR_CG) return solve_cg(A, d, b, x, rs, lim, max_iter, work);
+    if (solver == OR_BICGSTAB) return solve_bicgstab(A, d, b, x, rs, lim, max_iter, work);
+    return solve_gmres(A, d, b, x, rs, lim, max_iter, m, work);
 }
 
 static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *col,
@@ -336,8 +341,8 @@ static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *c
 int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
                    int nnz, int width, const int *ell_col, const double *values,
                    const double *b, double *x, int solver, int precond, double tol,
-                   int max_iter, int restart, int *iters, double *resid, int *status,
-                   int nthreads)
+                   int absolute, int max_iter, int restart, int *iters, double *resid,
+                   int *status, int nthreads)
 {
     size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
     int m = restart > 0 ? restart : 30;
@@ -351,7 +356,7 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
             or_mat A;
             make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
             or_result res = solve_one(&A, solver, precond, b + (size_t)s * n, x + (size_t)s * n,
-                                      tol, max_iter, m, ws);
+                                      tol, absolute, max_iter, m, ws);
             iters[s] = res.iters;
             status[s] = res.status;
             resid[s] = res.resid;

@@ -456,3 +456,54 @@ def test_status_codes(solver):
     # zero matrix -> breakdown
     x, it, res, st = O.batch_solve(P, np.zeros_like(bt.values), bt.b, solver=solver)
     assert np.all(st == O.BREAKDOWN)
+
+
+# --------------------------------------------------------------- absolute stop criterion
+# Tab. 2 lists an absolute and a relative stop criterion.  Absolute: stop when
+# ||r||_2 <= tol and report ||b - A x||_2; relative: ||r||_2 <= tol ||b||_2 and
+# report ||b - A x||_2 / ||b||_2.
+def signed_ones_batch(rng, B=24):
+    bt = W.chem_jacobian(n_batch=B, n=40, seed=11)
+    # entries +-1: ||b||^2 = n exactly, so ||b|| = sqrt(n) on both sides to the bit
+    b = np.where(rng.random(bt.b.shape) < 0.5, -1.0, 1.0)
+    return O.Pattern(bt.n, bt.row_ptr, bt.col_idx), bt, b
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_absolute_equals_relative_at_scaled_tol(solver):
+    rng = np.random.default_rng(3)
+    P, bt, b = signed_ones_batch(rng)
+    tol = 1e-9
+    rel = O.batch_solve(P, bt.values, b, solver=solver, tol=tol, max_iter=60)
+    ab = O.batch_solve(P, bt.values, b, solver=solver, tol=tol * math.sqrt(bt.n), max_iter=60,
+                       absolute=True)
+    for u, v in zip(rel[:2] + rel[3:], ab[:2] + ab[3:]):     # x, iters, status
+        assert np.array_equal(u, v)
+    assert np.allclose(ab[2], rel[2] * math.sqrt(bt.n), rtol=4 * EPS, atol=0)
+
+
+@pytest.mark.parametrize("solver", [O.BICGSTAB, O.GMRES])
+def test_absolute_criterion_follows_the_scale_of_b(solver):
+    """Scaling b by 2^10 scales every iterate exactly: the relative criterion
+    takes the same steps, the absolute one (same tol) needs more, and its
+    converged x meet ||b - A x|| <= tol by an independent dense evaluation."""
+    bt = W.chem_jacobian(n_batch=16, n=54, seed=2)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    tol = 1e-9
+    b2 = bt.b * 1024.0
+    r1 = O.batch_solve(P, bt.values, bt.b, solver=solver, tol=tol)
+    r2 = O.batch_solve(P, bt.values, b2, solver=solver, tol=tol)
+    assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[0] * 1024.0, r2[0])
+    a1 = O.batch_solve(P, bt.values, bt.b, solver=solver, tol=tol, absolute=True)
+    a2 = O.batch_solve(P, bt.values, b2, solver=solver, tol=tol, absolute=True)
+    assert np.all(a2[1] >= a1[1]) and np.sum(a2[1]) > np.sum(a1[1])
+    w = int(np.diff(bt.row_ptr).max())
+    for (x, it, res, st), bb in ((a1, bt.b), (a2, b2)):
+        assert np.all(st == O.CONVERGED)
+        for s in range(bt.n_batch):
+            A = O.to_dense(P, bt.values[s])
+            tr = np.linalg.norm(bb[s] - A @ x[s])
+            # both sides round b - A x within (w+2) eps (|b| + |A||x|) per component
+            bound = 2 * (w + 2) * EPS * (np.linalg.norm(bb[s]) + np.linalg.norm(np.abs(A) @ np.abs(x[s])))
+            assert res[s] <= tol and tr <= tol + bound
+            assert abs(res[s] - tr) <= bound
