@@ -32,8 +32,10 @@ extern "C" {
  * values [n_batch][nnz] in CSR order.  BS_ELL: rows padded to the width W of
  * the longest row, shared slot-major column array [W][n] (the paper's
  * "column-major" layout; slot s of row i at s*n + i, padding = -1); values
- * [n_batch][W][n] in the same layout, padding values ignored. */
-typedef enum { BS_CSR = 0, BS_ELL = 1 } bs_format;
+ * [n_batch][W][n] in the same layout, padding values ignored.  BS_DENSE
+ * (BatchDense): every entry stored, values [n_batch][n][n] row-major, solved on
+ * the full pattern of bs_pattern_create_dense. */
+typedef enum { BS_CSR = 0, BS_ELL = 1, BS_DENSE = 2 } bs_format;
 
 /* Solvers of Tab. 2.  BS_CG follows Sec. 3.5, Alg. 1 (stop test replaced by the
  * relative residual); BS_BICGSTAB is right-preconditioned BiCGSTAB; BS_GMRES is
@@ -54,7 +56,7 @@ typedef enum { BS_FP64 = 0, BS_MIXED = 1 } bs_precision;
 
 /* Per-system outcome written to status[]. */
 enum {
-  BS_CONVERGED = 0, /* true relative residual <= tol                          */
+  BS_CONVERGED = 0, /* true relative (or absolute) residual <= tol            */
   BS_MAX_ITER = 1,  /* iteration budget used up                               */
   BS_BREAKDOWN = 2, /* an exact zero divisor (rho, sigma, omega, p.Ap, Givens) */
   BS_NONFINITE = 3  /* a NaN or Inf appeared (input or arithmetic)             */
@@ -71,6 +73,9 @@ typedef enum {
 
 /* Flags for bs_options.flags. */
 #define BS_FLAG_X0_ZERO 1 /* ignore x on entry and start from x0 = 0 (x is not read) */
+#define BS_FLAG_ABS_TOL 4 /* absolute stop criterion (Tab. 2): converged when
+                             ||b - A x||_2 <= tol instead of tol * ||b||_2, and
+                             resid[] reports ||b - A x||_2 itself */
 #define BS_FLAG_PLAIN_LAYOUT 2 /* one-wave teams: lane i owns row i, x_i at buffer
                                   element i, CSR windows at min(row start, nnz - slots)
                                   (the pattern's bank-aware layout is not used) */
@@ -140,6 +145,15 @@ int bs_wave_layout(int32_t n_rows, int32_t nnz, const int32_t *row_ptr, const in
  * receives lane_row[64] | lane_win[64] | col_pos[n_rows] (HOST memory). */
 int bs_pattern_layout(bs_pattern pattern, int32_t *slots, int32_t *layout);
 
+/* The full pattern of n_rows x n_rows entries, for BatchDense values (Sec. 3.1,
+ * Tab. 2): a dense batch stores every entry of every matrix, [n_batch][n][n]
+ * row-major, which is the CSR order of this pattern; bs_batch_solve with
+ * BS_DENSE runs the BatchCsr kernels on it.  Rows longer than BS_MAX_ROW_NNZ
+ * (n_rows > 64) cannot be solved (BS_ERR_UNSUPPORTED at solve time).
+ * Errors: BS_ERR_INVALID_ARG (NULL out, n_rows < 1, n_rows^2 beyond int32),
+ * BS_ERR_NO_DEVICE / BS_ERR_HIP on upload. */
+int bs_pattern_create_dense(int32_t n_rows, bs_pattern *out);
+
 /* Copy the ELL slot-major column array [ell_width][n_rows] to HOST memory. */
 int bs_pattern_ell_cols(bs_pattern pattern, int32_t *ell_col_out);
 
@@ -150,7 +164,7 @@ int bs_values_csr_to_ell(bs_pattern pattern, int64_t n_batch, const double *csr_
 
 /* Number of stored values and indexes of a batched matrix (Sec. 3.1 storage
  * list): CSR n_batch*nnz values + (n_rows+1)+nnz indexes; ELL n_batch*W*n values
- * + W*n indexes.  Pure host function. */
+ * + W*n indexes; dense n_batch*n*n values, no indexes.  Pure host function. */
 int bs_matrix_storage(bs_format fmt, int64_t n_batch, int32_t n_rows, int32_t nnz,
                       int32_t ell_width, int64_t *value_count, int64_t *index_count);
 
@@ -175,17 +189,20 @@ typedef struct {
 /* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch
  * systems, each by one team of lanes (a sub-wave, a wave or a workgroup).
  *   fmt, pattern   format of `values` and the shared pattern (its n must equal n_rows)
- *   values         device, CSR [n_batch][nnz] or ELL [n_batch][W][n_rows]
+ *   values         device, CSR [n_batch][nnz], ELL [n_batch][W][n_rows] or dense
+ *                  [n_batch][n_rows][n_rows] (BS_DENSE needs the full pattern,
+ *                  BS_ERR_PATTERN otherwise)
  *   b              device [n_batch][n_rows]
  *   x              device [n_batch][n_rows]; in: initial guess (unless
  *                  BS_FLAG_X0_ZERO), out: the last iterate
- *   tol            relative tolerance: stop when ||b - A x||_2 <= tol ||b||_2,
- *                  confirmed on the true residual; tol > 0 and finite
+ *   tol            relative tolerance: stop when ||b - A x||_2 <= tol ||b||_2
+ *                  (with BS_FLAG_ABS_TOL: <= tol), confirmed on the true
+ *                  residual; tol > 0 and finite
  *   max_iter       >= 0; CG/BiCGSTAB iterations, GMRES Arnoldi steps (BS_MIXED:
  *                  inner iterations summed over refinement steps)
  *   iters, resid,  device int32/FP64/int32 [n_batch]: iterations, true relative
- *   status         residual of the returned x (absolute when ||b|| = 0), and the
- *                  bs status code; status may be NULL
+ *   status         residual of the returned x (absolute when ||b|| = 0 or with
+ *                  BS_FLAG_ABS_TOL), and the bs status code; status may be NULL
  *   opts           NULL for defaults
  * Errors: BS_ERR_INVALID_ARG (n_batch < 0, n_rows mismatch, bad enum, tol <= 0 or
  * non-finite, max_iter < 0, bad restart/team, NULL required pointer),

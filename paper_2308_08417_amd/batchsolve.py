@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbatchsolve.so")
 
 # enums of batchsolve.h
-CSR, ELL = 0, 1
+CSR, ELL, DENSE = 0, 1, 2
 CG, BICGSTAB, GMRES = 0, 1, 2
 PREC_NONE, PREC_JACOBI = 0, 1
 FP64, MIXED = 0, 1
@@ -26,6 +26,7 @@ CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_PATTERN, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_DEVICE = 0, -1, -2, -3, -4, -5
 FLAG_X0_ZERO = 1
 FLAG_PLAIN_LAYOUT = 2
+FLAG_ABS_TOL = 4
 MAX_ROWS, MAX_ROW_NNZ, MAX_RESTART = 2048, 64, 30
 
 
@@ -66,6 +67,7 @@ def lib() -> C.CDLL:
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.bs_pattern_create_csr.argtypes = [i32, i32, vp, vp, C.POINTER(vp)]
     L.bs_pattern_create_ell.argtypes = [i32, i32, vp, C.POINTER(vp)]
+    L.bs_pattern_create_dense.argtypes = [i32, C.POINTER(vp)]
     L.bs_pattern_destroy.argtypes = [vp]
     L.bs_pattern_query.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.bs_pattern_ell_cols.argtypes = [vp, vp]
@@ -106,7 +108,8 @@ def lib() -> C.CDLL:
     L.bs_error_string.restype = C.c_char_p
     L.bs_last_error.argtypes = []
     L.bs_last_error.restype = C.c_char_p
-    for name in ("bs_pattern_create_csr", "bs_pattern_create_ell", "bs_pattern_destroy",
+    for name in ("bs_pattern_create_csr", "bs_pattern_create_ell", "bs_pattern_create_dense",
+                 "bs_pattern_destroy",
                  "bs_pattern_query", "bs_pattern_ell_cols", "bs_wave_layout",
                  "bs_pattern_layout", "bs_values_csr_to_ell",
                  "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_varbatch_create",
@@ -163,6 +166,12 @@ def bs_pattern_create_csr(row_ptr, col_idx) -> int:
     _check(lib().bs_pattern_create_csr(rp.size - 1, ci.size, rp.ctypes.data,
                                        ci.ctypes.data if ci.size else None, C.byref(h)),
            "bs_pattern_create_csr")
+    return h.value
+
+
+def bs_pattern_create_dense(n_rows: int) -> int:
+    h = C.c_void_p()
+    _check(lib().bs_pattern_create_dense(n_rows, C.byref(h)), "bs_pattern_create_dense")
     return h.value
 
 
@@ -281,6 +290,12 @@ class Pattern:
     @classmethod
     def from_csr(cls, row_ptr, col_idx) -> "Pattern":
         h = bs_pattern_create_csr(row_ptr, col_idx)
+        return cls(h, **bs_pattern_query(h))
+
+    @classmethod
+    def dense(cls, n_rows: int) -> "Pattern":
+        """The full pattern, for BatchDense values ``[B][n][n]`` (``DENSE``)."""
+        h = bs_pattern_create_dense(n_rows)
         return cls(h, **bs_pattern_query(h))
 
     @classmethod

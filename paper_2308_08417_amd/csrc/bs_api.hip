@@ -311,6 +311,17 @@ int bs_pattern_create_csr(int32_t n_rows, int32_t nnz, const int32_t* row_ptr,
   return BS_OK;
 }
 
+int bs_pattern_create_dense(int32_t n_rows, bs_pattern* out) {
+  if (!out || n_rows < 1 || n_rows > 46340) return BS_ERR_INVALID_ARG;
+  *out = nullptr;
+  const int n = n_rows;
+  std::vector<int32_t> rp(n + 1), col((size_t)n * n);
+  for (int i = 0; i <= n; ++i) rp[i] = i * n;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) col[(size_t)i * n + j] = j;
+  return bs_pattern_create_csr(n, n * n, rp.data(), col.data(), out);
+}
+
 int bs_pattern_create_ell(int32_t n_rows, int32_t ell_width, const int32_t* ell_col,
                           bs_pattern* out) {
   if (!out || n_rows < 1 || ell_width < 0 || (ell_width > 0 && !ell_col))
@@ -435,6 +446,9 @@ int bs_matrix_storage(bs_format fmt, int64_t n_batch, int32_t n_rows, int32_t nn
   if (fmt == BS_CSR) {
     *value_count = n_batch * (int64_t)nnz;
     *index_count = (int64_t)n_rows + 1 + nnz;
+  } else if (fmt == BS_DENSE) {
+    *value_count = n_batch * (int64_t)n_rows * n_rows;
+    *index_count = 0;
   } else if (fmt == BS_ELL) {
     *value_count = n_batch * (int64_t)ell_width * n_rows;
     *index_count = (int64_t)ell_width * n_rows;
@@ -446,9 +460,15 @@ int bs_matrix_storage(bs_format fmt, int64_t n_batch, int32_t n_rows, int32_t nn
 
 int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_solver solver,
             const bs_options* opts, bs_plan_info* out) {
-  if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 || (fmt != BS_CSR && fmt != BS_ELL) ||
+  if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 ||
+      (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) ||
       (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES))
     return BS_ERR_INVALID_ARG;
+  if (fmt == BS_DENSE) {  // the full pattern in CSR order
+    nnz = n_rows * n_rows;
+    max_row_nnz = n_rows;
+    fmt = BS_CSR;
+  }
   Plan pl;
   const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, &pl);
   if (rc == BS_OK) *out = pl.info;
@@ -460,7 +480,12 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
                    bs_precond precond, double tol, int32_t max_iter, int32_t* iters,
                    double* resid, int32_t* status, const bs_options* opts, void* stream) {
   if (!pattern || n_batch < 0 || n_rows != pattern->n) return BS_ERR_INVALID_ARG;
-  if (fmt != BS_CSR && fmt != BS_ELL) return BS_ERR_INVALID_ARG;
+  if (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) return BS_ERR_INVALID_ARG;
+  // BatchDense: row-major [n][n] values are the CSR values of the full pattern
+  if (fmt == BS_DENSE) {
+    if ((int64_t)pattern->nnz != (int64_t)pattern->n * pattern->n) return BS_ERR_PATTERN;
+    fmt = BS_CSR;
+  }
   if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_INVALID_ARG;
   if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI) return BS_ERR_INVALID_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;

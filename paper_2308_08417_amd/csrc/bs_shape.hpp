@@ -50,6 +50,9 @@ struct KArgs {
   const int* layout;           // one-wave teams: lane_row[64] | lane_win[64] | col_pos[n], or null
 };
 
+// Flag bit of the absolute stop criterion (BS_FLAG_ABS_TOL).
+constexpr int kFlagAbsTol = 4;
+
 // team: lanes per system; R: rows per lane; NZ: register slots per row.
 template <int TEAM_, int R_, int NZ_>
 struct Shape {

@@ -22,6 +22,12 @@ namespace bs {
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// Stop level on ||r||_2 (Tab. 2): tol * ||b||_2 (relative) or tol (absolute).
+template <class G>
+__device__ __forceinline__ double stop_limit(const G& g, double bn) {
+  return (g.flags & kFlagAbsTol) ? g.tol : g.tol * bn;
+}
+
 // Shared epilogue: true residual for teams that do not have it, then outputs.
 template <class TM, class RW>
 __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
@@ -44,7 +50,8 @@ __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
     if (A.ok[r]) g.x[tm.row0 + A.row[r]] = x[r];
   if (tm.lane == 0) {
     g.iters[tm.sys] = k;
-    g.resid[tm.sys] = !finite(bn) ? bn : (bn == 0.0 ? rn : rn / bn);
+    // the true residual, relative to ||b|| unless the criterion is absolute
+    g.resid[tm.sys] = !finite(bn) ? bn : ((bn == 0.0 || (g.flags & kFlagAbsTol)) ? rn : rn / bn);
     // always one store (to the sink when no status is wanted): the persistent
     // loop counts on a fixed number of stores after each prefetch
     *(g.status ? g.status + tm.sys : g.sink) = st;
@@ -146,7 +153,7 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
   }
   const double bn = sqrt(q2[0]);
   double rn = sqrt(q2[1]);  // FP64 norm of the outer (or only) residual
-  const double lim = g.tol * bn;
+  const double lim = stop_limit(g, bn);
   int st = tm.live ? ST_RUNNING : ST_IDLE;
   bool rtrue = true;
   if (st == ST_RUNNING) {
@@ -392,7 +399,7 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
   const double bn = sqrt(q3[0]);
   double rn = sqrt(q3[1]), rho = q3[2];
   double rsq = q3[1];  // squared recurrence residual (the loop compares squares)
-  const double lim = g.tol * bn, lim2 = lim * lim;
+  const double lim = stop_limit(g, bn), lim2 = lim * lim;
   int st = tm.live ? ST_RUNNING : ST_IDLE;
   if (st == ST_RUNNING) {
     if (!finite(bn)) st = ST_NONFINITE;
@@ -539,7 +546,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   }
   tm.sum(q1);
   const double bn = sqrt(q1[0]);
-  const double lim = g.tol * bn;
+  const double lim = stop_limit(g, bn);
   int st = tm.live ? ST_RUNNING : ST_IDLE;
   double rn = 0.0;
   if (st == ST_RUNNING) {

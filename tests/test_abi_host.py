@@ -1,6 +1,7 @@
 """Host-side tests of the C ABI: the library loads, exports every declared entry
 point, and its pure host logic (pattern validation, storage counts, planner,
 error strings) behaves as documented.  No kernel is launched."""
+import ctypes as C
 import json
 import os
 import re
@@ -213,3 +214,20 @@ def test_varbatch_generator_layout():
         rp = vb.rowptr_all[vb.pat_rowptr_off[p]: vb.pat_rowptr_off[p] + n + 1]
         assert vb.val_off[s + 1] - vb.val_off[s] == rp[-1]
         assert np.diff(rp).max() <= 9
+
+
+def test_dense_format_host(L):
+    """BatchDense (Sec. 3.1 storage list, Tab. 2): n^2 values per matrix and no
+    indexes; planned as the full pattern in CSR order; rows over 64 entries
+    cannot be held in registers."""
+    assert bs.bs_matrix_storage(bs.DENSE, 1000, 54, 0, 0) == (1000 * 54 * 54, 0)
+    p = bs.bs_plan(bs.DENSE, 54, 0, 0, bs.BICGSTAB)
+    assert p["team"] == 64 and p["slots"] == 64
+    p = bs.bs_plan(bs.DENSE, 16, 0, 0, bs.GMRES)
+    assert p["team"] == 16 and p["slots"] >= 16
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_plan(bs.DENSE, 65, 0, 0, bs.CG)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    h = C.c_void_p()
+    assert L.bs_pattern_create_dense(0, C.byref(h)) == bs.ERR_INVALID_ARG
+    assert L.bs_pattern_create_dense(8, None) == bs.ERR_INVALID_ARG

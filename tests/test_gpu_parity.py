@@ -407,3 +407,104 @@ def test_chem_jacobian_full_size_sampled():
         err = np.linalg.norm(xg - o[0], axis=1) / np.linalg.norm(o[0], axis=1)
         assert np.all(err <= XTOL)
         assert np.all(np.abs(g[1][idx] - o[1]) <= ITOL)
+
+
+# ------------------------------------------------------------------ Tab. 2 completions
+def dense_batch(n, B, seed, spd=False):
+    """Dense diagonally dominant systems: off-diagonals U(-1, 1) (symmetric for
+    spd), diagonal 1 + sum of the row's |off-diagonal|; b ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    M = 2 * rng.random((B, n, n)) - 1
+    if spd:
+        M = np.triu(M, 1)
+        M = M + np.transpose(M, (0, 2, 1))
+    idx = np.arange(n)
+    M[:, idx, idx] = 0.0
+    M[:, idx, idx] = 1 + np.abs(M).sum(axis=2)
+    b = 2 * rng.random((B, n)) - 1
+    rp = (np.arange(n + 1) * n).astype(np.int32)
+    ci = np.tile(np.arange(n, dtype=np.int32), n)
+    return W.Batch("dense", n, rp, ci, np.ascontiguousarray(M.reshape(B, n * n)), b, np.zeros_like(b))
+
+
+@pytest.mark.parametrize("n", [16, 40, 64])
+@pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB, bs.GMRES])
+def test_batch_dense(n, solver):
+    """BatchDense: [B][n][n] row-major values on the full pattern; the oracle
+    solves the same numbers as CSR over the full pattern (the dense product)."""
+    bt = dense_batch(n, 300, seed=n, spd=(solver == bs.CG))
+    c = Case(bt)
+    P = bs.Pattern.dense(n)
+    assert P.nnz == n * n and P.max_row_nnz == n
+    vals = dev(bt.values)
+    say(f"  dense n={n} solver={solver}")
+    B = bt.n_batch
+    x = torch.zeros((B, n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    bs.bs_batch_solve(bs.DENSE, P.handle, vals, dev(bt.b), x, solver, bs.PREC_JACOBI, 1e-10, 500,
+                      it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO))
+    torch.cuda.synchronize()
+    g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    o = c.oracle(bs.CSR, solver)
+    check(c, g, o)
+    # a dense batch needs the full pattern
+    tri = W.tridiag_stencil(1, n=n)
+    Pt = bs.Pattern.from_csr(tri.row_ptr, tri.col_idx)
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_batch_solve(bs.DENSE, Pt.handle, vals, dev(bt.b), x, solver, bs.PREC_JACOBI, 1e-10,
+                          500, it, rs, st)
+    assert e.value.code == bs.ERR_PATTERN
+
+
+def check_absolute(case, g, o, tol, b, itol=ITOL, fmt=bs.CSR):
+    xg, ig, rg, sg = g
+    xo, io, ro, so = o
+    assert np.array_equal(sg, so)
+    conv = so == O.CONVERGED
+    v = case.oracle_values(fmt)
+    ofmt = O.CSR if fmt == bs.CSR else O.ELL
+    r = b - O.batch_spmv(case.OP, v, xg, fmt=ofmt)
+    rt = np.linalg.norm(r, axis=1)
+    absAx = O.batch_spmv(case.OP, np.abs(v), np.abs(xg), fmt=ofmt)
+    w = int(np.diff(case.batch.row_ptr).max())
+    bound = 2 * (w + 2) * np.finfo(float).eps * (np.linalg.norm(b, axis=1) + np.linalg.norm(absAx, axis=1))
+    assert np.all(rt[conv] <= tol + bound[conv]) and np.all(rg[conv] <= tol)
+    assert np.all(np.abs(rg - rt) <= bound + 1e-12 * rt)
+    nx = np.linalg.norm(xo, axis=1)
+    err = np.linalg.norm(xg - xo, axis=1) / np.where(nx > 0, nx, 1.0)
+    assert np.all(err[conv] <= XTOL)
+    assert np.all(np.abs(ig.astype(np.int64) - io) <= itol)
+
+
+@pytest.mark.parametrize("solver,prec", [(bs.BICGSTAB, bs.FP64), (bs.GMRES, bs.FP64),
+                                         (bs.BICGSTAB, bs.MIXED), (bs.GMRES, bs.MIXED)])
+def test_absolute_criterion(solver, prec):
+    """Absolute stop criterion (Tab. 2): b scaled by 2^10 so that it stops
+    later than the relative one; GPU against the oracle's absolute solve."""
+    bt = W.chem_jacobian(n_batch=2000, n=54, seed=4)
+    c = Case(bt)
+    b = bt.b * 1024.0
+    tol = 1e-8
+    g = c.gpu(bs.CSR, solver, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL, precision=prec)
+    o = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=SOLVER_O[solver], tol=tol,
+                      max_iter=500, absolute=True)
+    rel = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=SOLVER_O[solver], tol=tol,
+                        max_iter=500)
+    assert o[1].sum() > rel[1].sum()
+    check_absolute(c, g, o, tol, b, itol=ITOL if prec == bs.FP64 else 10**9)
+
+
+def test_absolute_criterion_cg_and_ell():
+    bt = W.tridiag_stencil(n_batch=500, n=48)
+    c = Case(bt)
+    b = bt.b * 4096.0
+    tol = 1e-9
+    o = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=O.CG, tol=tol, absolute=True)
+    g = c.gpu(bs.CSR, bs.CG, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL)
+    check_absolute(c, g, o, tol, b)
+    oe = O.batch_solve(c.OP, c.oracle_values(bs.ELL), b, fmt=O.ELL, solver=O.BICGSTAB, tol=tol,
+                       absolute=True)
+    ge = c.gpu(bs.ELL, bs.BICGSTAB, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL)
+    check_absolute(c, ge, oe, tol, b, fmt=bs.ELL)

@@ -118,6 +118,31 @@ class VCase:
             check(case, gg, o, tol=tol, itol=itol)
 
 
+def test_absolute_criterion_uneven():
+    """Absolute stop criterion (Tab. 2) in the uneven path: b scaled by 2^10;
+    the oracle solves each pattern's systems with the absolute criterion."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_gpu_parity import check_absolute
+    c = VCase(W.uneven_banded(300, 16, 1024, seed=7))
+    b = c.vb.b * 1024.0
+    tol = 1e-8
+    x, it, rs, st = c.outputs()
+    bs.bs_varbatch_solve(c.h.handle, c.dv, dev(b), x, bs.BICGSTAB, bs.PREC_JACOBI, tol, 1000, it,
+                         rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO | bs.FLAG_ABS_TOL))
+    torch.cuda.synchronize()
+    xg, ig, rg, sg = x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
+    assert np.all(sg == bs.CONVERGED)
+    for sys_, n, rp, ci, rows, vals in c.groups():
+        OP = O.Pattern(n, rp, ci)
+        v = c.values[vals].reshape(sys_.size, -1)
+        bb = b[rows].reshape(sys_.size, n)
+        o = O.batch_solve(OP, v, bb, solver=O.BICGSTAB, tol=tol, max_iter=1000, absolute=True)
+        case = SimpleNamespace(batch=SimpleNamespace(b=bb, row_ptr=rp), OP=OP,
+                               oracle_values=lambda fmt, v=v: v)
+        gg = (xg[rows].reshape(sys_.size, n), ig[sys_], rg[sys_], sg[sys_])
+        check_absolute(case, gg, o, tol, bb)
+
+
 def test_bicgstab_mixed_sizes():
     """Every team size 64..1024 in one launch (n from 16 to 1024)."""
     c = VCase(W.uneven_banded(400, 16, 1024, seed=1))
