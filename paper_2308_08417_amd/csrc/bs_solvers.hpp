@@ -570,6 +570,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   };
 
   int k = 0, j = 0, cycles = 0;
+  T vcur = (T)0;       // the basis vector the next Arnoldi step multiplies
   double gcur = 0.0;   // g_j, the entry the next rotation acts on
   double ilim = lim;   // the cycle's stopping level for |g|
   double beta_prev = INFINITY;
@@ -593,8 +594,9 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
         else if (k >= g.max_iter) st = ST_MAX_ITER;
         else if (MIXED && !(beta < beta_prev)) st = ST_BREAKDOWN;
         else {
-          if constexpr (NL > 0) lds_store<T>(vb, (T)(rc / beta));
-          else V[0] = (T)(rc / beta);
+          vcur = (T)(rc / beta);
+          if constexpr (NL > 0) lds_store<T>(vb, vcur);
+          else V[0] = vcur;
           gcur = beta;
           if constexpr (MIXED) ilim = fmax(g.inner_tol * beta, 0.5 * lim);
           beta_prev = beta;
@@ -607,14 +609,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!tm.any(st == ST_RUNNING)) break;
     // ---- one Arnoldi step for every running team (all of them are mid-cycle)
     const bool act = st == ST_RUNNING;
-    T vj = (T)0;
-    if constexpr (NL > 0) {
-      if (j < NL) vj = lds_load<T>(vb + (unsigned)j * vstride);  // one team per group: j uniform
-    }
-#pragma unroll
-    for (int i = NL; i < M; ++i)
-      if (j == i) vj = V[i - NL];
-    T z[1] = {dT * vj}, w[1];
+    T z[1] = {dT * vcur}, w[1];
     A.template spmv<0>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
     if constexpr (RW::TEAM >= 64) {
@@ -667,13 +662,29 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
         st = ST_NONFINITE;
       } else {
         // apply the previous rotations to column j
-        double hp = hcol[0];
+        double hp;
         const int cj = j * (j + 1) / 2;
-        for (int i = 0; i < j; ++i) {
-          const double hnx = hcol[i + 1];
-          const double c = cs[i], s = sn[i];
-          Rt[cj + i] = c * hp + s * hnx;
-          hp = -s * hp + c * hnx;
+        if constexpr (RW::TEAM >= 64) {
+          // column j and the rotations are loaded one entry per lane (every
+          // wave holds a copy): the chain reads them with readlane, not LDS loads
+          const int ju = __builtin_amdgcn_readfirstlane(j);
+          const int l = (int)lane_id();
+          const double hreg = l <= ju ? hcol[l] : 0.0;
+          const double creg = l < ju ? cs[l] : 0.0, sreg = l < ju ? sn[l] : 0.0;
+          hp = rdlane(hreg, 0);
+          for (int i = 0; i < ju; ++i) {
+            const double hnx = rdlane(hreg, i + 1), c = rdlane(creg, i), s = rdlane(sreg, i);
+            Rt[cj + i] = c * hp + s * hnx;
+            hp = -s * hp + c * hnx;
+          }
+        } else {
+          hp = hcol[0];
+          for (int i = 0; i < j; ++i) {
+            const double hnx = hcol[i + 1];
+            const double c = cs[i], s = sn[i];
+            Rt[cj + i] = c * hp + s * hnx;
+            hp = -s * hp + c * hnx;
+          }
         }
         const double dd = sqrt(hp * hp + hn * hn);
         if (dd == 0.0) {
@@ -688,12 +699,15 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
           end = fabs(gcur) <= ilim || hn == 0.0 || k >= g.max_iter || j == m - 1;
           if (!end) {
             const T vn = (T)((double)w[0] / hn);
+            vcur = vn;
             if constexpr (NL > 0) {
               if (j + 1 < NL) lds_store<T>(vb + (unsigned)(j + 1) * vstride, vn);
             }
+            // teams of a wave or more: j is the same in every lane
+            const int jn = RW::TEAM >= 64 ? __builtin_amdgcn_readfirstlane(j + 1) : j + 1;
 #pragma unroll
             for (int i = (NL > 1 ? NL : 1); i <= M; ++i)
-              if (j + 1 == i) V[i - NL] = vn;
+              if (jn == i) V[i - NL] = vn;
             j += 1;
           }
         }
@@ -703,15 +717,33 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (tm.any(end)) {
       const int jend = wave_max(end ? j : -1);
       double zacc = 0.0;
+      if constexpr (RW::TEAM >= 64) {
+        // column by column: lane l keeps g_l minus the known terms of row l;
+        // y_i = (that of lane i) / R_ii, then the rows above drop R_li y_i
+        if (end) {
+          const int je = __builtin_amdgcn_readfirstlane(j);
+          const int l = (int)lane_id();
+          double acc = l <= je ? gv[l] : 0.0;
 #pragma unroll
-      for (int i = M - 1; i >= 0; --i) {
-        if (i <= jend) {
-          if (end && i <= j) {
-            double acc = gv[i];
-            for (int l = i + 1; l <= j; ++l) acc = fma(-Rt[l * (l + 1) / 2 + i], yv[l], acc);
-            const double yi = acc / Rt[i * (i + 1) / 2 + i];
-            yv[i] = yi;
-            zacc = fma(yi, (double)basis(i), zacc);
+          for (int i = M - 1; i >= 0; --i) {
+            if (i <= je) {
+              const double yi = rdlane(acc, i) / Rt[i * (i + 1) / 2 + i];
+              if (l < i) acc = fma(-Rt[i * (i + 1) / 2 + l], yi, acc);
+              zacc = fma(yi, (double)basis(i), zacc);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+          if (i <= jend) {
+            if (end && i <= j) {
+              double acc = gv[i];
+              for (int l = i + 1; l <= j; ++l) acc = fma(-Rt[l * (l + 1) / 2 + i], yv[l], acc);
+              const double yi = acc / Rt[i * (i + 1) / 2 + i];
+              yv[i] = yi;
+              zacc = fma(yi, (double)basis(i), zacc);
+            }
           }
         }
       }
