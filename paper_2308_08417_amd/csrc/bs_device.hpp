@@ -544,10 +544,14 @@ struct Rows {
   // y = A v.  v is written to the team's vector buffer BUF, the team syncs, and
   // each lane gathers its rows' columns from LDS.  T is the arithmetic type;
   // the buffer always spaces elements 8 bytes apart.  The gathers go out in
-  // groups of kGather (an empty asm that the group's FMAs feed keeps the next
-  // group's gathers behind them, bounding the registers held by loads in
-  // flight); four partial sums per row keep the FMA chains short.
-  template <int BUF, class T, class AT>
+  // groups of kGather, one or two groups in flight (an empty asm that a group's
+  // FMAs feed keeps later groups behind them, bounding the registers held by
+  // loads in flight); four partial sums per row keep the FMA chains short.
+  // Shapes with room in their register budget keep two gather groups in
+  // flight; the others one.
+  static constexpr bool kPipe = S::R == 1 && S::NZ <= 28;
+
+  template <int BUF, bool PIPE = kPipe, class T, class AT>
   __device__ __forceinline__ void spmv(Team<S>& tm, const AT (&av)[S::R][S::NZ],
                                        const T (&v)[S::R], T (&y)[S::R]) const {
     constexpr int kGather = BS_GATHER;
@@ -560,16 +564,37 @@ struct Rows {
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
       T acc[4] = {0, 0, 0, 0};
+      if constexpr (PIPE) {
+        // two groups in flight: the next group's gathers are issued before
+        // this group's FMAs, so their LDS latency overlaps the arithmetic
+        T xa[kGather], xb[kGather] = {};
 #pragma unroll
-      for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
-        T xv[kGather];
+        for (int k = 0; k < kGather && k < S::NZ; ++k) xa[k] = lds_load<T>(c[r][k] + off);
 #pragma unroll
-        for (int k = k0; k < k0 + kGather && k < S::NZ; ++k) xv[k - k0] = lds_load<T>(c[r][k] + off);
+        for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
+          const int k1 = k0 + kGather;
 #pragma unroll
-        for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
-          acc[k % NA] = fma((T)av[r][k], xv[k - k0], acc[k % NA]);
-        // finish this group's FMAs before the next group's gathers are issued
-        __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+          for (int k = k1; k < k1 + kGather && k < S::NZ; ++k) xb[k - k1] = lds_load<T>(c[r][k] + off);
+#pragma unroll
+          for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
+            acc[k % NA] = fma((T)av[r][k], xa[k - k0], acc[k % NA]);
+          // the group after next is issued only after this group's FMAs
+          __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+#pragma unroll
+          for (int k = 0; k < kGather; ++k) xa[k] = xb[k];
+        }
+      } else {
+#pragma unroll
+        for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
+          T xv[kGather];
+#pragma unroll
+          for (int k = k0; k < k0 + kGather && k < S::NZ; ++k) xv[k - k0] = lds_load<T>(c[r][k] + off);
+#pragma unroll
+          for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
+            acc[k % NA] = fma((T)av[r][k], xv[k - k0], acc[k % NA]);
+          // finish this group's FMAs before the next group's gathers are issued
+          __asm__ volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])::"memory");
+        }
       }
       T s = acc[0];
       if constexpr (NA == 4) s = (acc[0] + acc[1]) + (acc[2] + acc[3]);

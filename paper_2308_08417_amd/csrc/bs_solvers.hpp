@@ -582,7 +582,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (tm.any(st == ST_RUNNING && start)) {
       const bool me = st == ST_RUNNING && start;
       double t[1];
-      A.template spmv<0>(tm, A.a, P.x, t);
+      A.template spmv<0, false>(tm, A.a, P.x, t);
       const double rc = P.b[0] - t[0];
       double q[1] = {rc * rc};
       tm.sum(q);
@@ -610,7 +610,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     // ---- one Arnoldi step for every running team (all of them are mid-cycle)
     const bool act = st == ST_RUNNING;
     T z[1] = {dT * vcur}, w[1];
-    A.template spmv<0>(tm, a_in, z, w);
+    A.template spmv<0, false>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
     if constexpr (RW::TEAM >= 64) {
       // Block Gram-Schmidt: blocks of four basis vectors taken in order, as
