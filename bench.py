@@ -9,7 +9,8 @@ residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
 forms of the same batch, the uneven batch (100k banded systems with n in
 [16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
-stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the learned
+stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the chemistry
+matrices stored as BatchDense (relative and absolute stop criteria), the learned
 warm start along a drifting sequence (mixed precision from the network's
 guess vs the plain FP64 solve), the HBM roofline of the solver kernel, and
 the CPU oracle's throughput on the host cores.
@@ -113,6 +114,51 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                      "max_resid": float(rs.max())}
+    del vals, b, x
+    return out
+
+
+def dense_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """BatchDense: the chemistry matrices (n = 54) stored densely, [B][54][54]
+    row-major, every entry (zeros included), BiCGSTAB + Jacobi to 1e-10 from
+    x0 = 0, relative and absolute stop criteria; the same systems as the
+    headline batch's first ``args.dense_batch``."""
+    bt = W.chem_jacobian(n_batch=args.dense_batch, n=54, fill=0.35, gamma=1e-6, seed=0)
+    B, n = bt.n_batch, bt.n
+    rows = np.repeat(np.arange(n), np.diff(bt.row_ptr))
+    dense = np.zeros((B, n, n))
+    dense[:, rows, bt.col_idx] = bt.values
+    P = bs.Pattern.dense(n)
+    vals = torch.from_numpy(dense.reshape(B, n * n)).to(dev)
+    del dense
+    b = torch.from_numpy(bt.b).to(dev)
+    x = torch.empty_like(b)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    out = {"workload": f"chem_jacobian_dense_b{B}_n{n}_bicgstab_jacobi", "n_batch": B, "n_rows": n}
+    alg = B * (8 * n * n + 16 * n + 16)
+    steps = max(5, args.steps // 5)
+    for name, flags in (("relative", 0), ("absolute", bs.FLAG_ABS_TOL)):
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO | flags)
+        a = (bs.DENSE, P.handle, vals, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter, iters,
+             resid, status, opts)
+        for _ in range(max(3, args.warmup // 10)):
+            bs.bs_batch_solve(*a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bs.bs_batch_solve(*a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+        out[name] = {"ms": ms, "systems_per_s": B / (ms * 1e-3),
+                     "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+                     "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
+    out["algorithmic_bytes_per_launch"] = int(alg)
     del vals, b, x
     return out
 
@@ -323,6 +369,9 @@ def main() -> int:
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch leg (100k systems, n in [16, 1024])")
     ap.add_argument("--uneven-batch", type=int, default=100_000)
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the BatchDense leg (2^16 chemistry systems stored densely)")
+    ap.add_argument("--dense-batch", type=int, default=1 << 16)
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the 9-point stencil leg (4096 systems, n = 992, FP64 vs mixed)")
     ap.add_argument("--stencil-batch", type=int, default=4096)
@@ -422,6 +471,12 @@ def main() -> int:
         uneven = uneven_leg(args, bs, W, torch, np, dev, tol, max_iter)
         progress(f"uneven: {uneven['fp64']['eager_ms']:.2f} ms (fp64, eager)")
 
+    dense = None
+    if not args.no_dense:
+        dense = dense_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress(f"dense: {dense['relative']['ms']:.3f} ms (relative), "
+                 f"{dense['absolute']['ms']:.3f} ms (absolute)")
+
     stencil = None
     if not args.no_stencil:
         stencil = stencil_leg(args, bs, W, torch, np, dev, tol, max_iter)
@@ -502,6 +557,7 @@ def main() -> int:
         "variants": variants,
         "uneven": uneven,
         "stencil": stencil,
+        "dense": dense,
         "warm_start": warm,
         "gen_seconds": gen_s,
         "kernel_source_sha": kernel_source_sha(),
