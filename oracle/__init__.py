@@ -18,7 +18,7 @@ from . import build as _build
 
 CSR, ELL = 0, 1
 CG, BICGSTAB, GMRES = 0, 1, 2
-PREC_NONE, PREC_JACOBI = 0, 1
+PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI = 0, 1, 2
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 
 _lib = None
@@ -33,7 +33,7 @@ def lib():
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
         I, I64, D = C.c_int, C.c_int64, C.c_double
         L.or_batch_solve.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p,
-                                     I, I, D, I, I, I, i32p, f64p, i32p, I]
+                                     I, I, I, D, I, I, I, i32p, f64p, i32p, I]
         L.or_batch_solve.restype = I
         L.or_batch_spmv.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p]
         L.or_batch_spmv.restype = None
@@ -42,6 +42,8 @@ def lib():
         L.or_batch_true_residual.restype = None
         L.or_batch_jacobi.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p]
         L.or_batch_jacobi.restype = None
+        L.or_batch_block_jacobi.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, I, f64p]
+        L.or_batch_block_jacobi.restype = None
         L.or_dot.argtypes = [I, f64p, f64p]
         L.or_dot.restype = D
         L.or_csr_to_ell.argtypes = [I, i32p, i32p, C.c_void_p]
@@ -101,11 +103,13 @@ def csr_values_to_ell(pat: Pattern, values) -> np.ndarray:
 
 def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = BICGSTAB,
                 precond: int = PREC_JACOBI, tol: float = 1e-10, max_iter: int = 500,
-                restart: int = 30, nthreads: Optional[int] = None, absolute: bool = False):
+                restart: int = 30, nthreads: Optional[int] = None, absolute: bool = False,
+                block_size: int = 4):
     """Solve every system; ``values`` in the layout of ``fmt``.
 
     Stop test (Tab. 2): relative ||r|| <= tol ||b|| by default, absolute
-    ||r|| <= tol with ``absolute``.  Returns ``(x, iters, resid, status)``;
+    ||r|| <= tol with ``absolute``.  ``precond``: none, scalar Jacobi, or block
+    Jacobi with blocks of ``block_size`` consecutive rows.  Returns ``(x, iters, resid, status)``;
     ``resid`` is the true residual ||b - A x||, divided by ||b|| for the
     relative criterion.
     """
@@ -119,8 +123,8 @@ def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = 
     nt = nthreads if nthreads is not None else (os.cpu_count() or 1)
     rp, ci, nnz, w, ec = pat.args(fmt)
     lib().or_batch_solve(fmt, B, pat.n, rp, ci, nnz, w, ec, v, b, x, solver, precond,
-                         float(tol), int(bool(absolute)), int(max_iter), int(restart), iters,
-                         resid, status, nt)
+                         int(block_size), float(tol), int(bool(absolute)), int(max_iter),
+                         int(restart), iters, resid, status, nt)
     return x, iters, resid, status
 
 
@@ -140,6 +144,17 @@ def true_residual(pat: Pattern, values, b, x, fmt: int = CSR,
     rp, ci, nnz, w, ec = pat.args(fmt)
     nt = nthreads if nthreads is not None else (os.cpu_count() or 1)
     lib().or_batch_true_residual(fmt, b.shape[0], pat.n, rp, ci, nnz, w, ec, v, b, x, out, nt)
+    return out
+
+
+def block_jacobi(pat: Pattern, values, bs: int, fmt: int = CSR) -> np.ndarray:
+    """Block-Jacobi inverse rows ``[B][n][bs]``: row i holds entries (i, b0..b0+bs-1)
+    of the inverse of its diagonal block (b0 = i - i % bs)."""
+    v = _f64(values)
+    B = v.shape[0]
+    out = np.empty((B, pat.n, bs))
+    rp, ci, nnz, w, ec = pat.args(fmt)
+    lib().or_batch_block_jacobi(fmt, B, pat.n, rp, ci, nnz, w, ec, v, int(bs), out)
     return out
 
 

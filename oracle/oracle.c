@@ -33,7 +33,8 @@
 
 enum { OR_CSR = 0, OR_ELL = 1 };
 enum { OR_CG = 0, OR_BICGSTAB = 1, OR_GMRES = 2 };
-enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1 };
+enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1, OR_PREC_BLOCK_JACOBI = 2 };
+enum { OR_MAX_BLOCK = 16 };
 enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_BREAKDOWN = 2, OR_NONFINITE = 3 };
 
 /* One system's matrix: the shared pattern plus this system's values.
@@ -98,6 +99,73 @@ static void jacobi_diag(const or_mat *A, int precond, double *d)
     }
 }
 
+/* Block Jacobi: blocks of bs consecutive rows (the last one may be shorter);
+ * D_b = the entries of A in the rows and columns of block b (absent entries
+ * zero).  Its inverse by Gauss-Jordan elimination of [D_b | I] without
+ * pivoting: for each pivot p, divide row p by its pivot, then subtract
+ * multiples of it from every other row.  A zero or non-finite pivot, or a
+ * non-finite entry of the result, makes the block the identity (as scalar
+ * Jacobi takes 1 for a zero diagonal).  inv[i*bs + j] = entry (i, b0 + j) of
+ * the inverse for row i of block b0 (0 past the last row).  work: 2*bs*bs. */
+static void block_jacobi(const or_mat *A, int bs, double *inv, double *work)
+{
+    int n = A->n;
+    for (int b0 = 0; b0 < n; b0 += bs) {
+        int m = n - b0 < bs ? n - b0 : bs, w2 = 2 * m, ok = 1;
+        double *G = work;                               /* m x 2m, row-major */
+        for (int r = 0; r < m; ++r) {
+            for (int c = 0; c < w2; ++c) G[r * w2 + c] = 0.0;
+            G[r * w2 + m + r] = 1.0;
+            int i = b0 + r;
+            if (A->fmt == OR_CSR) {
+                for (int k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                    if (A->col[k] >= b0 && A->col[k] < b0 + m) G[r * w2 + A->col[k] - b0] = A->val[k];
+            } else {
+                for (int sl = 0; sl < A->width; ++sl) {
+                    int c = A->ecol[(size_t)sl * n + i];
+                    if (c >= b0 && c < b0 + m) G[r * w2 + c - b0] = A->val[(size_t)sl * n + i];
+                }
+            }
+        }
+        for (int p = 0; p < m && ok; ++p) {
+            double piv = G[p * w2 + p];
+            if (piv == 0.0 || !isfinite(piv)) { ok = 0; break; }
+            for (int c = 0; c < w2; ++c) G[p * w2 + c] = G[p * w2 + c] / piv;
+            for (int r = 0; r < m; ++r) {
+                if (r == p) continue;
+                double f = G[r * w2 + p];
+                for (int c = 0; c < w2; ++c) G[r * w2 + c] = G[r * w2 + c] - f * G[p * w2 + c];
+            }
+        }
+        for (int r = 0; r < m && ok; ++r)
+            for (int c = 0; c < m; ++c)
+                if (!isfinite(G[r * w2 + m + c])) ok = 0;
+        for (int r = 0; r < m; ++r)
+            for (int j = 0; j < bs; ++j)
+                inv[(size_t)(b0 + r) * bs + j] =
+                    j >= m ? 0.0 : ok ? G[r * w2 + m + j] : (j == r ? 1.0 : 0.0);
+    }
+}
+
+/* The preconditioner as solvers apply it: z = M v, with M = diag(d) (scalar
+ * Jacobi, or d = 1 for none) or the block-Jacobi inverse (bs > 1). */
+typedef struct { int bs; const double *d, *inv; } or_prec;
+
+static void prec_apply(const or_prec *M, int n, const double *v, double *z)
+{
+    if (M->bs <= 1) {
+        for (int i = 0; i < n; ++i) z[i] = M->d[i] * v[i];
+        return;
+    }
+    for (int i = 0; i < n; ++i) {
+        int b0 = i - i % M->bs;
+        const double *row = M->inv + (size_t)i * M->bs;
+        double acc = 0.0;
+        for (int j = 0; j < M->bs && b0 + j < n; ++j) acc += row[j] * v[b0 + j];
+        z[i] = acc;
+    }
+}
+
 /* r = b - A x, returns ||r||_2; t is scratch. */
 static double true_residual(const or_mat *A, const double *b, const double *x,
                             double *r, double *t)
@@ -122,7 +190,7 @@ static or_result finish(const or_mat *A, const double *b, const double *x, doubl
 }
 
 /* ---- CG: Sec. 3.5, Alg. 1, with the residual-norm stop test ------------ */
-static or_result solve_cg(const or_mat *A, const double *d, const double *b, double *x,
+static or_result solve_cg(const or_mat *A, const or_prec *M, const double *b, double *x,
                           double rs, double lim, int max_iter, double *ws)
 {
     int n = A->n, k = 0, r_true;
@@ -132,7 +200,7 @@ static or_result solve_cg(const or_mat *A, const double *d, const double *b, dou
     rn = true_residual(A, b, x, r, t);
     r_true = 1;
 restart:
-    for (int i = 0; i < n; ++i) z[i] = d[i] * r[i];
+    prec_apply(M, n, r, z);
     for (int i = 0; i < n; ++i) p[i] = z[i];
     rho = dot(n, r, z);
     for (;;) {
@@ -155,7 +223,7 @@ restart:
         for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
         for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * t[i];
         r_true = 0;
-        for (int i = 0; i < n; ++i) z[i] = d[i] * r[i]; /* z = precond(r)   */
+        prec_apply(M, n, r, z);                          /* z = precond(r)   */
         double rho_new = dot(n, r, z);
         rn = nrm2(n, r);
         double beta = rho_new / rho;
@@ -166,7 +234,7 @@ restart:
 }
 
 /* ---- BiCGSTAB, right-preconditioned (van der Vorst 1992) --------------- */
-static or_result solve_bicgstab(const or_mat *A, const double *d, const double *b, double *x,
+static or_result solve_bicgstab(const or_mat *A, const or_prec *M, const double *b, double *x,
                                 double rs, double lim, int max_iter, double *ws)
 {
     int n = A->n, k = 0, r_true;
@@ -196,7 +264,7 @@ restart:
         if (rho == 0.0) return finish(A, b, x, rs, k, OR_BREAKDOWN, r, t);
         double beta = (rho / rho0) * (alpha / omega);
         for (int i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-        for (int i = 0; i < n; ++i) ph[i] = d[i] * p[i];
+        prec_apply(M, n, p, ph);
         spmv(A, ph, v);                                  /* v = A M p        */
         double sigma = dot(n, rh, v);
         if (!isfinite(sigma)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
@@ -212,7 +280,7 @@ restart:
             rn = sn;
             continue;
         }
-        for (int i = 0; i < n; ++i) sh[i] = d[i] * s[i];
+        prec_apply(M, n, s, sh);
         spmv(A, sh, t);                                  /* t = A M s        */
         double tt = dot(n, t, t), ts = dot(n, t, s);
         if (!isfinite(tt) || !isfinite(ts)) return finish(A, b, x, rs, k, OR_NONFINITE, r, t);
@@ -228,7 +296,7 @@ restart:
 
 /* ---- GMRES(m), right-preconditioned, modified Gram-Schmidt Arnoldi and
  *      Givens rotations (Saad 2003, Alg. 6.9 with right preconditioning) -- */
-static or_result solve_gmres(const or_mat *A, const double *d, const double *b, double *x,
+static or_result solve_gmres(const or_mat *A, const or_prec *M, const double *b, double *x,
                              double rs, double lim, int max_iter, int m, double *ws)
 {
     int n = A->n, k = 0;
@@ -248,7 +316,7 @@ static or_result solve_gmres(const or_mat *A, const double *d, const double *b, 
         int jend = -1;
         for (int j = 0; j < m; ++j) {
             double *vj = V + (size_t)j * n;
-            for (int i = 0; i < n; ++i) z[i] = d[i] * vj[i];
+            prec_apply(M, n, vj, z);
             spmv(A, z, w);                               /* w = A M v_j      */
             for (int i = 0; i <= j; ++i) {               /* MGS              */
                 double *vi = V + (size_t)i * n;
@@ -289,7 +357,8 @@ static or_result solve_gmres(const or_mat *A, const double *d, const double *b, 
             double *vj = V + (size_t)j * n;
             for (int i = 0; i < n; ++i) z[i] = z[i] + y[j] * vj[i];
         }
-        for (int i = 0; i < n; ++i) x[i] = x[i] + d[i] * z[i];
+        prec_apply(M, n, z, w);                      /* x += M (V y)     */
+        for (int i = 0; i < n; ++i) x[i] = x[i] + w[i];
     }
 }
 
@@ -302,13 +371,16 @@ static size_t workspace_doubles(int solver, int n, int m)
 
 /* absolute: 0 tests ||r|| <= tol * ||b|| and reports ||b - A x|| / ||b||,
  * 1 tests ||r|| <= tol and reports ||b - A x||. */
-static or_result solve_one(const or_mat *A, int solver, int precond, const double *b,
-                           double *x, double tol, int absolute, int max_iter, int m,
-                           double *ws)
+static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
+                           const double *b, double *x, double tol, int absolute, int max_iter,
+                           int m, double *ws)
 {
     int n = A->n;
-    double *d = ws;                         /* the first n doubles hold d */
-    double *work = ws + n;
+    double *d = ws;                         /* n doubles: d */
+    double *inv = ws + n;                   /* n * OR_MAX_BLOCK: block inverse rows */
+    double *gj = inv + (size_t)n * OR_MAX_BLOCK;   /* 2 * OR_MAX_BLOCK^2: elimination */
+    double *work = gj + 2 * OR_MAX_BLOCK * OR_MAX_BLOCK;
+    or_prec M;
     or_result res;
     double bn = nrm2(n, b);
     if (!isfinite(bn)) {
@@ -320,11 +392,17 @@ static or_result solve_one(const or_mat *A, int solver, int precond, const doubl
         res.iters = 0; res.status = OR_CONVERGED; res.resid = 0.0;
         return res;
     }
-    jacobi_diag(A, precond, d);
+    /* blocks of one row are scalar Jacobi */
+    jacobi_diag(A, precond == OR_PREC_BLOCK_JACOBI && bs <= 1 ? OR_PREC_JACOBI : precond, d);
+    M.bs = 1; M.d = d; M.inv = inv;
+    if (precond == OR_PREC_BLOCK_JACOBI && bs > 1) {
+        block_jacobi(A, bs, inv, gj);
+        M.bs = bs;
+    }
     double lim = absolute ? tol : tol * bn, rs = absolute ? 1.0 : bn;
-    if (solver == OR_CG) return solve_cg(A, d, b, x, rs, lim, max_iter, work);
-    if (solver == OR_BICGSTAB) return solve_bicgstab(A, d, b, x, rs, lim, max_iter, work);
-    return solve_gmres(A, d, b, x, rs, lim, max_iter, m, work);
+    if (solver == OR_CG) return solve_cg(A, &M, b, x, rs, lim, max_iter, work);
+    if (solver == OR_BICGSTAB) return solve_bicgstab(A, &M, b, x, rs, lim, max_iter, work);
+    return solve_gmres(A, &M, b, x, rs, lim, max_iter, m, work);
 }
 
 static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *col,
@@ -340,13 +418,15 @@ static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *c
  * values: CSR [n_batch][nnz], ELL [n_batch][width][n].  Returns 0. */
 int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
                    int nnz, int width, const int *ell_col, const double *values,
-                   const double *b, double *x, int solver, int precond, double tol,
-                   int absolute, int max_iter, int restart, int *iters, double *resid,
-                   int *status, int nthreads)
+                   const double *b, double *x, int solver, int precond, int block_size,
+                   double tol, int absolute, int max_iter, int restart, int *iters,
+                   double *resid, int *status, int nthreads)
 {
     size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
     int m = restart > 0 ? restart : 30;
-    size_t wsz = workspace_doubles(solver, n, m) + n;
+    size_t wsz = workspace_doubles(solver, n, m) + n + (size_t)n * OR_MAX_BLOCK +
+                 2 * OR_MAX_BLOCK * OR_MAX_BLOCK;
+    if (block_size < 1 || block_size > OR_MAX_BLOCK) block_size = 1;
     if (nthreads < 1) nthreads = 1;
     #pragma omp parallel num_threads(nthreads)
     {
@@ -355,8 +435,8 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
         for (int64_t s = 0; s < n_batch; ++s) {
             or_mat A;
             make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
-            or_result res = solve_one(&A, solver, precond, b + (size_t)s * n, x + (size_t)s * n,
-                                      tol, absolute, max_iter, m, ws);
+            or_result res = solve_one(&A, solver, precond, block_size, b + (size_t)s * n,
+                                      x + (size_t)s * n, tol, absolute, max_iter, m, ws);
             iters[s] = res.iters;
             status[s] = res.status;
             resid[s] = res.resid;
@@ -411,6 +491,20 @@ void or_batch_jacobi(int fmt, int64_t n_batch, int n, const int *row_ptr, const 
         or_mat A;
         make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
         jacobi_diag(&A, OR_PREC_JACOBI, d + (size_t)s * n);
+    }
+}
+
+/* Block-Jacobi inverse rows per system (for pinning): inv [n_batch][n][bs]. */
+void or_batch_block_jacobi(int fmt, int64_t n_batch, int n, const int *row_ptr,
+                           const int *col_idx, int nnz, int width, const int *ell_col,
+                           const double *values, int bs, double *inv)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    double work[2 * OR_MAX_BLOCK * OR_MAX_BLOCK];
+    for (int64_t s = 0; s < n_batch; ++s) {
+        or_mat A;
+        make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+        block_jacobi(&A, bs, inv + (size_t)s * n * bs, work);
     }
 }
 

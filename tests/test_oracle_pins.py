@@ -507,3 +507,71 @@ def test_absolute_criterion_follows_the_scale_of_b(solver):
             bound = 2 * (w + 2) * EPS * (np.linalg.norm(bb[s]) + np.linalg.norm(np.abs(A) @ np.abs(x[s])))
             assert res[s] <= tol and tr <= tol + bound
             assert abs(res[s] - tr) <= bound
+
+
+# --------------------------------------------------------------- block Jacobi
+# Blocks of bs consecutive rows; the inverse of each diagonal block by
+# Gauss-Jordan elimination without pivoting; a zero pivot makes the block the
+# identity.
+def dense_blocks(P, v, bs):
+    A = O.to_dense(P, v)
+    n = A.shape[0]
+    return [A[b0:b0 + bs, b0:b0 + bs] for b0 in range(0, n, bs)]
+
+
+@pytest.mark.parametrize("bs", [2, 4, 8, 16])
+def test_block_jacobi_inverse_matches_numpy(bs):
+    bt = W.chem_jacobian(n_batch=3, n=54, seed=5)       # 54 = ragged last block for bs 4, 8, 16
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    inv = O.block_jacobi(P, bt.values, bs)
+    inv_e = O.block_jacobi(P, O.csr_values_to_ell(P, bt.values), bs, fmt=O.ELL)
+    assert np.array_equal(inv, inv_e)
+    for s in range(bt.n_batch):
+        for bi, D in enumerate(dense_blocks(P, bt.values[s], bs)):
+            m = D.shape[0]
+            ref = np.linalg.inv(D)
+            got = inv[s, bi * bs: bi * bs + m, :m]
+            assert np.allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+            assert np.all(inv[s, bi * bs: bi * bs + m, m:] == 0)
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_block_size_one_is_scalar_jacobi(solver):
+    bt = W.chem_jacobian(n_batch=20, n=40, seed=6) if solver != O.CG else W.tridiag_stencil(20, n=40)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    a = O.batch_solve(P, bt.values, bt.b, solver=solver, precond=O.PREC_JACOBI)
+    b = O.batch_solve(P, bt.values, bt.b, solver=solver, precond=O.PREC_BLOCK_JACOBI, block_size=1)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("solver", [O.CG, O.BICGSTAB, O.GMRES])
+def test_block_jacobi_exact_on_block_diagonal(solver):
+    """A block-diagonal matrix with the preconditioner's blocks: M = A^{-1},
+    so the first step solves the system."""
+    rng = np.random.default_rng(9)
+    n, bs, B = 24, 4, 6
+    As = np.zeros((B, n, n))
+    for b0 in range(0, n, bs):
+        M = rng.random((B, bs, bs)) - 0.5
+        if solver == O.CG:
+            M = M @ np.transpose(M, (0, 2, 1)) + bs * np.eye(bs)
+        else:
+            M = M + bs * np.eye(bs)
+        As[:, b0:b0 + bs, b0:b0 + bs] = M
+    P, vals, b = batch_from_dense(As, rng.random((B, n)) - 0.5)
+    x, it, res, st = O.batch_solve(P, vals, b, solver=solver, precond=O.PREC_BLOCK_JACOBI,
+                                   block_size=bs, tol=1e-12)
+    assert np.all(st == O.CONVERGED) and np.all(it == 1)
+    for s in range(B):
+        assert np.allclose(x[s], np.linalg.solve(As[s], b[s]), rtol=1e-10, atol=1e-12)
+
+
+def test_block_jacobi_zero_pivot_gives_identity():
+    """[[0, 1], [1, 0]] is invertible but has a zero first pivot without
+    pivoting: that block becomes the identity; the other block is inverted."""
+    A = np.array([[0.0, 1, 0, 0], [1, 0, 0, 0], [0, 0, 2, 1], [0, 0, 1, 3]])
+    P, vals, _ = batch_from_dense(A[None], np.zeros((1, 4)))
+    inv = O.block_jacobi(P, vals, 2)[0]
+    assert np.array_equal(inv[:2], np.eye(2))
+    assert np.allclose(inv[2:], np.linalg.inv(A[2:, 2:]), rtol=1e-15)
