@@ -43,9 +43,13 @@ typedef enum { BS_CSR = 0, BS_ELL = 1, BS_DENSE = 2 } bs_format;
  * rotations. */
 typedef enum { BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2 } bs_solver;
 
-/* Preconditioners of Tab. 2: none, or scalar Jacobi d_i = 1/a_ii (1 where the
- * diagonal entry is zero or not stored). */
-typedef enum { BS_PREC_NONE = 0, BS_PREC_JACOBI = 1 } bs_precond;
+/* Preconditioners: none, scalar Jacobi of Tab. 2 (d_i = 1/a_ii, 1 where the
+ * diagonal entry is zero or not stored), or block Jacobi: the inverse of the
+ * block diagonal of A with blocks of bs_options.block_size consecutive rows
+ * (2, 4 or 8; the last block may be shorter), each block inverted by
+ * Gauss-Jordan elimination without pivoting, a block that meets a zero or
+ * non-finite pivot (or gives a non-finite inverse) taken as the identity. */
+typedef enum { BS_PREC_NONE = 0, BS_PREC_JACOBI = 1, BS_PREC_BLOCK_JACOBI = 2 } bs_precond;
 
 /* BS_FP64: everything in FP64.  BS_MIXED: iterative refinement whose outer loop
  * (true residual b - A x, its norm, the update of x) is FP64 and whose inner
@@ -184,6 +188,8 @@ typedef struct {
                            with BS_FLAG_X0_ZERO (BS_ERR_INVALID_ARG)              */
   int32_t *alt_used;    /* optional device int32[n_batch]: 1 where x_alt was
                            taken, 0 where x was; written only with x_alt          */
+  int32_t block_size;   /* BS_PREC_BLOCK_JACOBI: rows per block, 2, 4 or 8;
+                           0 selects 8 (BS_ERR_INVALID_ARG otherwise)             */
 } bs_options;
 
 /* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libbatchsolve.so")
 # enums of batchsolve.h
 CSR, ELL, DENSE = 0, 1, 2
 CG, BICGSTAB, GMRES = 0, 1, 2
-PREC_NONE, PREC_JACOBI = 0, 1
+PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI = 0, 1, 2
 FP64, MIXED = 0, 1
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_PATTERN, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_DEVICE = 0, -1, -2, -3, -4, -5
@@ -41,7 +41,8 @@ class BatchSolveError(RuntimeError):
 class bs_options(C.Structure):
     _fields_ = [("restart", C.c_int32), ("precision", C.c_int32), ("inner_tol", C.c_double),
                 ("flags", C.c_int32), ("team", C.c_int32), ("rows_per_lane", C.c_int32),
-                ("outer_iters", C.c_void_p), ("x_alt", C.c_void_p), ("alt_used", C.c_void_p)]
+                ("outer_iters", C.c_void_p), ("x_alt", C.c_void_p), ("alt_used", C.c_void_p),
+                ("block_size", C.c_int32)]
 
 
 class bs_plan_info(C.Structure):
@@ -243,9 +244,9 @@ def bs_matrix_storage(fmt: int, n_batch: int, n_rows: int, nnz: int, ell_width: 
 
 def make_options(restart: int = 0, precision: int = FP64, inner_tol: float = 0.0, flags: int = 0,
                  team: int = 0, rows_per_lane: int = 0, outer_iters=None, x_alt=None,
-                 alt_used=None) -> bs_options:
+                 alt_used=None, block_size: int = 0) -> bs_options:
     o = bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters),
-                   _ptr(x_alt), _ptr(alt_used))
+                   _ptr(x_alt), _ptr(alt_used), block_size)
     # the structure holds raw device pointers: keep their tensors alive with it
     o._keep = (outer_iters, x_alt, alt_used)
     return o

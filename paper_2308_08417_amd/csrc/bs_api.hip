@@ -129,7 +129,15 @@ bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) 
   return true;
 }
 
-int variant_of(bs_solver solver, int precision) {
+// block: block-Jacobi block size (0 without); block Jacobi is FP64 only.
+int variant_of(bs_solver solver, int precision, int block = 0) {
+  if (block > 1) {
+    if (precision == BS_MIXED) return -1;
+    if (solver == BS_CG) return bs::V_CG_BJ;
+    if (solver == BS_BICGSTAB) return bs::V_BICGSTAB_BJ;
+    if (solver == BS_GMRES) return bs::V_GMRES_BJ;
+    return -1;
+  }
   if (solver == BS_CG) return precision == BS_MIXED ? -1 : bs::V_CG;
   if (solver == BS_BICGSTAB) return precision == BS_MIXED ? bs::V_BICGSTAB_MIXED : bs::V_BICGSTAB;
   if (solver == BS_GMRES) return precision == BS_MIXED ? bs::V_GMRES_MIXED : bs::V_GMRES;
@@ -143,6 +151,9 @@ bs::KernelTable table_of(int variant) {
     case bs::V_BICGSTAB_MIXED: return bs::kernels_bicgstab_mixed();
     case bs::V_GMRES: return bs::kernels_gmres();
     case bs::V_GMRES_MIXED: return bs::kernels_gmres_mixed();
+    case bs::V_CG_BJ: return bs::kernels_cg_bj();
+    case bs::V_BICGSTAB_BJ: return bs::kernels_bicgstab_bj();
+    case bs::V_GMRES_BJ: return bs::kernels_gmres_bj();
     default: return {nullptr, 0};
   }
 }
@@ -194,19 +205,30 @@ int device_cus() {
 
 bool pow2_team(int t) { return t >= 16 && t <= 1024 && (t & (t - 1)) == 0; }
 
+// Block-Jacobi block size of a request: 0 without block Jacobi, else 2, 4 or
+// 8 (0 selects 8); -1 when the size is not one of these.
+int block_of(const bs_options* o, int precond = BS_PREC_BLOCK_JACOBI) {
+  if (precond != BS_PREC_BLOCK_JACOBI) return 0;
+  const int b = o ? o->block_size : 0;
+  if (b == 0) return 8;
+  return (b == 2 || b == 4 || b == 8) ? b : -1;
+}
+
 // Staging of CSR values through LDS is used while a workgroup's staging area
 // stays within this budget.
 constexpr int kStageBudget = 48 * 1024;
+constexpr int kLdsPerCu = 160 * 1024;
 
 struct Plan {
   bs_plan_info info;
   const bs::KernelEntry* k;
 };
 
+// block: block-Jacobi block size (0 without block Jacobi).
 int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver solver,
-              const bs_options* o, Plan* out) {
+              const bs_options* o, int block, Plan* out) {
   const int precision = o ? o->precision : BS_FP64;
-  const int variant = variant_of(solver, precision);
+  const int variant = variant_of(solver, precision, block);
   if (variant < 0) return BS_ERR_UNSUPPORTED;
   if (n > BS_MAX_ROWS || max_row > BS_MAX_ROW_NNZ) return BS_ERR_UNSUPPORTED;
   const int force_team = o ? o->team : 0, force_r = o ? o->rows_per_lane : 0;
@@ -235,10 +257,11 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   if (!k) return BS_ERR_UNSUPPORTED;
   const int rows = team * r;
   const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
-  const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED;
+  const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED || variant == bs::V_GMRES_BJ;
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const bool mixed = variant == bs::V_GMRES_MIXED;
-  const int vec = teams * bs::team_vec_bytes(rows, gm, wg, mixed) + bs::red_lds_bytes(waves);
+  const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block)) +
+                  bs::red_lds_bytes(waves);
   int stage = 0;
   if (waves == 1 && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget) stage = 1;
   out->k = k;
@@ -249,6 +272,8 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   out->info.systems_per_group = teams;
   out->info.lds_bytes = vec + (stage ? bs::stage_total_bytes(teams, stored, n, k->nz) : 0);
   out->info.stage_values = stage;
+  // a workgroup's LDS is at most that of a compute unit
+  if (out->info.lds_bytes > kLdsPerCu) return BS_ERR_UNSUPPORTED;
   return BS_OK;
 }
 
@@ -470,7 +495,10 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
     fmt = BS_CSR;
   }
   Plan pl;
-  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, &pl);
+  // planned with the block-Jacobi region when opts asks for a block size
+  const int block = opts && opts->block_size != 0 ? block_of(opts) : 0;
+  if (block < 0) return BS_ERR_INVALID_ARG;
+  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block, &pl);
   if (rc == BS_OK) *out = pl.info;
   return rc;
 }
@@ -487,8 +515,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     fmt = BS_CSR;
   }
   if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_INVALID_ARG;
-  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI) return BS_ERR_INVALID_ARG;
+  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI)
+    return BS_ERR_INVALID_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;
+  const int block = block_of(opts, precond);
+  if (block < 0) return BS_ERR_INVALID_ARG;
   int restart = bs::kMaxRestart;
   double inner_tol = 1e-6;
   int flags = 0;
@@ -504,7 +535,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   Plan pl;
   const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, pattern->width, solver,
-                           opts, &pl);
+                           opts, block, &pl);
   if (rc != BS_OK) return rc;
   bs::KArgs a;
   a.n_batch = n_batch;
@@ -524,6 +555,10 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
     a.team_bytes = bs::team_vec_bytes(rows, a.gmres, pl.info.group_size,
                                       a.gmres && opts && opts->precision == BS_MIXED);
+    // block Jacobi: inverse rows and the exchange buffer after the vectors
+    a.block = block;
+    a.bj_offset = a.team_bytes;
+    a.team_bytes += bs::bj_bytes(rows, block);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);

@@ -272,6 +272,12 @@ struct Team {
     }
   }
 
+  // This team's block-Jacobi region and its row count.
+  __device__ __forceinline__ double* bj_region(const KArgs& a) const {
+    return reinterpret_cast<double*>(lds + a.bj_offset);
+  }
+  static constexpr int bj_rows() { return S::ROWS; }
+
   // Whether any team of this wave satisfies p.  For multi-wave teams every
   // wave sees the same (team-uniform) predicate.
   __device__ __forceinline__ bool any(bool p) const { return wave_any(p); }
@@ -530,6 +536,7 @@ struct Rows {
 
   // Whether slot k of row r holds one of the row's entries (not the zero cell).
   __device__ __forceinline__ bool real(int r, int k) const { return c[r][k] != zc; }
+  __device__ __forceinline__ int nrows(const KArgs& g) const { return g.n; }
 
   // Scalar Jacobi: d = 1/a_ii, 1 where the diagonal is zero or absent; 0 for
   // lanes past the last row so padded entries stay zero.

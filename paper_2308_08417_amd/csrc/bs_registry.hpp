@@ -7,8 +7,10 @@
 
 namespace bs {
 
+// *_BJ: the FP64 solvers with the block-Jacobi preconditioner.
 enum Variant {
-  V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4, V_COUNT = 5
+  V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4,
+  V_CG_BJ = 5, V_BICGSTAB_BJ = 6, V_GMRES_BJ = 7, V_COUNT = 8
 };
 
 typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
@@ -31,6 +33,9 @@ KernelTable kernels_bicgstab();
 KernelTable kernels_bicgstab_mixed();
 KernelTable kernels_gmres();
 KernelTable kernels_gmres_mixed();
+KernelTable kernels_cg_bj();
+KernelTable kernels_bicgstab_bj();
+KernelTable kernels_gmres_bj();
 
 // Shapes compiled for every solver: one row per lane for teams of 16..1024
 // lanes, and 2 or 4 rows per lane for the largest systems.  Slots per row are

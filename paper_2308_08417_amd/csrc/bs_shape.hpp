@@ -48,7 +48,16 @@ struct KArgs {
   const double* x_alt;         // optional second initial guess [n_batch][n]
   int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
   const int* layout;           // one-wave teams: lane_row[64] | lane_win[64] | col_pos[n], or null
+  int block;                   // block-Jacobi block size (2, 4 or 8), 0 for scalar Jacobi / none
+  int bj_offset;               // byte offset of the block-Jacobi region in a team's LDS
 };
+
+// Block Jacobi: per team, the inverse rows (rows x block doubles) and a
+// row-indexed exchange buffer (rows doubles).
+constexpr int kMaxBlock = 8;
+__host__ __device__ constexpr int bj_bytes(int rows, int block) {
+  return block > 1 ? rows * (block + 1) * 8 : 0;
+}
 
 // Flag bit of the absolute stop criterion (BS_FLAG_ABS_TOL).
 constexpr int kFlagAbsTol = 4;

@@ -28,6 +28,163 @@ __device__ __forceinline__ double stop_limit(const G& g, double bn) {
   return (g.flags & kFlagAbsTol) ? g.tol : g.tol * bn;
 }
 
+// ------------------------------------------------------------ block Jacobi
+// Blocks of bs consecutive rows (bs = 2, 4 or 8; the last block may be
+// shorter); M = the inverse of the block diagonal of A.  Per team in LDS: the
+// inverse rows, row i at binv[i*bs .. i*bs+bs-1] holding entries (i, b0..b0+bs-1)
+// (b0 = i - i % bs), and a row-indexed exchange buffer pbuf[rows].  The rows
+// of one block always sit in one wave (bs divides the rows a wave holds), so a
+// wavefront-scope fence orders the exchanges; nothing extra stays in
+// registers.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Inverse of every diagonal block by Gauss-Jordan elimination in place without
+// pivoting: for each pivot p, row p is divided by its pivot (its diagonal entry
+// becoming 1/pivot), then every other row r subtracts a_rp times it (its entry p
+// becoming -a_rp/pivot).  A zero or non-finite pivot, or a non-finite entry of
+// the result, makes the block the identity.  The columns of a row's register
+// slots are found by gathering a vector that holds each row's own index.  All
+// lanes of the workgroup call it together.
+//
+// After the gather, every LDS access stays inside the wave that owns the rows:
+// a block's rows lie in one wave, and its failure flag is the exchange entry
+// of its first row.  Waves of a multi-wave team may therefore leave at
+// different times and go straight into bj_apply, which writes only the
+// entries of its own rows.
+template <class TM, class RW>
+__device__ void bj_setup(TM& tm, RW& A, const KArgs& g) {
+  constexpr int R = RW::R;
+  const int bs = g.block, n = A.nrows(g), rows = tm.bj_rows(), per = rows / R;
+  double* binv = tm.bj_region(g);
+  double* pbuf = binv + (size_t)rows * bs;
+  const int lane = tm.lane;
+  // clear the exchange buffer (also the per-block failure flags) and the rows
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + r * per;
+    pbuf[i] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < bs; ++j) binv[i * bs + j] = 0.0;
+  }
+  // each row's own index into buffer 1, then gather it through the slots
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (A.ok[r]) lds_store<double>(A.vrow[r] + RW::kBuf, (double)A.row[r]);
+  tm.sync();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = A.row[r], b0 = i - (i & (bs - 1));
+#pragma unroll
+    for (int k0 = 0; k0 < RW::NZ; k0 += 4) {
+      int col[4];
+#pragma unroll
+      for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
+        col[k - k0] = (int)lds_load<double>(A.c[r][k] + RW::kBuf);
+#pragma unroll
+      for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
+        if (A.ok[r] && A.real(r, k) && col[k - k0] >= b0 && col[k - k0] < b0 + bs)
+          binv[i * bs + (col[k - k0] - b0)] = A.a[r][k];
+      // four gathers in flight at a time
+      __asm__ volatile("" ::: "memory");
+    }
+  }
+  wave_lds_fence();
+#pragma unroll 1
+  for (int p = 0; p < bs; ++p) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = A.row[r], b0 = i - (i & (bs - 1));
+      if (A.ok[r] && i - b0 == p) {
+        const double piv = binv[i * bs + p];
+        if (piv == 0.0 || !__builtin_isfinite(piv)) pbuf[b0] = 1.0;
+        binv[i * bs + p] = 1.0;
+#pragma unroll 1
+        for (int j = 0; j < bs; ++j) binv[i * bs + j] = binv[i * bs + j] / piv;
+      }
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = A.row[r], b0 = i - (i & (bs - 1));
+      if (A.ok[r] && i - b0 != p && b0 + p < n) {
+        const double f = binv[i * bs + p];
+        binv[i * bs + p] = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < bs; ++j)
+          binv[i * bs + j] = fma(-f, binv[(b0 + p) * bs + j], binv[i * bs + j]);
+      }
+    }
+    wave_lds_fence();
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!A.ok[r]) continue;
+    const int i = A.row[r];
+    bool fin = true;
+#pragma unroll 1
+    for (int j = 0; j < bs; ++j) fin = fin && __builtin_isfinite(binv[i * bs + j]);
+    if (!fin) pbuf[i - (i & (bs - 1))] = 1.0;
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!A.ok[r]) continue;
+    const int i = A.row[r];
+    if (pbuf[i - (i & (bs - 1))] != 0.0) {
+#pragma unroll 1
+      for (int j = 0; j < bs; ++j) binv[i * bs + j] = (j == (i & (bs - 1))) ? 1.0 : 0.0;
+    }
+  }
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < R; ++r) pbuf[lane + r * per] = 0.0;
+  wave_lds_fence();
+}
+
+// z = M v for the block-Jacobi M (rows past n give 0).  All lanes of a wave call
+// it together.  Two entries are loaded at a time, bounding the registers held.
+template <class T, class TM, class RW>
+__device__ __forceinline__ void bj_apply(TM& tm, const RW& A, const KArgs& g,
+                                         const T (&v)[RW::R], T (&z)[RW::R]) {
+  constexpr int R = RW::R;
+  const int bs = g.block, rows = tm.bj_rows();
+  const double* binv = tm.bj_region(g);
+  double* pbuf = tm.bj_region(g) + (size_t)rows * bs;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (A.ok[r]) pbuf[A.row[r]] = (double)v[r];
+  wave_lds_fence();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    T acc = (T)0;
+    if (A.ok[r]) {
+      const int i = A.row[r], b0 = i - (i & (bs - 1));
+#pragma unroll 1
+      for (int j = 0; j < bs; j += 2)
+        acc = fma((T)binv[i * bs + j + 1], (T)pbuf[b0 + j + 1],
+                  fma((T)binv[i * bs + j], (T)pbuf[b0 + j], acc));
+    }
+    z[r] = acc;
+  }
+  wave_lds_fence();
+}
+
+// z = M v: block Jacobi in the BJ instances, else the diagonal d (scalar
+// Jacobi, or 1 without a preconditioner).
+template <bool BJ, class T, class TM, class RW>
+__device__ __forceinline__ void precond(TM& tm, const RW& A, const KArgs& g, const T (&d)[RW::R],
+                                        const T (&v)[RW::R], T (&z)[RW::R]) {
+  if constexpr (BJ) {
+    bj_apply(tm, A, g, v, z);
+  } else {
+#pragma unroll
+    for (int r = 0; r < RW::R; ++r) z[r] = d[r] * v[r];
+  }
+}
+
 // Shared epilogue: true residual for teams that do not have it, then outputs.
 template <class TM, class RW>
 __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
@@ -66,9 +223,10 @@ struct Prologue {
   double b[R], x[R], r[R], d[R];
 };
 
-template <class TM, class RW>
+template <bool BJ, class TM, class RW>
 __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue<RW::R>& P) {
   A.jacobi(g.precond, P.d);
+  if constexpr (BJ) bj_setup(tm, A, g);
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
   for (int r = 0; r < RW::R; ++r) {
@@ -119,11 +277,11 @@ __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue
 // FP32 and solve for a correction to the FP64 x, scaled by 1/||r||; the "true
 // residual confirmation" becomes the FP64 outer refinement step r = b - A x,
 // which also ends the inner solve when it meets inner_tol or breaks down.
-template <bool MIXED, class TM, class RW>
+template <bool MIXED, bool BJ, class TM, class RW>
 __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
   using T = typename std::conditional<MIXED, float, double>::type;
   Prologue<RW::R> P;
-  prologue(tm, A, g, P);
+  prologue<BJ>(tm, A, g, P);
   constexpr int R = RW::R;
 
   // FP32 copy of the rows and of the Jacobi diagonal for the inner solve.
@@ -288,10 +446,8 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
     const T beta = (rho * alpha) / (rho0 * omega);
     T ph[R], s[R], sh[R], t[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      p[i] = r[i] + beta * (p[i] - omega * v[i]);
-      ph[i] = d_in[i] * p[i];
-    }
+    for (int i = 0; i < R; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    precond<BJ>(tm, A, g, d_in, p, ph);
     A.template spmv<0>(tm, a_in, ph, v);
     T q1[1];
     {
@@ -308,10 +464,8 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
     }
     const T al = rho / sigma;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      s[i] = r[i] - al * v[i];
-      sh[i] = d_in[i] * s[i];
-    }
+    for (int i = 0; i < R; ++i) s[i] = r[i] - al * v[i];
+    precond<BJ>(tm, A, g, d_in, s, sh);
     A.template spmv<1>(tm, a_in, sh, t);
     T q3[3];
     {
@@ -380,14 +534,15 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
 // =================================================================== CG
 // Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
 // stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
-template <class TM, class RW>
+template <bool BJ, class TM, class RW>
 __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
   Prologue<RW::R> P;
-  prologue(tm, A, g, P);
+  prologue<BJ>(tm, A, g, P);
   constexpr int R = RW::R;
   double z[R], p[R];
+  precond<BJ>(tm, A, g, P.d, P.r, z);
 #pragma unroll
-  for (int i = 0; i < R; ++i) { z[i] = P.d[i] * P.r[i]; p[i] = z[i]; }
+  for (int i = 0; i < R; ++i) p[i] = z[i];
   double q3[3];
   {
     double p0[R], p1[R], p2[R];
@@ -423,9 +578,10 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
       double t[R], rc[R], zc[R], p0[R], p1[R], q[2];
       A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
+      for (int i = 0; i < R; ++i) rc[i] = P.b[i] - t[i];
+      precond<BJ>(tm, A, g, P.d, rc, zc);
+#pragma unroll
       for (int i = 0; i < R; ++i) {
-        rc[i] = P.b[i] - t[i];
-        zc[i] = P.d[i] * rc[i];
         p0[i] = rc[i] * rc[i];
         p1[i] = rc[i] * zc[i];
       }
@@ -470,8 +626,8 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
     for (int i = 0; i < R; ++i) {
       rr[i] = go ? fma(-alpha, t[i], P.r[i]) : P.r[i];
       if (go) P.x[i] = fma(alpha, p[i], P.x[i]);
-      z[i] = P.d[i] * rr[i];
     }
+    precond<BJ>(tm, A, g, P.d, rr, z);
     double q2[2];
     {
       double p0[R], p1[R];
@@ -514,13 +670,13 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 // after m steps; the rotations and the triangular solve stay FP64 and x is
 // updated in FP64.  A cycle that does not lower the FP64 residual ends the
 // solve with BREAKDOWN.
-template <bool MIXED, class TM, class RW>
+template <bool MIXED, bool BJ, class TM, class RW>
 __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   static_assert(RW::R == 1, "GMRES keeps one row per lane");
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr int M = kMaxRestart;
   Prologue<RW::R> P;
-  prologue(tm, A, g, P);
+  prologue<BJ>(tm, A, g, P);
   const int m = g.restart;
   // LDS scalars of this team
   double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(RW::ROWS));
@@ -609,7 +765,11 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     if (!tm.any(st == ST_RUNNING)) break;
     // ---- one Arnoldi step for every running team (all of them are mid-cycle)
     const bool act = st == ST_RUNNING;
-    T z[1] = {dT * vcur}, w[1];
+    T z[1], w[1];
+    {
+      const T vv[1] = {vcur}, dd[1] = {dT};
+      precond<BJ>(tm, A, g, dd, vv, z);
+    }
     A.template spmv<0, false>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
     if constexpr (RW::TEAM >= 64) {
@@ -747,8 +907,15 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
           }
         }
       }
+      // x += M V y (every lane of the wave applies M together)
+      double mz[1];
+      {
+        const double zz[1] = {zacc}, dd[1] = {d};
+        precond<BJ>(tm, A, g, dd, zz, mz);
+      }
       if (end) {
-        P.x[0] = fma(d, zacc, P.x[0]);
+        if constexpr (BJ) P.x[0] = P.x[0] + mz[0];
+        else P.x[0] = fma(d, zacc, P.x[0]);
         start = true;
       }
     }
@@ -812,19 +979,19 @@ constexpr int kWaitPrefetch = 0x0074;
     CALL;                                                                          \
   }
 
-template <class S, bool MIXED>
+template <class S, bool MIXED, bool BJ = false>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
-  BS_PERSISTENT_LOOP((bicgstab_system<MIXED>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((bicgstab_system<MIXED, BJ>(tm, A, ga)))
 }
 
-template <class S>
+template <class S, bool BJ = false>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
-  BS_PERSISTENT_LOOP((cg_system(tm, A, ga)))
+  BS_PERSISTENT_LOOP((cg_system<BJ>(tm, A, ga)))
 }
 
-template <class S, bool MIXED>
+template <class S, bool MIXED, bool BJ = false>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system<MIXED>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((gmres_system<MIXED, BJ>(tm, A, ga)))
 }
 
 #undef BS_PERSISTENT_LOOP

@@ -96,6 +96,13 @@ struct VarTeam {
     }
   }
 
+  // This team's block-Jacobi region (after the buffers and reduction slots)
+  // and its row count.
+  __device__ __forceinline__ double* bj_region(const KArgs& g) const {
+    return reinterpret_cast<double*>(lds + var_lds_bytes<VS>()) + (size_t)tix * T * VS::R * (g.block + 1);
+  }
+  __device__ __forceinline__ int bj_rows() const { return T * VS::R; }
+
   __device__ __forceinline__ bool any(bool p) const {
     if (wpt == 1) return wave_any(p);
     return __syncthreads_or(p ? 1 : 0) != 0;
@@ -139,6 +146,7 @@ struct VarRows {
   bool ok[R];
   int dslot[R];
   unsigned zero;
+  int n;  // rows of this team's system
   double dval[R], bval[R], xval[R], xalt[R];
 
   // Pattern and values of this team's system, straight from HBM.  Every load
@@ -146,7 +154,7 @@ struct VarRows {
   __device__ void load(const VarTeam<VS>& tm, const VArgs& va, unsigned lds_base) {
     const KArgs& g = va.base;
     const int s = tm.live ? (int)tm.sys : 0;
-    const int n = tm.live ? va.sys_rows[s] : 0;
+    n = tm.live ? va.sys_rows[s] : 0;
     const int p = va.sys_pat[s];
     const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
     zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
@@ -191,6 +199,7 @@ struct VarRows {
   }
 
   __device__ __forceinline__ bool real(int r, int k) const { return c[r][k] != zero; }
+  __device__ __forceinline__ int nrows(const KArgs&) const { return n; }
 
   __device__ void jacobi(int precond, double (&d)[R]) const {
 #pragma unroll
@@ -229,10 +238,11 @@ struct VarRows {
 
 __global__ void k_varlen_reset(int* counter) { *counter = 0; }
 
-template <class VS, int NZ, int SOLVER, bool MIXED>
+template <class VS, int NZ, int SOLVER, bool MIXED, bool BJ = false>
 __global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(VS::OCC)))
 void k_varlen(const VArgs va) {
-  __shared__ __align__(16) char smem[var_lds_bytes<VS>()];
+  // buffers and reduction slots, then (BJ) the block-Jacobi region of the largest block
+  __shared__ __align__(16) char smem[var_lds_bytes<VS>() + (BJ ? bj_bytes(VS::ROWS, kMaxBlock) : 0)];
   __shared__ int task_sh;
   const unsigned lds_base = lds_addr(smem);
   constexpr unsigned kBuf = var_buf_bytes<VS>();
@@ -261,8 +271,8 @@ void k_varlen(const VArgs va) {
     tm.row0 = tm.live ? a.row_off[tm.sys] : 0;
     VarRows<VS, NZ> A;
     A.load(tm, a, lds_base);
-    if constexpr (SOLVER == 0) cg_system(tm, A, a.base);
-    else bicgstab_system<MIXED>(tm, A, a.base);
+    if constexpr (SOLVER == 0) cg_system<BJ>(tm, A, a.base);
+    else bicgstab_system<MIXED, BJ>(tm, A, a.base);
   }
 }
 

@@ -36,16 +36,16 @@ int next_pow2(int v) {
 typedef hipError_t (*VLaunch)(const bs::VArgs&, unsigned grid, hipStream_t);
 typedef hipError_t (*VOccupancy)(int*);
 
-template <class VS, int NZ, int SOLVER, bool MIXED>
+template <class VS, int NZ, int SOLVER, bool MIXED, bool BJ>
 hipError_t vlaunch(const bs::VArgs& a, unsigned grid, hipStream_t s) {
-  hipLaunchKernelGGL((bs::k_varlen<VS, NZ, SOLVER, MIXED>), dim3(grid), dim3(VS::WG), 0, s, a);
+  hipLaunchKernelGGL((bs::k_varlen<VS, NZ, SOLVER, MIXED, BJ>), dim3(grid), dim3(VS::WG), 0, s, a);
   return hipGetLastError();
 }
 
-template <class VS, int NZ, int SOLVER, bool MIXED>
+template <class VS, int NZ, int SOLVER, bool MIXED, bool BJ>
 hipError_t voccupancy(int* blocks) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, reinterpret_cast<const void*>(&bs::k_varlen<VS, NZ, SOLVER, MIXED>), VS::WG, 0);
+      blocks, reinterpret_cast<const void*>(&bs::k_varlen<VS, NZ, SOLVER, MIXED, BJ>), VS::WG, 0);
 }
 
 // Workgroup shapes (lanes, rows per lane); each holds systems of up to 1024 rows.
@@ -58,27 +58,30 @@ constexpr int kNumOrders = 3;
 constexpr int kNumPolicies = kNumShapes * kNumOrders;
 constexpr int kMaxVarRows = 1024;
 
-// Compiled instances: shape x slots per row x (CG, BiCGSTAB, BiCGSTAB mixed).
+// Compiled instances: shape x slots per row x (CG, BiCGSTAB, BiCGSTAB mixed,
+// and CG and BiCGSTAB with block Jacobi).
 struct VEntry {
-  int wg, r, nz, solver, mixed;
+  int wg, r, nz, solver, mixed, bj;
   VLaunch fn;
   VOccupancy occ;
 };
-#define VE1(W, R, NZ, SO, MX)                                                         \
-  {W, R, NZ, SO, MX, &vlaunch<bs::VarShape<W, R>, NZ, SO, MX>,                         \
-   &voccupancy<bs::VarShape<W, R>, NZ, SO, MX>},
-#define VE(W, R, NZ) VE1(W, R, NZ, 0, false) VE1(W, R, NZ, 1, false) VE1(W, R, NZ, 1, true)
+#define VE1(W, R, NZ, SO, MX, BJ)                                                     \
+  {W, R, NZ, SO, MX, BJ, &vlaunch<bs::VarShape<W, R>, NZ, SO, MX, BJ>,                 \
+   &voccupancy<bs::VarShape<W, R>, NZ, SO, MX, BJ>},
+#define VE(W, R, NZ)                                                                  \
+  VE1(W, R, NZ, 0, false, false) VE1(W, R, NZ, 1, false, false) VE1(W, R, NZ, 1, true, false) \
+  VE1(W, R, NZ, 0, false, true) VE1(W, R, NZ, 1, false, true)
 #define VES(W, R) VE(W, R, 8) VE(W, R, 10) VE(W, R, 12) VE(W, R, 16)
 const VEntry kVTable[] = {VES(1024, 1) VES(512, 2) VES(256, 4)};
 #undef VES
 #undef VE
 #undef VE1
 
-const VEntry* find_v(int wg, int r, int nz, int solver, int mixed) {
+const VEntry* find_v(int wg, int r, int nz, int solver, int mixed, int bj) {
   const VEntry* best = nullptr;
   for (const VEntry& e : kVTable)
-    if (e.wg == wg && e.r == r && e.solver == solver && e.mixed == mixed && e.nz >= nz &&
-        (!best || e.nz < best->nz))
+    if (e.wg == wg && e.r == r && e.solver == solver && e.mixed == mixed && e.bj == bj &&
+        e.nz >= nz && (!best || e.nz < best->nz))
       best = &e;
   return best;
 }
@@ -165,7 +168,13 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
            bs_precond precond, double tol, int max_iter, int* iters, double* resid, int* status,
            const bs_options* o, hipStream_t stream) {
   if (solver != BS_CG && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
-  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI) return BS_ERR_INVALID_ARG;
+  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI)
+    return BS_ERR_INVALID_ARG;
+  int block = 0;
+  if (precond == BS_PREC_BLOCK_JACOBI) {
+    block = o && o->block_size ? o->block_size : 8;
+    if (block != 2 && block != 4 && block != 8) return BS_ERR_INVALID_ARG;
+  }
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;
   const int mixed = o && o->precision == BS_MIXED;
   if (o && o->precision != BS_FP64 && o->precision != BS_MIXED) return BS_ERR_INVALID_ARG;
@@ -174,13 +183,17 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   if (v.B == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   const VShapeInfo sh = kVShapes[v.policy / kNumOrders];
-  const VEntry* k = find_v(sh.wg, sh.r, std::max(v.max_row, 1), solver == BS_CG ? 0 : 1, mixed);
+  if (mixed && block > 1) return BS_ERR_UNSUPPORTED;
+  const VEntry* k = find_v(sh.wg, sh.r, std::max(v.max_row, 1), solver == BS_CG ? 0 : 1, mixed,
+                           block > 1 ? 1 : 0);
   if (!k) return BS_ERR_UNSUPPORTED;
   bs::VArgs a = v.args;
   bs::KArgs& g = a.base;
   g = bs::KArgs{};
   g.n_batch = v.B;
   g.precond = precond == BS_PREC_JACOBI ? 1 : 0;
+  g.block = block;
+  g.bj_offset = 0;  // the uneven kernel's block-Jacobi region is static
   g.flags = o ? o->flags : 0;
   g.max_iter = max_iter;
   g.restart = bs::kMaxRestart;

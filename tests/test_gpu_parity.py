@@ -83,11 +83,12 @@ class Case:
         return x.cpu().numpy(), iters.cpu().numpy(), resid.cpu().numpy(), status.cpu().numpy()
 
     def oracle(self, fmt, solver, precond=bs.PREC_JACOBI, tol=1e-10, max_iter=500, x0=None,
-               b=None, values=None, restart=30):
+               b=None, values=None, restart=30, block_size=8):
         v = self.oracle_values(fmt) if values is None else values
         return O.batch_solve(self.OP, v, self.batch.b if b is None else b, x0=x0,
                              fmt=O.CSR if fmt == bs.CSR else O.ELL, solver=SOLVER_O[solver],
-                             precond=precond, tol=tol, max_iter=max_iter, restart=restart)
+                             precond=precond, tol=tol, max_iter=max_iter, restart=restart,
+                             block_size=block_size)
 
 
 def check(case, g, o, tol=1e-10, fmt=bs.CSR, b=None, values=None, xtol=XTOL, itol=ITOL):
@@ -508,3 +509,90 @@ def test_absolute_criterion_cg_and_ell():
                        absolute=True)
     ge = c.gpu(bs.ELL, bs.BICGSTAB, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL)
     check_absolute(c, ge, oe, tol, b, fmt=bs.ELL)
+
+
+# ------------------------------------------------------------------ block Jacobi
+@pytest.mark.parametrize("bsz", [2, 4, 8])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+@pytest.mark.parametrize("gen", ["chem", "collision", "small"])
+def test_block_jacobi(gen, solver, bsz):
+    """Block-Jacobi preconditioner (blocks of bsz rows, the last one ragged
+    where bsz does not divide n) against the oracle: one-wave teams with the
+    bank-aware layout (n = 54), 1024-lane teams (n = 992), 32-lane teams sharing
+    a wave (n = 20).  GMRES on 1024-lane teams keeps its basis in LDS and has
+    no room for the block region: refused."""
+    bt = {"chem": lambda: W.chem_jacobian(1500, n=54, seed=8),
+          "collision": lambda: W.collision_stencil(24),
+          "small": lambda: W.chem_jacobian(700, n=20, seed=9)}[gen]()
+    c = Case(bt)
+    if gen == "collision" and solver == bs.GMRES:
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(bs.CSR, solver, precond=bs.PREC_BLOCK_JACOBI, block_size=bsz)
+        assert e.value.code == bs.ERR_UNSUPPORTED
+        return
+    for fmt in (bs.CSR, bs.ELL):
+        g = c.gpu(fmt, solver, precond=bs.PREC_BLOCK_JACOBI, block_size=bsz, max_iter=2000)
+        o = c.oracle(fmt, solver, precond=bs.PREC_BLOCK_JACOBI, block_size=bsz, max_iter=2000)
+        check(c, g, o, fmt=fmt)
+
+
+def spd_band(n, n_batch, seed):
+    """SPD pentadiagonal systems: a_ij = a_ji = -(1 + 0.5 U(0, 1)) for
+    0 < |i - j| <= 2, a_ii = 1.1 sum_j |a_ij| + 0.1."""
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    mask = np.abs(i - j) <= 2
+    rows, cols = np.nonzero(mask)
+    row_ptr = np.concatenate([[0], np.cumsum(mask.sum(1))]).astype(np.int32)
+    vals = np.empty((n_batch, rows.size))
+    for s in range(n_batch):
+        M = np.triu(-(1.0 + 0.5 * rng.random((n, n))), 1) * mask
+        M = M + M.T
+        np.fill_diagonal(M, 1.1 * np.abs(M).sum(1) + 0.1)
+        vals[s] = M[rows, cols]
+    b = 2 * rng.random((n_batch, n)) - 1
+    return W.Batch("spd_band", n, row_ptr, cols.astype(np.int32), vals, b, np.zeros_like(b))
+
+
+def test_block_jacobi_cg_and_rows_per_lane():
+    """CG on SPD systems (one wave per system, then 1024-lane teams of eleven
+    waves, where CG applies the preconditioner right after setting it up), and
+    two rows per lane (n = 1500: 1024-lane teams)."""
+    bt = spd_on_pattern(48, 400, seed=4)
+    c = Case(bt)
+    g = c.gpu(bs.CSR, bs.CG, precond=bs.PREC_BLOCK_JACOBI, block_size=4)
+    o = c.oracle(bs.CSR, bs.CG, precond=bs.PREC_BLOCK_JACOBI, block_size=4)
+    check(c, g, o)
+    cb = Case(spd_band(700, 30, seed=5))
+    for bsz in (2, 8):
+        g = cb.gpu(bs.CSR, bs.CG, precond=bs.PREC_BLOCK_JACOBI, block_size=bsz)
+        o = cb.oracle(bs.CSR, bs.CG, precond=bs.PREC_BLOCK_JACOBI, block_size=bsz)
+        check(cb, g, o)
+    c2 = Case(W.tridiag_stencil(n_batch=40, n=1500))
+    g = c2.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=4, max_iter=3000)
+    o = c2.oracle(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=4, max_iter=3000)
+    check(c2, g, o)
+    # two rows per lane of 1024-lane teams: blocks of 8 exceed a compute unit's LDS
+    with pytest.raises(bs.BatchSolveError) as e:
+        c2.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=8)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+def test_block_jacobi_zero_pivot_and_errors():
+    """A block whose first pivot is zero becomes the identity on both sides;
+    mixed precision with block Jacobi is refused; block sizes other than 2, 4
+    and 8 are invalid."""
+    bt = W.tridiag_stencil(n_batch=50, n=40)
+    v = bt.values.copy()
+    v[:, 0] = 0.0        # a_00 = 0 in every system
+    c = Case(bt)
+    g = c.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=4, values=dev(v))
+    o = c.oracle(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=4, values=v)
+    check(c, g, o, values=v)
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, precision=bs.MIXED)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    for bad in (3, 16, -2):
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=bad)
+        assert e.value.code == bs.ERR_INVALID_ARG
