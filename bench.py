@@ -7,7 +7,8 @@ stored entries at seed 0), A = I - 1e-6 J with J = +-10^U(-3,3), b ~ U(-1,1),
 x0 = 0 -- solved by FP64 BiCGSTAB with scalar Jacobi in BatchCsr to relative
 residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
-forms of the same batch, the uneven batch (100k banded systems with n in
+forms of the same batch and its solve with block Jacobi (blocks of 4 and 8
+rows), the uneven batch (100k banded systems with n in
 [16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
 stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the chemistry
 matrices stored as BatchDense (relative and absolute stop criteria), the learned
@@ -62,7 +63,8 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
     """Uneven batch in one persistent launch: ``args.uneven_batch`` banded
     nonsymmetric systems, n ~ U{16..1024}, band width ~ U{5..9}, BiCGSTAB +
     Jacobi to 1e-10, queue policy picked by the library's tuner, then timed as
-    eager launches and as replays of the captured graph (FP64 and mixed)."""
+    eager launches and as replays of the captured graph (FP64 and mixed with
+    scalar Jacobi, FP64 with block Jacobi on blocks of 8 rows)."""
     t0 = time.time()
     vb = W.uneven_banded(args.uneven_batch, 16, 1024, seed=0)
     gen_s = time.time() - t0
@@ -79,9 +81,11 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
            "n_batch": B, "total_rows": int(vb.b.size), "total_values": int(vb.values.size),
            "gen_seconds": gen_s}
     steps = max(3, args.steps // 4)
-    for name, prec in (("fp64", bs.FP64), ("mixed", bs.MIXED)):
-        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec)
-        args_ = (h.handle, vals, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter, iters, resid,
+    for name, prec, pc, bsz in (("fp64", bs.FP64, bs.PREC_JACOBI, 0),
+                                ("mixed", bs.MIXED, bs.PREC_JACOBI, 0),
+                                ("fp64_block_jacobi8", bs.FP64, bs.PREC_BLOCK_JACOBI, 8)):
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec, block_size=bsz)
+        args_ = (h.handle, vals, b, x, bs.BICGSTAB, pc, tol, max_iter, iters, resid,
                  status, opts)
         report = bs.bs_varbatch_tune(*args_, reps=2)
         torch.cuda.synchronize()
@@ -167,7 +171,7 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
     """Larger systems, FP64 against mixed precision: ``args.stencil_batch``
     nonsymmetric 9-point operators on a 32 x 31 grid (n = 992, 8554 stored
     entries), BiCGSTAB and GMRES(30) with scalar Jacobi to 1e-10 from x0 = 0,
-    BatchCsr.  One workgroup of 1024 lanes per system; the values stay in
+    BatchCsr, and BiCGSTAB with block Jacobi on blocks of 8 rows.  One workgroup of 1024 lanes per system; the values stay in
     registers, so the solve is bound by the LDS gathers of the SpMV and the
     team reductions, not by HBM."""
     t0 = time.time()
@@ -186,12 +190,17 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
            "nnz": nnz, "gen_seconds": gen_s}
     steps = max(5, args.steps // 10)
     alg = B * (8 * nnz + 16 * n + 16) + 4 * (n + 1) + 4 * nnz
-    for sname, solver in (("bicgstab", bs.BICGSTAB), ("gmres30", bs.GMRES)):
-        for pname, prec in (("fp64", bs.FP64), ("mixed", bs.MIXED)):
+    for sname, solver, pnames in (("bicgstab", bs.BICGSTAB, ("fp64", "mixed", "fp64_block_jacobi8")),
+                                  ("gmres30", bs.GMRES, ("fp64", "mixed"))):
+        for pname in pnames:
+            prec = bs.MIXED if pname == "mixed" else bs.FP64
+            bsz = 8 if pname.endswith("block_jacobi8") else 0
             opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec,
                                    restart=30 if solver == bs.GMRES else 0,
-                                   outer_iters=outer if prec == bs.MIXED else None)
-            a = (bs.CSR, P.handle, vals, b, x, solver, bs.PREC_JACOBI, tol, 2000, iters, resid,
+                                   outer_iters=outer if prec == bs.MIXED else None,
+                                   block_size=bsz)
+            pc = bs.PREC_BLOCK_JACOBI if bsz else bs.PREC_JACOBI
+            a = (bs.CSR, P.handle, vals, b, x, solver, pc, tol, 2000, iters, resid,
                  status, opts)
             for _ in range(max(3, args.warmup // 20)):
                 bs.bs_batch_solve(*a)
@@ -421,15 +430,16 @@ def main() -> int:
     tol, max_iter = 1e-10, 500
     torch.cuda.synchronize()
 
-    def run(fmt, precision):
+    def run(fmt, precision, block=0):
         v = vals_csr if fmt == bs.CSR else vals_ell
-        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=precision)
-        bs.bs_batch_solve(fmt, P.handle, v, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter,
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=precision, block_size=block)
+        pc = bs.PREC_BLOCK_JACOBI if block else bs.PREC_JACOBI
+        bs.bs_batch_solve(fmt, P.handle, v, b, x, bs.BICGSTAB, pc, tol, max_iter,
                           iters, resid, status, opts)
 
-    def timed(fmt, precision, steps, warmup):
+    def timed(fmt, precision, steps, warmup, block=0):
         for _ in range(warmup):
-            run(fmt, precision)
+            run(fmt, precision, block)
         torch.cuda.synchronize()
         # the K launches run back to back on this stream between two events;
         # one launch is one step, so the average launch duration is region / K
@@ -437,7 +447,7 @@ def main() -> int:
         t_wall = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            run(fmt, precision)
+            run(fmt, precision, block)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_wall
@@ -457,11 +467,15 @@ def main() -> int:
 
     variants = {}
     if not args.no_variants:
-        for name, fmt, prec in (("ell_fp64", bs.ELL, bs.FP64), ("csr_fp64", bs.CSR, bs.FP64),
-                                ("csr_mixed", bs.CSR, bs.MIXED), ("ell_mixed", bs.ELL, bs.MIXED)):
-            if fmt == headline_fmt and prec == bs.FP64:
+        for name, fmt, prec, blk in (("ell_fp64", bs.ELL, bs.FP64, 0),
+                                     ("csr_fp64", bs.CSR, bs.FP64, 0),
+                                     ("csr_mixed", bs.CSR, bs.MIXED, 0),
+                                     ("ell_mixed", bs.ELL, bs.MIXED, 0),
+                                     ("csr_fp64_block_jacobi4", bs.CSR, bs.FP64, 4),
+                                     ("csr_fp64_block_jacobi8", bs.CSR, bs.FP64, 8)):
+            if fmt == headline_fmt and prec == bs.FP64 and not blk:
                 continue
-            r = timed(fmt, prec, max(10, args.steps // 2), args.warmup)
+            r = timed(fmt, prec, max(10, args.steps // 2), args.warmup, blk)
             r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
             variants[name] = r
             progress(f"variant {name}: {r['ms_per_step']:.4f} ms")

@@ -584,7 +584,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.alt_used = opts ? opts->alt_used : nullptr;
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
   a.layout = (pattern->d_layout && pl.info.team == bs::kWave && pl.info.rows_per_lane == 1 &&
-              a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT))
+              a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT) &&
+              a.block <= 1)  // block Jacobi needs the rows of a block on consecutive lanes
                  ? pattern->d_layout
                  : nullptr;
   // Persistent grid: as many workgroups as can be resident at once, each
@@ -592,7 +593,10 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;
   const int cus = device_cus();
   if (cus < 1) return BS_ERR_HIP;
-  const int64_t resident = (int64_t)pl.k->occupancy((unsigned)pl.info.lds_bytes) * cus;
+  // Resident groups per CU, asked with 1 KiB more LDS per group than used: a
+  // group count that would fill the CU's LDS to the last granule is not always
+  // placed at once, and a group left over runs only after another one ends.
+  const int64_t resident = (int64_t)pl.k->occupancy((unsigned)pl.info.lds_bytes + 1024) * cus;
   const int64_t grid = std::min(groups, resident);
   const hipError_t e = pl.k->launch(a, (unsigned)grid, (unsigned)pl.info.lds_bytes,
                                     (hipStream_t)stream);

@@ -29,10 +29,20 @@ __device__ __forceinline__ double stop_limit(const G& g, double bn) {
 }
 
 // ------------------------------------------------------------ block Jacobi
+// v of lane src of this wave (a cross-lane permute through the LDS crossbar,
+// no memory access); every lane must be active.
+__device__ __forceinline__ double shfl(double v, int src) {
+  const int a = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 // Blocks of bs consecutive rows (bs = 2, 4 or 8; the last block may be
 // shorter); M = the inverse of the block diagonal of A.  Per team in LDS: the
-// inverse rows, row i at binv[i*bs .. i*bs+bs-1] holding entries (i, b0..b0+bs-1)
-// (b0 = i - i % bs), and a row-indexed exchange buffer pbuf[rows].  The rows
+// inverse stored by columns, binv[j*rows + i] = entry (i, b0 + j) (b0 = i - i %
+// bs), so that the lanes of a wave touch consecutive elements, and a
+// row-indexed exchange buffer pbuf[rows].  The rows
 // of one block always sit in one wave (bs divides the rows a wave holds), so a
 // wavefront-scope fence orders the exchanges; nothing extra stays in
 // registers.
@@ -67,7 +77,7 @@ __device__ void bj_setup(TM& tm, RW& A, const KArgs& g) {
     const int i = lane + r * per;
     pbuf[i] = 0.0;
 #pragma unroll 1
-    for (int j = 0; j < bs; ++j) binv[i * bs + j] = 0.0;
+    for (int j = 0; j < bs; ++j) binv[j * rows + i] = 0.0;
   }
   // each row's own index into buffer 1, then gather it through the slots
 #pragma unroll
@@ -86,56 +96,59 @@ __device__ void bj_setup(TM& tm, RW& A, const KArgs& g) {
 #pragma unroll
       for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
         if (A.ok[r] && A.real(r, k) && col[k - k0] >= b0 && col[k - k0] < b0 + bs)
-          binv[i * bs + (col[k - k0] - b0)] = A.a[r][k];
+          binv[(col[k - k0] - b0) * rows + i] = A.a[r][k];
       // four gathers in flight at a time
       __asm__ volatile("" ::: "memory");
     }
   }
   wave_lds_fence();
-#pragma unroll 1
-  for (int p = 0; p < bs; ++p) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = A.row[r], b0 = i - (i & (bs - 1));
-      if (A.ok[r] && i - b0 == p) {
-        const double piv = binv[i * bs + p];
-        if (piv == 0.0 || !__builtin_isfinite(piv)) pbuf[b0] = 1.0;
-        binv[i * bs + p] = 1.0;
-#pragma unroll 1
-        for (int j = 0; j < bs; ++j) binv[i * bs + j] = binv[i * bs + j] / piv;
-      }
-    }
-    wave_lds_fence();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = A.row[r], b0 = i - (i & (bs - 1));
-      if (A.ok[r] && i - b0 != p && b0 + p < n) {
-        const double f = binv[i * bs + p];
-        binv[i * bs + p] = 0.0;
-#pragma unroll 1
-        for (int j = 0; j < bs; ++j)
-          binv[i * bs + j] = fma(-f, binv[(b0 + p) * bs + j], binv[i * bs + j]);
-      }
-    }
-    wave_lds_fence();
-  }
+  // Gauss-Jordan in registers.  The rows of a block sit on consecutive lanes
+  // of one wave (row i on lane i of its team: the plain layout), so each lane
+  // reads the pivot row from its lane with a cross-lane permute.  Every row
+  // other than p subtracts its entry p times row p scaled by one reciprocal of
+  // the pivot; row p takes the scaled row.  A zero or non-finite pivot, or a
+  // non-finite entry of the result, raises the block's flag (the exchange
+  // entry of its first row, in the same wave) and the block becomes the
+  // identity.  All lanes run every step (the permutes read every lane).
+  const int me = threadIdx.x & (kWave - 1);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (!A.ok[r]) continue;
-    const int i = A.row[r];
-    bool fin = true;
-#pragma unroll 1
-    for (int j = 0; j < bs; ++j) fin = fin && __builtin_isfinite(binv[i * bs + j]);
-    if (!fin) pbuf[i - (i & (bs - 1))] = 1.0;
-  }
-  wave_lds_fence();
+    const int i = A.row[r], ib = i & (bs - 1), b0 = i - ib;
+    double m[kMaxBlock];
+    bool bad = false;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (!A.ok[r]) continue;
-    const int i = A.row[r];
-    if (pbuf[i - (i & (bs - 1))] != 0.0) {
+    for (int j = 0; j < kMaxBlock; ++j) m[j] = (A.ok[r] && j < bs) ? binv[j * rows + i] : 0.0;
 #pragma unroll 1
-      for (int j = 0; j < bs; ++j) binv[i * bs + j] = (j == (i & (bs - 1))) ? 1.0 : 0.0;
+    for (int p = 0; p < bs; ++p) {
+      const int src = me - ib + p;  // lane of row b0 + p
+      double q[kMaxBlock];
+#pragma unroll
+      for (int j = 0; j < kMaxBlock; ++j) q[j] = j < bs ? shfl(m[j], src) : 0.0;
+      double piv = q[0], f = m[0];
+#pragma unroll
+      for (int j = 1; j < kMaxBlock; ++j) {
+        piv = j == p ? q[j] : piv;
+        f = j == p ? m[j] : f;
+      }
+      const bool act = A.ok[r] && b0 + p < n, own = ib == p;
+      if (act && (piv == 0.0 || !__builtin_isfinite(piv))) bad = true;
+      const double rp = 1.0 / piv;
+#pragma unroll
+      for (int j = 0; j < kMaxBlock; ++j) {
+        const double qs = (j == p ? 1.0 : q[j]) * rp;  // row p after this step
+        const double upd = own ? qs : fma(-f, qs, j == p ? 0.0 : m[j]);
+        m[j] = act ? upd : m[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxBlock; ++j) bad = bad || (j < bs && !__builtin_isfinite(m[j]));
+    if (A.ok[r] && bad) pbuf[b0] = 1.0;
+    wave_lds_fence();
+    if (A.ok[r]) {
+      const bool ident = pbuf[b0] != 0.0;
+#pragma unroll
+      for (int j = 0; j < kMaxBlock; ++j)
+        if (j < bs) binv[j * rows + i] = ident ? (j == ib ? 1.0 : 0.0) : m[j];
     }
   }
   wave_lds_fence();
@@ -145,7 +158,7 @@ __device__ void bj_setup(TM& tm, RW& A, const KArgs& g) {
 }
 
 // z = M v for the block-Jacobi M (rows past n give 0).  All lanes of a wave call
-// it together.  Two entries are loaded at a time, bounding the registers held.
+// it together.
 template <class T, class TM, class RW>
 __device__ __forceinline__ void bj_apply(TM& tm, const RW& A, const KArgs& g,
                                          const T (&v)[RW::R], T (&z)[RW::R]) {
@@ -162,10 +175,20 @@ __device__ __forceinline__ void bj_apply(TM& tm, const RW& A, const KArgs& g,
     T acc = (T)0;
     if (A.ok[r]) {
       const int i = A.row[r], b0 = i - (i & (bs - 1));
-#pragma unroll 1
-      for (int j = 0; j < bs; j += 2)
-        acc = fma((T)binv[i * bs + j + 1], (T)pbuf[b0 + j + 1],
-                  fma((T)binv[i * bs + j], (T)pbuf[b0 + j], acc));
+      // four columns of the inverse row and of the block's slice of v per
+      // batch of loads
+#pragma unroll
+      for (int h = 0; h < kMaxBlock; h += 4) {
+        if (h >= bs) break;
+        double w[4], u[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          w[j] = h + j < bs ? binv[(h + j) * rows + i] : 0.0;
+          u[j] = h + j < bs ? pbuf[b0 + h + j] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = fma((T)w[j], (T)u[j], acc);
+      }
     }
     z[r] = acc;
   }
