@@ -17,8 +17,8 @@ import numpy as np
 from . import build as _build
 
 CSR, ELL = 0, 1
-CG, BICGSTAB, GMRES = 0, 1, 2
-PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI = 0, 1, 2
+CG, BICGSTAB, GMRES, TRSV_LOWER, TRSV_UPPER = 0, 1, 2, 3, 4
+PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI, PREC_ILU = 0, 1, 2, 3
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 
 _lib = None
@@ -44,6 +44,11 @@ def lib():
         L.or_batch_jacobi.restype = None
         L.or_batch_block_jacobi.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, I, f64p]
         L.or_batch_block_jacobi.restype = None
+        L.or_batch_ilu0.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, i32p]
+        L.or_batch_ilu0.restype = None
+        L.or_batch_ilu0_apply.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p,
+                                          f64p, f64p]
+        L.or_batch_ilu0_apply.restype = None
         L.or_dot.argtypes = [I, f64p, f64p]
         L.or_dot.restype = D
         L.or_csr_to_ell.argtypes = [I, i32p, i32p, C.c_void_p]
@@ -108,8 +113,10 @@ def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = 
     """Solve every system; ``values`` in the layout of ``fmt``.
 
     Stop test (Tab. 2): relative ||r|| <= tol ||b|| by default, absolute
-    ||r|| <= tol with ``absolute``.  ``precond``: none, scalar Jacobi, or block
-    Jacobi with blocks of ``block_size`` consecutive rows.  Returns ``(x, iters, resid, status)``;
+    ||r|| <= tol with ``absolute``.  ``precond``: none, scalar Jacobi, block
+    Jacobi with blocks of ``block_size`` consecutive rows, or ILU(0).
+    ``solver`` TRSV_LOWER / TRSV_UPPER solve with the lower / upper triangle of
+    A (diagonal included) by substitution.  Returns ``(x, iters, resid, status)``;
     ``resid`` is the true residual ||b - A x||, divided by ||b|| for the
     relative criterion.
     """
@@ -156,6 +163,29 @@ def block_jacobi(pat: Pattern, values, bs: int, fmt: int = CSR) -> np.ndarray:
     rp, ci, nnz, w, ec = pat.args(fmt)
     lib().or_batch_block_jacobi(fmt, B, pat.n, rp, ci, nnz, w, ec, v, int(bs), out)
     return out
+
+
+def ilu0(pat: Pattern, values, fmt: int = CSR):
+    """ILU(0) factors ``[B][n][n]`` (dense, L strictly below the diagonal with
+    unit diagonal implied, U on and above, zero off the pattern) and a flag per
+    system that is False where a pivot was zero or an entry not finite."""
+    v = _f64(values)
+    B = v.shape[0]
+    lu = np.empty((B, pat.n, pat.n))
+    ok = np.empty(B, np.int32)
+    rp, ci, nnz, w, ec = pat.args(fmt)
+    lib().or_batch_ilu0(fmt, B, pat.n, rp, ci, nnz, w, ec, v, lu, ok)
+    return lu, ok.astype(bool)
+
+
+def ilu0_apply(pat: Pattern, values, lu, v_in, fmt: int = CSR) -> np.ndarray:
+    """z = (L U)^{-1} v per system with the factors returned by ``ilu0``."""
+    v = _f64(values)
+    x = _f64(v_in)
+    z = np.empty_like(x)
+    rp, ci, nnz, w, ec = pat.args(fmt)
+    lib().or_batch_ilu0_apply(fmt, x.shape[0], pat.n, rp, ci, nnz, w, ec, v, _f64(lu), x, z)
+    return z
 
 
 def jacobi(pat: Pattern, values, fmt: int = CSR) -> np.ndarray:

@@ -24,6 +24,11 @@
  *     iteration; GMRES counts Arnoldi steps across restarts;
  *   - breakdown means an exact zero of the quantity that is divided by;
  *   - scalar Jacobi uses 1 where the diagonal entry is zero or not stored;
+ *   - ILU(0) is the incomplete factorization on the pattern of A (Saad 2003,
+ *     Sec. 10.3.2), without pivoting; if a pivot is zero or an entry of the
+ *     factors is not finite, the system is solved without a preconditioner;
+ *   - BatchTrsv solves with the lower (or upper) triangle of A, diagonal
+ *     included; a zero or absent diagonal entry is a breakdown (x = 0);
  *   - ||b|| = 0 returns x = 0 with zero iterations, converged.
  */
 #include <math.h>
@@ -32,8 +37,8 @@
 #include <string.h>
 
 enum { OR_CSR = 0, OR_ELL = 1 };
-enum { OR_CG = 0, OR_BICGSTAB = 1, OR_GMRES = 2 };
-enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1, OR_PREC_BLOCK_JACOBI = 2 };
+enum { OR_CG = 0, OR_BICGSTAB = 1, OR_GMRES = 2, OR_TRSV_LOWER = 3, OR_TRSV_UPPER = 4 };
+enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1, OR_PREC_BLOCK_JACOBI = 2, OR_PREC_ILU = 3 };
 enum { OR_MAX_BLOCK = 16 };
 enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_BREAKDOWN = 2, OR_NONFINITE = 3 };
 
@@ -147,12 +152,84 @@ static void block_jacobi(const or_mat *A, int bs, double *inv, double *work)
     }
 }
 
+/* A as a dense row-major n x n array F (absent entries 0) and its pattern as
+ * a 0/1 mask P of the same shape. */
+static void to_dense(const or_mat *A, double *F, unsigned char *P)
+{
+    int n = A->n;
+    for (size_t e = 0; e < (size_t)n * n; ++e) { F[e] = 0.0; P[e] = 0; }
+    for (int i = 0; i < n; ++i) {
+        if (A->fmt == OR_CSR) {
+            for (int k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) {
+                F[(size_t)i * n + A->col[k]] = A->val[k];
+                P[(size_t)i * n + A->col[k]] = 1;
+            }
+        } else {
+            for (int s = 0; s < A->width; ++s) {
+                int c = A->ecol[(size_t)s * n + i];
+                if (c < 0) continue;
+                F[(size_t)i * n + c] = A->val[(size_t)s * n + i];
+                P[(size_t)i * n + c] = 1;
+            }
+        }
+    }
+}
+
+/* ILU(0) (Tab. 2's BatchIlu; Saad 2003, Sec. 10.3.2, the IKJ form): on the
+ * dense copy F of A, for each row i and each k < i in the pattern of row i,
+ * in increasing k: F_ik /= F_kk, then F_ij -= F_ik F_kj for every j > k in the
+ * pattern of row i (F_kj is zero off the pattern, as it is never written).
+ * Afterwards F holds L (strictly below the diagonal, unit diagonal implied)
+ * and U (diagonal and above).  Returns 1, or 0 if a pivot F_kk is zero or an
+ * entry of the factors is not finite. */
+static int ilu0(int n, double *F, const unsigned char *P)
+{
+    for (int i = 1; i < n; ++i)
+        for (int k = 0; k < i; ++k) {
+            if (!P[(size_t)i * n + k]) continue;
+            F[(size_t)i * n + k] = F[(size_t)i * n + k] / F[(size_t)k * n + k];
+            for (int j = k + 1; j < n; ++j)
+                if (P[(size_t)i * n + j])
+                    F[(size_t)i * n + j] = F[(size_t)i * n + j] -
+                                           F[(size_t)i * n + k] * F[(size_t)k * n + j];
+        }
+    for (int k = 0; k < n; ++k)
+        if (F[(size_t)k * n + k] == 0.0) return 0;
+    for (size_t e = 0; e < (size_t)n * n; ++e)
+        if (P[e] && !isfinite(F[e])) return 0;
+    return 1;
+}
+
+/* z = (L U)^{-1} v: forward substitution with the unit lower factor, then
+ * backward substitution with the upper one, each sum in increasing column
+ * order over the pattern. */
+static void ilu_apply(int n, const double *F, const unsigned char *P, const double *v, double *z)
+{
+    for (int i = 0; i < n; ++i) {
+        double acc = v[i];
+        for (int k = 0; k < i; ++k)
+            if (P[(size_t)i * n + k]) acc = acc - F[(size_t)i * n + k] * z[k];
+        z[i] = acc;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double acc = z[i];
+        for (int j = i + 1; j < n; ++j)
+            if (P[(size_t)i * n + j]) acc = acc - F[(size_t)i * n + j] * z[j];
+        z[i] = acc / F[(size_t)i * n + i];
+    }
+}
+
 /* The preconditioner as solvers apply it: z = M v, with M = diag(d) (scalar
- * Jacobi, or d = 1 for none) or the block-Jacobi inverse (bs > 1). */
-typedef struct { int bs; const double *d, *inv; } or_prec;
+ * Jacobi, or d = 1 for none), the block-Jacobi inverse (bs > 1) or the ILU(0)
+ * factors (lu non-null). */
+typedef struct { int bs; const double *d, *inv, *lu; const unsigned char *mask; } or_prec;
 
 static void prec_apply(const or_prec *M, int n, const double *v, double *z)
 {
+    if (M->lu) {
+        ilu_apply(n, M->lu, M->mask, v, z);
+        return;
+    }
     if (M->bs <= 1) {
         for (int i = 0; i < n; ++i) z[i] = M->d[i] * v[i];
         return;
@@ -362,6 +439,47 @@ static or_result solve_gmres(const or_mat *A, const or_prec *M, const double *b,
     }
 }
 
+/* ---- BatchTrsv (Tab. 2): T x = b with T the lower (or upper) triangle of A,
+ *      diagonal included, by forward (backward) substitution.  A zero
+ *      diagonal entry is a breakdown: x = 0.  Iterations: 0. ---------------- */
+static or_result solve_trsv(const or_mat *A, int lower, const double *b, double *x,
+                            double rs, double *F, unsigned char *P, double *t)
+{
+    int n = A->n;
+    or_result res;
+    to_dense(A, F, P);
+    for (int i = 0; i < n; ++i)
+        if (F[(size_t)i * n + i] == 0.0) {
+            for (int j = 0; j < n; ++j) x[j] = 0.0;
+            res.iters = 0; res.status = OR_BREAKDOWN; res.resid = nrm2(n, b) / rs;
+            return res;
+        }
+    for (int q = 0; q < n; ++q) {
+        int i = lower ? q : n - 1 - q;
+        double acc = b[i];
+        int j0 = lower ? 0 : i + 1, j1 = lower ? i : n;
+        for (int j = j0; j < j1; ++j)
+            if (P[(size_t)i * n + j]) acc = acc - F[(size_t)i * n + j] * x[j];
+        x[i] = acc / F[(size_t)i * n + i];
+    }
+    /* true residual of the triangular system */
+    double acc2 = 0.0;
+    int fin = 1;
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        int j0 = lower ? 0 : i, j1 = lower ? i + 1 : n;
+        for (int j = j0; j < j1; ++j)
+            if (P[(size_t)i * n + j]) acc += F[(size_t)i * n + j] * x[j];
+        t[i] = b[i] - acc;
+        acc2 += t[i] * t[i];
+        if (!isfinite(x[i])) fin = 0;
+    }
+    res.iters = 0;
+    res.resid = sqrt(acc2) / rs;
+    res.status = (fin && isfinite(res.resid)) ? OR_CONVERGED : OR_NONFINITE;
+    return res;
+}
+
 static size_t workspace_doubles(int solver, int n, int m)
 {
     if (solver == OR_CG) return (size_t)4 * n + n;
@@ -373,7 +491,7 @@ static size_t workspace_doubles(int solver, int n, int m)
  * 1 tests ||r|| <= tol and reports ||b - A x||. */
 static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
                            const double *b, double *x, double tol, int absolute, int max_iter,
-                           int m, double *ws)
+                           int m, double *ws, double *F, unsigned char *P)
 {
     int n = A->n;
     double *d = ws;                         /* n doubles: d */
@@ -393,13 +511,19 @@ static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
         return res;
     }
     /* blocks of one row are scalar Jacobi */
+    double lim = absolute ? tol : tol * bn, rs = absolute ? 1.0 : bn;
+    if (solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER)
+        return solve_trsv(A, solver == OR_TRSV_LOWER, b, x, rs, F, P, work);
     jacobi_diag(A, precond == OR_PREC_BLOCK_JACOBI && bs <= 1 ? OR_PREC_JACOBI : precond, d);
-    M.bs = 1; M.d = d; M.inv = inv;
+    M.bs = 1; M.d = d; M.inv = inv; M.lu = NULL; M.mask = NULL;
     if (precond == OR_PREC_BLOCK_JACOBI && bs > 1) {
         block_jacobi(A, bs, inv, gj);
         M.bs = bs;
     }
-    double lim = absolute ? tol : tol * bn, rs = absolute ? 1.0 : bn;
+    if (precond == OR_PREC_ILU) {
+        to_dense(A, F, P);
+        if (ilu0(A->n, F, P)) { M.lu = F; M.mask = P; }
+    }
     if (solver == OR_CG) return solve_cg(A, &M, b, x, rs, lim, max_iter, work);
     if (solver == OR_BICGSTAB) return solve_bicgstab(A, &M, b, x, rs, lim, max_iter, work);
     return solve_gmres(A, &M, b, x, rs, lim, max_iter, m, work);
@@ -426,22 +550,27 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
     int m = restart > 0 ? restart : 30;
     size_t wsz = workspace_doubles(solver, n, m) + n + (size_t)n * OR_MAX_BLOCK +
                  2 * OR_MAX_BLOCK * OR_MAX_BLOCK;
+    int dense = precond == OR_PREC_ILU || solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER;
     if (block_size < 1 || block_size > OR_MAX_BLOCK) block_size = 1;
     if (nthreads < 1) nthreads = 1;
     #pragma omp parallel num_threads(nthreads)
     {
         double *ws = (double *)malloc(wsz * sizeof(double));
+        double *F = dense ? (double *)malloc((size_t)n * n * sizeof(double)) : NULL;
+        unsigned char *P = dense ? (unsigned char *)malloc((size_t)n * n) : NULL;
         #pragma omp for schedule(dynamic, 8)
         for (int64_t s = 0; s < n_batch; ++s) {
             or_mat A;
             make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
             or_result res = solve_one(&A, solver, precond, block_size, b + (size_t)s * n,
-                                      x + (size_t)s * n, tol, absolute, max_iter, m, ws);
+                                      x + (size_t)s * n, tol, absolute, max_iter, m, ws, F, P);
             iters[s] = res.iters;
             status[s] = res.status;
             resid[s] = res.resid;
         }
         free(ws);
+        free(F);
+        free(P);
     }
     return 0;
 }
@@ -506,6 +635,43 @@ void or_batch_block_jacobi(int fmt, int64_t n_batch, int n, const int *row_ptr,
         make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
         block_jacobi(&A, bs, inv + (size_t)s * n * bs, work);
     }
+}
+
+/* ILU(0) factors per system (for pinning): lu [n_batch][n][n] dense row-major,
+ * L strictly below the diagonal, U on and above, zero off the pattern;
+ * ok[s] = 0 where the factorization failed (zero pivot, non-finite entry). */
+void or_batch_ilu0(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                   int nnz, int width, const int *ell_col, const double *values, double *lu,
+                   int *ok)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    unsigned char *P = (unsigned char *)malloc((size_t)n * n);
+    for (int64_t s = 0; s < n_batch; ++s) {
+        or_mat A;
+        double *F = lu + (size_t)s * n * n;
+        make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+        to_dense(&A, F, P);
+        ok[s] = ilu0(n, F, P);
+    }
+    free(P);
+}
+
+/* z = (L U)^{-1} v per system with the factors of or_batch_ilu0 (for pinning). */
+void or_batch_ilu0_apply(int fmt, int64_t n_batch, int n, const int *row_ptr,
+                         const int *col_idx, int nnz, int width, const int *ell_col,
+                         const double *values, const double *lu, const double *v, double *z)
+{
+    size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
+    unsigned char *P = (unsigned char *)malloc((size_t)n * n);
+    double *G = (double *)malloc((size_t)n * n * sizeof(double));
+    for (int64_t s = 0; s < n_batch; ++s) {
+        or_mat A;
+        make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
+        to_dense(&A, G, P);
+        ilu_apply(n, lu + (size_t)s * n * n, P, v + (size_t)s * n, z + (size_t)s * n);
+    }
+    free(G);
+    free(P);
 }
 
 double or_dot(int n, const double *a, const double *b) { return dot(n, a, b); }

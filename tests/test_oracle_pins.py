@@ -575,3 +575,126 @@ def test_block_jacobi_zero_pivot_gives_identity():
     inv = O.block_jacobi(P, vals, 2)[0]
     assert np.array_equal(inv[:2], np.eye(2))
     assert np.allclose(inv[2:], np.linalg.inv(A[2:, 2:]), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ ILU(0), trsv
+def ilu_case(rng, n, fill, B=3, dom=1.5):
+    """Random pattern with a full diagonal, values U(-1, 1), diagonal dominant
+    by rows and columns (so LU without pivoting is stable and partial pivoting
+    keeps the diagonal)."""
+    mask = rng.random((n, n)) < fill
+    np.fill_diagonal(mask, True)
+    As = np.where(mask[None], rng.random((B, n, n)) * 2 - 1, 0.0)
+    for s in range(B):
+        off = np.abs(As[s]).sum(1) + np.abs(As[s]).sum(0)
+        As[s][np.diag_indices(n)] = dom * off + 1.0
+    rows, cols = np.nonzero(mask)
+    rp = np.concatenate([[0], np.cumsum(mask.sum(1))]).astype(np.int32)
+    P = O.Pattern(n, rp, cols.astype(np.int32))
+    return P, mask, As, np.ascontiguousarray(As[:, rows, cols])
+
+
+def test_ilu0_full_pattern_is_lu():
+    """On a full pattern ILU(0) is LU without pivoting: with column dominance
+    scipy's partially pivoted LU keeps the identity permutation and must give
+    the same factors."""
+    rng = np.random.default_rng(21)
+    P, mask, As, vals = ilu_case(rng, 12, 1.0)
+    lu, ok = O.ilu0(P, vals)
+    assert ok.all()
+    for s in range(As.shape[0]):
+        Pm, L, U = scipy.linalg.lu(As[s])
+        assert np.array_equal(Pm, np.eye(12))
+        assert np.allclose(np.tril(lu[s], -1), L - np.eye(12), rtol=1e-13, atol=1e-15)
+        assert np.allclose(np.triu(lu[s]), U, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,fill", [(9, 0.3), (40, 0.15), (64, 0.35)])
+def test_ilu0_matches_a_on_the_pattern(n, fill):
+    """The defining property of ILU(0): (L U)_ij = a_ij for every (i, j) of the
+    pattern, and L, U vanish off it.  A dropped or misplaced update breaks it."""
+    rng = np.random.default_rng(22 + n)
+    P, mask, As, vals = ilu_case(rng, n, fill)
+    lu, ok = O.ilu0(P, vals)
+    assert ok.all()
+    for s in range(As.shape[0]):
+        F = lu[s]
+        assert np.all(F[~mask] == 0)
+        L, U = np.tril(F, -1) + np.eye(n), np.triu(F)
+        prod = L @ U
+        scale = np.abs(L) @ np.abs(U)
+        assert np.all(np.abs(prod - As[s])[mask] <= 8 * n * EPS * scale[mask])
+    # ELL storage gives the same factors
+    lu_e, _ = O.ilu0(P, O.csr_values_to_ell(P, vals), fmt=O.ELL)
+    assert np.array_equal(lu, lu_e)
+
+
+def test_ilu0_apply_solves_lu():
+    """z = (L U)^{-1} v: L (U z) reproduces v."""
+    rng = np.random.default_rng(23)
+    P, mask, As, vals = ilu_case(rng, 30, 0.2)
+    lu, _ = O.ilu0(P, vals)
+    v = rng.random((3, 30)) - 0.5
+    z = O.ilu0_apply(P, vals, lu, v)
+    for s in range(3):
+        L, U = np.tril(lu[s], -1) + np.eye(30), np.triu(lu[s])
+        assert np.allclose(L @ (U @ z[s]), v[s], rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("solver", [O.BICGSTAB, O.GMRES])
+def test_ilu0_exact_on_tridiagonal(solver):
+    """A tridiagonal pattern is closed under elimination: ILU(0) is the exact LU,
+    M = A^{-1}, and the first step solves the system."""
+    bt = W.tridiag_stencil(n_batch=8, n=50, seed=3)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    x, it, res, st = O.batch_solve(P, bt.values, bt.b, solver=solver, precond=O.PREC_ILU,
+                                   tol=1e-12)
+    assert np.all(st == O.CONVERGED) and np.all(it == 1)
+    A = csr_dense(bt.n, bt.row_ptr, bt.col_idx, bt.values[0])
+    assert np.allclose(x[0], np.linalg.solve(A, bt.b[0]), rtol=1e-11, atol=1e-13)
+
+
+def test_ilu0_zero_pivot_runs_unpreconditioned():
+    """A zero pivot (a_00 = 0) makes M the identity: the result is bit-identical
+    to the unpreconditioned solve."""
+    rng = np.random.default_rng(24)
+    P, mask, As, vals = ilu_case(rng, 20, 0.3)
+    d0 = np.flatnonzero(P.col_idx[P.row_ptr[0]:P.row_ptr[1]] == 0)[0] + P.row_ptr[0]
+    vals = vals.copy()
+    vals[:, d0] = 0.0
+    _, ok = O.ilu0(P, vals)
+    assert not ok.any()
+    b = rng.random((3, 20)) - 0.5
+    a = O.batch_solve(P, vals, b, solver=O.GMRES, precond=O.PREC_ILU)
+    c = O.batch_solve(P, vals, b, solver=O.GMRES, precond=O.PREC_NONE)
+    for u, v in zip(a, c):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("lower", [True, False])
+def test_trsv_matches_scipy(lower):
+    """BatchTrsv: the triangle of A (diagonal included) solved by substitution
+    against scipy's triangular solver; entries of the other triangle are
+    ignored."""
+    rng = np.random.default_rng(25)
+    P, mask, As, vals = ilu_case(rng, 33, 0.25)
+    b = rng.random((3, 33)) - 0.5
+    x, it, res, st = O.batch_solve(P, vals, b, solver=O.TRSV_LOWER if lower else O.TRSV_UPPER)
+    assert np.all(st == O.CONVERGED) and np.all(it == 0)
+    for s in range(3):
+        T = np.tril(As[s]) if lower else np.triu(As[s])
+        ref = scipy.linalg.solve_triangular(T, b[s], lower=lower)
+        assert np.allclose(x[s], ref, rtol=1e-12, atol=1e-14)
+        assert res[s] <= 1e-14
+
+
+def test_trsv_zero_diagonal_breaks_down():
+    rng = np.random.default_rng(26)
+    P, mask, As, vals = ilu_case(rng, 10, 0.3)
+    d5 = np.flatnonzero(P.col_idx[P.row_ptr[5]:P.row_ptr[6]] == 5)[0] + P.row_ptr[5]
+    vals = vals.copy()
+    vals[1, d5] = 0.0
+    b = rng.random((3, 10)) - 0.5
+    x, it, res, st = O.batch_solve(P, vals, b, solver=O.TRSV_LOWER)
+    assert list(st) == [O.CONVERGED, O.BREAKDOWN, O.CONVERGED]
+    assert np.all(x[1] == 0) and res[1] == 1.0
