@@ -43,13 +43,22 @@ typedef enum { BS_CSR = 0, BS_ELL = 1, BS_DENSE = 2 } bs_format;
  * rotations. */
 typedef enum { BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2 } bs_solver;
 
-/* Preconditioners: none, scalar Jacobi of Tab. 2 (d_i = 1/a_ii, 1 where the
- * diagonal entry is zero or not stored), or block Jacobi: the inverse of the
+/* Preconditioners (Tab. 2): none; scalar Jacobi (d_i = 1/a_ii, 1 where the
+ * diagonal entry is zero or not stored); block Jacobi: the inverse of the
  * block diagonal of A with blocks of bs_options.block_size consecutive rows
  * (2, 4 or 8; the last block may be shorter), each block inverted by
  * Gauss-Jordan elimination without pivoting, a block that meets a zero or
- * non-finite pivot (or gives a non-finite inverse) taken as the identity. */
-typedef enum { BS_PREC_NONE = 0, BS_PREC_JACOBI = 1, BS_PREC_BLOCK_JACOBI = 2 } bs_precond;
+ * non-finite pivot (or gives a non-finite inverse) taken as the identity;
+ * ILU(0) (BatchIlu): the incomplete LU factorization on the pattern of A
+ * without pivoting, applied by a forward and a backward substitution, the
+ * identity for a system whose factorization meets a zero pivot or gives a
+ * non-finite entry.  ILU(0) takes systems of at most 64 rows (one wave each,
+ * BS_ERR_UNSUPPORTED beyond), BS_BICGSTAB or BS_GMRES in FP64 (CG needs a
+ * symmetric preconditioner: BS_ERR_UNSUPPORTED), and not the uneven-batch
+ * entry points.  Block Jacobi and ILU(0) are FP64 only. */
+typedef enum {
+  BS_PREC_NONE = 0, BS_PREC_JACOBI = 1, BS_PREC_BLOCK_JACOBI = 2, BS_PREC_ILU = 3
+} bs_precond;
 
 /* BS_FP64: everything in FP64.  BS_MIXED: iterative refinement whose outer loop
  * (true residual b - A x, its norm, the update of x) is FP64 and whose inner
@@ -233,6 +242,14 @@ typedef struct {
 
 int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_solver solver,
             const bs_options *opts, bs_plan_info *out);
+
+/* As bs_plan, for the given preconditioner (the LDS of the block-Jacobi
+ * inverse or of the ILU(0) factors included).  Same errors as bs_batch_solve's
+ * planning: BS_ERR_INVALID_ARG for a bad enum or block size,
+ * BS_ERR_UNSUPPORTED where no kernel shape serves the request. */
+int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz,
+                    bs_solver solver, bs_precond precond, const bs_options *opts,
+                    bs_plan_info *out);
 
 /* ---------------------------------------------------------------------------
  * Uneven batches: systems of different sizes and patterns solved by ONE

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libbatchsolve.so")
 # enums of batchsolve.h
 CSR, ELL, DENSE = 0, 1, 2
 CG, BICGSTAB, GMRES = 0, 1, 2
-PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI = 0, 1, 2
+PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI, PREC_ILU = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_PATTERN, ERR_UNSUPPORTED, ERR_HIP, ERR_NO_DEVICE = 0, -1, -2, -3, -4, -5
@@ -80,6 +80,8 @@ def lib() -> C.CDLL:
                                  vp, vp, vp, C.POINTER(bs_options), vp]
     L.bs_plan.argtypes = [C.c_int, i32, i32, i32, C.c_int, C.POINTER(bs_options),
                           C.POINTER(bs_plan_info)]
+    L.bs_plan_precond.argtypes = [C.c_int, i32, i32, i32, C.c_int, C.c_int,
+                                  C.POINTER(bs_options), C.POINTER(bs_plan_info)]
     sz = C.c_size_t
     L.bs_varbatch_create.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
     L.bs_varbatch_destroy.argtypes = [vp]
@@ -113,7 +115,8 @@ def lib() -> C.CDLL:
                  "bs_pattern_destroy",
                  "bs_pattern_query", "bs_pattern_ell_cols", "bs_wave_layout",
                  "bs_pattern_layout", "bs_values_csr_to_ell",
-                 "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_varbatch_create",
+                 "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_plan_precond",
+                 "bs_varbatch_create",
                  "bs_varbatch_destroy", "bs_varbatch_query", "bs_varbatch_set_policy",
                  "bs_varbatch_solve", "bs_varbatch_tune", "bs_varbatch_capture",
                  "bs_varbatch_replay", "bs_ws_create", "bs_ws_destroy", "bs_ws_param_count",
@@ -257,6 +260,15 @@ def bs_plan(fmt: int, n_rows: int, nnz: int, max_row_nnz: int, solver: int,
     out = bs_plan_info()
     _check(lib().bs_plan(fmt, n_rows, nnz, max_row_nnz, solver,
                          C.byref(opts) if opts is not None else None, C.byref(out)), "bs_plan")
+    return out.as_dict()
+
+
+def bs_plan_precond(fmt: int, n_rows: int, nnz: int, max_row_nnz: int, solver: int,
+                    precond: int, opts: Optional[bs_options] = None) -> dict:
+    out = bs_plan_info()
+    _check(lib().bs_plan_precond(fmt, n_rows, nnz, max_row_nnz, solver, precond,
+                                 C.byref(opts) if opts is not None else None, C.byref(out)),
+           "bs_plan_precond")
     return out.as_dict()
 
 

@@ -130,7 +130,13 @@ bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) 
 }
 
 // block: block-Jacobi block size (0 without); block Jacobi is FP64 only.
-int variant_of(bs_solver solver, int precision, int block = 0) {
+int variant_of(bs_solver solver, int precision, int block = 0, bool ilu = false) {
+  if (ilu) {
+    if (precision == BS_MIXED) return -1;
+    if (solver == BS_BICGSTAB) return bs::V_BICGSTAB_ILU;
+    if (solver == BS_GMRES) return bs::V_GMRES_ILU;
+    return -1;  // CG needs a symmetric preconditioner
+  }
   if (block > 1) {
     if (precision == BS_MIXED) return -1;
     if (solver == BS_CG) return bs::V_CG_BJ;
@@ -154,6 +160,8 @@ bs::KernelTable table_of(int variant) {
     case bs::V_CG_BJ: return bs::kernels_cg_bj();
     case bs::V_BICGSTAB_BJ: return bs::kernels_bicgstab_bj();
     case bs::V_GMRES_BJ: return bs::kernels_gmres_bj();
+    case bs::V_BICGSTAB_ILU: return bs::kernels_bicgstab_ilu();
+    case bs::V_GMRES_ILU: return bs::kernels_gmres_ilu();
     default: return {nullptr, 0};
   }
 }
@@ -224,14 +232,18 @@ struct Plan {
   const bs::KernelEntry* k;
 };
 
-// block: block-Jacobi block size (0 without block Jacobi).
+// block: block-Jacobi block size (0 without block Jacobi); ilu: ILU(0), whose
+// factors need one-wave teams (n <= 64, one system per wave).
 int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver solver,
-              const bs_options* o, int block, Plan* out) {
+              const bs_options* o, int block, bool ilu, Plan* out) {
   const int precision = o ? o->precision : BS_FP64;
-  const int variant = variant_of(solver, precision, block);
+  const int variant = variant_of(solver, precision, block, ilu);
   if (variant < 0) return BS_ERR_UNSUPPORTED;
   if (n > BS_MAX_ROWS || max_row > BS_MAX_ROW_NNZ) return BS_ERR_UNSUPPORTED;
-  const int force_team = o ? o->team : 0, force_r = o ? o->rows_per_lane : 0;
+  if (ilu && (n > bs::kWave || (o && ((o->team != 0 && o->team != bs::kWave) ||
+                                      o->rows_per_lane > 1))))
+    return BS_ERR_UNSUPPORTED;
+  const int force_team = ilu ? bs::kWave : o ? o->team : 0, force_r = o ? o->rows_per_lane : 0;
   if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
   if (force_r != 0 && force_r != 1 && force_r != 2 && force_r != 4) return BS_ERR_INVALID_ARG;
   // Sec. 3.6: at least one lane per row, rounded up to a power of two no
@@ -257,10 +269,12 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   if (!k) return BS_ERR_UNSUPPORTED;
   const int rows = team * r;
   const int wg = k->wg, teams = wg / team, waves = wg / bs::kWave;
-  const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED || variant == bs::V_GMRES_BJ;
+  const bool gm = variant == bs::V_GMRES || variant == bs::V_GMRES_MIXED ||
+                  variant == bs::V_GMRES_BJ || variant == bs::V_GMRES_ILU;
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const bool mixed = variant == bs::V_GMRES_MIXED;
-  const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block)) +
+  const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block) +
+                           (ilu ? bs::ilu_bytes(n) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
   if (waves == 1 && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget) stage = 1;
@@ -498,7 +512,31 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
   // planned with the block-Jacobi region when opts asks for a block size
   const int block = opts && opts->block_size != 0 ? block_of(opts) : 0;
   if (block < 0) return BS_ERR_INVALID_ARG;
-  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block, &pl);
+  const int rc =
+      make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block, false, &pl);
+  if (rc == BS_OK) *out = pl.info;
+  return rc;
+}
+
+int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz,
+                    bs_solver solver, bs_precond precond, const bs_options* opts,
+                    bs_plan_info* out) {
+  if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 ||
+      (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) ||
+      (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) ||
+      (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI &&
+       precond != BS_PREC_ILU))
+    return BS_ERR_INVALID_ARG;
+  if (fmt == BS_DENSE) {
+    nnz = n_rows * n_rows;
+    max_row_nnz = n_rows;
+    fmt = BS_CSR;
+  }
+  const int block = block_of(opts, precond);
+  if (block < 0) return BS_ERR_INVALID_ARG;
+  Plan pl;
+  const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block,
+                           precond == BS_PREC_ILU, &pl);
   if (rc == BS_OK) *out = pl.info;
   return rc;
 }
@@ -515,9 +553,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     fmt = BS_CSR;
   }
   if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_INVALID_ARG;
-  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI)
+  if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI &&
+      precond != BS_PREC_ILU)
     return BS_ERR_INVALID_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;
+  const bool ilu = precond == BS_PREC_ILU;
   const int block = block_of(opts, precond);
   if (block < 0) return BS_ERR_INVALID_ARG;
   int restart = bs::kMaxRestart;
@@ -535,7 +575,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   Plan pl;
   const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, pattern->width, solver,
-                           opts, block, &pl);
+                           opts, block, ilu, &pl);
   if (rc != BS_OK) return rc;
   bs::KArgs a;
   a.n_batch = n_batch;
@@ -555,10 +595,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
     a.team_bytes = bs::team_vec_bytes(rows, a.gmres, pl.info.group_size,
                                       a.gmres && opts && opts->precision == BS_MIXED);
-    // block Jacobi: inverse rows and the exchange buffer after the vectors
+    // block Jacobi (inverse and exchange buffer) or ILU(0) (factors) after the
+    // vectors
     a.block = block;
     a.bj_offset = a.team_bytes;
-    a.team_bytes += bs::bj_bytes(rows, block);
+    a.team_bytes += bs::bj_bytes(rows, block) + (ilu ? bs::ilu_bytes(pattern->n) : 0);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
@@ -585,7 +626,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
   a.layout = (pattern->d_layout && pl.info.team == bs::kWave && pl.info.rows_per_lane == 1 &&
               a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT) &&
-              a.block <= 1)  // block Jacobi needs the rows of a block on consecutive lanes
+              a.block <= 1 && !ilu)  // block Jacobi and ILU(0) need row i on lane i
                  ? pattern->d_layout
                  : nullptr;
   // Persistent grid: as many workgroups as can be resident at once, each

@@ -8,14 +8,14 @@ namespace {
 
 template <class S>
 hipError_t launch(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream) {
-  hipLaunchKernelGGL((k_gmres<S, false, true>), dim3(grid), dim3(S::WG), lds, stream, a);
+  hipLaunchKernelGGL((k_gmres<S, false, kPkBlock>), dim3(grid), dim3(S::WG), lds, stream, a);
   return hipGetLastError();
 }
 
 template <class S>
 int occupancy(unsigned lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_gmres<S, false, true>), S::WG,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_gmres<S, false, kPkBlock>), S::WG,
                                                    lds) != hipSuccess || n < 1)
     n = 1;
   return n;

@@ -7,10 +7,12 @@
 
 namespace bs {
 
-// *_BJ: the FP64 solvers with the block-Jacobi preconditioner.
+// *_BJ: the FP64 solvers with the block-Jacobi preconditioner; *_ILU: with
+// ILU(0) (one-wave shapes only).
 enum Variant {
   V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4,
-  V_CG_BJ = 5, V_BICGSTAB_BJ = 6, V_GMRES_BJ = 7, V_COUNT = 8
+  V_CG_BJ = 5, V_BICGSTAB_BJ = 6, V_GMRES_BJ = 7, V_BICGSTAB_ILU = 8, V_GMRES_ILU = 9,
+  V_COUNT = 10
 };
 
 typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
@@ -36,6 +38,8 @@ KernelTable kernels_gmres_mixed();
 KernelTable kernels_cg_bj();
 KernelTable kernels_bicgstab_bj();
 KernelTable kernels_gmres_bj();
+KernelTable kernels_bicgstab_ilu();
+KernelTable kernels_gmres_ilu();
 
 // Shapes compiled for every solver: one row per lane for teams of 16..1024
 // lanes, and 2 or 4 rows per lane for the largest systems.  Slots per row are
@@ -48,6 +52,9 @@ KernelTable kernels_gmres_bj();
   X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 64)                     \
   X(512, 1, 4) X(512, 1, 8) X(512, 1, 16) X(512, 1, 32)                                   \
   X(1024, 1, 4) X(1024, 1, 8) X(1024, 1, 12) X(1024, 1, 16)
+// One-wave teams (systems of up to 64 rows, one row per lane): the ILU(0) shapes.
+#define BS_SHAPES_W64(X)                                                                  \
+  X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 24) X(64, 1, 28) X(64, 1, 32) X(64, 1, 64)
 #define BS_SHAPES_RN(X)                                                                   \
   X(512, 2, 8) X(512, 2, 16) X(1024, 2, 8) X(256, 4, 8) X(512, 4, 8)
 

@@ -49,7 +49,7 @@ struct KArgs {
   int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
   const int* layout;           // one-wave teams: lane_row[64] | lane_win[64] | col_pos[n], or null
   int block;                   // block-Jacobi block size (2, 4 or 8), 0 for scalar Jacobi / none
-  int bj_offset;               // byte offset of the block-Jacobi region in a team's LDS
+  int bj_offset;               // byte offset of the block-Jacobi or ILU(0) region in a team's LDS
 };
 
 // Block Jacobi: per team, the inverse rows (rows x block doubles) and a
@@ -58,6 +58,13 @@ constexpr int kMaxBlock = 8;
 __host__ __device__ constexpr int bj_bytes(int rows, int block) {
   return block > 1 ? rows * (block + 1) * 8 : 0;
 }
+
+// Preconditioner kinds compiled into separate kernel instances: scalar
+// Jacobi (or none: d = 1), block Jacobi, ILU(0).
+constexpr int kPkScalar = 0, kPkBlock = 1, kPkIlu = 2;
+
+// ILU(0) of a one-wave team: the factors as an n x (n+1) row-major FP64 array.
+__host__ __device__ constexpr int ilu_bytes(int n) { return ((n * (n + 1) * 8) + 15) & ~15; }
 
 // Flag bit of the absolute stop criterion (BS_FLAG_ABS_TOL).
 constexpr int kFlagAbsTol = 4;

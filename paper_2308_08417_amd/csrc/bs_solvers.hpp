@@ -195,13 +195,151 @@ __device__ __forceinline__ void bj_apply(TM& tm, const RW& A, const KArgs& g,
   wave_lds_fence();
 }
 
-// z = M v: block Jacobi in the BJ instances, else the diagonal d (scalar
-// Jacobi, or 1 without a preconditioner).
-template <bool BJ, class T, class TM, class RW>
+// ------------------------------------------------------------------ ILU(0)
+// ILU(0) for one-wave teams (row i on lane i, one row per lane, n <= 64).  The
+// factors live in the team's LDS region as F, n x (n+1) row-major (the odd
+// stride puts the rows of a wave on distinct bank pairs): L strictly below the
+// diagonal (unit diagonal implied), U on and above, zero off the pattern.
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Factorization (Saad 2003, Sec. 10.3.2), right-looking: for pivot k, every row
+// i > k that holds column k replaces that entry by l_ik = a_ik / u_kk and
+// subtracts l_ik u_kj from each of its entries j > k; row k's pattern (a
+// wave-uniform bitmask read from lane k) bounds the columns visited, four per
+// batch of loads, and the row's own pattern mask gates every write, so nothing
+// fills in.  Each entry receives its updates in increasing k, as in the IKJ
+// form.  d gets 1/u_ii.  A zero pivot or a non-finite factor entry anywhere in
+// the system turns M into the identity (F zero, d = 1).
+template <class TM, class RW>
+__device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
+  static_assert(RW::R == 1 && RW::TEAM == kWave, "ILU(0) runs on one-wave teams");
+  const int n = g.n, st = n + 1;
+  double* F = tm.bj_region(g);
+  const int lane = tm.lane;
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;  // rows past n address row 0 and never store
+  for (int e = lane; e < n * st; e += kWave) F[e] = 0.0;
+  // columns of the register slots: gather a vector holding each row's index
+  if (ok) lds_store<double>(A.vrow[0] + RW::kBuf, (double)i);
+  tm.sync();
+  uint64_t mask = 0;
+#pragma unroll
+  for (int k0 = 0; k0 < RW::NZ; k0 += 4) {
+    int col[4];
+#pragma unroll
+    for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
+      col[k - k0] = (int)lds_load<double>(A.c[0][k] + RW::kBuf);
+#pragma unroll
+    for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
+      if (ok && A.real(0, k)) {
+        F[i * st + col[k - k0]] = A.a[0][k];
+        mask |= 1ull << col[k - k0];
+      }
+    __asm__ volatile("" ::: "memory");
+  }
+  wave_lds_fence();
+#pragma unroll 1
+  for (int k = 0; k + 1 < n; ++k) {
+    uint64_t cols = rdlane64(mask, k);
+    cols = k >= 63 ? 0 : cols & (~0ull << (k + 1));
+    const bool act = ok && i > k && ((mask >> k) & 1);
+    double l = 0.0;
+    if (act) {
+      l = F[i * st + k] / F[k * st + k];
+      F[i * st + k] = l;
+    }
+    while (cols) {  // wave-uniform
+      int j[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        j[q] = cols ? __builtin_ctzll(cols) : j[0];
+        cols &= cols - 1;
+      }
+      double u[4], f[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        u[q] = F[k * st + j[q]];
+        f[q] = F[i * st + j[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (act && ((mask >> j[q]) & 1) && (q == 0 || j[q] != j[0]))
+          F[i * st + j[q]] = fma(-l, u[q], f[q]);
+    }
+    wave_lds_fence();
+  }
+  // a zero pivot or a non-finite entry: the identity for the whole system
+  bool bad = false;
+  if (ok) {
+    bad = F[i * st + i] == 0.0;
+    for (int j0 = 0; j0 < n; j0 += 8) {
+      double f[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f[q] = j0 + q < n ? F[i * st + j0 + q] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) bad = bad || !__builtin_isfinite(f[q]);
+    }
+  }
+  if (wave_any(bad)) {
+    wave_lds_fence();
+    for (int e = lane; e < n * st; e += kWave) F[e] = 0.0;
+    d[0] = ok ? 1.0 : 0.0;
+  } else {
+    d[0] = ok ? 1.0 / F[i * st + i] : 0.0;
+  }
+  wave_lds_fence();
+}
+
+// z = (L U)^{-1} v by two column sweeps: forward, y_k (final on lane k) is
+// read out and every row i > k subtracts l_ik y_k; backward, z_j = y_j / u_jj
+// and every row i < j subtracts u_ij z_j.  Entries off the pattern are zero.
+// The sums run in increasing k (forward) and decreasing j (backward).  With M
+// the identity F is zero and d = 1, so z = v.
+template <class T, class TM, class RW>
+__device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
+                                          const T (&d)[RW::R], const T (&v)[RW::R],
+                                          T (&z)[RW::R]) {
+  const int n = g.n, st = n + 1;
+  const double* F = tm.bj_region(g);
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;
+  double acc = ok ? (double)v[0] : 0.0;
+  for (int k0 = 0; k0 < n; k0 += 8) {
+    double lk[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) lk[q] = (ok && i > k0 + q && k0 + q < n) ? F[i * st + k0 + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (k0 + q < n) acc = fma(-lk[q], rdlane(acc, k0 + q), acc);
+  }
+  for (int j0 = n - 1; j0 >= 0; j0 -= 8) {
+    double uj[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) uj[q] = (ok && j0 - q >= 0 && i < j0 - q) ? F[i * st + j0 - q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (j0 - q >= 0) {
+        const double zj = rdlane(acc * (double)d[0], j0 - q);
+        acc = fma(-uj[q], zj, acc);
+      }
+  }
+  z[0] = ok ? (T)(acc * (double)d[0]) : (T)0;
+}
+
+// z = M v: block Jacobi or ILU(0) in their instances, else the diagonal d
+// (scalar Jacobi, or 1 without a preconditioner).
+template <int PK, class T, class TM, class RW>
 __device__ __forceinline__ void precond(TM& tm, const RW& A, const KArgs& g, const T (&d)[RW::R],
                                         const T (&v)[RW::R], T (&z)[RW::R]) {
-  if constexpr (BJ) {
+  if constexpr (PK == kPkBlock) {
     bj_apply(tm, A, g, v, z);
+  } else if constexpr (PK == kPkIlu) {
+    ilu_apply(tm, A, g, d, v, z);
   } else {
 #pragma unroll
     for (int r = 0; r < RW::R; ++r) z[r] = d[r] * v[r];
@@ -246,10 +384,11 @@ struct Prologue {
   double b[R], x[R], r[R], d[R];
 };
 
-template <bool BJ, class TM, class RW>
+template <int PK, class TM, class RW>
 __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue<RW::R>& P) {
   A.jacobi(g.precond, P.d);
-  if constexpr (BJ) bj_setup(tm, A, g);
+  if constexpr (PK == kPkBlock) bj_setup(tm, A, g);
+  if constexpr (PK == kPkIlu) ilu_setup(tm, A, g, P.d);
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
   for (int r = 0; r < RW::R; ++r) {
@@ -300,11 +439,11 @@ __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue
 // FP32 and solve for a correction to the FP64 x, scaled by 1/||r||; the "true
 // residual confirmation" becomes the FP64 outer refinement step r = b - A x,
 // which also ends the inner solve when it meets inner_tol or breaks down.
-template <bool MIXED, bool BJ, class TM, class RW>
+template <bool MIXED, int PK, class TM, class RW>
 __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
   using T = typename std::conditional<MIXED, float, double>::type;
   Prologue<RW::R> P;
-  prologue<BJ>(tm, A, g, P);
+  prologue<PK>(tm, A, g, P);
   constexpr int R = RW::R;
 
   // FP32 copy of the rows and of the Jacobi diagonal for the inner solve.
@@ -470,7 +609,7 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
     T ph[R], s[R], sh[R], t[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
-    precond<BJ>(tm, A, g, d_in, p, ph);
+    precond<PK>(tm, A, g, d_in, p, ph);
     A.template spmv<0>(tm, a_in, ph, v);
     T q1[1];
     {
@@ -488,7 +627,7 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
     const T al = rho / sigma;
 #pragma unroll
     for (int i = 0; i < R; ++i) s[i] = r[i] - al * v[i];
-    precond<BJ>(tm, A, g, d_in, s, sh);
+    precond<PK>(tm, A, g, d_in, s, sh);
     A.template spmv<1>(tm, a_in, sh, t);
     T q3[3];
     {
@@ -557,13 +696,13 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
 // =================================================================== CG
 // Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
 // stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
-template <bool BJ, class TM, class RW>
+template <int PK, class TM, class RW>
 __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
   Prologue<RW::R> P;
-  prologue<BJ>(tm, A, g, P);
+  prologue<PK>(tm, A, g, P);
   constexpr int R = RW::R;
   double z[R], p[R];
-  precond<BJ>(tm, A, g, P.d, P.r, z);
+  precond<PK>(tm, A, g, P.d, P.r, z);
 #pragma unroll
   for (int i = 0; i < R; ++i) p[i] = z[i];
   double q3[3];
@@ -602,7 +741,7 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
       A.template spmv<0>(tm, A.a, P.x, t);
 #pragma unroll
       for (int i = 0; i < R; ++i) rc[i] = P.b[i] - t[i];
-      precond<BJ>(tm, A, g, P.d, rc, zc);
+      precond<PK>(tm, A, g, P.d, rc, zc);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         p0[i] = rc[i] * rc[i];
@@ -650,7 +789,7 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
       rr[i] = go ? fma(-alpha, t[i], P.r[i]) : P.r[i];
       if (go) P.x[i] = fma(alpha, p[i], P.x[i]);
     }
-    precond<BJ>(tm, A, g, P.d, rr, z);
+    precond<PK>(tm, A, g, P.d, rr, z);
     double q2[2];
     {
       double p0[R], p1[R];
@@ -693,13 +832,13 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 // after m steps; the rotations and the triangular solve stay FP64 and x is
 // updated in FP64.  A cycle that does not lower the FP64 residual ends the
 // solve with BREAKDOWN.
-template <bool MIXED, bool BJ, class TM, class RW>
+template <bool MIXED, int PK, class TM, class RW>
 __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   static_assert(RW::R == 1, "GMRES keeps one row per lane");
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr int M = kMaxRestart;
   Prologue<RW::R> P;
-  prologue<BJ>(tm, A, g, P);
+  prologue<PK>(tm, A, g, P);
   const int m = g.restart;
   // LDS scalars of this team
   double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(RW::ROWS));
@@ -791,7 +930,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
     T z[1], w[1];
     {
       const T vv[1] = {vcur}, dd[1] = {dT};
-      precond<BJ>(tm, A, g, dd, vv, z);
+      precond<PK>(tm, A, g, dd, vv, z);
     }
     A.template spmv<0, false>(tm, a_in, z, w);
     const int jmax = wave_max(act ? j : -1);
@@ -934,10 +1073,10 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
       double mz[1];
       {
         const double zz[1] = {zacc}, dd[1] = {d};
-        precond<BJ>(tm, A, g, dd, zz, mz);
+        precond<PK>(tm, A, g, dd, zz, mz);
       }
       if (end) {
-        if constexpr (BJ) P.x[0] = P.x[0] + mz[0];
+        if constexpr (PK != kPkScalar) P.x[0] = P.x[0] + mz[0];
         else P.x[0] = fma(d, zacc, P.x[0]);
         start = true;
       }
@@ -1002,19 +1141,19 @@ constexpr int kWaitPrefetch = 0x0074;
     CALL;                                                                          \
   }
 
-template <class S, bool MIXED, bool BJ = false>
+template <class S, bool MIXED, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
-  BS_PERSISTENT_LOOP((bicgstab_system<MIXED, BJ>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((bicgstab_system<MIXED, PK>(tm, A, ga)))
 }
 
-template <class S, bool BJ = false>
+template <class S, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
-  BS_PERSISTENT_LOOP((cg_system<BJ>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((cg_system<PK>(tm, A, ga)))
 }
 
-template <class S, bool MIXED, bool BJ = false>
+template <class S, bool MIXED, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system<MIXED, BJ>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((gmres_system<MIXED, PK>(tm, A, ga)))
 }
 
 #undef BS_PERSISTENT_LOOP

@@ -271,8 +271,8 @@ void k_varlen(const VArgs va) {
     tm.row0 = tm.live ? a.row_off[tm.sys] : 0;
     VarRows<VS, NZ> A;
     A.load(tm, a, lds_base);
-    if constexpr (SOLVER == 0) cg_system<BJ>(tm, A, a.base);
-    else bicgstab_system<MIXED, BJ>(tm, A, a.base);
+    if constexpr (SOLVER == 0) cg_system<BJ ? kPkBlock : kPkScalar>(tm, A, a.base);
+    else bicgstab_system<MIXED, BJ ? kPkBlock : kPkScalar>(tm, A, a.base);
   }
 }
 

@@ -168,6 +168,7 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
            bs_precond precond, double tol, int max_iter, int* iters, double* resid, int* status,
            const bs_options* o, hipStream_t stream) {
   if (solver != BS_CG && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
+  if (precond == BS_PREC_ILU) return BS_ERR_UNSUPPORTED;  // factors of up to 1024 rows
   if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI)
     return BS_ERR_INVALID_ARG;
   int block = 0;

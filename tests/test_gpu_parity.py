@@ -596,3 +596,64 @@ def test_block_jacobi_zero_pivot_and_errors():
         with pytest.raises(bs.BatchSolveError) as e:
             c.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_BLOCK_JACOBI, block_size=bad)
         assert e.value.code == bs.ERR_INVALID_ARG
+
+
+def full_pattern_batch(bt: W.Batch) -> W.Batch:
+    """The same systems on the full pattern (every entry stored, zeros included)."""
+    n = bt.n
+    rows = np.repeat(np.arange(n), np.diff(bt.row_ptr))
+    D = np.zeros((bt.n_batch, n, n))
+    D[:, rows, bt.col_idx] = bt.values
+    rp = (np.arange(n + 1) * n).astype(np.int32)
+    ci = np.tile(np.arange(n), n).astype(np.int32)
+    return W.Batch(bt.name + "_dense", n, rp, ci, D.reshape(bt.n_batch, n * n), bt.b, bt.x0)
+
+
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+@pytest.mark.parametrize("gen", ["chem", "stiff", "small", "tridiag", "dense"])
+def test_ilu(gen, solver):
+    """ILU(0) against the oracle: the chemistry pattern (n = 54, 28 slots), a
+    stiffer chemistry batch (gamma = 1e-3, a dozen or more iterations), n = 20,
+    a tridiagonal pattern and a full pattern (ILU(0) is the exact LU there: one
+    iteration), CSR and ELL."""
+    bt = {"chem": lambda: W.chem_jacobian(1200, n=54, seed=13),
+          "stiff": lambda: W.chem_jacobian(600, n=54, gamma=1e-3, seed=14),
+          "small": lambda: W.chem_jacobian(900, n=20, seed=15),
+          "tridiag": lambda: W.tridiag_stencil(n_batch=300, n=64, seed=16),
+          "dense": lambda: full_pattern_batch(W.chem_jacobian(200, n=30, gamma=1e-3, seed=17))}[gen]()
+    c = Case(bt)
+    for fmt in (bs.CSR, bs.ELL):
+        g = c.gpu(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
+        o = c.oracle(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
+        assert np.all(o[3] == O.CONVERGED)
+        # The GPU applies the factors with FMAs, one reciprocal per diagonal entry
+        # and a backward sweep in decreasing column order; on the stiff batch
+        # (up to 42 BiCGSTAB steps) such rounding moves a step count by a few.
+        itol = np.maximum(2, np.ceil(0.15 * o[1])) if gen == "stiff" else ITOL
+        check(c, g, o, fmt=fmt, itol=itol)
+        if gen in ("tridiag", "dense"):
+            assert np.all(g[1] == 1)
+
+
+def test_ilu_zero_pivot_and_errors():
+    """A zero first pivot makes M the identity on both sides (the solve runs
+    unpreconditioned); CG, mixed precision and systems of more than 64 rows are
+    refused."""
+    bt = W.tridiag_stencil(n_batch=200, n=40, seed=18)
+    v = bt.values.copy()
+    v[:, 0] = 0.0        # a_00 = 0 in every system (still invertible)
+    c = Case(bt)
+    for solver in (bs.BICGSTAB, bs.GMRES):
+        g = c.gpu(bs.CSR, solver, precond=bs.PREC_ILU, values=dev(v))
+        o = c.oracle(bs.CSR, solver, precond=bs.PREC_ILU, values=v)
+        u = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE, values=v)
+        assert np.all(o[3] == O.CONVERGED) and np.array_equal(o[1], u[1])
+        check(c, g, o, values=v)
+    for solver, opt in ((bs.CG, {}), (bs.BICGSTAB, {"precision": bs.MIXED})):
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(bs.CSR, solver, precond=bs.PREC_ILU, **opt)
+        assert e.value.code == bs.ERR_UNSUPPORTED
+    big = Case(W.tridiag_stencil(n_batch=4, n=65))
+    with pytest.raises(bs.BatchSolveError) as e:
+        big.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_ILU)
+    assert e.value.code == bs.ERR_UNSUPPORTED

@@ -143,6 +143,14 @@ def test_absolute_criterion_uneven():
         check_absolute(case, gg, o, tol, bb)
 
 
+def test_ilu_uneven_refused():
+    """ILU(0) keeps dense factors of one-wave systems: the uneven path refuses it."""
+    c = VCase(W.uneven_banded(20, 16, 200, seed=19))
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.BICGSTAB, precond=bs.PREC_ILU)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("bsz", [2, 8])
 def test_block_jacobi_uneven(bsz):
     """Block Jacobi in the uneven path: BiCGSTAB on every team size, CG on SPD
