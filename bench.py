@@ -11,7 +11,8 @@ forms of the same batch and its solve with block Jacobi (blocks of 4 and 8
 rows), the uneven batch (100k banded systems with n in
 [16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
 stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the chemistry
-matrices stored as BatchDense (relative and absolute stop criteria), the learned
+matrices stored as BatchDense (relative and absolute stop criteria), a stiffer
+chemistry batch (gamma = 1e-3) under scalar Jacobi, block Jacobi and ILU(0), the learned
 warm start along a drifting sequence (mixed precision from the network's
 guess vs the plain FP64 solve), the HBM roofline of the solver kernel, and
 the CPU oracle's throughput on the host cores.
@@ -163,6 +164,49 @@ def dense_leg(args, bs, W, torch, np, dev, tol, max_iter):
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
     out["algorithmic_bytes_per_launch"] = int(alg)
+    del vals, b, x
+    return out
+
+
+def stiff_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """Preconditioners on a stiffer chemistry batch: ``args.stiff_batch``
+    systems of the headline's pattern (n = 54) with gamma = 1e-3, BiCGSTAB and
+    GMRES(30) to 1e-10 from x0 = 0 with scalar Jacobi, block Jacobi (blocks of
+    8 rows) and ILU(0), BatchCsr."""
+    bt = W.chem_jacobian(n_batch=args.stiff_batch, n=54, fill=0.35, gamma=1e-3, seed=0)
+    B, n, nnz = bt.n_batch, bt.n, bt.nnz
+    P = bs.Pattern.from_csr(bt.row_ptr, bt.col_idx)
+    vals = torch.from_numpy(bt.values).to(dev)
+    b = torch.from_numpy(bt.b).to(dev)
+    x = torch.empty_like(b)
+    iters = torch.empty(B, dtype=torch.int32, device=dev)
+    resid = torch.empty(B, dtype=torch.float64, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    out = {"workload": f"chem_jacobian_stiff_b{B}_n{n}_gamma1e-3_csr", "n_batch": B,
+           "n_rows": n, "nnz": nnz}
+    steps = max(5, args.steps // 10)
+    for sname, solver in (("bicgstab", bs.BICGSTAB), ("gmres30", bs.GMRES)):
+        for pname, pc, bsz in (("jacobi", bs.PREC_JACOBI, 0), ("block_jacobi8", bs.PREC_BLOCK_JACOBI, 8),
+                               ("ilu0", bs.PREC_ILU, 0)):
+            opts = bs.make_options(flags=bs.FLAG_X0_ZERO, block_size=bsz,
+                                   restart=30 if solver == bs.GMRES else 0)
+            a = (bs.CSR, P.handle, vals, b, x, solver, pc, tol, 1000, iters, resid, status, opts)
+            for _ in range(max(3, args.warmup // 20)):
+                bs.bs_batch_solve(*a)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                bs.bs_batch_solve(*a)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+            out[f"{sname}_{pname}"] = {
+                "ms": ms, "systems_per_s": B / (ms * 1e-3),
+                "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+                "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                "max_resid": float(rs.max())}
     del vals, b, x
     return out
 
@@ -381,6 +425,9 @@ def main() -> int:
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the BatchDense leg (2^16 chemistry systems stored densely)")
     ap.add_argument("--dense-batch", type=int, default=1 << 16)
+    ap.add_argument("--no-stiff", action="store_true",
+                    help="skip the preconditioner leg (2^16 stiffer chemistry systems)")
+    ap.add_argument("--stiff-batch", type=int, default=1 << 16)
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the 9-point stencil leg (4096 systems, n = 992, FP64 vs mixed)")
     ap.add_argument("--stencil-batch", type=int, default=4096)
@@ -491,6 +538,12 @@ def main() -> int:
         progress(f"dense: {dense['relative']['ms']:.3f} ms (relative), "
                  f"{dense['absolute']['ms']:.3f} ms (absolute)")
 
+    stiff = None
+    if not args.no_stiff:
+        stiff = stiff_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress("stiff: " + ", ".join(f"{k} {v['ms']:.3f} ms ({v['iters_mean']:.1f} it)"
+                                       for k, v in stiff.items() if isinstance(v, dict)))
+
     stencil = None
     if not args.no_stencil:
         stencil = stencil_leg(args, bs, W, torch, np, dev, tol, max_iter)
@@ -571,6 +624,7 @@ def main() -> int:
         "variants": variants,
         "uneven": uneven,
         "stencil": stencil,
+        "stiff": stiff,
         "dense": dense,
         "warm_start": warm,
         "gen_seconds": gen_s,

@@ -277,7 +277,10 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
                            (ilu ? bs::ilu_bytes(n) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
-  if (waves == 1 && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget) stage = 1;
+  // ILU(0) is bound by its factorization and substitutions, not by loading
+  // the values: its LDS goes to more resident waves instead of staging
+  if (waves == 1 && !ilu && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
+    stage = 1;
   out->k = k;
   out->info.team = team;
   out->info.rows_per_lane = r;

@@ -63,8 +63,10 @@ __host__ __device__ constexpr int bj_bytes(int rows, int block) {
 // Jacobi (or none: d = 1), block Jacobi, ILU(0).
 constexpr int kPkScalar = 0, kPkBlock = 1, kPkIlu = 2;
 
-// ILU(0) of a one-wave team: the factors as an n x (n+1) row-major FP64 array.
-__host__ __device__ constexpr int ilu_bytes(int n) { return ((n * (n + 1) * 8) + 15) & ~15; }
+// ILU(0) of a one-wave team: the factors as an n-row FP64 array, row-major,
+// columns padded with zeros to a multiple of 8 plus one (an odd stride).
+__host__ __device__ constexpr int ilu_stride(int n) { return ((n + 7) & ~7) + 1; }
+__host__ __device__ constexpr int ilu_bytes(int n) { return ((n * ilu_stride(n) * 8) + 15) & ~15; }
 
 // Flag bit of the absolute stop criterion (BS_FLAG_ABS_TOL).
 constexpr int kFlagAbsTol = 4;

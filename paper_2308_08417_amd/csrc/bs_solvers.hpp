@@ -197,9 +197,10 @@ __device__ __forceinline__ void bj_apply(TM& tm, const RW& A, const KArgs& g,
 
 // ------------------------------------------------------------------ ILU(0)
 // ILU(0) for one-wave teams (row i on lane i, one row per lane, n <= 64).  The
-// factors live in the team's LDS region as F, n x (n+1) row-major (the odd
-// stride puts the rows of a wave on distinct bank pairs): L strictly below the
-// diagonal (unit diagonal implied), U on and above, zero off the pattern.
+// factors live in the team's LDS region as F, row-major with an odd stride
+// (the rows of a wave fall on distinct bank pairs) and zero columns padding
+// each row to a multiple of 8: L strictly below the diagonal (unit diagonal
+// implied), U on and above, zero off the pattern.
 
 __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -208,17 +209,19 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
 }
 
 // Factorization (Saad 2003, Sec. 10.3.2), right-looking: for pivot k, every row
-// i > k that holds column k replaces that entry by l_ik = a_ik / u_kk and
-// subtracts l_ik u_kj from each of its entries j > k; row k's pattern (a
-// wave-uniform bitmask read from lane k) bounds the columns visited, four per
-// batch of loads, and the row's own pattern mask gates every write, so nothing
-// fills in.  Each entry receives its updates in increasing k, as in the IKJ
-// form.  d gets 1/u_ii.  A zero pivot or a non-finite factor entry anywhere in
-// the system turns M into the identity (F zero, d = 1).
+// i > k that holds column k replaces that entry by l_ik = a_ik / u_kk (one
+// reciprocal of the pivot per step) and subtracts l_ik u_kj from each of its
+// entries j > k; row k's pattern (a wave-uniform bitmask read from lane k)
+// bounds the columns visited, eight per batch of loads, and a row's own
+// pattern mask selects which of them change, so nothing fills in (the others
+// are stored back unchanged).  Each entry receives its updates in increasing
+// k, as in the IKJ form.  d gets 1/u_ii.  A zero pivot or a non-finite factor
+// entry anywhere in the system turns M into the identity (F zero, d = 1).
 template <class TM, class RW>
 __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
   static_assert(RW::R == 1 && RW::TEAM == kWave, "ILU(0) runs on one-wave teams");
-  const int n = g.n, st = n + 1;
+  constexpr int kB = 8;
+  const int n = g.n, st = ilu_stride(n);
   double* F = tm.bj_region(g);
   const int lane = tm.lane;
   const bool ok = A.ok[0];
@@ -248,28 +251,30 @@ __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
     uint64_t cols = rdlane64(mask, k);
     cols = k >= 63 ? 0 : cols & (~0ull << (k + 1));
     const bool act = ok && i > k && ((mask >> k) & 1);
-    double l = 0.0;
-    if (act) {
-      l = F[i * st + k] / F[k * st + k];
-      F[i * st + k] = l;
-    }
+    const double rpiv = 1.0 / F[k * st + k];
+    const double aik = F[i * st + k];
+    const double l = act ? aik * rpiv : 0.0;
+    if (act) F[i * st + k] = l;
     while (cols) {  // wave-uniform
-      int j[4];
+      int j[kB];
+      bool has[kB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        j[q] = cols ? __builtin_ctzll(cols) : j[0];
+      for (int q = 0; q < kB; ++q) {
+        has[q] = cols != 0;
+        j[q] = has[q] ? __builtin_ctzll(cols) : k;
         cols &= cols - 1;
       }
-      double u[4], f[4];
+      double u[kB], f[kB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kB; ++q) {
         u[q] = F[k * st + j[q]];
         f[q] = F[i * st + j[q]];
       }
+      if (ok) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (act && ((mask >> j[q]) & 1) && (q == 0 || j[q] != j[0]))
-          F[i * st + j[q]] = fma(-l, u[q], f[q]);
+        for (int q = 0; q < kB; ++q)
+          if (has[q]) F[i * st + j[q]] = ((mask >> j[q]) & 1) ? fma(-l, u[q], f[q]) : f[q];
+      }
     }
     wave_lds_fence();
   }
@@ -280,7 +285,7 @@ __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
     for (int j0 = 0; j0 < n; j0 += 8) {
       double f[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) f[q] = j0 + q < n ? F[i * st + j0 + q] : 0.0;
+      for (int q = 0; q < 8; ++q) f[q] = F[i * st + j0 + q];
 #pragma unroll
       for (int q = 0; q < 8; ++q) bad = bad || !__builtin_isfinite(f[q]);
     }
@@ -297,38 +302,40 @@ __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
 
 // z = (L U)^{-1} v by two column sweeps: forward, y_k (final on lane k) is
 // read out and every row i > k subtracts l_ik y_k; backward, z_j = y_j / u_jj
-// and every row i < j subtracts u_ij z_j.  Entries off the pattern are zero.
-// The sums run in increasing k (forward) and decreasing j (backward).  With M
-// the identity F is zero and d = 1, so z = v.
+// and every row i < j subtracts u_ij z_j.  Entries off the pattern, and the
+// padding columns (read out from idle lanes, whose values are zero), add
+// nothing.  The sums run in increasing k (forward) and decreasing j
+// (backward).  With M the identity F is zero and d = 1, so z = v.
 template <class T, class TM, class RW>
 __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
                                           const T (&d)[RW::R], const T (&v)[RW::R],
                                           T (&z)[RW::R]) {
-  const int n = g.n, st = n + 1;
+  const int n = g.n, st = ilu_stride(n), n8 = st - 1;
   const double* F = tm.bj_region(g);
   const bool ok = A.ok[0];
   const int i = ok ? A.row[0] : 0;
+  const int ilo = ok ? i : kWave, ihi = ok ? i : -1;  // idle lanes take no term
+  const double dv = (double)d[0];
   double acc = ok ? (double)v[0] : 0.0;
-  for (int k0 = 0; k0 < n; k0 += 8) {
+  for (int k0 = 0; k0 < n8; k0 += 8) {
     double lk[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) lk[q] = (ok && i > k0 + q && k0 + q < n) ? F[i * st + k0 + q] : 0.0;
+    for (int q = 0; q < 8; ++q) lk[q] = F[i * st + k0 + q];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      if (k0 + q < n) acc = fma(-lk[q], rdlane(acc, k0 + q), acc);
+      acc = fma(ilo > k0 + q && ilo < kWave ? -lk[q] : 0.0, rdlane(acc, k0 + q), acc);
   }
-  for (int j0 = n - 1; j0 >= 0; j0 -= 8) {
+  for (int j0 = n8 - 8; j0 >= 0; j0 -= 8) {
     double uj[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) uj[q] = (ok && j0 - q >= 0 && i < j0 - q) ? F[i * st + j0 - q] : 0.0;
+    for (int q = 0; q < 8; ++q) uj[q] = F[i * st + j0 + 7 - q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (j0 - q >= 0) {
-        const double zj = rdlane(acc * (double)d[0], j0 - q);
-        acc = fma(-uj[q], zj, acc);
-      }
+    for (int q = 0; q < 8; ++q) {
+      const double zj = rdlane(acc * dv, j0 + 7 - q);
+      acc = fma(ihi < j0 + 7 - q && ihi >= 0 ? -uj[q] : 0.0, zj, acc);
+    }
   }
-  z[0] = ok ? (T)(acc * (double)d[0]) : (T)0;
+  z[0] = ok ? (T)(acc * dv) : (T)0;
 }
 
 // z = M v: block Jacobi or ILU(0) in their instances, else the diagonal d
