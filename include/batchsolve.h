@@ -40,8 +40,16 @@ typedef enum { BS_CSR = 0, BS_ELL = 1, BS_DENSE = 2 } bs_format;
 /* Solvers of Tab. 2.  BS_CG follows Sec. 3.5, Alg. 1 (stop test replaced by the
  * relative residual); BS_BICGSTAB is right-preconditioned BiCGSTAB; BS_GMRES is
  * right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and Givens
- * rotations. */
-typedef enum { BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2 } bs_solver;
+ * rotations.  BS_TRSV_LOWER / BS_TRSV_UPPER (BatchTrsv) solve T x = b directly
+ * for T the lower / upper triangle of A, diagonal included (entries of the
+ * other triangle are ignored), by substitution: iterations 0, resid the true
+ * residual of T, status BS_BREAKDOWN with x = 0 where a diagonal entry is zero
+ * or not stored, BS_NONFINITE where x is not finite; the preconditioner, tol
+ * and max_iter are validated but unused; systems of at most 64 rows, FP64
+ * (BS_ERR_UNSUPPORTED otherwise and on the uneven-batch entry points). */
+typedef enum {
+  BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2, BS_TRSV_LOWER = 3, BS_TRSV_UPPER = 4
+} bs_solver;
 
 /* Preconditioners (Tab. 2): none; scalar Jacobi (d_i = 1/a_ii, 1 where the
  * diagonal entry is zero or not stored); block Jacobi: the inverse of the

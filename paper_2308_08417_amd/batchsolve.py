@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libbatchsolve.so")
 
 # enums of batchsolve.h
 CSR, ELL, DENSE = 0, 1, 2
-CG, BICGSTAB, GMRES = 0, 1, 2
+CG, BICGSTAB, GMRES, TRSV_LOWER, TRSV_UPPER = 0, 1, 2, 3, 4
 PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI, PREC_ILU = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3

@@ -131,6 +131,10 @@ bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) 
 
 // block: block-Jacobi block size (0 without); block Jacobi is FP64 only.
 int variant_of(bs_solver solver, int precision, int block = 0, bool ilu = false) {
+  if (solver == BS_TRSV_LOWER || solver == BS_TRSV_UPPER) {
+    if (precision == BS_MIXED) return -1;
+    return solver == BS_TRSV_LOWER ? bs::V_TRSV_LOWER : bs::V_TRSV_UPPER;
+  }
   if (ilu) {
     if (precision == BS_MIXED) return -1;
     if (solver == BS_BICGSTAB) return bs::V_BICGSTAB_ILU;
@@ -162,6 +166,8 @@ bs::KernelTable table_of(int variant) {
     case bs::V_GMRES_BJ: return bs::kernels_gmres_bj();
     case bs::V_BICGSTAB_ILU: return bs::kernels_bicgstab_ilu();
     case bs::V_GMRES_ILU: return bs::kernels_gmres_ilu();
+    case bs::V_TRSV_LOWER: return bs::kernels_trsv_lower();
+    case bs::V_TRSV_UPPER: return bs::kernels_trsv_upper();
     default: return {nullptr, 0};
   }
 }
@@ -240,10 +246,13 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int variant = variant_of(solver, precision, block, ilu);
   if (variant < 0) return BS_ERR_UNSUPPORTED;
   if (n > BS_MAX_ROWS || max_row > BS_MAX_ROW_NNZ) return BS_ERR_UNSUPPORTED;
-  if (ilu && (n > bs::kWave || (o && ((o->team != 0 && o->team != bs::kWave) ||
-                                      o->rows_per_lane > 1))))
+  // ILU(0) and the triangular solves keep a dense n-row array per system
+  const bool dense_lds = ilu || solver == BS_TRSV_LOWER || solver == BS_TRSV_UPPER;
+  if (dense_lds && (n > bs::kWave || (o && ((o->team != 0 && o->team != bs::kWave) ||
+                                            o->rows_per_lane > 1))))
     return BS_ERR_UNSUPPORTED;
-  const int force_team = ilu ? bs::kWave : o ? o->team : 0, force_r = o ? o->rows_per_lane : 0;
+  const int force_team = dense_lds ? bs::kWave : o ? o->team : 0,
+            force_r = o ? o->rows_per_lane : 0;
   if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
   if (force_r != 0 && force_r != 1 && force_r != 2 && force_r != 4) return BS_ERR_INVALID_ARG;
   // Sec. 3.6: at least one lane per row, rounded up to a power of two no
@@ -274,7 +283,7 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const bool mixed = variant == bs::V_GMRES_MIXED;
   const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block) +
-                           (ilu ? bs::ilu_bytes(n) : 0)) +
+                           (dense_lds ? bs::ilu_bytes(n) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
   // ILU(0) is bound by its factorization and substitutions, not by loading
@@ -504,7 +513,7 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
             const bs_options* opts, bs_plan_info* out) {
   if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 ||
       (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) ||
-      (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES))
+      (solver < BS_CG || solver > BS_TRSV_UPPER))
     return BS_ERR_INVALID_ARG;
   if (fmt == BS_DENSE) {  // the full pattern in CSR order
     nnz = n_rows * n_rows;
@@ -526,7 +535,7 @@ int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_
                     bs_plan_info* out) {
   if (!out || n_rows < 1 || nnz < 0 || max_row_nnz < 0 ||
       (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) ||
-      (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) ||
+      (solver < BS_CG || solver > BS_TRSV_UPPER) ||
       (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI &&
        precond != BS_PREC_ILU))
     return BS_ERR_INVALID_ARG;
@@ -555,13 +564,15 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     if ((int64_t)pattern->nnz != (int64_t)pattern->n * pattern->n) return BS_ERR_PATTERN;
     fmt = BS_CSR;
   }
-  if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_INVALID_ARG;
+  if (solver < BS_CG || solver > BS_TRSV_UPPER) return BS_ERR_INVALID_ARG;
   if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI &&
       precond != BS_PREC_ILU)
     return BS_ERR_INVALID_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 0) return BS_ERR_INVALID_ARG;
-  const bool ilu = precond == BS_PREC_ILU;
-  const int block = block_of(opts, precond);
+  // the triangular solves take no preconditioner
+  const bool trsv = solver == BS_TRSV_LOWER || solver == BS_TRSV_UPPER;
+  const bool ilu = precond == BS_PREC_ILU && !trsv;
+  const int block = trsv ? 0 : block_of(opts, precond);
   if (block < 0) return BS_ERR_INVALID_ARG;
   int restart = bs::kMaxRestart;
   double inner_tol = 1e-6;
@@ -602,7 +613,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     // vectors
     a.block = block;
     a.bj_offset = a.team_bytes;
-    a.team_bytes += bs::bj_bytes(rows, block) + (ilu ? bs::ilu_bytes(pattern->n) : 0);
+    a.team_bytes += bs::bj_bytes(rows, block) + (ilu || trsv ? bs::ilu_bytes(pattern->n) : 0);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
@@ -629,7 +640,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
   a.layout = (pattern->d_layout && pl.info.team == bs::kWave && pl.info.rows_per_lane == 1 &&
               a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT) &&
-              a.block <= 1 && !ilu)  // block Jacobi and ILU(0) need row i on lane i
+              a.block <= 1 && !ilu && !trsv)  // these need row i on lane i
                  ? pattern->d_layout
                  : nullptr;
   // Persistent grid: as many workgroups as can be resident at once, each

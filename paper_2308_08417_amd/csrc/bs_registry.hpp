@@ -8,11 +8,11 @@
 namespace bs {
 
 // *_BJ: the FP64 solvers with the block-Jacobi preconditioner; *_ILU: with
-// ILU(0) (one-wave shapes only).
+// ILU(0) (one-wave shapes only); V_TRSV_*: the triangular solves (one-wave).
 enum Variant {
   V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4,
   V_CG_BJ = 5, V_BICGSTAB_BJ = 6, V_GMRES_BJ = 7, V_BICGSTAB_ILU = 8, V_GMRES_ILU = 9,
-  V_COUNT = 10
+  V_TRSV_LOWER = 10, V_TRSV_UPPER = 11, V_COUNT = 12
 };
 
 typedef hipError_t (*LaunchFn)(const KArgs& a, unsigned grid, unsigned lds, hipStream_t stream);
@@ -40,6 +40,8 @@ KernelTable kernels_bicgstab_bj();
 KernelTable kernels_gmres_bj();
 KernelTable kernels_bicgstab_ilu();
 KernelTable kernels_gmres_ilu();
+KernelTable kernels_trsv_lower();
+KernelTable kernels_trsv_upper();
 
 // Shapes compiled for every solver: one row per lane for teams of 16..1024
 // lanes, and 2 or 4 rows per lane for the largest systems.  Slots per row are

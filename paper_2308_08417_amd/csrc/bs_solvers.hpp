@@ -700,6 +700,84 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
   finish(tm, A, g, P.b, P.x, st, k, outer, bn, rn, st == ST_CONVERGED || st == ST_IDLE);
 }
 
+// =================================================================== Trsv
+// BatchTrsv (Tab. 2): T x = b for T the lower (upper) triangle of A, diagonal
+// included, one-wave teams (row i on lane i, n <= 64).  The row's register
+// values outside the triangle are zeroed, so the shared epilogue's true
+// residual is that of T; the triangle goes to the LDS region as for ILU(0)
+// and one column sweep solves it: x_k = acc_k / t_kk (final on lane k when
+// column k is reached) is read out, and every later row subtracts t_ik x_k.
+// A zero diagonal entry is a breakdown (x = 0); iterations: 0.
+template <bool LOWER, class TM, class RW>
+__device__ __forceinline__ void trsv_system(TM& tm, RW& A, const KArgs& g) {
+  static_assert(RW::R == 1 && RW::TEAM == kWave, "BatchTrsv runs on one-wave teams");
+  const int n = g.n, st = ilu_stride(n), n8 = st - 1;
+  double* F = tm.bj_region(g);
+  const int lane = tm.lane;
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;
+  for (int e = lane; e < n * st; e += kWave) F[e] = 0.0;
+  if (ok) lds_store<double>(A.vrow[0] + RW::kBuf, (double)i);
+  tm.sync();
+#pragma unroll
+  for (int k0 = 0; k0 < RW::NZ; k0 += 4) {
+    int col[4];
+#pragma unroll
+    for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k)
+      col[k - k0] = (int)lds_load<double>(A.c[0][k] + RW::kBuf);
+#pragma unroll
+    for (int k = k0; k < k0 + 4 && k < RW::NZ; ++k) {
+      const bool keep = ok && A.real(0, k) && (LOWER ? col[k - k0] <= i : col[k - k0] >= i);
+      if (keep) F[i * st + col[k - k0]] = A.a[0][k];
+      A.a[0][k] = keep ? A.a[0][k] : 0.0;
+    }
+    __asm__ volatile("" ::: "memory");
+  }
+  wave_lds_fence();
+  double b[1] = {A.bval[0]}, x[1] = {A.xval[0]}, q[1] = {b[0] * b[0]};
+  tm.sum(q);
+  const double bn = sqrt(q[0]);
+  const double tii = ok ? F[i * st + i] : 1.0;
+  int stt = tm.live ? ST_CONVERGED : ST_IDLE;
+  if (tm.live && !finite(bn)) {
+    stt = ST_NONFINITE;
+  } else if (bn == 0.0 || wave_any(tm.live && tii == 0.0)) {
+    if (tm.live && bn != 0.0) stt = ST_BREAKDOWN;
+    x[0] = 0.0;
+  } else {
+    const double dv = ok ? 1.0 / tii : 0.0;
+    const int ilo = ok ? i : kWave, ihi = ok ? i : -1;  // idle lanes take no term
+    double acc = ok ? b[0] : 0.0;
+    if constexpr (LOWER) {
+      for (int k0 = 0; k0 < n8; k0 += 8) {
+        double t[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) t[p] = F[i * st + k0 + p];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const double xk = rdlane(acc * dv, k0 + p);
+          acc = fma(ilo > k0 + p && ilo < kWave ? -t[p] : 0.0, xk, acc);
+        }
+      }
+    } else {
+      for (int j0 = n8 - 8; j0 >= 0; j0 -= 8) {
+        double t[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) t[p] = F[i * st + j0 + 7 - p];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const double xj = rdlane(acc * dv, j0 + 7 - p);
+          acc = fma(ihi < j0 + 7 - p && ihi >= 0 ? -t[p] : 0.0, xj, acc);
+        }
+      }
+    }
+    x[0] = ok ? acc * dv : 0.0;
+    if (tm.live && wave_any(ok && !finite(x[0]))) stt = ST_NONFINITE;
+  }
+  wave_lds_fence();
+  finish(tm, A, g, b, x, stt, 0, 0, bn, 0.0, false);
+}
+
 // =================================================================== CG
 // Preconditioned CG, Sec. 3.5 Alg. 1 step for step, with the relative-residual
 // stop test.  Per iteration: one SpMV and two reductions (p.t; r.z, r.r).
@@ -1151,6 +1229,11 @@ constexpr int kWaitPrefetch = 0x0074;
 template <class S, bool MIXED, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
   BS_PERSISTENT_LOOP((bicgstab_system<MIXED, PK>(tm, A, ga)))
+}
+
+template <class S, bool LOWER>
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_trsv(const KArgs g) {
+  BS_PERSISTENT_LOOP((trsv_system<LOWER>(tm, A, ga)))
 }
 
 template <class S, int PK = kPkScalar>

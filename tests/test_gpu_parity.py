@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 from paper_2308_08417_amd import batchsolve as bs  # noqa: E402
 
-SOLVER_O = {bs.CG: O.CG, bs.BICGSTAB: O.BICGSTAB, bs.GMRES: O.GMRES}
+SOLVER_O = {bs.CG: O.CG, bs.BICGSTAB: O.BICGSTAB, bs.GMRES: O.GMRES, bs.TRSV_LOWER: O.TRSV_LOWER,
+            bs.TRSV_UPPER: O.TRSV_UPPER}
 XTOL, ITOL = 1e-8, 2
 
 
@@ -656,4 +657,53 @@ def test_ilu_zero_pivot_and_errors():
     big = Case(W.tridiag_stencil(n_batch=4, n=65))
     with pytest.raises(bs.BatchSolveError) as e:
         big.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_ILU)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("lower", [True, False])
+@pytest.mark.parametrize("gen", ["chem", "small", "full"])
+def test_trsv(gen, lower):
+    """BatchTrsv against the oracle: the triangle of the chemistry matrices
+    (n = 54), n = 20, and a full pattern, CSR and ELL: x, the residual of the
+    triangle, zero iterations."""
+    bt = {"chem": lambda: W.chem_jacobian(1000, n=54, gamma=1e-3, seed=21),
+          "small": lambda: W.chem_jacobian(700, n=20, gamma=1e-3, seed=22),
+          "full": lambda: full_pattern_batch(W.chem_jacobian(300, n=40, gamma=1e-3, seed=23))}[gen]()
+    c = Case(bt)
+    solver = bs.TRSV_LOWER if lower else bs.TRSV_UPPER
+    for fmt in (bs.CSR, bs.ELL):
+        xg, ig, rg, sg = c.gpu(fmt, solver, precond=bs.PREC_NONE)
+        xo, io, ro, so = c.oracle(fmt, solver, precond=bs.PREC_NONE)
+        assert np.all(so == O.CONVERGED) and np.array_equal(sg, so)
+        assert np.all(ig == 0) and np.all(io == 0)
+        nx = np.linalg.norm(xo, axis=1)
+        assert np.all(np.linalg.norm(xg - xo, axis=1) <= 1e-12 * nx)
+        assert np.all(rg <= 1e-13) and np.all(np.abs(rg - ro) <= 1e-13)
+
+
+def test_trsv_breakdown_and_errors():
+    """A zero diagonal entry: BREAKDOWN with x = 0 and residual 1 (relative), as
+    in the oracle; b = 0 gives x = 0; mixed precision and systems of more than
+    64 rows are refused."""
+    bt = W.chem_jacobian(200, n=30, seed=24)
+    d5 = int(np.flatnonzero(bt.col_idx[bt.row_ptr[5]:bt.row_ptr[6]] == 5)[0]) + int(bt.row_ptr[5])
+    v = bt.values.copy()
+    v[7, d5] = 0.0
+    b = bt.b.copy()
+    b[9] = 0.0
+    c = Case(bt)
+    for solver in (bs.TRSV_LOWER, bs.TRSV_UPPER):
+        xg, ig, rg, sg = c.gpu(bs.CSR, solver, precond=bs.PREC_NONE, values=dev(v), b=b)
+        xo, io, ro, so = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE, values=v, b=b)
+        assert np.array_equal(sg, so)
+        assert sg[7] == bs.BREAKDOWN and np.all(xg[7] == 0) and rg[7] == 1.0
+        assert sg[9] == bs.CONVERGED and np.all(xg[9] == 0) and rg[9] == 0.0
+        ok = sg == bs.CONVERGED
+        assert np.allclose(xg[ok], xo[ok], rtol=1e-12, atol=1e-14)
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.CSR, bs.TRSV_LOWER, precond=bs.PREC_NONE, precision=bs.MIXED)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    big = Case(W.tridiag_stencil(n_batch=4, n=65))
+    with pytest.raises(bs.BatchSolveError) as e:
+        big.gpu(bs.CSR, bs.TRSV_UPPER, precond=bs.PREC_NONE)
     assert e.value.code == bs.ERR_UNSUPPORTED
