@@ -7,8 +7,8 @@ stored entries at seed 0), A = I - 1e-6 J with J = +-10^U(-3,3), b ~ U(-1,1),
 x0 = 0 -- solved by FP64 BiCGSTAB with scalar Jacobi in BatchCsr to relative
 residual 1e-10.  One step = one launch of the fused kernel over the whole batch,
 inputs resident in HBM.  The line also reports the BatchEll and mixed-precision
-forms of the same batch and its solve with block Jacobi (blocks of 4 and 8
-rows), the uneven batch (100k banded systems with n in
+forms of the same batch, its solve with block Jacobi (blocks of 4 and 8
+rows) and its triangles solved by BatchTrsv, the uneven batch (100k banded systems with n in
 [16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
 stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the chemistry
 matrices stored as BatchDense (relative and absolute stop criteria), a stiffer
@@ -477,16 +477,16 @@ def main() -> int:
     tol, max_iter = 1e-10, 500
     torch.cuda.synchronize()
 
-    def run(fmt, precision, block=0):
+    def run(fmt, precision, block=0, solver=bs.BICGSTAB):
         v = vals_csr if fmt == bs.CSR else vals_ell
         opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=precision, block_size=block)
         pc = bs.PREC_BLOCK_JACOBI if block else bs.PREC_JACOBI
-        bs.bs_batch_solve(fmt, P.handle, v, b, x, bs.BICGSTAB, pc, tol, max_iter,
+        bs.bs_batch_solve(fmt, P.handle, v, b, x, solver, pc, tol, max_iter,
                           iters, resid, status, opts)
 
-    def timed(fmt, precision, steps, warmup, block=0):
+    def timed(fmt, precision, steps, warmup, block=0, solver=bs.BICGSTAB):
         for _ in range(warmup):
-            run(fmt, precision, block)
+            run(fmt, precision, block, solver)
         torch.cuda.synchronize()
         # the K launches run back to back on this stream between two events;
         # one launch is one step, so the average launch duration is region / K
@@ -494,7 +494,7 @@ def main() -> int:
         t_wall = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            run(fmt, precision, block)
+            run(fmt, precision, block, solver)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_wall
@@ -523,6 +523,14 @@ def main() -> int:
             if fmt == headline_fmt and prec == bs.FP64 and not blk:
                 continue
             r = timed(fmt, prec, max(10, args.steps // 2), args.warmup, blk)
+            r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
+            variants[name] = r
+            progress(f"variant {name}: {r['ms_per_step']:.4f} ms")
+        # BatchTrsv on the same matrices (their lower / upper triangles): one
+        # substitution per system, reported against the same algorithmic bytes
+        for name, solver in (("csr_trsv_lower", bs.TRSV_LOWER), ("csr_trsv_upper", bs.TRSV_UPPER)):
+            r = timed(bs.CSR, bs.FP64, max(10, args.steps // 2), args.warmup, 0, solver)
+            r["all_converged"] = bool(np.all(status.cpu().numpy() == bs.CONVERGED))
             r["systems_per_s"] = B / (r["ms_per_step"] * 1e-3)
             variants[name] = r
             progress(f"variant {name}: {r['ms_per_step']:.4f} ms")
