@@ -707,3 +707,40 @@ def test_trsv_breakdown_and_errors():
     with pytest.raises(bs.BatchSolveError) as e:
         big.gpu(bs.CSR, bs.TRSV_UPPER, precond=bs.PREC_NONE)
     assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("precond,bsz", [(bs.PREC_BLOCK_JACOBI, 4), (bs.PREC_ILU, 0)])
+def test_stronger_preconditioners_absolute_and_dense(precond, bsz):
+    """Block Jacobi and ILU(0) under the absolute stop criterion, and through the
+    BatchDense entry (the full pattern: ILU(0) is the exact LU, one step)."""
+    bt = W.chem_jacobian(n_batch=1000, n=54, gamma=1e-4, seed=25)
+    c = Case(bt)
+    b = bt.b * 1024.0
+    tol = 1e-8
+    for solver in (bs.BICGSTAB, bs.GMRES):
+        g = c.gpu(bs.CSR, solver, precond=precond, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL,
+                  block_size=bsz, max_iter=1000)
+        o = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=SOLVER_O[solver], tol=tol,
+                          precond=precond, block_size=max(bsz, 1), max_iter=1000, absolute=True)
+        rel = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=SOLVER_O[solver], tol=tol,
+                            precond=precond, block_size=max(bsz, 1), max_iter=1000)
+        assert o[1].sum() > rel[1].sum()
+        check_absolute(c, g, o, tol, b)
+    n = 40
+    db = full_pattern_batch(W.chem_jacobian(n_batch=300, n=n, gamma=1e-4, seed=26))
+    cd = Case(db)
+    P = bs.Pattern.dense(n)
+    B = db.n_batch
+    for solver in (bs.BICGSTAB, bs.GMRES):
+        x = torch.zeros((B, n), dtype=torch.float64, device="cuda:0")
+        it = torch.empty(B, dtype=torch.int32, device="cuda:0")
+        rs = torch.empty(B, dtype=torch.float64, device="cuda:0")
+        st = torch.empty(B, dtype=torch.int32, device="cuda:0")
+        bs.bs_batch_solve(bs.DENSE, P.handle, dev(db.values), dev(db.b), x, solver, precond, 1e-10,
+                          500, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO, block_size=bsz))
+        torch.cuda.synchronize()
+        g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+        o = cd.oracle(bs.CSR, solver, precond=precond, block_size=max(bsz, 1))
+        check(cd, g, o)
+        if precond == bs.PREC_ILU:
+            assert np.all(g[1] == 1)
