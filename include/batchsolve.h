@@ -207,6 +207,13 @@ typedef struct {
                            taken, 0 where x was; written only with x_alt          */
   int32_t block_size;   /* BS_PREC_BLOCK_JACOBI: rows per block, 2, 4 or 8;
                            0 selects 8 (BS_ERR_INVALID_ARG otherwise)             */
+  int32_t n_rhs;        /* right-hand sides per matrix, k >= 1; 0 selects 1.  With
+                           k > 1, n_batch counts matrices and every matrix is
+                           solved k times: b and x are [n_batch][k][n_rows], and
+                           iters, resid, status, outer_iters, x_alt and alt_used
+                           hold n_batch*k entries in the same order; each solve
+                           reads its matrix's values (bs_batch_solve only;
+                           BS_ERR_UNSUPPORTED on the uneven-batch entry points) */
 } bs_options;
 
 /* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch

@@ -42,7 +42,7 @@ class bs_options(C.Structure):
     _fields_ = [("restart", C.c_int32), ("precision", C.c_int32), ("inner_tol", C.c_double),
                 ("flags", C.c_int32), ("team", C.c_int32), ("rows_per_lane", C.c_int32),
                 ("outer_iters", C.c_void_p), ("x_alt", C.c_void_p), ("alt_used", C.c_void_p),
-                ("block_size", C.c_int32)]
+                ("block_size", C.c_int32), ("n_rhs", C.c_int32)]
 
 
 class bs_plan_info(C.Structure):
@@ -247,9 +247,9 @@ def bs_matrix_storage(fmt: int, n_batch: int, n_rows: int, nnz: int, ell_width: 
 
 def make_options(restart: int = 0, precision: int = FP64, inner_tol: float = 0.0, flags: int = 0,
                  team: int = 0, rows_per_lane: int = 0, outer_iters=None, x_alt=None,
-                 alt_used=None, block_size: int = 0) -> bs_options:
+                 alt_used=None, block_size: int = 0, n_rhs: int = 0) -> bs_options:
     o = bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters),
-                   _ptr(x_alt), _ptr(alt_used), block_size)
+                   _ptr(x_alt), _ptr(alt_used), block_size, n_rhs)
     # the structure holds raw device pointers: keep their tensors alive with it
     o._keep = (outer_iters, x_alt, alt_used)
     return o
@@ -280,9 +280,15 @@ def bs_batch_solve(fmt: int, pattern: int, values, b, x, solver: int, precond: i
 
     ``values``/``b``/``x``: float64 device tensors ``[B, nnz]`` (CSR) or ``[B, W*n]``
     (ELL), ``[B, n]``, ``[B, n]``; ``iters``/``status`` int32 ``[B]``; ``resid``
-    float64 ``[B]``.  Asynchronous: synchronise the stream before reading results.
+    float64 ``[B]``.  With ``opts.n_rhs = k > 1``, B counts matrices and ``b``/``x``
+    (and the per-solve outputs) hold ``B*k`` rows, matrix by matrix.
+    Asynchronous: synchronise the stream before reading results.
     """
-    n_batch, n_rows = b.shape
+    n_solves, n_rows = b.shape
+    k = opts.n_rhs if opts is not None and opts.n_rhs > 1 else 1
+    if n_solves % k:
+        raise ValueError("b holds a whole number of right-hand sides per matrix")
+    n_batch = n_solves // k
     _check(lib().bs_batch_solve(fmt, n_batch, n_rows, pattern, _ptr(values), _ptr(b), _ptr(x),
                                 solver, precond, float(tol), int(max_iter), _ptr(iters),
                                 _ptr(resid), _ptr(status),

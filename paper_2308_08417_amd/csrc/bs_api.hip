@@ -585,6 +585,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     if (opts->inner_tol > 0.0) inner_tol = opts->inner_tol;
     flags = opts->flags;
   }
+  // several right-hand sides per matrix: one solve per (matrix, right-hand side)
+  const int nrhs = opts && opts->n_rhs > 0 ? opts->n_rhs : 1;
+  if (opts && opts->n_rhs < 0) return BS_ERR_INVALID_ARG;
+  if (n_batch > INT64_MAX / nrhs) return BS_ERR_INVALID_ARG;
+  const int64_t n_solves = n_batch * nrhs;
   if (n_batch == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   Plan pl;
@@ -592,7 +597,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
                            opts, block, ilu, &pl);
   if (rc != BS_OK) return rc;
   bs::KArgs a;
-  a.n_batch = n_batch;
+  a.n_batch = n_solves;
+  a.nrhs = nrhs;
   a.n = pattern->n;
   a.nnz = pattern->nnz;
   a.width = pattern->width;
@@ -645,7 +651,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
                  : nullptr;
   // Persistent grid: as many workgroups as can be resident at once, each
   // walking over the batch (never more than there are systems).
-  const int64_t groups = (n_batch + pl.info.systems_per_group - 1) / pl.info.systems_per_group;
+  const int64_t groups = (n_solves + pl.info.systems_per_group - 1) / pl.info.systems_per_group;
   const int cus = device_cus();
   if (cus < 1) return BS_ERR_HIP;
   // Resident groups per CU, asked with 1 KiB more LDS per group than used: a

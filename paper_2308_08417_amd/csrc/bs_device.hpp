@@ -361,7 +361,7 @@ struct Rows {
     }
   }
 
-  // Prefetch the values and right-hand sides of the systems base..base+TEAMS-1
+  // Prefetch the values and right-hand sides of the solves base..base+TEAMS-1
   // into the group's staging area with direct global-to-LDS loads of 16 bytes
   // per lane: each instruction of the wave fills 1 KiB of LDS, lane l the 16
   // bytes at offset 16l, from a source chosen per lane.  Every block is copied
@@ -377,7 +377,7 @@ struct Rows {
     if constexpr (S::TEAMS == 1) {
       // one system per wave: each region is a run of whole KiB; lanes past the
       // block's last chunk fetch that chunk again
-      const uintptr_t v0 = (uintptr_t)(g.values + base * per);
+      const uintptr_t v0 = (uintptr_t)(g.values + matrix_of(g, base) * per);
       const uintptr_t va = v0 & ~(uintptr_t)15;
       const unsigned vlast = (unsigned)(((v0 + (uintptr_t)per * 8 - 1) & ~(uintptr_t)15) - va);
       for (unsigned d0 = 0; d0 < vr; d0 += 1024)
@@ -408,7 +408,7 @@ struct Rows {
         if (d0 + l16 < region && sy < g.n_batch) {
           uintptr_t start, end;
           if (o < vr) {
-            start = (uintptr_t)(g.values + sy * per);
+            start = (uintptr_t)(g.values + matrix_of(g, sy) * per);
             end = start + (uintptr_t)per * 8;
           } else {
             o -= vr;
@@ -429,7 +429,7 @@ struct Rows {
   // prefetched LDS block; other groups read HBM directly.
   __device__ void load_values(Team<S>& tm, const KArgs& g) {
     const int64_t per = g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n;
-    const double* vals = g.values + (tm.live ? tm.sys * per : 0);
+    const double* vals = g.values + (tm.live ? matrix_of(g, tm.sys) * per : 0);
     const double* bb = g.b + (tm.live ? tm.sys * g.n : 0);
     // Per-lane offsets are passed through an empty asm once per system so the
     // compiler recomputes the per-slot addresses here instead of hoisting them

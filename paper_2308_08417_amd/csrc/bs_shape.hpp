@@ -48,9 +48,16 @@ struct KArgs {
   const double* x_alt;         // optional second initial guess [n_batch][n]
   int* alt_used;               // optional [n_batch]: 1 where x_alt was taken
   const int* layout;           // one-wave teams: lane_row[64] | lane_win[64] | col_pos[n], or null
+  int nrhs;                    // right-hand sides per matrix: solve s reads matrix s / nrhs
   int block;                   // block-Jacobi block size (2, 4 or 8), 0 for scalar Jacobi / none
   int bj_offset;               // byte offset of the block-Jacobi or ILU(0) region in a team's LDS
 };
+
+// Matrix of solve s (several right-hand sides per matrix: solves s*k..s*k+k-1
+// share matrix s).
+__host__ __device__ __forceinline__ int64_t matrix_of(const KArgs& g, int64_t s) {
+  return g.nrhs == 1 ? s : s / g.nrhs;
+}
 
 // Block Jacobi: per team, the inverse rows (rows x block doubles) and a
 // row-indexed exchange buffer (rows doubles).

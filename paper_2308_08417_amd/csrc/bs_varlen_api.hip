@@ -169,6 +169,7 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
            const bs_options* o, hipStream_t stream) {
   if (solver != BS_CG && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
   if (precond == BS_PREC_ILU) return BS_ERR_UNSUPPORTED;  // factors of up to 1024 rows
+  if (o && o->n_rhs > 1) return BS_ERR_UNSUPPORTED;        // one right-hand side per system
   if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI && precond != BS_PREC_BLOCK_JACOBI)
     return BS_ERR_INVALID_ARG;
   int block = 0;
@@ -191,6 +192,7 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   bs::VArgs a = v.args;
   bs::KArgs& g = a.base;
   g = bs::KArgs{};
+  g.nrhs = 1;
   g.n_batch = v.B;
   g.precond = precond == BS_PREC_JACOBI ? 1 : 0;
   g.block = block;

@@ -744,3 +744,48 @@ def test_stronger_preconditioners_absolute_and_dense(precond, bsz):
         check(cd, g, o)
         if precond == bs.PREC_ILU:
             assert np.all(g[1] == 1)
+
+
+@pytest.mark.parametrize("gen,solver,fmt", [("chem", bs.BICGSTAB, bs.CSR), ("chem", bs.GMRES, bs.ELL),
+                                            ("small", bs.BICGSTAB, bs.CSR),
+                                            ("collision", bs.BICGSTAB, bs.CSR)])
+def test_multi_rhs(gen, solver, fmt):
+    """Three right-hand sides per matrix (n_rhs = 3): bit-identical to solving
+    the matrices replicated once per right-hand side, and within the parity bar
+    of the oracle.  One team per wave with staged values (n = 54), two teams
+    per wave (n = 20), 1024-lane teams (n = 992)."""
+    k = 3
+    bt = {"chem": lambda: W.chem_jacobian(400, n=54, seed=27),
+          "small": lambda: W.chem_jacobian(500, n=20, seed=28),
+          "collision": lambda: W.collision_stencil(12)}[gen]()
+    B, n = bt.n_batch, bt.n
+    rng = np.random.default_rng(29)
+    b = 2 * rng.random((B * k, n)) - 1
+    c = Case(bt)
+    x = torch.zeros((B * k, n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B * k, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    say(f"  multi-rhs {gen} solver={solver} fmt={fmt}")
+    bs.bs_batch_solve(fmt, c.P.handle, c.values(fmt), dev(b), x, solver, bs.PREC_JACOBI, 1e-10,
+                      1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k))
+    torch.cuda.synchronize()
+    g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    rep = W.Batch(bt.name + "_rep", n, bt.row_ptr, bt.col_idx, np.repeat(bt.values, k, axis=0), b,
+                  np.zeros_like(b))
+    cr = Case(rep)
+    gr = cr.gpu(fmt, solver, max_iter=1000)
+    for u, v in zip(g, gr):
+        assert np.array_equal(u, v)
+    o = cr.oracle(fmt, solver, max_iter=1000)
+    check(cr, g, o, fmt=fmt)
+
+
+def test_multi_rhs_errors():
+    bt = W.chem_jacobian(10, n=54, seed=30)
+    c = Case(bt)
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.CSR, bs.BICGSTAB, n_rhs=-1)
+    assert e.value.code == bs.ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        c.gpu(bs.CSR, bs.BICGSTAB, n_rhs=3)      # 10 rows of b: not a multiple of 3

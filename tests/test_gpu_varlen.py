@@ -144,10 +144,14 @@ def test_absolute_criterion_uneven():
 
 
 def test_ilu_uneven_refused():
-    """ILU(0) keeps dense factors of one-wave systems: the uneven path refuses it."""
+    """ILU(0) keeps dense factors of one-wave systems, and the uneven path takes
+    one right-hand side per system: both are refused."""
     c = VCase(W.uneven_banded(20, 16, 200, seed=19))
     with pytest.raises(bs.BatchSolveError) as e:
         c.gpu(bs.BICGSTAB, precond=bs.PREC_ILU)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.BICGSTAB, n_rhs=2)
     assert e.value.code == bs.ERR_UNSUPPORTED
 
 
