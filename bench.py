@@ -12,7 +12,8 @@ rows) and its triangles solved by BatchTrsv, the uneven batch (100k banded syste
 [16, 1024] in one persistent launch, eager and graph-replayed), 4096 9-point
 stencil systems of n = 992 (BiCGSTAB and GMRES(30), FP64 and mixed), the chemistry
 matrices stored as BatchDense (relative and absolute stop criteria), a stiffer
-chemistry batch (gamma = 1e-3) under scalar Jacobi, block Jacobi and ILU(0), the learned
+chemistry batch (gamma = 1e-3) under scalar Jacobi, block Jacobi and ILU(0), 2^14
+chemistry matrices with 8 right-hand sides each, the learned
 warm start along a drifting sequence (mixed precision from the network's
 guess vs the plain FP64 solve), the HBM roofline of the solver kernel, and
 the CPU oracle's throughput on the host cores.
@@ -207,6 +208,48 @@ def stiff_leg(args, bs, W, torch, np, dev, tol, max_iter):
                 "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                 "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                 "max_resid": float(rs.max())}
+    del vals, b, x
+    return out
+
+
+def multi_rhs_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """Several right-hand sides per matrix: ``args.rhs_batch`` chemistry matrices
+    (the headline's pattern and distribution) with ``args.n_rhs`` right-hand sides
+    each, b ~ U(-1, 1), BiCGSTAB + Jacobi to 1e-10 from x0 = 0, BatchCsr; the
+    same number of solves as the headline when rhs_batch * n_rhs = 2^17."""
+    bt = W.chem_jacobian(n_batch=args.rhs_batch, n=54, fill=0.35, gamma=1e-6, seed=0)
+    B, n, nnz, k = bt.n_batch, bt.n, bt.nnz, args.n_rhs
+    P = bs.Pattern.from_csr(bt.row_ptr, bt.col_idx)
+    vals = torch.from_numpy(bt.values).to(dev)
+    rng = np.random.default_rng(1)
+    b = torch.from_numpy(2.0 * rng.random((B * k, n)) - 1.0).to(dev)
+    x = torch.empty_like(b)
+    iters = torch.empty(B * k, dtype=torch.int32, device=dev)
+    resid = torch.empty(B * k, dtype=torch.float64, device=dev)
+    status = torch.empty(B * k, dtype=torch.int32, device=dev)
+    opts = bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k)
+    a = (bs.CSR, P.handle, vals, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter, iters, resid,
+         status, opts)
+    for _ in range(max(10, args.warmup // 4)):
+        bs.bs_batch_solve(*a)
+    torch.cuda.synchronize()
+    steps = max(10, args.steps // 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        bs.bs_batch_solve(*a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+    # algorithmic bytes: each matrix's values once, every solve's b, x and outputs
+    alg = B * 8 * nnz + B * k * (16 * n + 16) + 4 * (n + 1) + 4 * nnz
+    out = {"workload": f"chem_jacobian_b{B}x{k}rhs_n{n}_csr_bicgstab_jacobi", "matrices": B,
+           "n_rhs": k, "solves": B * k, "ms": ms, "solves_per_s": B * k / (ms * 1e-3),
+           "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": int(alg),
+           "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+           "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
     del vals, b, x
     return out
 
@@ -425,6 +468,10 @@ def main() -> int:
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the BatchDense leg (2^16 chemistry systems stored densely)")
     ap.add_argument("--dense-batch", type=int, default=1 << 16)
+    ap.add_argument("--no-multi-rhs", action="store_true",
+                    help="skip the several-right-hand-sides leg (2^14 matrices x 8)")
+    ap.add_argument("--rhs-batch", type=int, default=1 << 14)
+    ap.add_argument("--n-rhs", type=int, default=8)
     ap.add_argument("--no-stiff", action="store_true",
                     help="skip the preconditioner leg (2^16 stiffer chemistry systems)")
     ap.add_argument("--stiff-batch", type=int, default=1 << 16)
@@ -546,6 +593,11 @@ def main() -> int:
         progress(f"dense: {dense['relative']['ms']:.3f} ms (relative), "
                  f"{dense['absolute']['ms']:.3f} ms (absolute)")
 
+    multi = None
+    if not args.no_multi_rhs:
+        multi = multi_rhs_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress(f"multi-rhs: {multi['ms']:.4f} ms for {multi['solves']} solves")
+
     stiff = None
     if not args.no_stiff:
         stiff = stiff_leg(args, bs, W, torch, np, dev, tol, max_iter)
@@ -633,6 +685,7 @@ def main() -> int:
         "uneven": uneven,
         "stencil": stencil,
         "stiff": stiff,
+        "multi_rhs": multi,
         "dense": dense,
         "warm_start": warm,
         "gen_seconds": gen_s,
