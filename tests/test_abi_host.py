@@ -231,3 +231,31 @@ def test_dense_format_host(L):
     h = C.c_void_p()
     assert L.bs_pattern_create_dense(0, C.byref(h)) == bs.ERR_INVALID_ARG
     assert L.bs_pattern_create_dense(8, None) == bs.ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of bs_options and bs_plan_info have the header's size
+    and field offsets (a C program built with gcc against include/batchsolve.h)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = [f[0] for f in bs.bs_options._fields_]
+    pfields = [f[0] for f in bs.bs_plan_info._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "batchsolve.h"',
+           "int main(void) {", '  printf("%zu %zu\\n", sizeof(bs_options), sizeof(bs_plan_info));']
+    src += [f'  printf("%zu\\n", offsetof(bs_options, {f}));' for f in fields]
+    src += [f'  printf("%zu\\n", offsetof(bs_plan_info, {f}));' for f in pfields]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "abi.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(c), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == C.sizeof(bs.bs_options) and vals[1] == C.sizeof(bs.bs_plan_info)
+    offs = vals[2:]
+    assert offs[:len(fields)] == [getattr(bs.bs_options, f).offset for f in fields]
+    assert offs[len(fields):] == [getattr(bs.bs_plan_info, f).offset for f in pfields]
