@@ -286,9 +286,10 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
                            (dense_lds ? bs::ilu_bytes(n) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
-  // ILU(0) is bound by its factorization and substitutions, not by loading
-  // the values: its LDS goes to more resident waves instead of staging
-  if (waves == 1 && !ilu && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
+  // ILU(0) and the triangular solves are bound by their substitution chains,
+  // not by loading the values: their LDS goes to more resident waves instead
+  // of staging
+  if (waves == 1 && !dense_lds && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
     stage = 1;
   out->k = k;
   out->info.team = team;
