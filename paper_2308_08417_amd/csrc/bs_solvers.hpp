@@ -42,22 +42,24 @@ __device__ __forceinline__ double shfl(double v, int src) {
 // shorter); M = the inverse of the block diagonal of A.  Per team in LDS: the
 // inverse stored by columns, binv[j*rows + i] = entry (i, b0 + j) (b0 = i - i %
 // bs), so that the lanes of a wave touch consecutive elements, and a
-// row-indexed exchange buffer pbuf[rows].  The rows
-// of one block always sit in one wave (bs divides the rows a wave holds), so a
-// wavefront-scope fence orders the exchanges; nothing extra stays in
-// registers.
+// row-indexed exchange buffer pbuf[rows].  The rows of one block always sit in
+// one wave, on consecutive lanes (bs divides the rows a wave holds, and block
+// Jacobi runs with row i on lane i of its team), so a wavefront-scope fence
+// orders the exchanges.
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront", "local");
   __builtin_amdgcn_wave_barrier();
 }
 
-// Inverse of every diagonal block by Gauss-Jordan elimination in place without
-// pivoting: for each pivot p, row p is divided by its pivot (its diagonal entry
-// becoming 1/pivot), then every other row r subtracts a_rp times it (its entry p
-// becoming -a_rp/pivot).  A zero or non-finite pivot, or a non-finite entry of
-// the result, makes the block the identity.  The columns of a row's register
-// slots are found by gathering a vector that holds each row's own index.  All
-// lanes of the workgroup call it together.
+// Inverse of every diagonal block by Gauss-Jordan elimination without
+// pivoting: for each pivot p, row p is scaled by the pivot's reciprocal (its
+// diagonal entry becoming 1/pivot), then every other row r subtracts a_rp times
+// it (its entry p becoming -a_rp/pivot).  A zero or non-finite pivot, or a
+// non-finite entry of the result, makes the block the identity.  The block's
+// entries are scattered from the register slots (their columns found by
+// gathering a vector that holds each row's own index), the elimination runs in
+// registers, and the result is stored by columns.  All lanes of the workgroup
+// call it together.
 //
 // After the gather, every LDS access stays inside the wave that owns the rows:
 // a block's rows lie in one wave, and its failure flag is the exchange entry
