@@ -35,6 +35,9 @@ def lib():
         L.or_batch_solve.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p,
                                      I, I, I, D, I, I, I, i32p, f64p, i32p, I]
         L.or_batch_solve.restype = I
+        L.or_batch_solve_log.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p,
+                                         I, I, I, D, I, I, I, i32p, f64p, i32p, I, i32p, I]
+        L.or_batch_solve_log.restype = I
         L.or_batch_spmv.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, f64p]
         L.or_batch_spmv.restype = None
         L.or_batch_true_residual.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p,
@@ -133,6 +136,29 @@ def batch_solve(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = 
                          int(block_size), float(tol), int(bool(absolute)), int(max_iter),
                          int(restart), iters, resid, status, nt)
     return x, iters, resid, status
+
+
+def batch_solve_log(pat: Pattern, values, b, x0=None, fmt: int = CSR, solver: int = BICGSTAB,
+                    precond: int = PREC_JACOBI, tol: float = 1e-10, max_iter: int = 500,
+                    log_cap: int = 16, nthreads: Optional[int] = None, absolute: bool = False,
+                    block_size: int = 4):
+    """``batch_solve`` (CG or BiCGSTAB) that also returns each system's restart
+    log ``[B][log_cap]``: entry 0 counts the restarts from the true residual,
+    entries 1.. hold the iteration count at which each one happened."""
+    v = _f64(values)
+    b = _f64(b)
+    B = b.shape[0]
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, order="C")
+    iters = np.zeros(B, np.int32)
+    resid = np.zeros(B)
+    status = np.zeros(B, np.int32)
+    log = np.zeros((B, log_cap), np.int32)
+    nt = nthreads if nthreads is not None else (os.cpu_count() or 1)
+    rp, ci, nnz, w, ec = pat.args(fmt)
+    lib().or_batch_solve_log(fmt, B, pat.n, rp, ci, nnz, w, ec, v, b, x, solver, precond,
+                             int(block_size), float(tol), int(bool(absolute)), int(max_iter), 30,
+                             iters, resid, status, nt, log, int(log_cap))
+    return x, iters, resid, status, log
 
 
 def batch_spmv(pat: Pattern, values, x, fmt: int = CSR) -> np.ndarray:

@@ -266,9 +266,20 @@ static or_result finish(const or_mat *A, const double *b, const double *x, doubl
     return res;
 }
 
+/* Restart log (reading P2): when log is not NULL, log[0] counts the restarts
+ * from the true residual and log[1..cap-1] receive the iteration count at
+ * which each of the first cap-1 of them happened.  It only records; it never
+ * changes what the solvers compute. */
+static void log_restart(int *log, int cap, int k)
+{
+    if (!log) return;
+    if (log[0] + 1 < cap) log[log[0] + 1] = k;
+    log[0] += 1;
+}
+
 /* ---- CG: Sec. 3.5, Alg. 1, with the residual-norm stop test ------------ */
 static or_result solve_cg(const or_mat *A, const or_prec *M, const double *b, double *x,
-                          double rs, double lim, int max_iter, double *ws)
+                          double rs, double lim, int max_iter, double *ws, int *log, int cap)
 {
     int n = A->n, k = 0, r_true;
     double *r = ws, *z = ws + n, *p = ws + 2 * n, *t = ws + 3 * n;
@@ -288,6 +299,7 @@ restart:
             r_true = 1;
             if (rn <= lim) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
             if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
+            log_restart(log, cap, k);
             goto restart;
         }
         if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
@@ -312,7 +324,8 @@ restart:
 
 /* ---- BiCGSTAB, right-preconditioned (van der Vorst 1992) --------------- */
 static or_result solve_bicgstab(const or_mat *A, const or_prec *M, const double *b, double *x,
-                                double rs, double lim, int max_iter, double *ws)
+                                double rs, double lim, int max_iter, double *ws, int *log,
+                                int cap)
 {
     int n = A->n, k = 0, r_true;
     double *r = ws, *rh = ws + n, *p = ws + 2 * n, *v = ws + 3 * n;
@@ -332,6 +345,7 @@ restart:
             r_true = 1;
             if (rn <= lim) return finish(A, b, x, rs, k, OR_CONVERGED, r, t);
             if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
+            log_restart(log, cap, k);
             goto restart;
         }
         if (k >= max_iter) return finish(A, b, x, rs, k, OR_MAX_ITER, r, t);
@@ -491,7 +505,7 @@ static size_t workspace_doubles(int solver, int n, int m)
  * 1 tests ||r|| <= tol and reports ||b - A x||. */
 static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
                            const double *b, double *x, double tol, int absolute, int max_iter,
-                           int m, double *ws, double *F, unsigned char *P)
+                           int m, double *ws, double *F, unsigned char *P, int *log, int cap)
 {
     int n = A->n;
     double *d = ws;                         /* n doubles: d */
@@ -524,8 +538,9 @@ static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
         to_dense(A, F, P);
         if (ilu0(A->n, F, P)) { M.lu = F; M.mask = P; }
     }
-    if (solver == OR_CG) return solve_cg(A, &M, b, x, rs, lim, max_iter, work);
-    if (solver == OR_BICGSTAB) return solve_bicgstab(A, &M, b, x, rs, lim, max_iter, work);
+    if (solver == OR_CG) return solve_cg(A, &M, b, x, rs, lim, max_iter, work, log, cap);
+    if (solver == OR_BICGSTAB)
+        return solve_bicgstab(A, &M, b, x, rs, lim, max_iter, work, log, cap);
     return solve_gmres(A, &M, b, x, rs, lim, max_iter, m, work);
 }
 
@@ -539,12 +554,14 @@ static void make_mat(or_mat *A, int fmt, int n, const int *row_ptr, const int *c
 /* ------------------------------- exports -------------------------------- */
 
 /* Solve every system of the batch; x holds x0 on entry and the result on exit.
- * values: CSR [n_batch][nnz], ELL [n_batch][width][n].  Returns 0. */
-int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
-                   int nnz, int width, const int *ell_col, const double *values,
-                   const double *b, double *x, int solver, int precond, int block_size,
-                   double tol, int absolute, int max_iter, int restart, int *iters,
-                   double *resid, int *status, int nthreads)
+ * values: CSR [n_batch][nnz], ELL [n_batch][width][n].  restart_log (may be
+ * NULL): [n_batch][log_cap] int32, the restart log of each system (CG and
+ * BiCGSTAB; see log_restart).  Returns 0. */
+int or_batch_solve_log(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                       int nnz, int width, const int *ell_col, const double *values,
+                       const double *b, double *x, int solver, int precond, int block_size,
+                       double tol, int absolute, int max_iter, int restart, int *iters,
+                       double *resid, int *status, int nthreads, int *restart_log, int log_cap)
 {
     size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
     int m = restart > 0 ? restart : 30;
@@ -553,6 +570,7 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
     int dense = precond == OR_PREC_ILU || solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER;
     if (block_size < 1 || block_size > OR_MAX_BLOCK) block_size = 1;
     if (nthreads < 1) nthreads = 1;
+    if (log_cap < 1) restart_log = NULL;
     #pragma omp parallel num_threads(nthreads)
     {
         double *ws = (double *)malloc(wsz * sizeof(double));
@@ -561,9 +579,12 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
         #pragma omp for schedule(dynamic, 8)
         for (int64_t s = 0; s < n_batch; ++s) {
             or_mat A;
+            int *log = restart_log ? restart_log + (size_t)s * log_cap : NULL;
+            if (log) for (int i = 0; i < log_cap; ++i) log[i] = 0;
             make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
             or_result res = solve_one(&A, solver, precond, block_size, b + (size_t)s * n,
-                                      x + (size_t)s * n, tol, absolute, max_iter, m, ws, F, P);
+                                      x + (size_t)s * n, tol, absolute, max_iter, m, ws, F, P,
+                                      log, log_cap);
             iters[s] = res.iters;
             status[s] = res.status;
             resid[s] = res.resid;
@@ -573,6 +594,18 @@ int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
         free(P);
     }
     return 0;
+}
+
+/* As or_batch_solve_log without the restart log. */
+int or_batch_solve(int fmt, int64_t n_batch, int n, const int *row_ptr, const int *col_idx,
+                   int nnz, int width, const int *ell_col, const double *values,
+                   const double *b, double *x, int solver, int precond, int block_size,
+                   double tol, int absolute, int max_iter, int restart, int *iters,
+                   double *resid, int *status, int nthreads)
+{
+    return or_batch_solve_log(fmt, n_batch, n, row_ptr, col_idx, nnz, width, ell_col, values,
+                              b, x, solver, precond, block_size, tol, absolute, max_iter,
+                              restart, iters, resid, status, nthreads, NULL, 0);
 }
 
 /* y = A x for every system. */

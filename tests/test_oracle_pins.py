@@ -458,6 +458,66 @@ def test_status_codes(solver):
     assert np.all(st == O.BREAKDOWN)
 
 
+# --------------------------------------------------------------- restart from the true residual
+# Reading P2: when the recurrence residual passes the test but the true
+# residual b - A x does not, the method starts again from x as if it were a new
+# initial guess (BiCGSTAB resets its shadow residual, rho0 = alpha = omega = 1
+# and p = v = 0; CG rebuilds z, p and rho from the true residual).  So a solve
+# that restarts at iteration k must equal, bit for bit, a fresh solve started
+# from its iterate x_k with the remaining budget, its count offset by k.  x_k
+# itself is the iterate a solve with max_iter = k returns (it ends there with
+# MAX_ITER).  A reset that is forgotten (a stale r^, rho0, alpha, omega, p, v or
+# z) makes the continued solve differ from the fresh one.
+def restart_cases():
+    bt8 = W.tridiag_stencil(n_batch=4, n=8, seed=0)
+    sp_rng = np.random.default_rng(5)
+    n = 12
+    As = []
+    for _ in range(3):
+        M = sp_rng.standard_normal((n, n))
+        As.append(M @ M.T + n * np.eye(n))          # SPD, kappa of a few
+    Pd, vd, bd = batch_from_dense(np.stack(As), sp_rng.standard_normal((3, n)))
+    P8 = O.Pattern(bt8.n, bt8.row_ptr, bt8.col_idx)
+    return [
+        ("bicgstab_tridiag", P8, bt8.values, bt8.b, O.BICGSTAB, O.PREC_JACOBI, 1e-30, 25),
+        ("bicgstab_none", P8, bt8.values, bt8.b, O.BICGSTAB, O.PREC_NONE, 1e-30, 40),
+        ("cg_tridiag", P8, bt8.values, bt8.b, O.CG, O.PREC_JACOBI, 1e-20, 120),
+        ("cg_spd_dense", Pd, vd, bd, O.CG, O.PREC_NONE, 1e-22, 150),
+    ]
+
+
+@pytest.mark.parametrize("case", restart_cases(), ids=lambda c: c[0])
+def test_restart_equals_fresh_solve(case):
+    name, P, vals, b, solver, prec, tol, max_iter = case
+    x, it, res, st, log = O.batch_solve_log(P, vals, b, solver=solver, precond=prec, tol=tol,
+                                            max_iter=max_iter)
+    assert np.all(log[:, 0] >= 1), f"{name}: every system must restart at least once"
+    checked = 0
+    differs_off_restart = 0
+    for s in range(b.shape[0]):
+        for k in log[s, 1:1 + min(int(log[s, 0]), 3)]:
+            k = int(k)
+            one = slice(s, s + 1)
+            xk, ik, _, sk = O.batch_solve(P, vals[one], b[one], solver=solver, precond=prec,
+                                          tol=tol, max_iter=k)
+            assert sk[0] == O.MAX_ITER and ik[0] == k
+            xf, itf, rf, sf = O.batch_solve(P, vals[one], b[one], x0=xk, solver=solver,
+                                            precond=prec, tol=tol, max_iter=max_iter - k)
+            assert np.array_equal(xf[0], x[s]), f"{name} system {s}: restart at {k} differs"
+            assert itf[0] + k == it[s] and sf[0] == st[s] and rf[0] == res[s]
+            checked += 1
+            # one iteration past the restart point the Krylov state is not fresh:
+            # a solve restarted there by hand takes a different path
+            if k + 1 < it[s]:
+                xo, _, _, _ = O.batch_solve(P, vals[one], b[one], solver=solver, precond=prec,
+                                            tol=tol, max_iter=k + 1)
+                xg, _, _, _ = O.batch_solve(P, vals[one], b[one], x0=xo, solver=solver,
+                                            precond=prec, tol=tol, max_iter=max_iter - k - 1)
+                differs_off_restart += int(not np.array_equal(xg[0], x[s]))
+    assert checked >= b.shape[0]
+    assert differs_off_restart >= 1
+
+
 # --------------------------------------------------------------- absolute stop criterion
 # Tab. 2 lists an absolute and a relative stop criterion.  Absolute: stop when
 # ||r||_2 <= tol and report ||b - A x||_2; relative: ||r||_2 <= tol ||b||_2 and
