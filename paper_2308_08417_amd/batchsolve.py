@@ -156,6 +156,60 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+_DTYPES = {"f64": "torch.float64", "f32": "torch.float32", "i32": "torch.int32"}
+
+
+def _expect(t, name: str, dtype: str, numel: int, optional: bool = False,
+            at_least: bool = False) -> None:
+    """Check a tensor argument before its raw pointer reaches the library: the
+    kernels trust the element type and count, so a wrong one would make them
+    read or write past the allocation.  ``dtype`` is "f64", "f32" or "i32";
+    ``numel`` the element count the call will touch.  Raises ValueError."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if str(t.dtype) != _DTYPES[dtype]:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {_DTYPES[dtype]}")
+    if t.numel() < numel if at_least else t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {'at least ' if at_least else ''}"
+                         f"{numel}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+
+
+def check_solve_args(fmt: int, n_rows: int, nnz: int, ell_width: int, values, b, x, iters, resid,
+                     status=None, opts: Optional["bs_options"] = None) -> tuple:
+    """Element types and counts of a ``bs_batch_solve`` call for a pattern of
+    ``n_rows`` rows, ``nnz`` entries and ELL width ``ell_width``; returns
+    ``(n_batch, n_solves)``.  Raises ValueError on any mismatch."""
+    if b is None or b.dim() != 2 or b.shape[1] != n_rows:
+        raise ValueError(f"b: expected a [n_solves][{n_rows}] tensor")
+    k = opts.n_rhs if opts is not None and opts.n_rhs > 1 else 1
+    n_solves = int(b.shape[0])
+    if n_solves % k:
+        raise ValueError("b holds a whole number of right-hand sides per matrix")
+    n_batch = n_solves // k
+    stored = {CSR: nnz, ELL: ell_width * n_rows, DENSE: n_rows * n_rows}.get(fmt)
+    if stored is None:
+        raise ValueError(f"unknown format {fmt}")
+    _expect(values, "values", "f64", n_batch * stored)
+    _expect(b, "b", "f64", n_solves * n_rows)
+    _expect(x, "x", "f64", n_solves * n_rows)
+    _expect(iters, "iters", "i32", n_solves)
+    _expect(resid, "resid", "f64", n_solves)
+    _expect(status, "status", "i32", n_solves, optional=True)
+    if opts is not None:
+        keep = getattr(opts, "_keep", (None, None, None))
+        if (opts.outer_iters or opts.x_alt or opts.alt_used) and keep == (None, None, None):
+            raise ValueError("options with device pointers must come from make_options")
+        outer, x_alt, alt_used = keep
+        _expect(outer, "outer_iters", "i32", n_solves, optional=True)
+        _expect(x_alt, "x_alt", "f64", n_solves * n_rows, optional=True)
+        _expect(alt_used, "alt_used", "i32", n_solves, optional=True)
+    return n_batch, n_solves
+
+
 def _stream(stream) -> Optional[int]:
     if stream is not None:
         return int(stream)
@@ -284,11 +338,10 @@ def bs_batch_solve(fmt: int, pattern: int, values, b, x, solver: int, precond: i
     (and the per-solve outputs) hold ``B*k`` rows, matrix by matrix.
     Asynchronous: synchronise the stream before reading results.
     """
-    n_solves, n_rows = b.shape
-    k = opts.n_rhs if opts is not None and opts.n_rhs > 1 else 1
-    if n_solves % k:
-        raise ValueError("b holds a whole number of right-hand sides per matrix")
-    n_batch = n_solves // k
+    q = bs_pattern_query(pattern)
+    n_rows = q["n_rows"]
+    n_batch, _ = check_solve_args(fmt, n_rows, q["nnz"], q["ell_width"], values, b, x, iters,
+                                  resid, status, opts)
     _check(lib().bs_batch_solve(fmt, n_batch, n_rows, pattern, _ptr(values), _ptr(b), _ptr(x),
                                 solver, precond, float(tol), int(max_iter), _ptr(iters),
                                 _ptr(resid), _ptr(status),
@@ -341,7 +394,10 @@ def solve(pattern: Pattern, values, b, x=None, fmt: int = CSR, solver: int = BIC
     dev = b.device
     if x is None:
         x = torch.empty_like(b)
-        opts = opts if opts is not None else make_options()
+        # a copy: the caller's options stay as they were
+        base = opts if opts is not None else make_options()
+        opts = bs_options.from_buffer_copy(base)
+        opts._keep = getattr(base, "_keep", (None, None, None))
         opts.flags |= FLAG_X0_ZERO
     iters = torch.empty(B, dtype=torch.int32, device=dev)
     resid = torch.empty(B, dtype=torch.float64, device=dev)
@@ -356,6 +412,10 @@ def _host(a, dt) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a), dtype=dt)
 
 
+# systems of each uneven-batch handle made here (for the argument checks)
+_VB_SYSTEMS: dict = {}
+
+
 def bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_all, sys_pat) -> int:
     pr, pro, rpa = _host(pat_rows, np.int32), _host(pat_rowptr_off, np.int64), _host(rowptr_all, np.int32)
     pco, ca, sp = _host(pat_col_off, np.int64), _host(col_all, np.int32), _host(sys_pat, np.int32)
@@ -365,10 +425,12 @@ def bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_al
                                     ca.ctypes.data if ca.size else None,
                                     sp.ctypes.data if sp.size else None, C.byref(h)),
            "bs_varbatch_create")
+    _VB_SYSTEMS[h.value] = int(sp.size)
     return h.value
 
 
 def bs_varbatch_destroy(handle: int) -> None:
+    _VB_SYSTEMS.pop(handle, None)
     _check(lib().bs_varbatch_destroy(handle), "bs_varbatch_destroy")
 
 
@@ -384,7 +446,27 @@ def bs_varbatch_set_policy(handle: int, policy: int) -> None:
     _check(lib().bs_varbatch_set_policy(handle, policy), "bs_varbatch_set_policy")
 
 
+def check_varbatch_args(total_values: int, total_rows: int, n_batch: int, values, b, x, iters,
+                        resid, status=None, opts: Optional["bs_options"] = None) -> None:
+    """Element types and counts of an uneven-batch solve; raises ValueError."""
+    _expect(values, "values", "f64", total_values)
+    _expect(b, "b", "f64", total_rows)
+    _expect(x, "x", "f64", total_rows)
+    _expect(iters, "iters", "i32", n_batch)
+    _expect(resid, "resid", "f64", n_batch)
+    _expect(status, "status", "i32", n_batch, optional=True)
+    if opts is not None:
+        outer, x_alt, alt_used = getattr(opts, "_keep", (None, None, None))
+        if x_alt is not None or alt_used is not None:
+            raise ValueError("the uneven-batch path takes no second initial guess")
+        _expect(outer, "outer_iters", "i32", n_batch, optional=True)
+
+
 def _vargs(handle, values, b, x, solver, precond, tol, max_iter, iters, resid, status, opts):
+    q = bs_varbatch_query(handle)
+    n_batch = _VB_SYSTEMS[handle]
+    check_varbatch_args(q["total_values"], q["total_rows"], n_batch, values, b, x, iters, resid,
+                        status, opts)
     return (handle, _ptr(values), _ptr(b), _ptr(x), solver, precond, float(tol), int(max_iter),
             _ptr(iters), _ptr(resid), _ptr(status), C.byref(opts) if opts is not None else None)
 
@@ -437,6 +519,7 @@ class VarBatch:
 
     def __del__(self):
         if getattr(self, "handle", 0) and _lib is not None:
+            _VB_SYSTEMS.pop(self.handle, None)
             _lib.bs_varbatch_destroy(self.handle)
             self.handle = 0
 
@@ -450,16 +533,39 @@ def _f64h(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
 
 
+# (n, nnz) of each learned-start model made here (for the argument checks)
+_WS_SHAPES: dict = {}
+
+
 def bs_ws_create(n: int, row_ptr, col_idx) -> int:
     rp, ci = _host_i32(row_ptr), _host_i32(col_idx)
     h = C.c_void_p()
     _check(lib().bs_ws_create(n, ci.size, rp.ctypes.data, ci.ctypes.data if ci.size else None,
                               C.byref(h)), "bs_ws_create")
+    _WS_SHAPES[h.value] = (int(n), int(ci.size))
     return h.value
 
 
 def bs_ws_destroy(handle: int) -> None:
+    _WS_SHAPES.pop(handle, None)
     _check(lib().bs_ws_destroy(handle), "bs_ws_destroy")
+
+
+def check_ws_args(n: int, nnz: int, n_rows: int, *, values=None, b=None, x_prev=None,
+                  x_next=None, x0=None, feat=None, delta=None, rows=None, y=None,
+                  n_feat_rows: Optional[int] = None) -> None:
+    """Element types and counts of a learned-start call on a model of n
+    unknowns and nnz pattern entries; ``n_rows`` is the number of systems or
+    samples the call processes (``n_feat_rows`` the rows of ``feat``/``delta``
+    when ``rows`` selects among them).  Raises ValueError."""
+    fr = n_rows if n_feat_rows is None else n_feat_rows
+    for t, name, dt, cnt in ((values, "values", "f64", n_rows * nnz),
+                             (b, "b", "f64", n_rows * n), (x_prev, "x_prev", "f64", n_rows * n),
+                             (x_next, "x_next", "f64", n_rows * n), (x0, "x0", "f64", n_rows * n),
+                             (feat, "feat", "f32", fr * 3 * n), (delta, "delta", "f32", fr * n),
+                             (y, "y", "f32", n_rows * n)):
+        _expect(t, name, dt, cnt, optional=True)
+    _expect(rows, "rows", "i32", n_rows, optional=True, at_least=True)
 
 
 def bs_ws_param_count(handle: int) -> int:
@@ -483,12 +589,20 @@ def bs_ws_get_params(handle: int) -> np.ndarray:
 
 def bs_ws_features(handle: int, values, b, x_prev, feat, x_next=None, delta=None,
                    stream=None) -> None:
+    n, nnz = _WS_SHAPES[handle]
+    B = b.numel() // n
+    check_ws_args(n, nnz, B, values=values, b=b, x_prev=x_prev, x_next=x_next, feat=feat,
+                  delta=delta)
+    if (x_next is None) != (delta is None):
+        raise ValueError("x_next and delta go together")
     _check(lib().bs_ws_features(handle, b.shape[0], _ptr(values), _ptr(b), _ptr(x_prev),
                                 _ptr(x_next), _ptr(feat), _ptr(delta), _stream(stream)),
            "bs_ws_features")
 
 
 def bs_ws_fit_scaling(handle: int, feat, delta, stream=None) -> None:
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, feat.shape[0], feat=feat, delta=delta)
     _check(lib().bs_ws_fit_scaling(handle, feat.shape[0], _ptr(feat), _ptr(delta),
                                    _stream(stream)), "bs_ws_fit_scaling")
 
@@ -507,6 +621,9 @@ def bs_ws_set_scaling(handle: int, mu_f, sd_f, sd_d) -> None:
 
 
 def bs_ws_forward(handle: int, feat, y, rows=None, stream=None) -> None:
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, y.shape[0], feat=feat, rows=rows, y=y,
+                  n_feat_rows=feat.shape[0] if rows is not None else None)
     _check(lib().bs_ws_forward(handle, y.shape[0], _ptr(feat), _ptr(rows), _ptr(y),
                                _stream(stream)), "bs_ws_forward")
 
@@ -514,6 +631,13 @@ def bs_ws_forward(handle: int, feat, y, rows=None, stream=None) -> None:
 def bs_ws_grad(handle: int, feat, delta, grad, loss, rows=None, n_samples=None,
                stream=None) -> None:
     M = n_samples if n_samples is not None else (rows.shape[0] if rows is not None else feat.shape[0])
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, M, feat=feat, delta=delta, rows=rows,
+                  n_feat_rows=feat.shape[0])
+    if rows is None and feat.shape[0] < M:
+        raise ValueError(f"feat: {feat.shape[0]} rows, expected at least {M}")
+    _expect(grad, "grad", "f32", bs_ws_param_count(handle))
+    _expect(loss, "loss", "f32", 1, optional=True)
     _check(lib().bs_ws_grad(handle, M, _ptr(feat), _ptr(delta), _ptr(rows), _ptr(grad), _ptr(loss),
                             _stream(stream)), "bs_ws_grad")
 
@@ -521,11 +645,19 @@ def bs_ws_grad(handle: int, feat, delta, grad, loss, rows=None, n_samples=None,
 def bs_ws_train_step(handle: int, feat, delta, lr: float, loss=None, rows=None, n_samples=None,
                      stream=None) -> None:
     M = n_samples if n_samples is not None else (rows.shape[0] if rows is not None else feat.shape[0])
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, M, feat=feat, delta=delta, rows=rows,
+                  n_feat_rows=feat.shape[0])
+    if rows is None and feat.shape[0] < M:
+        raise ValueError(f"feat: {feat.shape[0]} rows, expected at least {M}")
+    _expect(loss, "loss", "f32", 1, optional=True)
     _check(lib().bs_ws_train_step(handle, M, _ptr(feat), _ptr(delta), _ptr(rows), float(lr),
                                   _ptr(loss), _stream(stream)), "bs_ws_train_step")
 
 
 def bs_ws_infer(handle: int, values, b, x_prev, x0, stream=None) -> None:
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, b.numel() // n, values=values, b=b, x_prev=x_prev, x0=x0)
     _check(lib().bs_ws_infer(handle, b.shape[0], _ptr(values), _ptr(b), _ptr(x_prev), _ptr(x0),
                              _stream(stream)), "bs_ws_infer")
 
@@ -540,5 +672,6 @@ class WarmStartModel:
 
     def __del__(self):
         if getattr(self, "handle", 0) and _lib is not None:
+            _WS_SHAPES.pop(self.handle, None)
             _lib.bs_ws_destroy(self.handle)
             self.handle = 0
