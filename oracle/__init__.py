@@ -19,6 +19,9 @@ from . import build as _build
 CSR, ELL = 0, 1
 CG, BICGSTAB, GMRES, TRSV_LOWER, TRSV_UPPER = 0, 1, 2, 3, 4
 PREC_NONE, PREC_JACOBI, PREC_BLOCK_JACOBI, PREC_ILU = 0, 1, 2, 3
+# ILU(0) with the column-oriented backward substitution (same operations,
+# decreasing column order): the oracle's second order, for rounding studies
+PREC_ILU_COL = 4
 CONVERGED, MAX_ITER, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 
 _lib = None
@@ -50,7 +53,7 @@ def lib():
         L.or_batch_ilu0.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p, i32p]
         L.or_batch_ilu0.restype = None
         L.or_batch_ilu0_apply.argtypes = [I, I64, I, i32p, i32p, I, I, i32p, f64p, f64p,
-                                          f64p, f64p]
+                                          f64p, f64p, I]
         L.or_batch_ilu0_apply.restype = None
         L.or_dot.argtypes = [I, f64p, f64p]
         L.or_dot.restype = D
@@ -204,13 +207,15 @@ def ilu0(pat: Pattern, values, fmt: int = CSR):
     return lu, ok.astype(bool)
 
 
-def ilu0_apply(pat: Pattern, values, lu, v_in, fmt: int = CSR) -> np.ndarray:
-    """z = (L U)^{-1} v per system with the factors returned by ``ilu0``."""
+def ilu0_apply(pat: Pattern, values, lu, v_in, fmt: int = CSR, col: bool = False) -> np.ndarray:
+    """z = (L U)^{-1} v per system with the factors returned by ``ilu0``
+    (``col``: column-oriented backward substitution)."""
     v = _f64(values)
     x = _f64(v_in)
     z = np.empty_like(x)
     rp, ci, nnz, w, ec = pat.args(fmt)
-    lib().or_batch_ilu0_apply(fmt, x.shape[0], pat.n, rp, ci, nnz, w, ec, v, _f64(lu), x, z)
+    lib().or_batch_ilu0_apply(fmt, x.shape[0], pat.n, rp, ci, nnz, w, ec, v, _f64(lu), x, z,
+                              int(bool(col)))
     return z
 
 

@@ -6,14 +6,18 @@ this module; the product path never does.
 The learned warm start predicts the change of the solution between two time
 steps of a sequence of related batches.  For system s at step t:
 
-  features   f = [diag(A_t), b_t, x_{t-1}]                      (3n values)
+  features   f = [diag(A_t), b_t - x_{t-1}, x_{t-1}]            (3n values)
   normalised z = (f - mu_f) / sigma_f   (per component, training-set moments)
   network    h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), y = h2 W3 + b3
   guess      x0 = x_{t-1} + sigma_d * y
   target     y* = (x_t - x_{t-1}) / sigma_d
 
 with sigma_d the per-component standard deviation of x_t - x_{t-1} over the
-training set.  Loss: mean squared error over samples and components.  Training
+training set.  The features carry the information of (diag(A_t), b_t,
+x_{t-1}); the middle block is the difference b_t - x_{t-1}, formed in FP64
+before any rounding, because the change of the solution from one step to the
+next is of the order of that difference, which is far below the precision a
+bfloat16 input keeps of b_t and x_{t-1} themselves.  Loss: mean squared error over samples and components.  Training
 uses Adam (Kingma and Ba 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
 The guess is kept only if its residual is not larger than that of x_{t-1}.
 
@@ -83,9 +87,10 @@ def param_count(F: int, H: int, O: int) -> int:
 
 
 def features(diag, b, x_prev) -> np.ndarray:
-    """[diag(A), b, x_prev] per system: arrays [B, n] -> [B, 3n]."""
-    return np.concatenate([np.asarray(diag, np.float64), np.asarray(b, np.float64),
-                           np.asarray(x_prev, np.float64)], axis=1)
+    """[diag(A), b - x_prev, x_prev] per system: arrays [B, n] -> [B, 3n]."""
+    xp = np.asarray(x_prev, np.float64)
+    return np.concatenate([np.asarray(diag, np.float64), np.asarray(b, np.float64) - xp, xp],
+                          axis=1)
 
 
 def csr_diagonal(n: int, row_ptr, col_idx, values) -> np.ndarray:

@@ -38,7 +38,13 @@
 
 enum { OR_CSR = 0, OR_ELL = 1 };
 enum { OR_CG = 0, OR_BICGSTAB = 1, OR_GMRES = 2, OR_TRSV_LOWER = 3, OR_TRSV_UPPER = 4 };
-enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1, OR_PREC_BLOCK_JACOBI = 2, OR_PREC_ILU = 3 };
+/* OR_PREC_ILU_COL: ILU(0) with the column-oriented backward substitution (the
+ * same factors and operations, the backward sums taken in decreasing column
+ * order); the library computes only OR_PREC_ILU's result, the oracle offers
+ * both orders so that a test can see how far rounding order alone moves a
+ * solve. */
+enum { OR_PREC_NONE = 0, OR_PREC_JACOBI = 1, OR_PREC_BLOCK_JACOBI = 2, OR_PREC_ILU = 3,
+       OR_PREC_ILU_COL = 4 };
 enum { OR_MAX_BLOCK = 16 };
 enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_BREAKDOWN = 2, OR_NONFINITE = 3 };
 
@@ -201,15 +207,29 @@ static int ilu0(int n, double *F, const unsigned char *P)
 }
 
 /* z = (L U)^{-1} v: forward substitution with the unit lower factor, then
- * backward substitution with the upper one, each sum in increasing column
- * order over the pattern. */
-static void ilu_apply(int n, const double *F, const unsigned char *P, const double *v, double *z)
+ * backward substitution with the upper one.  The forward sums run in
+ * increasing column order over the pattern.  The backward substitution is
+ * row-oriented (row i sums its terms u_ij z_j in increasing j, then divides by
+ * u_ii) unless col is set; then it is column-oriented (the other textbook
+ * form: z_j is divided by u_jj as soon as column j is reached, and every row
+ * above subtracts u_ij z_j, so row i takes its terms in decreasing j).  Both
+ * are the same operations in a different order. */
+static void ilu_apply(int n, const double *F, const unsigned char *P, const double *v, double *z,
+                      int col)
 {
     for (int i = 0; i < n; ++i) {
         double acc = v[i];
         for (int k = 0; k < i; ++k)
             if (P[(size_t)i * n + k]) acc = acc - F[(size_t)i * n + k] * z[k];
         z[i] = acc;
+    }
+    if (col) {
+        for (int j = n - 1; j >= 0; --j) {
+            z[j] = z[j] / F[(size_t)j * n + j];
+            for (int i = 0; i < j; ++i)
+                if (P[(size_t)i * n + j]) z[i] = z[i] - F[(size_t)i * n + j] * z[j];
+        }
+        return;
     }
     for (int i = n - 1; i >= 0; --i) {
         double acc = z[i];
@@ -222,12 +242,12 @@ static void ilu_apply(int n, const double *F, const unsigned char *P, const doub
 /* The preconditioner as solvers apply it: z = M v, with M = diag(d) (scalar
  * Jacobi, or d = 1 for none), the block-Jacobi inverse (bs > 1) or the ILU(0)
  * factors (lu non-null). */
-typedef struct { int bs; const double *d, *inv, *lu; const unsigned char *mask; } or_prec;
+typedef struct { int bs, col; const double *d, *inv, *lu; const unsigned char *mask; } or_prec;
 
 static void prec_apply(const or_prec *M, int n, const double *v, double *z)
 {
     if (M->lu) {
-        ilu_apply(n, M->lu, M->mask, v, z);
+        ilu_apply(n, M->lu, M->mask, v, z, M->col);
         return;
     }
     if (M->bs <= 1) {
@@ -529,12 +549,13 @@ static or_result solve_one(const or_mat *A, int solver, int precond, int bs,
     if (solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER)
         return solve_trsv(A, solver == OR_TRSV_LOWER, b, x, rs, F, P, work);
     jacobi_diag(A, precond == OR_PREC_BLOCK_JACOBI && bs <= 1 ? OR_PREC_JACOBI : precond, d);
-    M.bs = 1; M.d = d; M.inv = inv; M.lu = NULL; M.mask = NULL;
+    M.bs = 1; M.col = precond == OR_PREC_ILU_COL; M.d = d; M.inv = inv; M.lu = NULL;
+    M.mask = NULL;
     if (precond == OR_PREC_BLOCK_JACOBI && bs > 1) {
         block_jacobi(A, bs, inv, gj);
         M.bs = bs;
     }
-    if (precond == OR_PREC_ILU) {
+    if (precond == OR_PREC_ILU || precond == OR_PREC_ILU_COL) {
         to_dense(A, F, P);
         if (ilu0(A->n, F, P)) { M.lu = F; M.mask = P; }
     }
@@ -567,7 +588,8 @@ int or_batch_solve_log(int fmt, int64_t n_batch, int n, const int *row_ptr, cons
     int m = restart > 0 ? restart : 30;
     size_t wsz = workspace_doubles(solver, n, m) + n + (size_t)n * OR_MAX_BLOCK +
                  2 * OR_MAX_BLOCK * OR_MAX_BLOCK;
-    int dense = precond == OR_PREC_ILU || solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER;
+    int dense = precond == OR_PREC_ILU || precond == OR_PREC_ILU_COL ||
+                solver == OR_TRSV_LOWER || solver == OR_TRSV_UPPER;
     if (block_size < 1 || block_size > OR_MAX_BLOCK) block_size = 1;
     if (nthreads < 1) nthreads = 1;
     if (log_cap < 1) restart_log = NULL;
@@ -689,10 +711,12 @@ void or_batch_ilu0(int fmt, int64_t n_batch, int n, const int *row_ptr, const in
     free(P);
 }
 
-/* z = (L U)^{-1} v per system with the factors of or_batch_ilu0 (for pinning). */
+/* z = (L U)^{-1} v per system with the factors of or_batch_ilu0 (for pinning);
+ * col selects the column-oriented backward substitution. */
 void or_batch_ilu0_apply(int fmt, int64_t n_batch, int n, const int *row_ptr,
                          const int *col_idx, int nnz, int width, const int *ell_col,
-                         const double *values, const double *lu, const double *v, double *z)
+                         const double *values, const double *lu, const double *v, double *z,
+                         int col)
 {
     size_t stride = fmt == OR_CSR ? (size_t)nnz : (size_t)width * n;
     unsigned char *P = (unsigned char *)malloc((size_t)n * n);
@@ -701,7 +725,7 @@ void or_batch_ilu0_apply(int fmt, int64_t n_batch, int n, const int *row_ptr,
         or_mat A;
         make_mat(&A, fmt, n, row_ptr, col_idx, width, ell_col, values + (size_t)s * stride);
         to_dense(&A, G, P);
-        ilu_apply(n, lu + (size_t)s * n * n, P, v + (size_t)s * n, z + (size_t)s * n);
+        ilu_apply(n, lu + (size_t)s * n * n, P, v + (size_t)s * n, z + (size_t)s * n, col);
     }
     free(G);
     free(P);

@@ -689,16 +689,44 @@ def test_ilu0_matches_a_on_the_pattern(n, fill):
     assert np.array_equal(lu, lu_e)
 
 
-def test_ilu0_apply_solves_lu():
-    """z = (L U)^{-1} v: L (U z) reproduces v."""
+@pytest.mark.parametrize("col", [False, True])
+def test_ilu0_apply_solves_lu(col):
+    """z = (L U)^{-1} v: L (U z) reproduces v, with the row- and with the
+    column-oriented backward substitution."""
     rng = np.random.default_rng(23)
     P, mask, As, vals = ilu_case(rng, 30, 0.2)
     lu, _ = O.ilu0(P, vals)
     v = rng.random((3, 30)) - 0.5
-    z = O.ilu0_apply(P, vals, lu, v)
+    z = O.ilu0_apply(P, vals, lu, v, col=col)
     for s in range(3):
         L, U = np.tril(lu[s], -1) + np.eye(30), np.triu(lu[s])
         assert np.allclose(L @ (U @ z[s]), v[s], rtol=1e-12, atol=1e-14)
+        assert np.allclose(z[s], scipy.linalg.solve_triangular(
+            U, scipy.linalg.solve_triangular(L, v[s], lower=True, unit_diagonal=True)),
+            rtol=1e-12, atol=1e-14)
+
+
+def test_ilu0_backward_orders_differ_only_in_rounding():
+    """The two backward orders are the same operations: with at most one term
+    per row above the diagonal (a bidiagonal U) they agree bit for bit, and
+    where rows hold several terms they differ in the last bits only."""
+    bt = W.tridiag_stencil(n_batch=6, n=40, seed=8)
+    P = O.Pattern(bt.n, bt.row_ptr, bt.col_idx)
+    lu, ok = O.ilu0(P, bt.values)
+    v = np.random.default_rng(2).random((6, 40)) - 0.5
+    assert ok.all()
+    assert np.array_equal(O.ilu0_apply(P, bt.values, lu, v), O.ilu0_apply(P, bt.values, lu, v, col=True))
+    x1 = O.batch_solve(P, bt.values, bt.b, precond=O.PREC_ILU, tol=1e-12)
+    x2 = O.batch_solve(P, bt.values, bt.b, precond=O.PREC_ILU_COL, tol=1e-12)
+    for a, b in zip(x1, x2):
+        assert np.array_equal(a, b)
+    rng = np.random.default_rng(31)
+    P2, mask, As, vals = ilu_case(rng, 40, 0.3)
+    lu2, _ = O.ilu0(P2, vals)
+    w = rng.random((len(vals), 40)) - 0.5
+    za, zb = O.ilu0_apply(P2, vals, lu2, w), O.ilu0_apply(P2, vals, lu2, w, col=True)
+    assert not np.array_equal(za, zb)
+    assert np.allclose(za, zb, rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("solver", [O.BICGSTAB, O.GMRES])
