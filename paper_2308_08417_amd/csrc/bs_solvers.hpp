@@ -211,14 +211,15 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
 }
 
 // Factorization (Saad 2003, Sec. 10.3.2), right-looking: for pivot k, every row
-// i > k that holds column k replaces that entry by l_ik = a_ik / u_kk (one
-// reciprocal of the pivot per step) and subtracts l_ik u_kj from each of its
-// entries j > k; row k's pattern (a wave-uniform bitmask read from lane k)
+// i > k that holds column k replaces that entry by l_ik = a_ik / u_kk (a
+// division, as the IKJ form writes it) and subtracts l_ik u_kj from each of
+// its entries j > k; row k's pattern (a wave-uniform bitmask read from lane k)
 // bounds the columns visited, eight per batch of loads, and a row's own
 // pattern mask selects which of them change, so nothing fills in (the others
 // are stored back unchanged).  Each entry receives its updates in increasing
-// k, as in the IKJ form.  d gets 1/u_ii.  A zero pivot or a non-finite factor
-// entry anywhere in the system turns M into the identity (F zero, d = 1).
+// k, as in the IKJ form.  d gets the pivot u_ii (1 on idle lanes), which the
+// backward sweep divides by.  A zero pivot or a non-finite factor entry
+// anywhere in the system turns M into the identity (F zero, d = 1).
 template <class TM, class RW>
 __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
   static_assert(RW::R == 1 && RW::TEAM == kWave, "ILU(0) runs on one-wave teams");
@@ -253,9 +254,9 @@ __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
     uint64_t cols = rdlane64(mask, k);
     cols = k >= 63 ? 0 : cols & (~0ull << (k + 1));
     const bool act = ok && i > k && ((mask >> k) & 1);
-    const double rpiv = 1.0 / F[k * st + k];
+    const double piv = F[k * st + k];
     const double aik = F[i * st + k];
-    const double l = act ? aik * rpiv : 0.0;
+    const double l = act ? aik / piv : 0.0;
     if (act) F[i * st + k] = l;
     while (cols) {  // wave-uniform
       int j[kB];
@@ -295,19 +296,20 @@ __device__ void ilu_setup(TM& tm, RW& A, const KArgs& g, double (&d)[RW::R]) {
   if (wave_any(bad)) {
     wave_lds_fence();
     for (int e = lane; e < n * st; e += kWave) F[e] = 0.0;
-    d[0] = ok ? 1.0 : 0.0;
+    d[0] = 1.0;
   } else {
-    d[0] = ok ? 1.0 / F[i * st + i] : 0.0;
+    d[0] = ok ? F[i * st + i] : 1.0;
   }
   wave_lds_fence();
 }
 
 // z = (L U)^{-1} v by two column sweeps: forward, y_k (final on lane k) is
 // read out and every row i > k subtracts l_ik y_k; backward, z_j = y_j / u_jj
-// and every row i < j subtracts u_ij z_j.  Entries off the pattern, and the
-// padding columns (read out from idle lanes, whose values are zero), add
-// nothing.  The sums run in increasing k (forward) and decreasing j
-// (backward).  With M the identity F is zero and d = 1, so z = v.
+// (a division by the pivot d of lane j) and every row i < j subtracts u_ij z_j.
+// Entries off the pattern, and the padding columns (read out from idle lanes,
+// whose values are zero and whose d is 1), add nothing.  The sums run in
+// increasing k (forward) and decreasing j (backward).  With M the identity F
+// is zero and d = 1, so z = v.
 template <class T, class TM, class RW>
 __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
                                           const T (&d)[RW::R], const T (&v)[RW::R],
@@ -333,11 +335,11 @@ __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
     for (int q = 0; q < 8; ++q) uj[q] = F[i * st + j0 + 7 - q];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const double zj = rdlane(acc * dv, j0 + 7 - q);
+      const double zj = rdlane(acc / dv, j0 + 7 - q);
       acc = fma(ihi < j0 + 7 - q && ihi >= 0 ? -uj[q] : 0.0, zj, acc);
     }
   }
-  z[0] = ok ? (T)(acc * dv) : (T)0;
+  z[0] = ok ? (T)(acc / dv) : (T)0;
 }
 
 // z = M v: block Jacobi or ILU(0) in their instances, else the diagonal d

@@ -627,11 +627,18 @@ def test_ilu(gen, solver):
         g = c.gpu(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
         o = c.oracle(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
         assert np.all(o[3] == O.CONVERGED)
-        # The GPU applies the factors with FMAs, one reciprocal per diagonal entry
-        # and a backward sweep in decreasing column order; on the stiff batch
-        # (up to 42 BiCGSTAB steps) such rounding moves a step count by a few.
-        itol = np.maximum(2, np.ceil(0.15 * o[1])) if gen == "stiff" else ITOL
-        check(c, g, o, fmt=fmt, itol=itol)
+        # Both sides divide by the pivots; the GPU's sweeps use FMAs and it
+        # sums the backward sweep column by column.  How far such rounding
+        # alone moves a count is measured on the oracle itself: its row- and
+        # column-oriented backward substitutions (the same operations in
+        # another order) give per system spread = |k_row - k_col|, and the bar
+        # is 2 plus that spread (2 wherever the orders agree).
+        oc = c.oracle(fmt, solver, precond=O.PREC_ILU_COL, max_iter=1000)
+        assert np.array_equal(oc[3], o[3])
+        spread = np.abs(oc[1].astype(np.int64) - o[1])
+        say(f"  oracle order spread: max {spread.max()}, systems with spread > 0: "
+            f"{int((spread > 0).sum())} of {len(spread)}")
+        check(c, g, o, fmt=fmt, itol=ITOL + spread)
         if gen in ("tridiag", "dense"):
             assert np.all(g[1] == 1)
 
