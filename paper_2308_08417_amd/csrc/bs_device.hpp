@@ -170,6 +170,20 @@ __device__ __forceinline__ int wave_max(int v) {
   return max(max(a, b), max(c, d));
 }
 
+// One 16-byte-per-lane direct-to-LDS load of a wave: lane l's 16 bytes at src
+// land at LDS byte lds + 16 l (lds wave-uniform, held in M0).  Issued from
+// inline asm so that the compiler does not see a load in flight that writes
+// LDS: it would then take the LDS counter as out of order and drain every LDS
+// read of the solve with lgkmcnt(0).  The instruction has no register result
+// (nothing lands in a register later); the caller waits for it with an
+// explicit vmcnt before reading the LDS bytes.
+__device__ __forceinline__ void dma16(const void* src, unsigned lds) {
+  __asm__ volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                   :
+                   : "v"(src), "s"(lds)
+                   : "memory", "m0");
+}
+
 // 32-bit LDS addresses: gathers go through address-space-3 pointers so that a
 // buffer's constant offset folds into the ds_read immediate.
 typedef __attribute__((address_space(3))) char lds_char;
@@ -373,7 +387,6 @@ struct Rows {
     const int per = g.fmt == 0 ? g.nnz : g.width * g.n;
     const unsigned l16 = 16u * (unsigned)lane_id();
     const unsigned vr = (unsigned)g.stage_vals_bytes;
-    typedef __attribute__((address_space(3))) void lds_void;
     if constexpr (S::TEAMS == 1) {
       // one system per wave: each region is a run of whole KiB; lanes past the
       // block's last chunk fetch that chunk again
@@ -381,15 +394,13 @@ struct Rows {
       const uintptr_t va = v0 & ~(uintptr_t)15;
       const unsigned vlast = (unsigned)(((v0 + (uintptr_t)per * 8 - 1) & ~(uintptr_t)15) - va);
       for (unsigned d0 = 0; d0 < vr; d0 += 1024)
-        __builtin_amdgcn_global_load_lds((const void*)(va + min(d0 + l16, vlast)),
-                                         (lds_void*)(tm.stage_all + d0), 16, 0, 0);
+        dma16((const void*)(va + min(d0 + l16, vlast)), lds_addr(tm.stage_all + d0));
       const uintptr_t b0 = (uintptr_t)(g.b + base * g.n);
       const uintptr_t ba = b0 & ~(uintptr_t)15;
       const unsigned blast = (unsigned)(((b0 + (uintptr_t)g.n * 8 - 1) & ~(uintptr_t)15) - ba);
       const unsigned br = (unsigned)g.stage_team_bytes - vr;
       for (unsigned d0 = 0; d0 < br; d0 += 1024)
-        __builtin_amdgcn_global_load_lds((const void*)(ba + min(d0 + l16, blast)),
-                                         (lds_void*)(tm.stage_all + vr + d0), 16, 0, 0);
+        dma16((const void*)(ba + min(d0 + l16, blast)), lds_addr(tm.stage_all + vr + d0));
     } else {
       // several teams per wave: map every lane's 16 destination bytes to its
       // team, region and chunk; lanes with nothing to fetch re-read the values
@@ -418,7 +429,7 @@ struct Rows {
           const uintptr_t chunk = (start & ~(uintptr_t)15) + o;
           if (chunk < end) src = chunk;
         }
-        __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(tm.stage_all + d0), 16, 0, 0);
+        dma16((const void*)src, lds_addr(tm.stage_all + d0));
       }
     }
   }
