@@ -176,9 +176,10 @@ __device__ __forceinline__ int wave_max(int v) {
 // LDS: it would then take the LDS counter as out of order and drain every LDS
 // read of the solve with lgkmcnt(0).  The instruction has no register result
 // (nothing lands in a register later); the caller waits for it with an
-// explicit vmcnt before reading the LDS bytes.
+// explicit vmcnt before reading the LDS bytes.  Non-temporal: the values are
+// read once, so they should not displace lines the outputs are merged in.
 __device__ __forceinline__ void dma16(const void* src, unsigned lds) {
-  __asm__ volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+  __asm__ volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt"
                    :
                    : "v"(src), "s"(lds)
                    : "memory", "m0");
@@ -216,6 +217,7 @@ struct Team {
   char* stage;      // this team's part of it: values, then b
   double* red;      // cross-wave reduction slots (multi-wave teams)
   int phase;        // which half of `red` the next reduction uses
+
 
   __device__ Team(char* smem, const KArgs& a) {
     const int t = threadIdx.x;
@@ -295,6 +297,7 @@ struct Team {
   // Whether any team of this wave satisfies p.  For multi-wave teams every
   // wave sees the same (team-uniform) predicate.
   __device__ __forceinline__ bool any(bool p) const { return wave_any(p); }
+
 };
 
 // ---------------------------------------------------------------- sparse rows

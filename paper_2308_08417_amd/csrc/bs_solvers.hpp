@@ -362,6 +362,16 @@ template <class TM, class RW>
 __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
                                        const double (&b)[RW::R], const double (&x)[RW::R], int st,
                                        int k, int outer, double bn, double rn, bool have_rn) {
+  // the output addresses first: their scalar loads then overlap the residual
+  // below instead of waiting one after another before each store
+  double* const gx = g.x;
+  int* const gi = g.iters;
+  double* const gr = g.resid;
+  const bool has_status = g.status != nullptr;
+  int* const gs = has_status ? g.status : g.sink;
+  int* const go = g.outer;
+  const int flags = g.flags;
+  __asm__ volatile("" ::"s"(gx), "s"(gi), "s"(gr), "s"(gs), "s"(go), "s"(flags));
   const bool need = tm.live && !have_rn;
   if (tm.any(need)) {
     double t[RW::R], q[1];
@@ -376,15 +386,15 @@ __device__ __forceinline__ void finish(TM& tm, const RW& A, const KArgs& g,
   if (!tm.live) return;
 #pragma unroll
   for (int r = 0; r < RW::R; ++r)
-    if (A.ok[r]) g.x[tm.row0 + A.row[r]] = x[r];
+    if (A.ok[r]) gx[tm.row0 + A.row[r]] = x[r];
   if (tm.lane == 0) {
-    g.iters[tm.sys] = k;
+    gi[tm.sys] = k;
     // the true residual, relative to ||b|| unless the criterion is absolute
-    g.resid[tm.sys] = !finite(bn) ? bn : ((bn == 0.0 || (g.flags & kFlagAbsTol)) ? rn : rn / bn);
+    gr[tm.sys] = !finite(bn) ? bn : ((bn == 0.0 || (flags & kFlagAbsTol)) ? rn : rn / bn);
     // always one store (to the sink when no status is wanted): the persistent
     // loop counts on a fixed number of stores after each prefetch
-    *(g.status ? g.status + tm.sys : g.sink) = st;
-    if (g.outer) g.outer[tm.sys] = outer;
+    gs[has_status ? tm.sys : 0] = st;
+    if (go) go[tm.sys] = outer;
   }
 }
 
@@ -1178,10 +1188,12 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
 
 // =================================================================== kernels
 // Each workgroup loads the shared pattern into registers once and then walks
-// over the batch: teams take systems blockIdx*TEAMS + tix, stepping by the grid.
-// Single-wave groups prefetch the next round's systems into LDS while the
-// current round is solved: wait for the prefetch, copy the block into registers,
-// wait for those LDS reads, start the next prefetch, solve.
+// over the batch: in every round the G workgroups take G consecutive slots of
+// T systems (T teams each), workgroup b the slot xcd_slot(b) of the round,
+// team t the system slot * T + t.  Single-wave groups prefetch the next
+// round's systems into LDS while the current round is solved: wait for the
+// prefetch, copy the block into registers, wait for those LDS reads, start the
+// next prefetch, solve.
 // Vector memory operations retire in issue order.  After the first round the
 // last ones a wave issued are the previous system's four output stores (x,
 // iters, resid, status), all after this round's prefetch: waiting until at most
@@ -1189,6 +1201,16 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
 // waiting for the stores to be acknowledged.  s_waitcnt vmcnt(4) expcnt(7)
 // lgkmcnt(0).
 constexpr int kWaitPrefetch = 0x0074;
+
+// Workgroups are placed on the 8 XCDs round-robin (workgroup b on XCD b mod 8),
+// and each XCD has its own L2.  Slot of workgroup b in a round of the grid:
+// XCD x takes the contiguous slots x*G/8 .. (x+1)*G/8-1, so
+// neighbouring systems (whose values, right-hand sides and outputs share cache
+// lines at their edges) are handled inside one XCD and their partial lines
+// merge in one L2.  Identity when G is not a multiple of 8.
+__device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
+  return (G & 7u) ? b : (b & 7u) * (G >> 3) + (b >> 3);
+}
 
 // The loop body reads the arguments through ga, at an address offset by a
 // zero the compiler cannot see through: otherwise it hoists every argument
@@ -1200,13 +1222,14 @@ constexpr int kWaitPrefetch = 0x0074;
   Rows<S> A;                                                                       \
   A.load_pattern(tm, g);                                                           \
   const int64_t stride = (int64_t)gridDim.x * S::TEAMS;                            \
+  const int64_t slot0 = (int64_t)xcd_slot(blockIdx.x, gridDim.x) * S::TEAMS;      \
   bool staged = false;                                                             \
   if constexpr (S::WAVES == 1) {                                                   \
     staged = g.stage != 0;                                                         \
-    if (staged) A.prefetch(tm, g, (int64_t)blockIdx.x * S::TEAMS);                 \
+    if (staged) A.prefetch(tm, g, slot0);                                          \
   }                                                                                \
   bool first_round = true;                                                         \
-  for (int64_t base = (int64_t)blockIdx.x * S::TEAMS; base < g.n_batch; base += stride) { \
+  for (int64_t base = slot0; base < g.n_batch; base += stride) {                   \
     int opaque_zero;                                                               \
     __asm__ volatile("s_mov_b32 %0, 0" : "=s"(opaque_zero));                       \
     const KArgs& ga = (&g)[opaque_zero];                                           \
