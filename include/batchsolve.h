@@ -214,6 +214,14 @@ typedef struct {
                            hold n_batch*k entries in the same order; each solve
                            reads its matrix's values (bs_batch_solve only;
                            BS_ERR_UNSUPPORTED on the uneven-batch entry points) */
+  int32_t varlen_policy;/* bs_batch_solve_varlen: queue policy + 1, 1..9 (the
+                           policies of bs_varbatch_set_policy); 0 selects policy 3
+                           (workgroups of 512 lanes x 2 rows, largest tasks first) */
+  int32_t structure_generation; /* bs_batch_solve_varlen: the caller's count of
+                           changes to the batch's structure arrays.  The library
+                           reads and validates those arrays once per (addresses,
+                           batch shape, device, generation); a caller that
+                           rewrites them in place must change this number */
 } bs_options;
 
 /* The fused batched solve (Sec. 3.2-3.6): one kernel launch solves all n_batch
@@ -340,11 +348,62 @@ int bs_varbatch_capture(bs_varbatch vb, const double *values, const double *b, d
                         int32_t *iters, double *resid, int32_t *status, const bs_options *opts);
 int bs_varbatch_replay(bs_varbatch vb, void *stream);
 
+/* Uneven batch on caller-owned DEVICE arrays (the boundary of the batched
+ * solve for systems of different sizes; paper Sec. 3.1 describes one shared
+ * pattern per batch, here each system names one of n_patterns CSR patterns).
+ *   sys_rows  [n_batch] rows of system s (1..1024; equal to its pattern's rows)
+ *   row_off   [n_batch+1] first row of system s in b and x; row_off[0] = 0,
+ *             row_off[s+1] - row_off[s] = sys_rows[s]
+ *   val_off   [n_batch+1] first value of system s; val_off[0] = 0, each system
+ *             holds its pattern's nnz values in CSR order
+ *   pat_id    [n_batch] pattern of system s, 0..n_patterns-1
+ *   pat_rowptr_off, pat_col_off [n_patterns]: where pattern p's row_ptr
+ *             (rows+1 entries, starting at 0) and columns start in rowptr_all
+ *             and col_all; patterns no system uses are not read
+ *   values, b, x, iters, resid, status: as bs_varbatch_solve
+ *   ws, ws_bytes  device workspace of at least bs_varlen_workspace_size(n_batch)
+ *             bytes, 256-byte aligned; it holds the task queue of this call and
+ *             must not be changed by the caller between calls that use it
+ * Every row holds at most 16 entries, no column twice, all in range.  The
+ * first call for a structure copies the structure arrays to the host (one
+ * synchronisation of `stream`), validates them and builds the task queue; later
+ * calls with the same addresses, shape and opts->structure_generation launch
+ * at once (asynchronously), re-uploading the task queue only when ws or the
+ * queue policy changed.  Solvers and options as bs_varbatch_solve.
+ * Errors: BS_ERR_INVALID_ARG (NULL pointer, inconsistent offsets or rows,
+ * workspace too small or misaligned, bad option), BS_ERR_PATTERN (malformed
+ * pattern, pat_id out of range), BS_ERR_UNSUPPORTED (more than 1024 rows, a
+ * row longer than 16, unsupported solver or preconditioner), BS_ERR_HIP.
+ * n_batch = 0 is a no-op. */
+int bs_batch_solve_varlen(int64_t n_batch, const int32_t *sys_rows, const int64_t *row_off,
+                          const int64_t *val_off, int32_t n_patterns, const int32_t *pat_id,
+                          const int64_t *pat_rowptr_off, const int64_t *pat_col_off,
+                          const int32_t *rowptr_all, const int32_t *col_all,
+                          const double *values, const double *b, double *x, bs_solver solver,
+                          bs_precond precond, double tol, int32_t max_iter, int32_t *iters,
+                          double *resid, int32_t *status, const bs_options *opts, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Bytes of workspace bs_batch_solve_varlen needs for n_batch systems (the task
+ * counter, up to n_batch tasks and the queue order).  Pure host function;
+ * 0 for n_batch < 0. */
+size_t bs_varlen_workspace_size(int64_t n_batch);
+
+/* Bytes of device workspace bs_batch_solve needs for this request: 0.  The
+ * fused fixed-size kernels keep every Krylov vector on chip (registers and
+ * LDS) and read and write only the caller's arrays, so the solve takes no
+ * workspace; the query exists so that a caller written against a workspace
+ * protocol can size one.  Pure host function; 0 also for invalid arguments. */
+size_t bs_workspace_size(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
+                         bs_solver solver, const bs_options *opts);
+
 /* ---------------------------------------------------------------------------
  * Learned initial guess for sequences of related batches (systems that drift
  * from one time step to the next, as along an integration in time; the paper
  * solves such sequences, Sec. 4.3).  A three-layer perceptron maps the
- * features f = [diag(A_t), b_t, x_{t-1}] of a system (3n values, normalised by
+ * features f = [diag(A_t), b_t - x_{t-1}, x_{t-1}] of a system (3n values: the
+ * information of diag(A_t), b_t and x_{t-1}, with the difference formed in FP64
+ * so that the small step change survives the BF16 inputs; normalised by
  * training-set means and standard deviations) through two hidden ReLU layers
  * of width 256 to y (n values); the guess is x0 = x_{t-1} + sigma_d * y, with
  * sigma_d the per-component standard deviation of x_t - x_{t-1} over the
@@ -404,6 +463,31 @@ int bs_ws_train_step(bs_ws_model m, int64_t n_samples, const float *feat, const 
  * batch itself (one fused kernel). */
 int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double *values, const double *b,
                 const double *x_prev, double *x0, void *stream);
+
+/* Packed inference weights: everything the network's inference reads (BF16
+ * weights, FP32 biases, FP64 scaling) in one caller-owned device buffer, so
+ * that the inference below takes a plain pointer instead of a model handle.
+ * bs_ws_packed_bytes(n): its size for systems of n unknowns (0 outside
+ * 1..64; pure host function).  bs_ws_pack copies a model's current weights and
+ * scaling into `weights` (device, at least that many bytes, 256-byte
+ * aligned), asynchronously on stream.  Layout, each region 256-byte aligned:
+ * W1^T, W2^T, W3^T as BF16 [256][3n rounded up to 64], [256][256], [n
+ * rounded up to 32][256]; b1, b2, b3 FP32; feature means, feature deviations
+ * and sigma_d FP64.  Errors: BS_ERR_INVALID_ARG (NULL, short or misaligned
+ * buffer), BS_ERR_HIP. */
+size_t bs_ws_packed_bytes(int32_t n);
+int bs_ws_pack(bs_ws_model m, void *weights, size_t bytes, void *stream);
+
+/* x0 = x_prev + sigma_d * y(f) for n_batch systems of n unknowns, from packed
+ * weights (bs_ws_pack) and the systems' diagonals given directly:
+ *   diag, b, x_prev  device [n_batch][n] FP64 (diag[s][i] = A_s[i][i])
+ *   x0               device [n_batch][n] FP64, written
+ * Features f = [diag, b - x_prev, x_prev] as in bs_ws_infer, which gathers the
+ * diagonal out of the CSR values itself.  One kernel, asynchronous on stream.
+ * Errors: BS_ERR_INVALID_ARG (NULL or misaligned pointer, n < 1, n_batch < 0),
+ * BS_ERR_UNSUPPORTED (n > 64), BS_ERR_HIP.  n_batch = 0 is a no-op. */
+int bs_ws_infer_packed(int64_t n_batch, int32_t n, const void *weights, const double *diag,
+                       const double *b, const double *x_prev, double *x0, void *stream);
 
 /* Text for a bs_error code; never NULL. */
 const char *bs_error_string(int code);

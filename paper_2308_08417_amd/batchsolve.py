@@ -42,7 +42,8 @@ class bs_options(C.Structure):
     _fields_ = [("restart", C.c_int32), ("precision", C.c_int32), ("inner_tol", C.c_double),
                 ("flags", C.c_int32), ("team", C.c_int32), ("rows_per_lane", C.c_int32),
                 ("outer_iters", C.c_void_p), ("x_alt", C.c_void_p), ("alt_used", C.c_void_p),
-                ("block_size", C.c_int32), ("n_rhs", C.c_int32)]
+                ("block_size", C.c_int32), ("n_rhs", C.c_int32), ("varlen_policy", C.c_int32),
+                ("structure_generation", C.c_int32)]
 
 
 class bs_plan_info(C.Structure):
@@ -93,6 +94,14 @@ def lib() -> C.CDLL:
     L.bs_varbatch_tune.argtypes = _vsolve + [i32, C.c_char_p, C.c_char_p, sz, vp]
     L.bs_varbatch_capture.argtypes = _vsolve
     L.bs_varbatch_replay.argtypes = [vp, vp]
+    L.bs_batch_solve_varlen.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                        C.c_int, C.c_int, dbl, i32, vp, vp, vp,
+                                        C.POINTER(bs_options), vp, sz, vp]
+    L.bs_batch_solve_varlen.restype = C.c_int
+    L.bs_varlen_workspace_size.argtypes = [i64]
+    L.bs_varlen_workspace_size.restype = sz
+    L.bs_workspace_size.argtypes = [C.c_int, i64, i32, vp, C.c_int, C.POINTER(bs_options)]
+    L.bs_workspace_size.restype = sz
     f32p = vp
     L.bs_ws_create.argtypes = [i32, i32, vp, vp, C.POINTER(vp)]
     L.bs_ws_destroy.argtypes = [vp]
@@ -107,6 +116,12 @@ def lib() -> C.CDLL:
     L.bs_ws_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.bs_ws_train_step.argtypes = [vp, i64, vp, vp, vp, C.c_float, vp, vp]
     L.bs_ws_infer.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.bs_ws_packed_bytes.argtypes = [i32]
+    L.bs_ws_packed_bytes.restype = sz
+    L.bs_ws_pack.argtypes = [vp, vp, sz, vp]
+    L.bs_ws_pack.restype = C.c_int
+    L.bs_ws_infer_packed.argtypes = [i64, i32, vp, vp, vp, vp, vp, vp]
+    L.bs_ws_infer_packed.restype = C.c_int
     L.bs_error_string.argtypes = [C.c_int]
     L.bs_error_string.restype = C.c_char_p
     L.bs_last_error.argtypes = []
@@ -156,7 +171,8 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
-_DTYPES = {"f64": "torch.float64", "f32": "torch.float32", "i32": "torch.int32"}
+_DTYPES = {"f64": "torch.float64", "f32": "torch.float32", "i32": "torch.int32",
+           "i64": "torch.int64"}
 
 
 def _expect(t, name: str, dtype: str, numel: int, optional: bool = False,
@@ -301,9 +317,11 @@ def bs_matrix_storage(fmt: int, n_batch: int, n_rows: int, nnz: int, ell_width: 
 
 def make_options(restart: int = 0, precision: int = FP64, inner_tol: float = 0.0, flags: int = 0,
                  team: int = 0, rows_per_lane: int = 0, outer_iters=None, x_alt=None,
-                 alt_used=None, block_size: int = 0, n_rhs: int = 0) -> bs_options:
+                 alt_used=None, block_size: int = 0, n_rhs: int = 0, varlen_policy: int = 0,
+                 structure_generation: int = 0) -> bs_options:
     o = bs_options(restart, precision, inner_tol, flags, team, rows_per_lane, _ptr(outer_iters),
-                   _ptr(x_alt), _ptr(alt_used), block_size, n_rhs)
+                   _ptr(x_alt), _ptr(alt_used), block_size, n_rhs, varlen_policy,
+                   structure_generation)
     # the structure holds raw device pointers: keep their tensors alive with it
     o._keep = (outer_iters, x_alt, alt_used)
     return o
@@ -504,6 +522,60 @@ def bs_varbatch_replay(handle: int, stream=None) -> None:
     _check(lib().bs_varbatch_replay(handle, _stream(stream)), "bs_varbatch_replay")
 
 
+def bs_varlen_workspace_size(n_batch: int) -> int:
+    return int(lib().bs_varlen_workspace_size(int(n_batch)))
+
+
+def bs_workspace_size(fmt: int, n_batch: int, n_rows: int, pattern: int, solver: int,
+                      opts: Optional[bs_options] = None) -> int:
+    return int(lib().bs_workspace_size(fmt, int(n_batch), int(n_rows), pattern, solver,
+                                       C.byref(opts) if opts is not None else None))
+
+
+def check_varlen_args(n_batch: int, n_patterns: int, sys_rows, row_off, val_off, pat_id,
+                      pat_rowptr_off, pat_col_off, rowptr_all, col_all, ws) -> None:
+    """Element types and counts of the structure arrays of
+    ``bs_batch_solve_varlen`` and the size of its workspace; raises ValueError.
+    (The contents are validated by the library.)"""
+    _expect(sys_rows, "sys_rows", "i32", n_batch)
+    _expect(pat_id, "pat_id", "i32", n_batch)
+    _expect(row_off, "row_off", "i64", n_batch + 1)
+    _expect(val_off, "val_off", "i64", n_batch + 1)
+    _expect(pat_rowptr_off, "pat_rowptr_off", "i64", n_patterns)
+    _expect(pat_col_off, "pat_col_off", "i64", n_patterns)
+    for t, name in ((rowptr_all, "rowptr_all"), (col_all, "col_all")):
+        if t is None or str(t.dtype) != _DTYPES["i32"]:
+            raise ValueError(f"{name}: expected an int32 tensor")
+    if ws is None or ws.numel() * ws.element_size() < bs_varlen_workspace_size(n_batch):
+        raise ValueError("ws: smaller than bs_varlen_workspace_size(n_batch)")
+
+
+def bs_batch_solve_varlen(sys_rows, row_off, val_off, pat_id, pat_rowptr_off, pat_col_off,
+                          rowptr_all, col_all, values, b, x, solver: int, precond: int,
+                          tol: float, max_iter: int, iters, resid, status=None,
+                          opts: Optional[bs_options] = None, ws=None, stream=None) -> None:
+    """Uneven batch on device tensors the caller owns (``bs_batch_solve_varlen``):
+    int32 ``sys_rows``/``pat_id`` [B], int64 ``row_off``/``val_off`` [B+1] and
+    ``pat_rowptr_off``/``pat_col_off`` [P], int32 ``rowptr_all``/``col_all``;
+    ``ws`` a device tensor of at least ``bs_varlen_workspace_size(B)`` bytes."""
+    n_batch = int(sys_rows.numel())
+    n_patterns = int(pat_rowptr_off.numel())
+    check_varlen_args(n_batch, n_patterns, sys_rows, row_off, val_off, pat_id, pat_rowptr_off,
+                      pat_col_off, rowptr_all, col_all, ws)
+    _expect(iters, "iters", "i32", n_batch)
+    _expect(resid, "resid", "f64", n_batch)
+    _expect(status, "status", "i32", n_batch, optional=True)
+    for t, name in ((values, "values"), (b, "b"), (x, "x")):
+        if t is None or str(t.dtype) != _DTYPES["f64"]:
+            raise ValueError(f"{name}: expected a float64 tensor")
+    _check(lib().bs_batch_solve_varlen(
+        n_batch, _ptr(sys_rows), _ptr(row_off), _ptr(val_off), n_patterns, _ptr(pat_id),
+        _ptr(pat_rowptr_off), _ptr(pat_col_off), _ptr(rowptr_all), _ptr(col_all), _ptr(values),
+        _ptr(b), _ptr(x), solver, precond, float(tol), int(max_iter), _ptr(iters), _ptr(resid),
+        _ptr(status), C.byref(opts) if opts is not None else None, _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream)), "bs_batch_solve_varlen")
+
+
 class VarBatch:
     """Owns an uneven-batch handle (see ``bs_varbatch_create``)."""
 
@@ -660,6 +732,31 @@ def bs_ws_infer(handle: int, values, b, x_prev, x0, stream=None) -> None:
     check_ws_args(n, nnz, b.numel() // n, values=values, b=b, x_prev=x_prev, x0=x0)
     _check(lib().bs_ws_infer(handle, b.shape[0], _ptr(values), _ptr(b), _ptr(x_prev), _ptr(x0),
                              _stream(stream)), "bs_ws_infer")
+
+
+def bs_ws_packed_bytes(n: int) -> int:
+    return int(lib().bs_ws_packed_bytes(int(n)))
+
+
+def bs_ws_pack(handle: int, weights, stream=None) -> None:
+    """Copy the model's inference weights into the uint8 device tensor ``weights``
+    (at least ``bs_ws_packed_bytes(n)`` bytes)."""
+    n, _ = _WS_SHAPES[handle]
+    if weights is None or weights.numel() * weights.element_size() < bs_ws_packed_bytes(n):
+        raise ValueError("weights: smaller than bs_ws_packed_bytes(n)")
+    _check(lib().bs_ws_pack(handle, _ptr(weights), weights.numel() * weights.element_size(),
+                            _stream(stream)), "bs_ws_pack")
+
+
+def bs_ws_infer_packed(weights, n: int, diag, b, x_prev, x0, stream=None) -> None:
+    """x0 from packed weights and the diagonals ``diag`` [B][n] (float64)."""
+    B = b.numel() // n
+    if weights is None or weights.numel() * weights.element_size() < bs_ws_packed_bytes(n):
+        raise ValueError("weights: smaller than bs_ws_packed_bytes(n)")
+    for t, name in ((diag, "diag"), (b, "b"), (x_prev, "x_prev"), (x0, "x0")):
+        _expect(t, name, "f64", B * n)
+    _check(lib().bs_ws_infer_packed(B, int(n), _ptr(weights), _ptr(diag), _ptr(b), _ptr(x_prev),
+                                    _ptr(x0), _stream(stream)), "bs_ws_infer_packed")
 
 
 class WarmStartModel:

@@ -554,6 +554,17 @@ int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_
   return rc;
 }
 
+size_t bs_workspace_size(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
+                         bs_solver solver, const bs_options* opts) {
+  (void)fmt;
+  (void)n_batch;
+  (void)n_rows;
+  (void)pattern;
+  (void)solver;
+  (void)opts;
+  return 0;
+}
+
 int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
                    const double* values, const double* b, double* x, bs_solver solver,
                    bs_precond precond, double tol, int32_t max_iter, int32_t* iters,

@@ -96,9 +96,11 @@ struct Src {
   const float* feat;
   const float* delta;
   const int* rows;
-  // inference: the batch itself (FP64), CSR values with the diagonal's position
+  // inference: the batch itself (FP64), CSR values with the diagonal's position,
+  // or the diagonals themselves when diag is not null
   int nnz;
   const int* diag_pos;          // [n] position of A[i][i] in a system's values, -1 if none
+  const double* diag;           // [rows][n] diagonal of every system, or null
   const double* values;
   const double* b;
   const double* x_prev;

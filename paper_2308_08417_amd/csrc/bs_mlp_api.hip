@@ -44,11 +44,6 @@ struct bs_ws_model_s {
   char* d_ws = nullptr;
   size_t ws_bytes = 0;
   int64_t ws_Mp = 0;
-  uint16_t *zT = nullptr, *h1T = nullptr, *h2T = nullptr, *dz1T = nullptr, *dz2T = nullptr,
-           *dyT = nullptr;
-  float *part = nullptr, *bgrad = nullptr, *loss_part = nullptr;
-  int64_t part_ld = 0;
-  int64_t part_off[3] = {0, 0, 0};
 };
 
 namespace {
@@ -76,41 +71,76 @@ Net net_of(const bs_ws_model_s& m) {
   return t;
 }
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int ensure_ws(bs_ws_model_s& m, int64_t M) {
-  const int64_t Mp = (M + kTile - 1) / kTile * kTile;
-  if (m.d_ws && Mp <= m.ws_Mp) return BS_OK;
+// Training workspace of a step over Mp samples (a multiple of the tile) for
+// features padded to Fp and outputs padded to Op: the activations and their
+// gradients feature-major, the weight-gradient partials of every 512-sample
+// chunk, the bias gradients and the per-tile losses.  Every region is written
+// in full by the step before it is read, so none needs clearing.
+struct WorkLayout {
+  size_t zT, h1, h2, d1, d2, dy, part, bg, lp, total;
+  int64_t part_off[3], part_ld;
+};
+constexpr WorkLayout work_layout(int Fp, int Op, int64_t Mp) {
+  WorkLayout w{};
   const int64_t chunks = (Mp + kChunk - 1) / kChunk;
-  m.part_off[0] = 0;
-  m.part_off[1] = (int64_t)m.Fp * kH;
-  m.part_off[2] = m.part_off[1] + (int64_t)kH * kH;
-  m.part_ld = m.part_off[2] + (int64_t)kH * m.Op;
+  w.part_off[0] = 0;
+  w.part_off[1] = (int64_t)Fp * kH;
+  w.part_off[2] = w.part_off[1] + (int64_t)kH * kH;
+  w.part_ld = w.part_off[2] + (int64_t)kH * Op;
   size_t off = 0;
-  auto take = [&](size_t bytes) { const size_t at = off; off = align256(off + bytes); return at; };
-  const size_t o_zT = take((size_t)m.Fp * Mp * 2), o_h1 = take((size_t)kH * Mp * 2),
-               o_h2 = take((size_t)kH * Mp * 2), o_d1 = take((size_t)kH * Mp * 2),
-               o_d2 = take((size_t)kH * Mp * 2), o_dy = take((size_t)m.Op * Mp * 2),
-               o_part = take((size_t)chunks * m.part_ld * 4), o_bg = take((size_t)(2 * kH + m.Op) * 4),
-               o_lp = take((size_t)(Mp / kTile) * 4);
-  if (m.d_ws) (void)hipFree(m.d_ws);
-  m.d_ws = nullptr;
-  hipError_t e = hipMalloc(&m.d_ws, off);
-  if (e != hipSuccess) {
-    m.ws_Mp = 0;
-    return hip_err(e, "learned-start workspace");
+  w.zT = off; off = align256(off + (size_t)Fp * Mp * 2);
+  w.h1 = off; off = align256(off + (size_t)kH * Mp * 2);
+  w.h2 = off; off = align256(off + (size_t)kH * Mp * 2);
+  w.d1 = off; off = align256(off + (size_t)kH * Mp * 2);
+  w.d2 = off; off = align256(off + (size_t)kH * Mp * 2);
+  w.dy = off; off = align256(off + (size_t)Op * Mp * 2);
+  w.part = off; off = align256(off + (size_t)chunks * w.part_ld * 4);
+  w.bg = off; off = align256(off + (size_t)(2 * kH + Op) * 4);
+  w.lp = off; off = align256(off + (size_t)(Mp / kTile) * 4);
+  w.total = off;
+  return w;
+}
+
+// The workspace's regions at a base address.
+struct Work {
+  uint16_t *zT, *h1T, *h2T, *dz1T, *dz2T, *dyT;
+  float *part, *bgrad, *loss_part;
+  int64_t part_ld, part_off[3];
+};
+Work work_at(char* base, const WorkLayout& l) {
+  Work w;
+  w.zT = (uint16_t*)(base + l.zT);
+  w.h1T = (uint16_t*)(base + l.h1);
+  w.h2T = (uint16_t*)(base + l.h2);
+  w.dz1T = (uint16_t*)(base + l.d1);
+  w.dz2T = (uint16_t*)(base + l.d2);
+  w.dyT = (uint16_t*)(base + l.dy);
+  w.part = (float*)(base + l.part);
+  w.bgrad = (float*)(base + l.bg);
+  w.loss_part = (float*)(base + l.lp);
+  w.part_ld = l.part_ld;
+  for (int L = 0; L < 3; ++L) w.part_off[L] = l.part_off[L];
+  return w;
+}
+
+// The model's own workspace for M samples, grown (reallocated) on demand.
+int ensure_ws(bs_ws_model_s& m, int64_t M, Work* out) {
+  const int64_t Mp = (M + kTile - 1) / kTile * kTile;
+  if (!m.d_ws || Mp > m.ws_Mp) {
+    const WorkLayout l = work_layout(m.Fp, m.Op, Mp);
+    if (m.d_ws) (void)hipFree(m.d_ws);
+    m.d_ws = nullptr;
+    hipError_t e = hipMalloc(&m.d_ws, l.total);
+    if (e != hipSuccess) {
+      m.ws_Mp = 0;
+      return hip_err(e, "learned-start workspace");
+    }
+    m.ws_bytes = l.total;
+    m.ws_Mp = Mp;
   }
-  m.ws_bytes = off;
-  m.ws_Mp = Mp;
-  m.zT = (uint16_t*)(m.d_ws + o_zT);
-  m.h1T = (uint16_t*)(m.d_ws + o_h1);
-  m.h2T = (uint16_t*)(m.d_ws + o_h2);
-  m.dz1T = (uint16_t*)(m.d_ws + o_d1);
-  m.dz2T = (uint16_t*)(m.d_ws + o_d2);
-  m.dyT = (uint16_t*)(m.d_ws + o_dy);
-  m.part = (float*)(m.d_ws + o_part);
-  m.bgrad = (float*)(m.d_ws + o_bg);
-  m.loss_part = (float*)(m.d_ws + o_lp);
+  *out = work_at(m.d_ws, work_layout(m.Fp, m.Op, Mp));
   return BS_OK;
 }
 
@@ -141,11 +171,9 @@ hipError_t launch_apply(const Apply& a, hipStream_t st) {
 
 // Forward + backward over M samples and the gradient gather (and an Adam step
 // if update): the shared body of bs_ws_grad and bs_ws_train_step.
-int run_grad(bs_ws_model_s& m, int64_t M, const float* feat, const float* delta, const int* rows,
-             float* grad_out, float* loss_out, int update, float lr, hipStream_t st) {
-  if (M < 1 || !feat || !delta) return BS_ERR_INVALID_ARG;
-  int rc = ensure_ws(m, M);
-  if (rc != BS_OK) return rc;
+int run_grad(bs_ws_model_s& m, const Work& w, int64_t M, const float* feat, const float* delta,
+             const int* rows, float* grad_out, float* loss_out, int update, float lr,
+             hipStream_t st) {
   const int64_t Mp = (M + kTile - 1) / kTile * kTile;
   const int tiles = (int)(Mp / kTile);
   Src src;
@@ -156,24 +184,24 @@ int run_grad(bs_ws_model_s& m, int64_t M, const float* feat, const float* delta,
   Train tr;
   tr.M = M;
   tr.Mp = Mp;
-  tr.zT = m.zT;
-  tr.h1T = m.h1T;
-  tr.h2T = m.h2T;
-  tr.dz1T = m.dz1T;
-  tr.dz2T = m.dz2T;
-  tr.dyT = m.dyT;
-  tr.loss_part = m.loss_part;
+  tr.zT = w.zT;
+  tr.h1T = w.h1T;
+  tr.h2T = w.h2T;
+  tr.dz1T = w.dz1T;
+  tr.dz2T = w.dz2T;
+  tr.dyT = w.dyT;
+  tr.loss_part = w.loss_part;
   tr.y_out = nullptr;
   hipLaunchKernelGGL(k_mlp<kTrain>, dim3(tiles), dim3(kWG), 0, st, net_of(m), src, tr, M);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "learned-start forward/backward");
   WGrad g;
-  g.aT[0] = m.zT;
-  g.aT[1] = m.h1T;
-  g.aT[2] = m.h2T;
-  g.dT[0] = m.dz1T;
-  g.dT[1] = m.dz2T;
-  g.dT[2] = m.dyT;
+  g.aT[0] = w.zT;
+  g.aT[1] = w.h1T;
+  g.aT[2] = w.h2T;
+  g.dT[0] = w.dz1T;
+  g.dT[1] = w.dz2T;
+  g.dT[2] = w.dyT;
   g.kin[0] = m.Fp;
   g.kin[1] = kH;
   g.kin[2] = kH;
@@ -187,39 +215,39 @@ int run_grad(bs_ws_model_s& m, int64_t M, const float* feat, const float* delta,
     start += (g.kin[L] / 64) * g.tiles_c[L];
   }
   g.tile_start[3] = start;
-  for (int L = 0; L < 3; ++L) g.part_off[L] = m.part_off[L];
-  g.part_ld = m.part_ld;
+  for (int L = 0; L < 3; ++L) g.part_off[L] = w.part_off[L];
+  g.part_ld = w.part_ld;
   g.Mp = Mp;
   g.chunk = kChunk;
-  g.part = m.part;
+  g.part = w.part;
   const int chunks = (int)((Mp + kChunk - 1) / kChunk);
   hipLaunchKernelGGL(k_mlp_wgrad, dim3(start, chunks), dim3(kWG), 0, st, g);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "learned-start weight gradients");
   BGrad bg;
-  bg.dT[0] = m.dz1T;
-  bg.dT[1] = m.dz2T;
-  bg.dT[2] = m.dyT;
+  bg.dT[0] = w.dz1T;
+  bg.dT[1] = w.dz2T;
+  bg.dT[2] = w.dyT;
   bg.rows[0] = kH;
   bg.rows[1] = kH;
   bg.rows[2] = m.Op;
   bg.Mp = Mp;
-  bg.out = m.bgrad;
+  bg.out = w.bgrad;
   hipLaunchKernelGGL(k_mlp_bgrad, dim3(2 * kH + m.Op), dim3(kWG), 0, st, bg);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "learned-start bias gradients");
   if (loss_out) {
-    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(64), 0, st, m.loss_part, tiles,
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(64), 0, st, w.loss_part, tiles,
                        1.0 / ((double)M * m.O), loss_out);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e, "learned-start loss");
   }
   Apply a = apply_of(m);
-  a.part = m.part;
-  a.part_ld = m.part_ld;
-  for (int L = 0; L < 3; ++L) a.part_off[L] = m.part_off[L];
+  a.part = w.part;
+  a.part_ld = w.part_ld;
+  for (int L = 0; L < 3; ++L) a.part_off[L] = w.part_off[L];
   a.chunks = chunks;
-  a.bgrad = m.bgrad;
+  a.bgrad = w.bgrad;
   a.grad_out = grad_out;
   a.update = update;
   if (update) {
@@ -232,6 +260,37 @@ int run_grad(bs_ws_model_s& m, int64_t M, const float* feat, const float* delta,
   if (e != hipSuccess) return hip_err(e, "learned-start update");
   if (update) ++m.step;
   return BS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Packed inference weights (bs_ws_pack / bs_ws_infer_packed): for systems of
+// n unknowns, regions in this order, each starting at a multiple of 256 bytes:
+// W1^T BF16 [256][Fp], W2^T BF16 [256][256], W3^T BF16 [Op][256], b1 FP32
+// [256], b2 FP32 [256], b3 FP32 [n], feature means FP64 [3n], feature
+// deviations FP64 [3n], sigma_d FP64 [n]; Fp = 3n rounded up to 64, Op = n
+// rounded up to 32 (padding entries zero).
+struct Packed {
+  size_t w1t, w2t, w3t, b1, b2, b3, mu, sd, sdd, total;
+};
+Packed packed_layout(int n) {
+  const int F = 3 * n, Fp = round_up(F, 64), Op = round_up(n, 32);
+  Packed p;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t at = off; off = align256(off + bytes); return at; };
+  p.w1t = take((size_t)kH * Fp * 2);
+  p.w2t = take((size_t)kH * kH * 2);
+  p.w3t = take((size_t)Op * kH * 2);
+  p.b1 = take((size_t)kH * 4);
+  p.b2 = take((size_t)kH * 4);
+  p.b3 = take((size_t)n * 4);
+  p.mu = take((size_t)F * 8);
+  p.sd = take((size_t)F * 8);
+  p.sdd = take((size_t)n * 8);
+  p.total = off;
+  return p;
 }
 
 }  // namespace
@@ -437,13 +496,21 @@ int bs_ws_forward(bs_ws_model m, int64_t n_samples, const float* feat, const int
 int bs_ws_grad(bs_ws_model m, int64_t n_samples, const float* feat, const float* delta,
                const int32_t* rows, float* grad, float* loss, void* stream) {
   if (!m || !grad) return BS_ERR_INVALID_ARG;
-  return run_grad(*m, n_samples, feat, delta, rows, grad, loss, 0, 0.f, (hipStream_t)stream);
+  if (n_samples < 1 || !feat || !delta) return BS_ERR_INVALID_ARG;
+  Work w;
+  const int rc = ensure_ws(*m, n_samples, &w);
+  if (rc != BS_OK) return rc;
+  return run_grad(*m, w, n_samples, feat, delta, rows, grad, loss, 0, 0.f, (hipStream_t)stream);
 }
 
 int bs_ws_train_step(bs_ws_model m, int64_t n_samples, const float* feat, const float* delta,
                      const int32_t* rows, float lr, float* loss, void* stream) {
   if (!m || !(lr > 0.f) || !std::isfinite(lr)) return BS_ERR_INVALID_ARG;
-  return run_grad(*m, n_samples, feat, delta, rows, nullptr, loss, 1, lr, (hipStream_t)stream);
+  if (n_samples < 1 || !feat || !delta) return BS_ERR_INVALID_ARG;
+  Work w;
+  const int rc = ensure_ws(*m, n_samples, &w);
+  if (rc != BS_OK) return rc;
+  return run_grad(*m, w, n_samples, feat, delta, rows, nullptr, loss, 1, lr, (hipStream_t)stream);
 }
 
 int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double* values, const double* b,
@@ -467,6 +534,73 @@ int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double* values, const doub
                      tr, n_batch);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? BS_OK : hip_err(e, "learned-start inference");
+}
+
+size_t bs_ws_packed_bytes(int32_t n) {
+  if (n < 1 || n > kMaxN) return 0;
+  return packed_layout(n).total;
+}
+
+int bs_ws_pack(bs_ws_model m, void* weights, size_t bytes, void* stream) {
+  if (!m || !weights) return BS_ERR_INVALID_ARG;
+  const Packed p = packed_layout(m->n);
+  if (bytes < p.total || ((uintptr_t)weights & 255)) return BS_ERR_INVALID_ARG;
+  char* w = static_cast<char*>(weights);
+  const Net t = net_of(*m);
+  const hipStream_t st = (hipStream_t)stream;
+  struct Piece { size_t dst; const void* src; size_t bytes; };
+  const Piece pieces[] = {
+      {p.w1t, t.w1t, (size_t)kH * m->Fp * 2}, {p.w2t, t.w2t, (size_t)kH * kH * 2},
+      {p.w3t, t.w3t, (size_t)m->Op * kH * 2}, {p.b1, t.b1, (size_t)kH * 4},
+      {p.b2, t.b2, (size_t)kH * 4},           {p.b3, t.b3, (size_t)m->O * 4},
+      {p.mu, t.mu_f, (size_t)m->F * 8},       {p.sd, t.sd_f, (size_t)m->F * 8},
+      {p.sdd, t.sd_d, (size_t)m->O * 8}};
+  for (const Piece& q : pieces) {
+    const hipError_t e = hipMemcpyAsync(w + q.dst, q.src, q.bytes, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_err(e, "pack learned-start weights");
+  }
+  return BS_OK;
+}
+
+int bs_ws_infer_packed(int64_t n_batch, int32_t n, const void* weights, const double* diag,
+                       const double* b, const double* x_prev, double* x0, void* stream) {
+  if (n_batch < 0 || n < 1) return BS_ERR_INVALID_ARG;
+  if (n > kMaxN) return BS_ERR_UNSUPPORTED;
+  if (n_batch == 0) return BS_OK;
+  if (!weights || !diag || !b || !x_prev || !x0 || ((uintptr_t)weights & 255))
+    return BS_ERR_INVALID_ARG;
+  const Packed p = packed_layout(n);
+  const char* w = static_cast<const char*>(weights);
+  Net t;
+  std::memset(&t, 0, sizeof t);
+  t.n = n;
+  t.F = 3 * n;
+  t.Fp = round_up(t.F, 64);
+  t.O = n;
+  t.Op = round_up(n, 32);
+  t.w1t = reinterpret_cast<const uint16_t*>(w + p.w1t);
+  t.w2t = reinterpret_cast<const uint16_t*>(w + p.w2t);
+  t.w3t = reinterpret_cast<const uint16_t*>(w + p.w3t);
+  t.b1 = reinterpret_cast<const float*>(w + p.b1);
+  t.b2 = reinterpret_cast<const float*>(w + p.b2);
+  t.b3 = reinterpret_cast<const float*>(w + p.b3);
+  t.mu_f = reinterpret_cast<const double*>(w + p.mu);
+  t.sd_f = reinterpret_cast<const double*>(w + p.sd);
+  t.sd_d = reinterpret_cast<const double*>(w + p.sdd);
+  Src src;
+  std::memset(&src, 0, sizeof src);
+  src.diag = diag;
+  src.b = b;
+  src.x_prev = x_prev;
+  src.x0 = x0;
+  Train tr;
+  std::memset(&tr, 0, sizeof tr);
+  tr.M = n_batch;
+  const unsigned tiles = (unsigned)((n_batch + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_mlp<kInfer>, dim3(tiles), dim3(kWG), 0, (hipStream_t)stream, t, src, tr,
+                     n_batch);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BS_OK : hip_err(e, "learned-start inference (packed weights)");
 }
 
 }  // extern "C"

@@ -60,10 +60,14 @@ __global__ __launch_bounds__(kWG) void k_mlp(const Net net, const Src src, const
       double v;
       if constexpr (MODE == kInfer) {
         if (f < n) {
-          const int p = src.diag_pos[f];
-          v = p >= 0 ? src.values[m * src.nnz + p] : 0.0;
+          if (src.diag) {
+            v = src.diag[m * n + f];
+          } else {
+            const int p = src.diag_pos[f];
+            v = p >= 0 ? src.values[m * src.nnz + p] : 0.0;
+          }
         } else if (f < 2 * n) {
-          v = src.b[m * n + (f - n)];
+          v = src.b[m * n + (f - n)] - src.x_prev[m * n + (f - n)];
         } else {
           v = src.x_prev[m * n + (f - 2 * n)];
         }
@@ -365,7 +369,8 @@ __global__ void k_mlp_loss(const float* part, int tiles, double scale, float* ou
   }
 }
 
-// Raw training data: features [diag, b, x_prev] and the change x_next - x_prev.
+// Raw training data: features [diag, b - x_prev, x_prev] (the difference in
+// FP64, then rounded) and the change x_next - x_prev.
 __global__ __launch_bounds__(kWG) void k_mlp_features(int64_t M, int n, int nnz, const int* diag_pos,
                                                       const double* values, const double* b,
                                                       const double* x_prev, const double* x_next,
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(kWG) void k_mlp_features(int64_t M, int n, int nnz,
       const int p = diag_pos[c];
       feat[m * F + c] = p >= 0 ? (float)values[m * nnz + p] : 0.f;
     } else if (c < 2 * n) {
-      feat[m * F + c] = (float)b[m * n + c - n];
+      feat[m * F + c] = (float)(b[m * n + c - n] - x_prev[m * n + c - n]);
     } else if (c < F) {
       feat[m * F + c] = (float)x_prev[m * n + c - 2 * n];
     } else {

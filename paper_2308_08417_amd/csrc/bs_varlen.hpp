@@ -33,6 +33,10 @@ struct VTask {
   int pad;
 };
 
+// The batch is described by the CSR arrays themselves (validated on the host
+// before any launch): the kernel reads each row's start and length from its
+// pattern's row_ptr, its columns in CSR order, and finds the diagonal among
+// them while loading.
 struct VArgs {
   KArgs base;             // solver settings and the per-system outputs
   int64_t n_tasks;
@@ -42,13 +46,10 @@ struct VArgs {
   const int* sys_pat;     // [B] pattern of each system
   const int64_t* row_off; // [B+1] first row of each system in b and x
   const int64_t* val_off; // [B+1] first value of each system (CSR order)
-  const int64_t* pat_rp;  // [P] offset of the pattern's row_ptr in prow_ptr
-  const int64_t* pat_row; // [P] offset of the pattern's per-row arrays
-  const int64_t* pat_sc;  // [P] offset of the pattern's slot-major columns
-  const int* prow_ptr;    // concatenated row_ptr arrays
-  const int* prow_len;    // concatenated row lengths
-  const int* pdiag;       // concatenated diagonal slots (-1 if none)
-  const int* pslot_col;   // concatenated [W_p][n_p] slot-major columns
+  const int64_t* pat_rp;  // [P] offset of the pattern's row_ptr in rowptr_all
+  const int64_t* pat_col; // [P] offset of the pattern's columns in col_all
+  const int* rowptr_all;  // concatenated row_ptr arrays (each starting at 0)
+  const int* col_all;     // concatenated column arrays, CSR order
   int* counter;           // task counter, zero at launch
 };
 
@@ -150,7 +151,8 @@ struct VarRows {
   double dval[R], bval[R], xval[R], xalt[R];
 
   // Pattern and values of this team's system, straight from HBM.  Every load
-  // is guarded: an idle lane, row or slot reads nothing.
+  // is guarded: an idle lane, row or slot reads nothing.  The diagonal slot is
+  // the first entry of the row whose column is the row itself.
   __device__ void load(const VarTeam<VS>& tm, const VArgs& va, unsigned lds_base) {
     const KArgs& g = va.base;
     const int s = tm.live ? (int)tm.sys : 0;
@@ -158,9 +160,8 @@ struct VarRows {
     const int p = va.sys_pat[s];
     const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
     zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
-    const int64_t pr = va.pat_row[p];
-    const int* rps = va.prow_ptr + va.pat_rp[p];
-    const int* sc = va.pslot_col + va.pat_sc[p];
+    const int* rps = va.rowptr_all + va.pat_rp[p];
+    const int* cols = va.col_all + va.pat_col[p];
     const double* vals = g.values + va.val_off[s];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -170,9 +171,8 @@ struct VarRows {
       const int rr = row[r];
       int len = 0, ds = -1, rp = 0;
       if (ok[r]) {
-        len = va.prow_len[pr + rr];
-        ds = va.pdiag[pr + rr];
         rp = rps[rr];
+        len = rps[rr + 1] - rp;
       }
 #pragma unroll
       for (int k = 0; k < NZ; ++k) {
@@ -180,9 +180,10 @@ struct VarRows {
         int col = 0;
         double v = 0.0;
         if (has) {
-          col = sc[(size_t)k * n + rr];
+          col = cols[rp + k];
           v = __builtin_nontemporal_load(vals + rp + k);
         }
+        ds = (has && col == rr && ds < 0) ? k : ds;
         c[r][k] = has ? tb + col * 8 : zero;
         a[r][k] = v;
       }

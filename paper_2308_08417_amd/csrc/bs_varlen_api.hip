@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,13 +89,21 @@ const VEntry* find_v(int wg, int r, int nz, int solver, int mixed, int bj) {
 
 }  // namespace
 
-struct bs_varbatch_s {
+// Validated host description of an uneven batch: per system its row count,
+// pattern and offsets, and the longest row of any pattern.
+struct VarDesc {
   int64_t B = 0;
-  int P = 0, max_row = 0, device = -1, policy = 0;
+  int P = 0, max_row = 0;
+  std::vector<int> sys_rows, sys_pat;
+  std::vector<int64_t> row_off, val_off;
+};
+
+struct bs_varbatch_s {
+  VarDesc d;
+  int device = -1, policy = 0;
   int policy_next = 0;  // policy of the tasks being uploaded
-  std::vector<int> sys_rows, sys_pat, pat_n, pat_nnz;
-  std::vector<int64_t> row_off, val_off, pat_rp, pat_row, pat_sc;
-  std::vector<int> prow_ptr, prow_len, pdiag, pslot_col;
+  std::vector<int64_t> pat_rp, pat_col;  // offsets into the concatenated copies
+  std::vector<int> rowptr_all, col_all;
   std::vector<bs::VTask> tasks;
   std::vector<int> order;
   // device
@@ -110,9 +119,44 @@ struct bs_varbatch_s {
 
 namespace {
 
+bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) {
+  for (int k = 0; k < len; ++k) {
+    const int c = cols[k];
+    if (c < 0 || c >= n || mark[c] == stamp) return false;
+    mark[c] = stamp;
+  }
+  return true;
+}
+
+// Checks pattern p (n rows, row_ptr rp within rowptr_len entries of its array,
+// columns from cols within col_len entries): row_ptr starts at 0 and never
+// decreases, every column lies in [0, n) and appears once per row, no row is
+// longer than 16.  Returns its nnz through *nnz.
+int check_pattern(int n, const int32_t* rp, int64_t rp_room, const int32_t* cols, int64_t col_room,
+                  int* longest, int64_t* nnz, std::vector<int>& mark) {
+  if (n < 1) return BS_ERR_INVALID_ARG;
+  if (n > kMaxVarRows) return BS_ERR_UNSUPPORTED;
+  if (rp_room < (int64_t)n + 1) return BS_ERR_PATTERN;
+  if (rp[0] != 0) return BS_ERR_PATTERN;
+  int maxr = 0;
+  for (int i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return BS_ERR_PATTERN;
+    maxr = std::max(maxr, rp[i + 1] - rp[i]);
+  }
+  if (rp[n] > col_room) return BS_ERR_PATTERN;
+  if (maxr > 16) return BS_ERR_UNSUPPORTED;
+  mark.assign(n, -1);
+  for (int i = 0; i < n; ++i)
+    if (!row_ok(cols + rp[i], rp[i + 1] - rp[i], n, mark, i)) return BS_ERR_PATTERN;
+  *longest = maxr;
+  *nnz = rp[n];
+  return BS_OK;
+}
+
 // Tasks for a policy (see bs_varbatch_set_policy): workgroup shape
 // policy / 3, queue order policy % 3.
-void build_tasks(bs_varbatch_s& v, int policy) {
+void build_tasks(const VarDesc& v, int policy, std::vector<bs::VTask>& tasks,
+                 std::vector<int>& order_out) {
   const VShapeInfo sh = kVShapes[policy / kNumOrders];
   const int order = policy % kNumOrders;
   std::vector<int> team(v.B);
@@ -130,31 +174,38 @@ void build_tasks(bs_varbatch_s& v, int policy) {
     if (order == 2) return false;
     return v.val_off[a + 1] - v.val_off[a] > v.val_off[b + 1] - v.val_off[b];
   });
-  v.order = idx;
-  v.tasks.clear();
+  order_out = idx;
+  tasks.clear();
   for (int64_t i = 0; i < v.B;) {
     const int t = team[idx[i]], cap = sh.wg / t;
     int c = 0;
     while (i + c < v.B && c < cap && team[idx[i + c]] == t) ++c;
-    v.tasks.push_back({t, (int)i, c, 0});
+    tasks.push_back({t, (int)i, c, 0});
     i += c;
   }
 }
 
-int upload_tasks(bs_varbatch_s& v) {
-  // what the kernel assumes of every task: a power-of-two team of at least a
-  // wave that holds each of its systems, and teams that fit one workgroup
-  const VShapeInfo sh = kVShapes[v.policy_next / kNumOrders];
+// What the kernel assumes of every task: a power-of-two team of at least a
+// wave that holds each of its systems, teams that fit one workgroup, and the
+// tasks covering the queue order once.
+int check_tasks(const VarDesc& v, int policy, const std::vector<bs::VTask>& tasks,
+                const std::vector<int>& order) {
+  const VShapeInfo sh = kVShapes[policy / kNumOrders];
   int64_t covered = 0;
-  for (const bs::VTask& t : v.tasks) {
+  for (const bs::VTask& t : tasks) {
     if (t.team < bs::kWave || t.team > sh.wg || (t.team & (t.team - 1)) || t.count < 1 ||
         (int64_t)t.count * t.team > sh.wg || t.first != covered)
       return BS_ERR_INVALID_ARG;
     for (int i = 0; i < t.count; ++i)
-      if (v.sys_rows[v.order[t.first + i]] > t.team * sh.r) return BS_ERR_INVALID_ARG;
+      if (v.sys_rows[order[t.first + i]] > t.team * sh.r) return BS_ERR_INVALID_ARG;
     covered += t.count;
   }
-  if (covered != v.B) return BS_ERR_INVALID_ARG;
+  return covered == v.B ? BS_OK : BS_ERR_INVALID_ARG;
+}
+
+int upload_tasks(bs_varbatch_s& v) {
+  const int rc = check_tasks(v.d, v.policy_next, v.tasks, v.order);
+  if (rc != BS_OK) return rc;
   hipError_t e = hipMemcpy(v.d_tasks, v.tasks.data(), v.tasks.size() * sizeof(bs::VTask),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_err(e, "upload tasks");
@@ -164,7 +215,10 @@ int upload_tasks(bs_varbatch_s& v) {
   return BS_OK;
 }
 
-int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, bs_solver solver,
+// One persistent launch over the tasks of `policy` (already on the device),
+// with the structure pointers of `args` and the task counter `counter`.
+int launch(const VarDesc& v, bs::VArgs a, int policy, int device, int* counter,
+           const double* values, const double* b, double* x, bs_solver solver,
            bs_precond precond, double tol, int max_iter, int* iters, double* resid, int* status,
            const bs_options* o, hipStream_t stream) {
   if (solver != BS_CG && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
@@ -184,12 +238,11 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   if (o && (o->inner_tol < 0.0 || !std::isfinite(o->inner_tol))) return BS_ERR_INVALID_ARG;
   if (v.B == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
-  const VShapeInfo sh = kVShapes[v.policy / kNumOrders];
+  const VShapeInfo sh = kVShapes[policy / kNumOrders];
   if (mixed && block > 1) return BS_ERR_UNSUPPORTED;
   const VEntry* k = find_v(sh.wg, sh.r, std::max(v.max_row, 1), solver == BS_CG ? 0 : 1, mixed,
                            block > 1 ? 1 : 0);
   if (!k) return BS_ERR_UNSUPPORTED;
-  bs::VArgs a = v.args;
   bs::KArgs& g = a.base;
   g = bs::KArgs{};
   g.nrhs = 1;
@@ -214,31 +267,30 @@ int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, b
   g.x_alt = o ? o->x_alt : nullptr;
   g.alt_used = o ? o->alt_used : nullptr;
   if (g.x_alt && (g.flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
+  a.counter = counter;
   int cus = 0;
-  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, v.device);
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return hip_err(e, "device attribute");
-  hipLaunchKernelGGL(bs::k_varlen_reset, dim3(1), dim3(1), 0, stream, v.d_counter);
+  hipLaunchKernelGGL(bs::k_varlen_reset, dim3(1), dim3(1), 0, stream, counter);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_err(e, "counter reset");
   int per_cu = 0;
   e = k->occ(&per_cu);
   if (e != hipSuccess) return hip_err(e, "occupancy");
   const int64_t resident = (int64_t)cus * std::max(per_cu, 1);
-  const unsigned grid = (unsigned)std::min<int64_t>(resident, (int64_t)v.tasks.size());
+  const unsigned grid = (unsigned)std::min<int64_t>(resident, a.n_tasks);
   e = k->fn(a, grid, stream);
   return e == hipSuccess ? BS_OK : hip_err(e, "uneven-batch launch");
 }
 
-bool row_ok(const int* cols, int len, int n, std::vector<int>& mark, int stamp) {
-  for (int k = 0; k < len; ++k) {
-    const int c = cols[k];
-    if (c < 0 || c >= n || mark[c] == stamp) return false;
-    mark[c] = stamp;
-  }
-  return true;
+int launch(bs_varbatch_s& v, const double* values, const double* b, double* x, bs_solver solver,
+           bs_precond precond, double tol, int max_iter, int* iters, double* resid, int* status,
+           const bs_options* o, hipStream_t stream) {
+  return launch(v.d, v.args, v.policy, v.device, v.d_counter, values, b, x, solver, precond, tol,
+                max_iter, iters, resid, status, o, stream);
 }
 
-std::string tune_key(const bs_varbatch_s& v, bs_solver solver, int mixed) {
+std::string tune_key(const VarDesc& v, bs_solver solver, int mixed) {
   // histogram of team classes and the longest row
   int hist[16] = {0};
   for (int64_t s = 0; s < v.B; ++s) {
@@ -251,6 +303,143 @@ std::string tune_key(const bs_varbatch_s& v, bs_solver solver, int mixed) {
   k += "_w" + std::to_string(v.max_row) + "_s" + std::to_string((int)solver) + "_m" +
        std::to_string(mixed);
   return k;
+}
+
+int have_device(int* device) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    bs::set_last_error("no HIP device");
+    return BS_ERR_NO_DEVICE;
+  }
+  const hipError_t e = hipGetDevice(device);
+  return e == hipSuccess ? BS_OK : hip_err(e, "hipGetDevice");
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace of bs_batch_solve_varlen: the task counter, the tasks, the queue
+// order.
+struct WsLayout {
+  size_t counter, tasks, order, total;
+};
+WsLayout ws_layout(int64_t B) {
+  WsLayout w;
+  w.counter = 0;
+  w.tasks = 256;
+  w.order = w.tasks + align256((size_t)(B + 1) * sizeof(bs::VTask));
+  w.total = w.order + align256((size_t)(B + 1) * sizeof(int));
+  return w;
+}
+
+// ---------------------------------------------------------------- caller-owned batches
+// bs_batch_solve_varlen reads the caller's structure arrays once (one copy to
+// the host), validates them and keeps what it derived, keyed by the arrays'
+// addresses, the batch shape, the device and the caller's generation number.
+struct VarKey {
+  int device;
+  int64_t B;
+  int P;
+  int32_t generation;
+  const void* ptr[8];
+  bool operator==(const VarKey& o) const {
+    if (device != o.device || B != o.B || P != o.P || generation != o.generation) return false;
+    for (int i = 0; i < 8; ++i)
+      if (ptr[i] != o.ptr[i]) return false;
+    return true;
+  }
+};
+
+struct VarEntry {
+  VarKey key;
+  VarDesc d;
+  int policy = -1;  // policy of the tasks below
+  std::vector<bs::VTask> tasks;
+  std::vector<int> order;
+  const void* ws = nullptr;  // workspace that holds these tasks, or null
+  int ws_policy = -1;
+  uint64_t used = 0;
+};
+
+std::mutex g_var_mu;
+std::vector<VarEntry> g_var_cache;
+uint64_t g_var_clock = 0;
+constexpr size_t kVarCacheEntries = 8;
+
+template <class T>
+int d2h(std::vector<T>& dst, const T* src, int64_t count, hipStream_t st) {
+  dst.resize((size_t)std::max<int64_t>(count, 0));
+  if (count <= 0) return BS_OK;
+  hipError_t e = hipMemcpyAsync(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? BS_OK : hip_err(e, "read uneven-batch structure");
+}
+
+// Reads and validates a caller-owned uneven batch.
+int read_batch(VarDesc& d, int64_t B, const int32_t* sys_rows, const int64_t* row_off,
+               const int64_t* val_off, int32_t P, const int32_t* pat_id,
+               const int64_t* pat_rowptr_off, const int64_t* pat_col_off,
+               const int32_t* rowptr_all, const int32_t* col_all, hipStream_t st) {
+  d = VarDesc{};
+  d.B = B;
+  d.P = P;
+  std::vector<int64_t> prp, pco;
+  int rc = d2h(d.sys_rows, sys_rows, B, st);
+  if (rc == BS_OK) rc = d2h(d.sys_pat, pat_id, B, st);
+  if (rc == BS_OK) rc = d2h(d.row_off, row_off, B + 1, st);
+  if (rc == BS_OK) rc = d2h(d.val_off, val_off, B + 1, st);
+  if (rc == BS_OK) rc = d2h(prp, pat_rowptr_off, P, st);
+  if (rc == BS_OK) rc = d2h(pco, pat_col_off, P, st);
+  if (rc != BS_OK) return rc;
+  // rows of each pattern: those of the systems that use it (all the same)
+  std::vector<int> rows(P, 0);
+  for (int64_t s = 0; s < B; ++s) {
+    const int p = d.sys_pat[s];
+    if (p < 0 || p >= P) return BS_ERR_PATTERN;
+    const int n = d.sys_rows[s];
+    if (n < 1) return BS_ERR_INVALID_ARG;
+    if (n > kMaxVarRows) return BS_ERR_UNSUPPORTED;
+    if (rows[p] != 0 && rows[p] != n) return BS_ERR_INVALID_ARG;
+    rows[p] = n;
+  }
+  int64_t rp_len = 0;
+  for (int p = 0; p < P; ++p)
+    if (rows[p]) {
+      if (prp[p] < 0 || pco[p] < 0) return BS_ERR_INVALID_ARG;
+      rp_len = std::max(rp_len, prp[p] + rows[p] + 1);
+    }
+  std::vector<int32_t> rpa, cola;
+  rc = d2h(rpa, rowptr_all, rp_len, st);
+  if (rc != BS_OK) return rc;
+  std::vector<int64_t> nnz(P, 0);
+  int64_t col_len = 0;
+  for (int p = 0; p < P; ++p)
+    if (rows[p]) {
+      const int32_t* rp = rpa.data() + prp[p];
+      for (int i = 0; i <= rows[p]; ++i)
+        if (rp[i] < 0 || (i && rp[i] < rp[i - 1])) return BS_ERR_PATTERN;
+      nnz[p] = rp[rows[p]];
+      col_len = std::max(col_len, pco[p] + nnz[p]);
+    }
+  rc = d2h(cola, col_all, col_len, st);
+  if (rc != BS_OK) return rc;
+  std::vector<int> mark;
+  for (int p = 0; p < P; ++p)
+    if (rows[p]) {
+      int longest = 0;
+      int64_t nz = 0;
+      rc = check_pattern(rows[p], rpa.data() + prp[p], rp_len - prp[p], cola.data() + pco[p],
+                         col_len - pco[p], &longest, &nz, mark);
+      if (rc != BS_OK) return rc;
+      d.max_row = std::max(d.max_row, longest);
+    }
+  // offsets: each system's rows and values follow the previous system's
+  if (d.row_off[0] != 0 || d.val_off[0] != 0) return BS_ERR_INVALID_ARG;
+  for (int64_t s = 0; s < B; ++s) {
+    if (d.row_off[s + 1] - d.row_off[s] != d.sys_rows[s]) return BS_ERR_INVALID_ARG;
+    if (d.val_off[s + 1] - d.val_off[s] != nnz[d.sys_pat[s]]) return BS_ERR_INVALID_ARG;
+  }
+  return BS_OK;
 }
 
 }  // namespace
@@ -267,13 +456,12 @@ int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t* pat_r
   if (n_batch > 0x7fffffff) return BS_ERR_UNSUPPORTED;
   *out = nullptr;
   bs_varbatch_s* v = new bs_varbatch_s();
-  v->B = n_batch;
-  v->P = n_patterns;
-  v->pat_n.resize(n_patterns);
-  v->pat_nnz.resize(n_patterns);
+  VarDesc& d = v->d;
+  d.B = n_batch;
+  d.P = n_patterns;
   v->pat_rp.resize(n_patterns);
-  v->pat_row.resize(n_patterns);
-  v->pat_sc.resize(n_patterns);
+  v->pat_col.resize(n_patterns);
+  std::vector<int64_t> nnz(n_patterns, 0);
   std::vector<int> mark;
   int rc = BS_OK;
   for (int p = 0; p < n_patterns && rc == BS_OK; ++p) {
@@ -282,75 +470,43 @@ int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t* pat_r
     if (n > kMaxVarRows) { rc = BS_ERR_UNSUPPORTED; break; }
     const int32_t* rp = rowptr_all + pat_rowptr_off[p];
     const int32_t* ci = col_all + pat_col_off[p];
-    if (rp[0] != 0) { rc = BS_ERR_PATTERN; break; }
-    int maxr = 0;
-    for (int i = 0; i < n; ++i) {
-      if (rp[i + 1] < rp[i]) { rc = BS_ERR_PATTERN; break; }
-      maxr = std::max(maxr, rp[i + 1] - rp[i]);
-    }
+    int longest = 0;
+    rc = check_pattern(n, rp, (int64_t)n + 1, ci, INT64_MAX, &longest, &nnz[p], mark);
     if (rc != BS_OK) break;
-    if (maxr > 16) { rc = BS_ERR_UNSUPPORTED; break; }
-    mark.assign(n, -1);
-    for (int i = 0; i < n && rc == BS_OK; ++i)
-      if (!row_ok(ci + rp[i], rp[i + 1] - rp[i], n, mark, i)) rc = BS_ERR_PATTERN;
-    if (rc != BS_OK) break;
-    v->max_row = std::max(v->max_row, maxr);
-    v->pat_n[p] = n;
-    v->pat_nnz[p] = rp[n];
-    v->pat_rp[p] = (int64_t)v->prow_ptr.size();
-    v->prow_ptr.insert(v->prow_ptr.end(), rp, rp + n + 1);
-    v->pat_row[p] = (int64_t)v->prow_len.size();
-    for (int i = 0; i < n; ++i) {
-      const int len = rp[i + 1] - rp[i];
-      v->prow_len.push_back(len);
-      int ds = -1;
-      for (int k = 0; k < len; ++k)
-        if (ci[rp[i] + k] == i) { ds = k; break; }
-      v->pdiag.push_back(ds);
-    }
-    v->pat_sc[p] = (int64_t)v->pslot_col.size();
-    const size_t base = v->pslot_col.size();
-    v->pslot_col.resize(base + (size_t)maxr * n + 1, -1);
-    for (int s = 0; s < maxr; ++s)
-      for (int i = 0; i < n; ++i)
-        if (s < rp[i + 1] - rp[i]) v->pslot_col[base + (size_t)s * n + i] = ci[rp[i] + s];
+    d.max_row = std::max(d.max_row, longest);
+    // the handle's own copies: row_ptr and columns of every pattern, concatenated
+    v->pat_rp[p] = (int64_t)v->rowptr_all.size();
+    v->rowptr_all.insert(v->rowptr_all.end(), rp, rp + n + 1);
+    v->pat_col[p] = (int64_t)v->col_all.size();
+    v->col_all.insert(v->col_all.end(), ci, ci + nnz[p]);
   }
   if (rc == BS_OK) {
-    v->sys_pat.assign(sys_pat, sys_pat + n_batch);
-    v->sys_rows.resize(n_batch);
-    v->row_off.assign(n_batch + 1, 0);
-    v->val_off.assign(n_batch + 1, 0);
+    d.sys_pat.assign(sys_pat, sys_pat + n_batch);
+    d.sys_rows.resize(n_batch);
+    d.row_off.assign(n_batch + 1, 0);
+    d.val_off.assign(n_batch + 1, 0);
     for (int64_t s = 0; s < n_batch; ++s) {
       const int p = sys_pat[s];
       if (p < 0 || p >= n_patterns) { rc = BS_ERR_PATTERN; break; }
-      v->sys_rows[s] = v->pat_n[p];
-      v->row_off[s + 1] = v->row_off[s] + v->pat_n[p];
-      v->val_off[s + 1] = v->val_off[s] + v->pat_nnz[p];
+      d.sys_rows[s] = pat_rows[p];
+      d.row_off[s + 1] = d.row_off[s] + pat_rows[p];
+      d.val_off[s + 1] = d.val_off[s] + nnz[p];
     }
   }
+  if (rc == BS_OK) rc = have_device(&v->device);
   if (rc == BS_OK) {
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
-      (void)hipGetLastError();
-      bs::set_last_error("no HIP device");
-      rc = BS_ERR_NO_DEVICE;
-    }
-  }
-  if (rc == BS_OK) {
-    hipError_t e = hipGetDevice(&v->device);
     // one allocation for the policy-independent arrays
     const size_t sz = [&] {
       size_t z = 0;
-      z += (v->B ? v->B : 1) * 2 * sizeof(int);                  // sys_rows, sys_pat
-      z += (v->B + 1) * 2 * sizeof(int64_t);                     // row_off, val_off
-      z += (v->P ? v->P : 1) * 3 * sizeof(int64_t);              // pattern offsets
-      z += (v->prow_ptr.size() + v->prow_len.size() + v->pdiag.size() + v->pslot_col.size() + 4) *
-           sizeof(int);
+      z += (d.B ? d.B : 1) * 2 * sizeof(int);                    // sys_rows, sys_pat
+      z += (d.B + 1) * 2 * sizeof(int64_t);                      // row_off, val_off
+      z += (d.P ? d.P : 1) * 2 * sizeof(int64_t);                // pattern offsets
+      z += (v->rowptr_all.size() + v->col_all.size() + 2) * sizeof(int);
       return z + 256;
     }();
-    if (e == hipSuccess) e = hipMalloc(&v->d_static, sz);
-    if (e == hipSuccess) e = hipMalloc(&v->d_tasks, (size_t)(v->B + 1) * sizeof(bs::VTask));
-    if (e == hipSuccess) e = hipMalloc(&v->d_order, (size_t)(v->B + 1) * sizeof(int));
+    hipError_t e = hipMalloc(&v->d_static, sz);
+    if (e == hipSuccess) e = hipMalloc(&v->d_tasks, (size_t)(d.B + 1) * sizeof(bs::VTask));
+    if (e == hipSuccess) e = hipMalloc(&v->d_order, (size_t)(d.B + 1) * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&v->d_counter, 256);
     if (e != hipSuccess) rc = hip_err(e, "varbatch allocation");
     if (rc == BS_OK) {
@@ -363,42 +519,36 @@ int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t* pat_r
         off += bytes;
         return at;
       };
-      const size_t o_rows = put(v->sys_rows.data(), v->B * sizeof(int));
-      const size_t o_pat = put(v->sys_pat.data(), v->B * sizeof(int));
-      const size_t o_roff = put(v->row_off.data(), (v->B + 1) * sizeof(int64_t));
-      const size_t o_voff = put(v->val_off.data(), (v->B + 1) * sizeof(int64_t));
-      const size_t o_prp = put(v->pat_rp.data(), v->P * sizeof(int64_t));
-      const size_t o_prow = put(v->pat_row.data(), v->P * sizeof(int64_t));
-      const size_t o_psc = put(v->pat_sc.data(), v->P * sizeof(int64_t));
-      const size_t o_rp = put(v->prow_ptr.data(), v->prow_ptr.size() * sizeof(int));
-      const size_t o_len = put(v->prow_len.data(), v->prow_len.size() * sizeof(int));
-      const size_t o_dg = put(v->pdiag.data(), v->pdiag.size() * sizeof(int));
-      const size_t o_sc = put(v->pslot_col.data(), v->pslot_col.size() * sizeof(int));
+      const size_t o_rows = put(d.sys_rows.data(), d.B * sizeof(int));
+      const size_t o_pat = put(d.sys_pat.data(), d.B * sizeof(int));
+      const size_t o_roff = put(d.row_off.data(), (d.B + 1) * sizeof(int64_t));
+      const size_t o_voff = put(d.val_off.data(), (d.B + 1) * sizeof(int64_t));
+      const size_t o_prp = put(v->pat_rp.data(), d.P * sizeof(int64_t));
+      const size_t o_pco = put(v->pat_col.data(), d.P * sizeof(int64_t));
+      const size_t o_rp = put(v->rowptr_all.data(), v->rowptr_all.size() * sizeof(int));
+      const size_t o_col = put(v->col_all.data(), v->col_all.size() * sizeof(int));
       if (off > sz) {
         rc = BS_ERR_INVALID_ARG;
       } else {
         e = hipMemcpy(v->d_static, h.data(), sz, hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_err(e, "varbatch upload");
       }
-      char* d = v->d_static;
-      v->args.sys_rows = (const int*)(d + o_rows);
-      v->args.sys_pat = (const int*)(d + o_pat);
-      v->args.row_off = (const int64_t*)(d + o_roff);
-      v->args.val_off = (const int64_t*)(d + o_voff);
-      v->args.pat_rp = (const int64_t*)(d + o_prp);
-      v->args.pat_row = (const int64_t*)(d + o_prow);
-      v->args.pat_sc = (const int64_t*)(d + o_psc);
-      v->args.prow_ptr = (const int*)(d + o_rp);
-      v->args.prow_len = (const int*)(d + o_len);
-      v->args.pdiag = (const int*)(d + o_dg);
-      v->args.pslot_col = (const int*)(d + o_sc);
+      char* dd = v->d_static;
+      v->args.sys_rows = (const int*)(dd + o_rows);
+      v->args.sys_pat = (const int*)(dd + o_pat);
+      v->args.row_off = (const int64_t*)(dd + o_roff);
+      v->args.val_off = (const int64_t*)(dd + o_voff);
+      v->args.pat_rp = (const int64_t*)(dd + o_prp);
+      v->args.pat_col = (const int64_t*)(dd + o_pco);
+      v->args.rowptr_all = (const int*)(dd + o_rp);
+      v->args.col_all = (const int*)(dd + o_col);
       v->args.tasks = v->d_tasks;
       v->args.order = v->d_order;
       v->args.counter = v->d_counter;
     }
     if (rc == BS_OK) {
       v->policy_next = 0;
-      build_tasks(*v, 0);
+      build_tasks(d, 0, v->tasks, v->order);
       rc = upload_tasks(*v);
     }
   }
@@ -426,8 +576,8 @@ int bs_varbatch_destroy(bs_varbatch v) {
 int bs_varbatch_query(bs_varbatch v, int64_t* total_rows, int64_t* total_values, int32_t* n_tasks,
                       int32_t* policy) {
   if (!v) return BS_ERR_INVALID_ARG;
-  if (total_rows) *total_rows = v->row_off.empty() ? 0 : v->row_off.back();
-  if (total_values) *total_values = v->val_off.empty() ? 0 : v->val_off.back();
+  if (total_rows) *total_rows = v->d.row_off.empty() ? 0 : v->d.row_off.back();
+  if (total_values) *total_values = v->d.val_off.empty() ? 0 : v->d.val_off.back();
   if (n_tasks) *n_tasks = (int32_t)v->tasks.size();
   if (policy) *policy = v->policy;
   return BS_OK;
@@ -440,13 +590,13 @@ int bs_varbatch_set_policy(bs_varbatch v, int32_t policy) {
   if (v->gexec) { (void)hipGraphExecDestroy(v->gexec); v->gexec = nullptr; }
   if (v->graph) { (void)hipGraphDestroy(v->graph); v->graph = nullptr; }
   v->policy_next = policy;
-  build_tasks(*v, policy);
+  build_tasks(v->d, policy, v->tasks, v->order);
   const int rc = upload_tasks(*v);
   if (rc == BS_OK) {
     v->policy = policy;
   } else {  // restore the previous tasks
     v->policy_next = v->policy;
-    build_tasks(*v, v->policy);
+    build_tasks(v->d, v->policy, v->tasks, v->order);
     (void)upload_tasks(*v);
   }
   return rc;
@@ -469,7 +619,7 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
   if (!v || reps < 1) return BS_ERR_INVALID_ARG;
   const hipStream_t st = (hipStream_t)stream;
   const int mixed = opts && opts->precision == BS_MIXED;
-  const std::string key = tune_key(*v, solver, mixed);
+  const std::string key = tune_key(v->d, solver, mixed);
   if (cache_path) {
     FILE* f = std::fopen(cache_path, "r");
     if (f) {
@@ -492,8 +642,8 @@ int bs_varbatch_tune(bs_varbatch v, const double* values, const double* b, doubl
   int best = 0;
   // every timed solve starts from the caller's x0 (kept in a copy) unless the
   // flags say x0 = 0; the copy back is timed for every policy alike
-  const bool keep_x0 = !(opts && (opts->flags & BS_FLAG_X0_ZERO)) && v->B > 0 && x;
-  const size_t xbytes = (size_t)v->row_off.back() * sizeof(double);
+  const bool keep_x0 = !(opts && (opts->flags & BS_FLAG_X0_ZERO)) && v->d.B > 0 && x;
+  const size_t xbytes = (size_t)v->d.row_off.back() * sizeof(double);
   double* x0 = nullptr;
   if (keep_x0) {
     hipError_t e = hipMalloc(&x0, xbytes);
@@ -584,6 +734,101 @@ int bs_varbatch_capture(bs_varbatch v, const double* values, const double* b, do
   e = hipGraphInstantiate(&v->gexec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_err(e, "graph instantiate");
   return BS_OK;
+}
+
+size_t bs_varlen_workspace_size(int64_t n_batch) {
+  if (n_batch < 0) return 0;
+  return ws_layout(n_batch).total;
+}
+
+int bs_batch_solve_varlen(int64_t n_batch, const int32_t* sys_rows, const int64_t* row_off,
+                          const int64_t* val_off, int32_t n_patterns, const int32_t* pat_id,
+                          const int64_t* pat_rowptr_off, const int64_t* pat_col_off,
+                          const int32_t* rowptr_all, const int32_t* col_all,
+                          const double* values, const double* b, double* x, bs_solver solver,
+                          bs_precond precond, double tol, int32_t max_iter, int32_t* iters,
+                          double* resid, int32_t* status, const bs_options* opts, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (n_batch < 0 || n_patterns < 0) return BS_ERR_INVALID_ARG;
+  if (n_batch > 0x7fffffff) return BS_ERR_UNSUPPORTED;
+  if (n_batch == 0) return BS_OK;
+  if (!sys_rows || !row_off || !val_off || !pat_id || n_patterns < 1 || !pat_rowptr_off ||
+      !pat_col_off || !rowptr_all || !col_all || !ws)
+    return BS_ERR_INVALID_ARG;
+  const WsLayout wl = ws_layout(n_batch);
+  if (ws_bytes < wl.total || ((uintptr_t)ws & 255)) return BS_ERR_INVALID_ARG;
+  const int vp = opts ? opts->varlen_policy : 0;
+  if (vp < 0 || vp > kNumPolicies) return BS_ERR_INVALID_ARG;
+  const int policy = vp == 0 ? 3 : vp - 1;
+  int device = -1;
+  int rc = have_device(&device);
+  if (rc != BS_OK) return rc;
+  const hipStream_t st = (hipStream_t)stream;
+  VarKey key{};
+  key.device = device;
+  key.B = n_batch;
+  key.P = n_patterns;
+  key.generation = opts ? opts->structure_generation : 0;
+  const void* ptrs[8] = {sys_rows, row_off, val_off, pat_id, pat_rowptr_off, pat_col_off,
+                         rowptr_all, col_all};
+  for (int i = 0; i < 8; ++i) key.ptr[i] = ptrs[i];
+  std::lock_guard<std::mutex> lock(g_var_mu);
+  VarEntry* ent = nullptr;
+  for (VarEntry& e : g_var_cache)
+    if (e.key == key) ent = &e;
+  if (!ent) {
+    VarEntry fresh;
+    fresh.key = key;
+    rc = read_batch(fresh.d, n_batch, sys_rows, row_off, val_off, n_patterns, pat_id,
+                    pat_rowptr_off, pat_col_off, rowptr_all, col_all, st);
+    if (rc != BS_OK) return rc;
+    if (g_var_cache.size() >= kVarCacheEntries) {  // drop the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < g_var_cache.size(); ++i)
+        if (g_var_cache[i].used < g_var_cache[lru].used) lru = i;
+      g_var_cache.erase(g_var_cache.begin() + (long)lru);
+    }
+    g_var_cache.push_back(std::move(fresh));
+    ent = &g_var_cache.back();
+  }
+  ent->used = ++g_var_clock;
+  if (ent->policy != policy) {
+    build_tasks(ent->d, policy, ent->tasks, ent->order);
+    rc = check_tasks(ent->d, policy, ent->tasks, ent->order);
+    if (rc != BS_OK) return rc;
+    ent->policy = policy;
+    ent->ws = nullptr;
+  }
+  char* w = static_cast<char*>(ws);
+  if (ent->ws != ws || ent->ws_policy != policy) {
+    // the task queue into the caller's workspace (pageable source: the copy is
+    // complete when the call returns)
+    hipError_t e = hipMemcpyAsync(w + wl.tasks, ent->tasks.data(),
+                                  ent->tasks.size() * sizeof(bs::VTask), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(w + wl.order, ent->order.data(), ent->order.size() * sizeof(int),
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_err(e, "upload uneven-batch tasks");
+    // another workspace may have held this entry's tasks: now only this one does
+    for (VarEntry& o : g_var_cache)
+      if (o.ws == ws) o.ws = nullptr;
+    ent->ws = ws;
+    ent->ws_policy = policy;
+  }
+  bs::VArgs a{};
+  a.n_tasks = (int64_t)ent->tasks.size();
+  a.tasks = reinterpret_cast<const bs::VTask*>(w + wl.tasks);
+  a.order = reinterpret_cast<const int*>(w + wl.order);
+  a.sys_rows = sys_rows;
+  a.sys_pat = pat_id;
+  a.row_off = row_off;
+  a.val_off = val_off;
+  a.pat_rp = pat_rowptr_off;
+  a.pat_col = pat_col_off;
+  a.rowptr_all = rowptr_all;
+  a.col_all = col_all;
+  return launch(ent->d, a, policy, device, reinterpret_cast<int*>(w + wl.counter), values, b, x,
+                solver, precond, tol, max_iter, iters, resid, status, opts, st);
 }
 
 int bs_varbatch_replay(bs_varbatch v, void* stream) {

@@ -343,14 +343,17 @@ def uneven_banded(n_batch: int = 100_000, n_min: int = 16, n_max: int = 1024,
 # --------------------------------------------------------------------------
 def chem_trajectory(n_batch: int = 1 << 16, n: int = 54, steps: int = 64,
                     fill: float = 0.35, gamma0: float = 1e-6, drift: float = 0.01,
-                    seed: int = 0) -> Iterator[Batch]:
-    """Yield ``steps`` batches ``A_t = I - gamma_t J_t`` with ``b`` fixed per system.
+                    seed: int = 0, b_drift: float = 0.0) -> Iterator[Batch]:
+    """Yield ``steps`` batches ``A_t = I - gamma_t J_t``.
 
     ``gamma_t = gamma_{t-1} (1 + drift U(-1,1))`` per system and
-    ``J_t = J_{t-1} o (1 + drift U(-1,1))`` per stored entry.  Draw order:
-    pattern; ``J_0`` as (sign, exponent) pairs ``(B, nnz, 2)``; ``b (B, n)``;
-    then for every ``t >= 1``: ``rng.random(B)`` for gamma, ``rng.random((B, nnz))``
-    for J.  Each yielded batch owns its arrays.
+    ``J_t = J_{t-1} o (1 + drift U(-1,1))`` per stored entry.  ``b`` is fixed
+    per system when ``b_drift = 0``; otherwise ``b_t = b_{t-1} o (1 + b_drift
+    U(-1,1))`` per component (a right-hand side that moves along the
+    sequence).  Draw order: pattern; ``J_0`` as (sign, exponent) pairs
+    ``(B, nnz, 2)``; ``b (B, n)``; then for every ``t >= 1``: ``rng.random(B)``
+    for gamma, ``rng.random((B, nnz))`` for J, and with ``b_drift > 0``
+    ``rng.random((B, n))`` for b.  Each yielded batch owns its arrays.
     """
     rng = np.random.default_rng(seed)
     row_ptr, col_idx = chem_pattern(n, fill, rng=rng)
@@ -367,10 +370,12 @@ def chem_trajectory(n_batch: int = 1 << 16, n: int = 54, steps: int = 64,
         if t > 0:
             gam = gam * (1.0 + drift * (2.0 * rng.random(n_batch) - 1.0))
             J *= 1.0 + drift * (2.0 * _uniform(rng, (n_batch, nnz)) - 1.0)
+            if b_drift > 0.0:
+                b = b * (1.0 + b_drift * (2.0 * _uniform(rng, (n_batch, n)) - 1.0))
         values = -gam[:, None] * J
         values[:, is_diag] += 1.0
         yield Batch("chem_trajectory", n, row_ptr, col_idx, values, b.copy(),
-                    np.zeros((n_batch, n)), {"seed": seed, "t": t})
+                    np.zeros((n_batch, n)), {"seed": seed, "t": t, "b_drift": b_drift})
 
 
 # --------------------------------------------------------------------------

@@ -259,3 +259,14 @@ def test_struct_layouts_match_the_header(tmp_path):
     offs = vals[2:]
     assert offs[:len(fields)] == [getattr(bs.bs_options, f).offset for f in fields]
     assert offs[len(fields):] == [getattr(bs.bs_plan_info, f).offset for f in pfields]
+
+
+def test_workspace_sizes(L):
+    """bs_workspace_size: the fused fixed-size solve takes no workspace.
+    bs_varlen_workspace_size: the counter, up to one task per system (16 bytes)
+    and the queue order (4 bytes per system), each region 256-byte aligned."""
+    assert bs.bs_workspace_size(bs.CSR, 1 << 17, 54, 0, bs.BICGSTAB) == 0
+    assert bs.bs_varlen_workspace_size(-1) == 0
+    for B in (0, 1, 100, 100_000):
+        want = 256 + (-(-(B + 1) * 16 // 256)) * 256 + (-(-(B + 1) * 4 // 256)) * 256
+        assert bs.bs_varlen_workspace_size(B) == want

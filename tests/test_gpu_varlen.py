@@ -358,3 +358,104 @@ def test_uneven_full_size_sampled():
             assert np.all(np.abs(g[1][sys_[sel]] - o[1]) <= 2)
     say(f"  uneven full size: worst true residual {worst:.2e}")
     assert worst <= 1e-10
+
+
+# ------------------------------------------------------------------ caller-owned arrays
+def varlen_arrays(vb: W.VarBatch):
+    """The structure of an uneven batch as the device tensors the caller owns."""
+    n_rows = np.asarray(vb.pat_rows)[vb.pat_id].astype(np.int32)
+    return dict(sys_rows=dev(n_rows), row_off=dev(np.asarray(vb.row_off, np.int64)),
+                val_off=dev(np.asarray(vb.val_off, np.int64)),
+                pat_id=dev(np.asarray(vb.pat_id, np.int32)),
+                pat_rowptr_off=dev(np.asarray(vb.pat_rowptr_off, np.int64)),
+                pat_col_off=dev(np.asarray(vb.pat_col_off, np.int64)),
+                rowptr_all=dev(np.asarray(vb.rowptr_all, np.int32)),
+                col_all=dev(np.asarray(vb.col_all, np.int32)))
+
+
+def varlen_solve(c: VCase, arrs, ws, solver=bs.BICGSTAB, precond=bs.PREC_JACOBI, tol=1e-10,
+                 max_iter=1000, **opt):
+    x, it, rs, st = c.outputs()
+    opts = bs.make_options(flags=bs.FLAG_X0_ZERO, **opt)
+    bs.bs_batch_solve_varlen(**arrs, values=c.dv, b=c.db, x=x, solver=solver, precond=precond,
+                             tol=tol, max_iter=max_iter, iters=it, resid=rs, status=st, opts=opts,
+                             ws=ws)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("policy", [3, 0, 8])
+def test_varlen_caller_arrays_match_handle(policy):
+    """bs_batch_solve_varlen on caller-owned device arrays gives, for the same
+    queue policy, the bits of the handle API's solve; both meet the oracle's
+    bar.  A second call (cached structure, workspace reused) gives the same
+    bits again, and so does a fresh workspace."""
+    vb = W.uneven_banded(400, 16, 1024, seed=31)
+    c = VCase(vb)
+    arrs = varlen_arrays(vb)
+    B = vb.n_batch
+    ws = torch.empty(bs.bs_varlen_workspace_size(B), dtype=torch.uint8, device="cuda:0")
+    bs.bs_varbatch_set_policy(c.h.handle, policy)
+    h = c.gpu(bs.BICGSTAB)
+    g1 = varlen_solve(c, arrs, ws, varlen_policy=policy + 1)
+    g2 = varlen_solve(c, arrs, ws, varlen_policy=policy + 1)
+    ws2 = torch.empty_like(ws)
+    g3 = varlen_solve(c, arrs, ws2, varlen_policy=policy + 1)
+    for g in (g1, g2, g3):
+        for a_, b_ in zip(g, h):
+            assert np.array_equal(a_, b_, equal_nan=True)
+    c.check(g1, bs.BICGSTAB)
+
+
+def test_varlen_generation_and_errors():
+    """Changing the structure in place takes a new generation number (the
+    library then re-reads and re-validates it); inconsistent or malformed
+    structure arrays and a short workspace are refused before any launch."""
+    vb = W.uneven_banded(120, 16, 300, seed=32)
+    c = VCase(vb)
+    arrs = varlen_arrays(vb)
+    B = vb.n_batch
+    ws = torch.empty(bs.bs_varlen_workspace_size(B), dtype=torch.uint8, device="cuda:0")
+    g = varlen_solve(c, arrs, ws, structure_generation=1)
+    c.check(g, bs.BICGSTAB)
+    # CG on the same structure, another generation (re-read): the oracle's bar
+    vb2 = W.uneven_banded(120, 16, 300, w_min=5, w_max=5, seed=33)   # symmetric bands
+    c2 = VCase(vb2, values=symmetric_values(vb2, 4))
+    arrs2 = varlen_arrays(vb2)
+    g2 = varlen_solve(c2, arrs2, ws, solver=bs.CG, structure_generation=2)
+    c2.check(g2, bs.CG)
+
+    def refused(codes, **change):
+        a = dict(arrs)
+        a.update(change)
+        with pytest.raises(bs.BatchSolveError) as e:
+            varlen_solve(c, a, ws, structure_generation=10 + len(change))
+        assert e.value.code in codes
+
+    bad_rows = varlen_arrays(vb)["sys_rows"].clone()
+    bad_rows[5] += 1
+    # one row more than its pattern: the offsets disagree with the rows, or
+    # (a pattern only this system uses) its row_ptr read one entry too far is
+    # no longer nondecreasing
+    refused((bs.ERR_INVALID_ARG, bs.ERR_PATTERN), sys_rows=bad_rows)
+    bad_pat = arrs["pat_id"].clone()
+    bad_pat[0] = len(vb.pat_rows)                       # no such pattern
+    refused((bs.ERR_PATTERN,), pat_id=bad_pat)
+    bad_off = arrs["val_off"].clone()
+    bad_off[3] += 1                                     # values of system 2 one short
+    refused((bs.ERR_INVALID_ARG,), val_off=bad_off)
+    bad_col = arrs["col_all"].clone()
+    bad_col[1] = bad_col[0]                             # a column twice in a row
+    refused((bs.ERR_PATTERN,), col_all=bad_col)
+    small = torch.empty(bs.bs_varlen_workspace_size(B) - 256, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(ValueError):
+        varlen_solve(c, arrs, small)
+    # past the binding's check, the library refuses the short workspace itself
+    x, it, rs, st = c.outputs()
+    rc = bs.lib().bs_batch_solve_varlen(
+        B, arrs["sys_rows"].data_ptr(), arrs["row_off"].data_ptr(), arrs["val_off"].data_ptr(),
+        len(vb.pat_rows), arrs["pat_id"].data_ptr(), arrs["pat_rowptr_off"].data_ptr(),
+        arrs["pat_col_off"].data_ptr(), arrs["rowptr_all"].data_ptr(), arrs["col_all"].data_ptr(),
+        c.dv.data_ptr(), c.db.data_ptr(), x.data_ptr(), bs.BICGSTAB, bs.PREC_JACOBI, 1e-10, 100,
+        it.data_ptr(), rs.data_ptr(), st.data_ptr(), None, small.data_ptr(), small.numel(), None)
+    assert rc == bs.ERR_INVALID_ARG

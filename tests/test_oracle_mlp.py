@@ -123,7 +123,9 @@ def test_features_and_diagonal():
     d = M.csr_diagonal(3, rp, ci, v)
     assert np.array_equal(d, [[4.0, 0.0, 9.0], [5.0, 0.0, -1.0]])
     f = M.features(d, np.ones((2, 3)), np.full((2, 3), 2.0))
-    assert f.shape == (2, 9) and np.array_equal(f[:, 3:6], np.ones((2, 3)))
+    assert f.shape == (2, 9) and np.array_equal(f[:, :3], d)
+    assert np.array_equal(f[:, 3:6], -np.ones((2, 3)))          # b - x_prev
+    assert np.array_equal(f[:, 6:], np.full((2, 3), 2.0))
 
 
 def test_predict_and_choice():
