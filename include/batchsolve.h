@@ -459,6 +459,21 @@ int bs_ws_grad(bs_ws_model m, int64_t n_samples, const float *feat, const float 
 int bs_ws_train_step(bs_ws_model m, int64_t n_samples, const float *feat, const float *delta,
                      const int32_t *rows, float lr, float *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): bs_ws_train_step without its
+ * workspace allocation.  The step's workspace (activations, their gradients,
+ * the weight-gradient partials, the per-tile losses) is a file-scope device
+ * array of 7 MiB on each device the library runs on, held until the process
+ * ends; the call itself allocates nothing (it launches the same kernels as
+ * bs_ws_train_step, asynchronously on stream).  Steps of at most 2048 samples:
+ * BS_ERR_UNSUPPORTED beyond.  Every call on one device shares that device's
+ * array, so calls that overlap on one device (two streams, two threads, or two
+ * models) race: serialise them.  Other arguments and errors as
+ * bs_ws_train_step. */
+int bs_ws_train_step_noalloc(bs_ws_model m, int64_t n_samples, const float *feat,
+                             const float *delta, const int32_t *rows, float lr, float *loss,
+                             void *stream);
+
 /* x0 = x_prev + sigma_d * y(f) for n_batch systems, features built from the
  * batch itself (one fused kernel). */
 int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double *values, const double *b,

@@ -116,6 +116,8 @@ def lib() -> C.CDLL:
     L.bs_ws_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.bs_ws_train_step.argtypes = [vp, i64, vp, vp, vp, C.c_float, vp, vp]
     L.bs_ws_infer.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.bs_ws_train_step_noalloc.argtypes = [vp, i64, vp, vp, vp, C.c_float, vp, vp]
+    L.bs_ws_train_step_noalloc.restype = C.c_int
     L.bs_ws_packed_bytes.argtypes = [i32]
     L.bs_ws_packed_bytes.restype = sz
     L.bs_ws_pack.argtypes = [vp, vp, sz, vp]
@@ -725,6 +727,22 @@ def bs_ws_train_step(handle: int, feat, delta, lr: float, loss=None, rows=None, 
     _expect(loss, "loss", "f32", 1, optional=True)
     _check(lib().bs_ws_train_step(handle, M, _ptr(feat), _ptr(delta), _ptr(rows), float(lr),
                                   _ptr(loss), _stream(stream)), "bs_ws_train_step")
+
+
+def bs_ws_train_step_noalloc(handle: int, feat, delta, lr: float, loss=None, rows=None,
+                             n_samples=None, stream=None) -> None:
+    """``bs_ws_train_step`` on the library's static workspace (no allocation;
+    at most 2048 samples)."""
+    M = n_samples if n_samples is not None else (rows.shape[0] if rows is not None else feat.shape[0])
+    n, nnz = _WS_SHAPES[handle]
+    check_ws_args(n, nnz, M, feat=feat, delta=delta, rows=rows,
+                  n_feat_rows=feat.shape[0])
+    if rows is None and feat.shape[0] < M:
+        raise ValueError(f"feat: {feat.shape[0]} rows, expected at least {M}")
+    _expect(loss, "loss", "f32", 1, optional=True)
+    _check(lib().bs_ws_train_step_noalloc(handle, M, _ptr(feat), _ptr(delta), _ptr(rows),
+                                          float(lr), _ptr(loss), _stream(stream)),
+           "bs_ws_train_step_noalloc")
 
 
 def bs_ws_infer(handle: int, values, b, x_prev, x0, stream=None) -> None:

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -266,6 +267,41 @@ int run_grad(bs_ws_model_s& m, const Work& w, int64_t M, const float* feat, cons
 
 namespace {
 
+// Workspace of bs_ws_train_step_noalloc: a file-scope device array sized for
+// the largest step it takes (2048 samples of the largest model, n = 64:
+// features padded to 192, outputs to 64), about 7 MiB on every device the
+// library runs on, held until the process ends.  Host code never passes the
+// array's name to a kernel: its address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t kScratchSamples = 2048;
+constexpr size_t kScratchBytes =
+    work_layout(round_up(3 * kMaxN, 64), round_up(kMaxN, 32), kScratchSamples).total;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+// This device's address of `scratch` (looked up once per device).
+int scratch_base(char** out) {
+  static std::mutex mu;
+  static std::vector<char*> addr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)");
+    addr[dev] = static_cast<char*>(p);
+  }
+  *out = addr[dev];
+  return BS_OK;
+}
+
 // Packed inference weights (bs_ws_pack / bs_ws_infer_packed): for systems of
 // n unknowns, regions in this order, each starting at a multiple of 256 bytes:
 // W1^T BF16 [256][Fp], W2^T BF16 [256][256], W3^T BF16 [Op][256], b1 FP32
@@ -511,6 +547,25 @@ int bs_ws_train_step(bs_ws_model m, int64_t n_samples, const float* feat, const 
   const int rc = ensure_ws(*m, n_samples, &w);
   if (rc != BS_OK) return rc;
   return run_grad(*m, w, n_samples, feat, delta, rows, nullptr, loss, 1, lr, (hipStream_t)stream);
+}
+
+int bs_ws_train_step_noalloc(bs_ws_model m, int64_t n_samples, const float* feat,
+                             const float* delta, const int32_t* rows, float lr, float* loss,
+                             void* stream) {
+  if (!m || !(lr > 0.f) || !std::isfinite(lr)) return BS_ERR_INVALID_ARG;
+  if (n_samples < 1 || !feat || !delta) return BS_ERR_INVALID_ARG;
+  if (n_samples > kScratchSamples) {
+    bs::set_last_error("bs_ws_train_step_noalloc: more than 2048 samples");
+    return BS_ERR_UNSUPPORTED;
+  }
+  char* base = nullptr;
+  const int rc = scratch_base(&base);
+  if (rc != BS_OK) return rc;
+  const int64_t Mp = (n_samples + kTile - 1) / kTile * kTile;
+  const WorkLayout l = work_layout(m->Fp, m->Op, Mp);
+  if (l.total > kScratchBytes) return BS_ERR_UNSUPPORTED;  // cannot happen for n <= 64
+  return run_grad(*m, work_at(base, l), n_samples, feat, delta, rows, nullptr, loss, 1, lr,
+                  (hipStream_t)stream);
 }
 
 int bs_ws_infer(bs_ws_model m, int64_t n_batch, const double* values, const double* b,
