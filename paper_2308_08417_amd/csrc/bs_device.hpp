@@ -313,13 +313,22 @@ struct Team {
 // (shift = row start - w); the other slots hold neighbouring rows' values,
 // which meet the zero cell.  Each slot is then one LDS read at a constant
 // offset.  ELL rows use slot k for the row's k-th stored entry.
-template <class S>
+//
+// MX (the mixed-precision kernels): gather addresses are kept for 4-byte
+// elements, the FP32 vectors' stride (consecutive elements on consecutive
+// banks), and the FP64 SpMVs of the outer residual use 2 * address - base.
+// Slots without an entry point at byte 4*ROWS in the FP32 view, whose FP64
+// image is the usual zero cell at 8*ROWS; an FP64 SpMV may overwrite the FP32
+// zero cell, so every FP32 SpMV writes it again.
+template <class S, bool MX = false>
 struct Rows {
   static constexpr int R = S::R, NZ = S::NZ, ROWS = S::ROWS, WG = S::WG, TEAM = S::TEAM;
+  static constexpr unsigned kElem = MX ? 4 : 8;  // bytes between elements in c and vrow
   double a[S::R][S::NZ];
   unsigned c[S::R][S::NZ];
   unsigned vrow[S::R];  // LDS address of the lane's own rows in buffer 0
   unsigned zc;          // LDS address of the zero cell in buffer 0
+  unsigned b0;          // LDS address of buffer 0
   int row[S::R];
   bool ok[S::R];   // row < n
   int len[S::R];
@@ -336,11 +345,15 @@ struct Rows {
   // Also clears the team's zero cells.
   __device__ void load_pattern(const Team<S>& tm, const KArgs& g) {
     const unsigned base = lds_addr(tm.lds);
-    const unsigned zero = base + S::ROWS * 8;
+    const unsigned zero = base + S::ROWS * kElem;
     zc = zero;
+    b0 = base;
     if (tm.lane == 0) {
 #pragma unroll
-      for (int b = 0; b < kVecBuffers; ++b) lds_store<double>(zero + b * kBuf, 0.0);
+      for (int b = 0; b < kVecBuffers; ++b) {
+        lds_store<double>(base + S::ROWS * 8 + b * kBuf, 0.0);
+        if constexpr (MX) lds_store<float>(zero + b * kBuf, 0.0f);
+      }
     }
     // A one-wave team may take the pattern's bank-aware layout: the row each
     // lane owns, its CSR window, and the buffer element of every x_j (64 lanes,
@@ -351,7 +364,7 @@ struct Rows {
       row[r] = lay ? lay[tm.lane] : tm.lane + r * S::TEAM;
       ok[r] = row[r] >= 0 && row[r] < g.n;
       const int rr = ok[r] ? row[r] : 0;
-      vrow[r] = base + (lay ? (ok[r] ? lay[2 * kWave + rr] : S::ROWS) : row[r]) * 8;
+      vrow[r] = base + (lay ? (ok[r] ? lay[2 * kWave + rr] : S::ROWS) : row[r]) * kElem;
       len[r] = ok[r] ? g.row_len[rr] : 0;
       const int ds = ok[r] ? g.diag_slot[rr] : -1;
       const int rp = g.row_ptr[rr];
@@ -369,7 +382,7 @@ struct Rows {
         const bool has = j >= 0 && j < len[r];
         const int col = g.slot_col[has ? (size_t)j * g.n + rr : 0];
         const int el = lay ? lay[2 * kWave + col] : col;
-        c[r][k] = has ? base + el * 8 : zero;
+        c[r][k] = has ? base + el * kElem : zero;
         // keep the full address in the register: otherwise the compiler keeps
         // col*8 and re-adds the (link-time) LDS base before every gather
         __asm__ volatile("" : "+v"(c[r][k]));
@@ -577,9 +590,24 @@ struct Rows {
                                        const T (&v)[S::R], T (&y)[S::R]) const {
     constexpr int kGather = BS_GATHER;
     constexpr unsigned off = BUF * kBuf;
+    // FP64 vectors in a mixed kernel: twice the 4-byte-element address, formed
+    // at each use (the empty asm keeps the compiler from holding a second set
+    // of addresses in registers through the solve for these rare SpMVs)
+    constexpr bool kWide = MX && sizeof(T) == 8;
+    auto at = [&](unsigned a) -> unsigned {
+      if constexpr (kWide) {
+        __asm__ volatile("" : "+v"(a));
+        return 2u * a - b0;
+      } else {
+        return a;
+      }
+    };
 #pragma unroll
     for (int r = 0; r < S::R; ++r)
-      if (ok[r]) lds_store<T>(vrow[r] + off, v[r]);
+      if (ok[r]) lds_store<T>(at(vrow[r]) + off, v[r]);
+    if constexpr (MX && sizeof(T) == 4) {
+      if (tm.lane == 0) lds_store<float>(zc + off, 0.0f);
+    }
     tm.sync();
     constexpr int NA = S::NZ >= 4 ? 4 : S::NZ;
 #pragma unroll
@@ -590,12 +618,12 @@ struct Rows {
         // this group's FMAs, so their LDS latency overlaps the arithmetic
         T xa[kGather], xb[kGather] = {};
 #pragma unroll
-        for (int k = 0; k < kGather && k < S::NZ; ++k) xa[k] = lds_load<T>(c[r][k] + off);
+        for (int k = 0; k < kGather && k < S::NZ; ++k) xa[k] = lds_load<T>(at(c[r][k]) + off);
 #pragma unroll
         for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
           const int k1 = k0 + kGather;
 #pragma unroll
-          for (int k = k1; k < k1 + kGather && k < S::NZ; ++k) xb[k - k1] = lds_load<T>(c[r][k] + off);
+          for (int k = k1; k < k1 + kGather && k < S::NZ; ++k) xb[k - k1] = lds_load<T>(at(c[r][k]) + off);
 #pragma unroll
           for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
             acc[k % NA] = fma((T)av[r][k], xa[k - k0], acc[k % NA]);
@@ -609,7 +637,7 @@ struct Rows {
         for (int k0 = 0; k0 < S::NZ; k0 += kGather) {
           T xv[kGather];
 #pragma unroll
-          for (int k = k0; k < k0 + kGather && k < S::NZ; ++k) xv[k - k0] = lds_load<T>(c[r][k] + off);
+          for (int k = k0; k < k0 + kGather && k < S::NZ; ++k) xv[k - k0] = lds_load<T>(at(c[r][k]) + off);
 #pragma unroll
           for (int k = k0; k < k0 + kGather && k < S::NZ; ++k)
             acc[k % NA] = fma((T)av[r][k], xv[k - k0], acc[k % NA]);

@@ -1216,10 +1216,10 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
 // zero the compiler cannot see through: otherwise it hoists every argument
 // load out of the loop and keeps them all in scalar registers through the
 // solve, where they spill into vector-register lanes.
-#define BS_PERSISTENT_LOOP(CALL)                                                    \
+#define BS_PERSISTENT_LOOP(MX, CALL)                                                \
   extern __shared__ __align__(16) char smem[];                                     \
   Team<S> tm(smem, g);                                                             \
-  Rows<S> A;                                                                       \
+  Rows<S, MX> A;                                                                   \
   A.load_pattern(tm, g);                                                           \
   const int64_t stride = (int64_t)gridDim.x * S::TEAMS;                            \
   const int64_t slot0 = (int64_t)xcd_slot(blockIdx.x, gridDim.x) * S::TEAMS;      \
@@ -1253,24 +1253,32 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
     CALL;                                                                          \
   }
 
+// Mixed kernels keep their FP32 vectors at a 4-byte LDS stride when a team
+// holds more rows than a wave: the gathers of the large systems then meet
+// fewer bank conflicts (the 992-row stencil solves 8% faster), while the
+// one-wave systems (54 rows) lose more to the extra address arithmetic of the
+// FP64 residual SpMVs than they gain.
+template <class S, bool MIXED>
+constexpr bool kLds32 = MIXED && (S::ROWS > kWave);
+
 template <class S, bool MIXED, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
-  BS_PERSISTENT_LOOP((bicgstab_system<MIXED, PK>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((kLds32<S, MIXED>), (bicgstab_system<MIXED, PK>(tm, A, ga)))
 }
 
 template <class S, bool LOWER>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_trsv(const KArgs g) {
-  BS_PERSISTENT_LOOP((trsv_system<LOWER>(tm, A, ga)))
+  BS_PERSISTENT_LOOP(false, (trsv_system<LOWER>(tm, A, ga)))
 }
 
 template <class S, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC))) void k_cg(const KArgs g) {
-  BS_PERSISTENT_LOOP((cg_system<PK>(tm, A, ga)))
+  BS_PERSISTENT_LOOP(false, (cg_system<PK>(tm, A, ga)))
 }
 
 template <class S, bool MIXED, int PK = kPkScalar>
 __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_gmres(const KArgs g) {
-  BS_PERSISTENT_LOOP((gmres_system<MIXED, PK>(tm, A, ga)))
+  BS_PERSISTENT_LOOP((kLds32<S, MIXED>), (gmres_system<MIXED, PK>(tm, A, ga)))
 }
 
 #undef BS_PERSISTENT_LOOP
