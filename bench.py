@@ -62,11 +62,12 @@ def load_traffic(name: str):
 
 
 def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
-    """Uneven batch in one persistent launch: ``args.uneven_batch`` banded
-    nonsymmetric systems, n ~ U{16..1024}, band width ~ U{5..9}, BiCGSTAB +
-    Jacobi to 1e-10, queue policy picked by the library's tuner, then timed as
-    eager launches and as replays of the captured graph (FP64 and mixed with
-    scalar Jacobi, FP64 with block Jacobi on blocks of 8 rows)."""
+    """Uneven batch: ``args.uneven_batch`` banded nonsymmetric systems,
+    n ~ U{16..1024}, band width ~ U{5..9}, BiCGSTAB + Jacobi to 1e-10; the
+    library's tuner picks one launch for the batch or one per size class (shape,
+    walk, placement), then timed as eager launches and as replays of the
+    captured graph (FP64 and mixed with scalar Jacobi, FP64 with block Jacobi on
+    blocks of 8 rows, and FP64 with the same batch given as ELL patterns)."""
     t0 = time.time()
     vb = W.uneven_banded(args.uneven_batch, 16, 1024, seed=0)
     gen_s = time.time() - t0
@@ -82,12 +83,17 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
     out = {"workload": f"uneven_banded_b{B}_n16-1024_w5-9_bicgstab_jacobi",
            "n_batch": B, "total_rows": int(vb.b.size), "total_values": int(vb.values.size),
            "gen_seconds": gen_s}
+    pr, pw, pco, ca, pid, ell_vals = vb.ell()
+    h_ell = bs.VarBatch(pr, pw, pco, ca, pid, ell=True)
+    vals_ell = torch.from_numpy(ell_vals).to(dev)
     steps = max(3, args.steps // 4)
-    for name, prec, pc, bsz in (("fp64", bs.FP64, bs.PREC_JACOBI, 0),
-                                ("mixed", bs.MIXED, bs.PREC_JACOBI, 0),
-                                ("fp64_block_jacobi8", bs.FP64, bs.PREC_BLOCK_JACOBI, 8)):
+    for name, hh, vv, prec, pc, bsz in (
+            ("fp64", h, vals, bs.FP64, bs.PREC_JACOBI, 0),
+            ("mixed", h, vals, bs.MIXED, bs.PREC_JACOBI, 0),
+            ("fp64_block_jacobi8", h, vals, bs.FP64, bs.PREC_BLOCK_JACOBI, 8),
+            ("fp64_ell_input", h_ell, vals_ell, bs.FP64, bs.PREC_JACOBI, 0)):
         opts = bs.make_options(flags=bs.FLAG_X0_ZERO, precision=prec, block_size=bsz)
-        args_ = (h.handle, vals, b, x, bs.BICGSTAB, pc, tol, max_iter, iters, resid,
+        args_ = (hh.handle, vv, b, x, bs.BICGSTAB, pc, tol, max_iter, iters, resid,
                  status, opts)
         report = bs.bs_varbatch_tune(*args_, reps=2)
         torch.cuda.synchronize()
@@ -99,28 +105,30 @@ def uneven_leg(args, bs, W, torch, np, dev, tol, max_iter):
         torch.cuda.synchronize()
         eager_ms = e0.elapsed_time(e1) / steps
         bs.bs_varbatch_capture(*args_)
-        bs.bs_varbatch_replay(h.handle)
+        bs.bs_varbatch_replay(hh.handle)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(steps):
-            bs.bs_varbatch_replay(h.handle)
+            bs.bs_varbatch_replay(hh.handle)
         e1.record()
         torch.cuda.synchronize()
         graph_ms = e0.elapsed_time(e1) / steps
         st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
-        # algorithmic bytes: every system's values, b and x once, the outputs,
-        # and each distinct pattern once
+        # algorithmic bytes: every system's stored values, b and x once, the
+        # outputs, and each distinct pattern once
         alg = (8 * vb.values.size + 16 * vb.b.size + 16 * B + 4 * vb.rowptr_all.size
-               + 8 * vb.col_all.size)
+               + 4 * vb.col_all.size)
         ms = min(eager_ms, graph_ms)
-        out[name] = {"tune": report, "eager_ms": eager_ms, "graph_ms": graph_ms,
+        policy, codes = bs.bs_varbatch_get_plan(hh.handle)
+        out[name] = {"tune": report, "plan": {"policy": policy, "class_codes": codes},
+                     "eager_ms": eager_ms, "graph_ms": graph_ms,
                      "systems_per_s": B / (ms * 1e-3),
                      "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": int(alg),
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                      "max_resid": float(rs.max())}
-    del vals, b, x
+    del vals, vals_ell, b, x
     return out
 
 
@@ -165,7 +173,7 @@ def dense_leg(args, bs, W, torch, np, dev, tol, max_iter):
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
     out["algorithmic_bytes_per_launch"] = int(alg)
-    del vals, b, x
+    del vals, vals_ell, b, x
     return out
 
 
@@ -208,7 +216,7 @@ def stiff_leg(args, bs, W, torch, np, dev, tol, max_iter):
                 "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                 "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                 "max_resid": float(rs.max())}
-    del vals, b, x
+    del vals, vals_ell, b, x
     return out
 
 
@@ -250,7 +258,7 @@ def multi_rhs_leg(args, bs, W, torch, np, dev, tol, max_iter):
            "algorithmic_bytes_per_launch": int(alg),
            "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
            "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
-    del vals, b, x
+    del vals, vals_ell, b, x
     return out
 
 
@@ -309,7 +317,7 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
                 r["outer_mean"] = float(outer.float().mean().item())
             out[f"{sname}_{pname}"] = r
     out["algorithmic_bytes_per_launch"] = int(alg)
-    del vals, b, x
+    del vals, vals_ell, b, x
     return out
 
 
@@ -689,7 +697,10 @@ def main() -> int:
     uneven = None
     if not args.no_uneven:
         uneven = uneven_leg(args, bs, W, torch, np, dev, tol, max_iter)
-        progress(f"uneven: {uneven['fp64']['eager_ms']:.2f} ms (fp64, eager)")
+        progress("uneven: " + ", ".join(f"{k} {uneven[k]['eager_ms']:.2f} ms"
+                                        for k in ("fp64", "mixed", "fp64_block_jacobi8",
+                                                  "fp64_ell_input"))
+                 + f" (eager); fp64 plan {uneven['fp64']['tune'].split()[0]}")
 
     dense = None
     if not args.no_dense:

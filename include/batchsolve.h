@@ -214,9 +214,10 @@ typedef struct {
                            hold n_batch*k entries in the same order; each solve
                            reads its matrix's values (bs_batch_solve only;
                            BS_ERR_UNSUPPORTED on the uneven-batch entry points) */
-  int32_t varlen_policy;/* bs_batch_solve_varlen: queue policy + 1, 1..9 (the
+  int32_t varlen_policy;/* bs_batch_solve_varlen: queue policy + 1, 1..18 (the
                            policies of bs_varbatch_set_policy); 0 selects policy 3
-                           (workgroups of 512 lanes x 2 rows, largest tasks first) */
+                           (workgroups of 512 lanes x 2 rows, largest tasks first;
+                           12, the streamed placement, for rows over 16 entries) */
   int32_t structure_generation; /* bs_batch_solve_varlen: the caller's count of
                            changes to the batch's structure arrays.  The library
                            reads and validates those arrays once per (addresses,
@@ -280,9 +281,21 @@ int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_
  * pattern, Sec. 3.1; its per-device size thresholds, Sec. 3.6, become an
  * autotuned choice here).  Systems are grouped by size class into tasks of one
  * to sixteen systems, ordered largest first, and taken from an atomic work
- * queue by the workgroups of one persistent launch; each system is solved by a
- * team of 64 or more lanes that own R rows each (n_rows <= 1024, longest row
- * <= 16).  Workgroup shapes: 1024 lanes x 1 row, 512 x 2, 256 x 4.
+ * queue by the workgroups of a persistent launch; each system is solved by a
+ * team of 64 or more lanes that own R rows each (n_rows <= 1024).  Workgroup
+ * shapes: 1024 lanes x 1 row, 512 x 2, 256 x 4.
+ *
+ * Placement of the matrix (Sec. 3.5 keeps what fits on chip and leaves the rest
+ * in global memory): "registers" holds every row's values and gather addresses
+ * in registers through the solve (rows of at most 16 entries); "streamed"
+ * keeps only where each row starts and reads the entries and values again from
+ * memory at every product (rows of any length; fewer registers, more resident
+ * waves).  Walk order: "csr" reads a row's entries one after another, "ell"
+ * reads slot k of every row of the team together (the slot-major ELL order of
+ * Sec. 3.1).  A solve runs either as one launch for the whole batch (a queue
+ * policy, bs_varbatch_set_policy) or as one launch per size class, each with its
+ * own shape, walk and placement (a plan, bs_varbatch_set_plan); the autotuner
+ * bs_varbatch_tune times both and keeps the faster.
  * ------------------------------------------------------------------------- */
 typedef struct bs_varbatch_s *bs_varbatch;
 
@@ -292,27 +305,61 @@ typedef struct bs_varbatch_s *bs_varbatch;
  * entries) and columns at col_all[pat_col_off[p] ..]; system s uses pattern
  * sys_pat[s].  Values of system s are its pattern's nnz doubles in CSR order,
  * stored after those of system s-1; b and x likewise with n_rows doubles.
+ * The initial policy is 0 (registers) when no row is longer than 16, else 9
+ * (streamed).
  * Errors: BS_ERR_INVALID_ARG, BS_ERR_PATTERN (as for bs_pattern_create_csr, or
  * sys_pat out of range), BS_ERR_UNSUPPORTED (a pattern with more than 1024
- * rows or a row longer than 16), BS_ERR_NO_DEVICE / BS_ERR_HIP. */
+ * rows), BS_ERR_NO_DEVICE / BS_ERR_HIP. */
 int bs_varbatch_create(int64_t n_batch, int32_t n_patterns, const int32_t *pat_rows,
                        const int64_t *pat_rowptr_off, const int32_t *rowptr_all,
                        const int64_t *pat_col_off, const int32_t *col_all, const int32_t *sys_pat,
                        bs_varbatch *out);
 
+/* Same for ELL patterns (BatchEll, Sec. 3.1): pattern p has pat_rows[p] rows
+ * and pat_width[p] slots, its slot-major columns [pat_width[p]][pat_rows[p]] at
+ * col_all[pat_col_off[p] ..] (slot k of row i at k*rows + i; -1 = padding,
+ * which must follow a row's stored entries).  Values of system s are
+ * pat_width*pat_rows doubles in the same slot-major layout (padding values are
+ * not read), stored after those of system s-1.  The library derives each
+ * pattern's row-ordered and slot-major walks from the columns.
+ * Errors as bs_varbatch_create (BS_ERR_PATTERN also for an entry after
+ * padding; BS_ERR_UNSUPPORTED for a width above 1024). */
+int bs_varbatch_create_ell(int64_t n_batch, int32_t n_patterns, const int32_t *pat_rows,
+                           const int32_t *pat_width, const int64_t *pat_col_off,
+                           const int32_t *col_all, const int32_t *sys_pat, bs_varbatch *out);
+
 int bs_varbatch_destroy(bs_varbatch vb);
 
-/* Totals: rows (= length of b and x), values, queue tasks, current policy. */
+/* Totals: rows (= length of b and x), values, queue tasks, current policy
+ * (-1 while a per-class plan is in force). */
 int bs_varbatch_query(bs_varbatch vb, int64_t *total_rows, int64_t *total_values, int32_t *n_tasks,
                       int32_t *policy);
 
-/* Policy p (0..8) = workgroup shape p / 3 (0: 1024 lanes x 1 row per lane,
- * 1: 512 x 2, 2: 256 x 4) and queue order p % 3: 0 = team of the next power
- * of two >= n / R lanes (at least 64), largest tasks first; 1 = teams twice
- * that size (fewer systems per task); 2 = as 0 with the systems of a class
- * kept in batch order.  Policy 0 after bs_varbatch_create.
- * BS_ERR_INVALID_ARG for p outside 0..8. */
+/* One launch for the whole batch under policy p (0..17): placement p / 9
+ * (0 registers, 1 streamed), workgroup shape (p % 9) / 3 (0: 1024 lanes x 1 row
+ * per lane, 1: 512 x 2, 2: 256 x 4) and queue order p % 3: 0 = team of the next
+ * power of two >= n / R lanes (at least 64), largest tasks first; 1 = teams
+ * twice that size (fewer systems per task); 2 = as 0 with the systems of a
+ * class kept in batch order.  The walk is the input's own order (csr for CSR
+ * patterns, ell for ELL patterns).  A solve under a register policy with a row
+ * longer than 16 fails with BS_ERR_UNSUPPORTED.
+ * BS_ERR_INVALID_ARG for p outside 0..17. */
 int bs_varbatch_set_policy(bs_varbatch vb, int32_t policy);
+
+/* One launch per size class (n <= 64, <= 128, <= 256, <= 512, <= 1024 rows;
+ * largest class first, each taking its own tasks from its own counter):
+ * class_codes[5], one per class, code = shape + 3 * walk + 6 * placement with
+ * shape as above (0..2), walk 0 csr / 1 ell, placement 0 registers / 1
+ * streamed; codes of classes without systems are not used but must be valid.
+ * A solve fails with BS_ERR_UNSUPPORTED when a class's choice has no kernel
+ * (registers with a row longer than 16, or streamed with block Jacobi).
+ * BS_ERR_INVALID_ARG for a code outside 0..11. */
+int bs_varbatch_set_plan(bs_varbatch vb, const int32_t *class_codes);
+
+/* The plan in force: *policy as bs_varbatch_query, class_codes[5] the
+ * per-class codes (all -1 under a single-launch policy).  Either pointer may
+ * be NULL. */
+int bs_varbatch_get_plan(bs_varbatch vb, int32_t *policy, int32_t *class_codes);
 
 /* Solve all systems (BS_CG or BS_BICGSTAB; BS_MIXED for BiCGSTAB), arguments
  * as in bs_batch_solve with the concatenated layouts above.  One launch of
@@ -322,12 +369,17 @@ int bs_varbatch_solve(bs_varbatch vb, const double *values, const double *b, dou
                       int32_t *iters, double *resid, int32_t *status, const bs_options *opts,
                       void *stream);
 
-/* Autotuner: time every queue policy on these inputs (1 warm-up and `reps`
- * timed solves each, synchronising `stream`), keep the fastest, and write a
- * one-line report "policy=<p> times_ms=<t0>,..,<t8>" into report (may be
- * NULL).  If cache_path is not NULL the choice is looked up in / appended to
- * that text file, keyed by the size-class histogram, solver and precision; a
- * cached choice is applied without timing or solving.  Each timed solve
+/* Autotuner: on these inputs (1 warm-up and `reps` timed solves per
+ * candidate, synchronising `stream`) time every single-launch policy, then
+ * every class choice for each size class launched alone, then the plan of the
+ * best choice per class as a whole; keep the fastest of that plan and the
+ * best policy.  One-line report (report may be NULL): "policy=<p or
+ * split:c0,..,c4> times_ms=<t0>,..,<t17> classes=<class>:<code>=<lanes>x<rows>/
+ * <walk>/<placement>:<ms>,.. split_ms=<t> key=<key>", '-' for a policy with no
+ * kernel for this request.  If cache_path is not NULL the choice is looked up
+ * in / appended to that text file, keyed by the format, the size-class
+ * histogram and longest rows, solver, precision and preconditioner; a cached
+ * choice is applied without timing or solving.  Each timed solve
  * starts from the caller's x (kept in a temporary device copy) unless
  * opts->flags has BS_FLAG_X0_ZERO; after timing, one more solve with the
  * chosen policy leaves x/iters/resid/status as bs_varbatch_solve would. */
@@ -337,10 +389,11 @@ int bs_varbatch_tune(bs_varbatch vb, const double *values, const double *b, doub
                      int32_t reps, const char *cache_path, char *report, size_t report_len,
                      void *stream);
 
-/* Capture the counter reset and the solve (with these arguments) into a HIP
- * graph owned by the handle, replacing any previous one; bs_varbatch_replay
- * launches it on `stream`.  The graph holds no memset nodes.  A change of
- * queue policy (bs_varbatch_set_policy, bs_varbatch_tune) drops the graph;
+/* Capture the counter reset and the solve's launches (with these arguments)
+ * into a HIP graph owned by the handle, replacing any previous one;
+ * bs_varbatch_replay launches it on `stream`.  The graph holds no memset
+ * nodes.  A change of plan (bs_varbatch_set_policy, bs_varbatch_set_plan,
+ * bs_varbatch_tune) drops the graph;
  * bs_varbatch_replay then fails with BS_ERR_INVALID_ARG until the next
  * capture. */
 int bs_varbatch_capture(bs_varbatch vb, const double *values, const double *b, double *x,
@@ -364,16 +417,19 @@ int bs_varbatch_replay(bs_varbatch vb, void *stream);
  *   ws, ws_bytes  device workspace of at least bs_varlen_workspace_size(n_batch)
  *             bytes, 256-byte aligned; it holds the task queue of this call and
  *             must not be changed by the caller between calls that use it
- * Every row holds at most 16 entries, no column twice, all in range.  The
- * first call for a structure copies the structure arrays to the host (one
- * synchronisation of `stream`), validates them and builds the task queue; later
+ * No column twice in a row, all in range.  Policy: opts->varlen_policy - 1
+ * (a single-launch policy of bs_varbatch_set_policy, 0..17); 0 selects 3
+ * (512 x 2, registers), or 12 (streamed) when a row holds more than 16
+ * entries.  The first call for a structure copies the structure arrays to the
+ * host (one synchronisation of `stream`), validates them and builds the task queue; later
  * calls with the same addresses, shape and opts->structure_generation launch
  * at once (asynchronously), re-uploading the task queue only when ws or the
  * queue policy changed.  Solvers and options as bs_varbatch_solve.
  * Errors: BS_ERR_INVALID_ARG (NULL pointer, inconsistent offsets or rows,
  * workspace too small or misaligned, bad option), BS_ERR_PATTERN (malformed
  * pattern, pat_id out of range), BS_ERR_UNSUPPORTED (more than 1024 rows, a
- * row longer than 16, unsupported solver or preconditioner), BS_ERR_HIP.
+ * row longer than 16 under a register policy, unsupported solver or
+ * preconditioner), BS_ERR_HIP.
  * n_batch = 0 is a no-op. */
 int bs_batch_solve_varlen(int64_t n_batch, const int32_t *sys_rows, const int64_t *row_off,
                           const int64_t *val_off, int32_t n_patterns, const int32_t *pat_id,

@@ -89,6 +89,9 @@ def lib() -> C.CDLL:
     L.bs_varbatch_query.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
                                     C.POINTER(i32)]
     L.bs_varbatch_set_policy.argtypes = [vp, i32]
+    L.bs_varbatch_create_ell.argtypes = [i64, i32, vp, vp, vp, vp, vp, C.POINTER(vp)]
+    L.bs_varbatch_set_plan.argtypes = [vp, vp]
+    L.bs_varbatch_get_plan.argtypes = [vp, vp, vp]
     _vsolve = [vp, vp, vp, vp, C.c_int, C.c_int, dbl, i32, vp, vp, vp, C.POINTER(bs_options)]
     L.bs_varbatch_solve.argtypes = _vsolve + [vp]
     L.bs_varbatch_tune.argtypes = _vsolve + [i32, C.c_char_p, C.c_char_p, sz, vp]
@@ -133,7 +136,8 @@ def lib() -> C.CDLL:
                  "bs_pattern_query", "bs_pattern_ell_cols", "bs_wave_layout",
                  "bs_pattern_layout", "bs_values_csr_to_ell",
                  "bs_matrix_storage", "bs_batch_solve", "bs_plan", "bs_plan_precond",
-                 "bs_varbatch_create",
+                 "bs_varbatch_create", "bs_varbatch_create_ell", "bs_varbatch_set_plan",
+                 "bs_varbatch_get_plan",
                  "bs_varbatch_destroy", "bs_varbatch_query", "bs_varbatch_set_policy",
                  "bs_varbatch_solve", "bs_varbatch_tune", "bs_varbatch_capture",
                  "bs_varbatch_replay", "bs_ws_create", "bs_ws_destroy", "bs_ws_param_count",
@@ -449,6 +453,36 @@ def bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_al
     return h.value
 
 
+def bs_varbatch_create_ell(pat_rows, pat_width, pat_col_off, col_all, sys_pat) -> int:
+    """ELL patterns: slot-major columns [width][rows] per pattern, -1 padding."""
+    pr, pw, pco = _host(pat_rows, np.int32), _host(pat_width, np.int32), _host(pat_col_off, np.int64)
+    ca, sp = _host(col_all, np.int32), _host(sys_pat, np.int32)
+    h = C.c_void_p()
+    _check(lib().bs_varbatch_create_ell(sp.size, pr.size, pr.ctypes.data, pw.ctypes.data,
+                                        pco.ctypes.data, ca.ctypes.data if ca.size else None,
+                                        sp.ctypes.data if sp.size else None, C.byref(h)),
+           "bs_varbatch_create_ell")
+    _VB_SYSTEMS[h.value] = int(sp.size)
+    return h.value
+
+
+def bs_varbatch_set_plan(handle: int, class_codes) -> None:
+    """One launch per size class; ``class_codes`` holds 5 codes
+    (shape + 3 * walk + 6 * placement)."""
+    cc = _host(class_codes, np.int32)
+    if cc.size != 5:
+        raise ValueError("class_codes: expected 5 codes")
+    _check(lib().bs_varbatch_set_plan(handle, cc.ctypes.data), "bs_varbatch_set_plan")
+
+
+def bs_varbatch_get_plan(handle: int) -> tuple:
+    """(policy, [5 class codes]); policy -1 under a per-class plan."""
+    p = C.c_int32()
+    cc = np.zeros(5, np.int32)
+    _check(lib().bs_varbatch_get_plan(handle, C.byref(p), cc.ctypes.data), "bs_varbatch_get_plan")
+    return p.value, cc.tolist()
+
+
 def bs_varbatch_destroy(handle: int) -> None:
     _VB_SYSTEMS.pop(handle, None)
     _check(lib().bs_varbatch_destroy(handle), "bs_varbatch_destroy")
@@ -504,8 +538,9 @@ def bs_varbatch_solve(handle: int, values, b, x, solver: int, precond: int, tol:
 def bs_varbatch_tune(handle: int, values, b, x, solver: int, precond: int, tol: float,
                      max_iter: int, iters, resid, status=None, opts: Optional[bs_options] = None,
                      reps: int = 3, cache_path: Optional[str] = None, stream=None) -> str:
-    """Time the queue policies, keep the fastest; returns the report line."""
-    buf = C.create_string_buffer(512)
+    """Time the single-launch policies and the per-class plans, keep the
+    fastest; returns the report line."""
+    buf = C.create_string_buffer(1024)
     _check(lib().bs_varbatch_tune(*_vargs(handle, values, b, x, solver, precond, tol, max_iter,
                                           iters, resid, status, opts), int(reps),
                                   cache_path.encode() if cache_path else None, buf, len(buf),
@@ -579,12 +614,12 @@ def bs_batch_solve_varlen(sys_rows, row_off, val_off, pat_id, pat_rowptr_off, pa
 
 
 class VarBatch:
-    """Owns an uneven-batch handle (see ``bs_varbatch_create``)."""
+    """Owns an uneven-batch handle (see ``bs_varbatch_create``; with
+    ``ell=True`` the arguments are those of ``bs_varbatch_create_ell``)."""
 
-    def __init__(self, pat_rows, pat_rowptr_off, rowptr_all, pat_col_off, col_all, sys_pat):
-        self.handle = bs_varbatch_create(pat_rows, pat_rowptr_off, rowptr_all, pat_col_off,
-                                         col_all, sys_pat)
-        self.n_batch = int(np.asarray(sys_pat).size)
+    def __init__(self, *args, ell: bool = False):
+        self.handle = bs_varbatch_create_ell(*args) if ell else bs_varbatch_create(*args)
+        self.n_batch = int(np.asarray(args[-1]).size)
         q = bs_varbatch_query(self.handle)
         self.total_rows, self.total_values = q["total_rows"], q["total_values"]
 

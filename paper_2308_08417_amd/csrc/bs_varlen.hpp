@@ -33,10 +33,22 @@ struct VTask {
   int pad;
 };
 
-// The batch is described by the CSR arrays themselves (validated on the host
-// before any launch): the kernel reads each row's start and length from its
-// pattern's row_ptr, its columns in CSR order, and finds the diagonal among
-// them while loading.
+// Where a kernel finds a row's columns and the positions of its values in the
+// system's value block (the source, SRC):
+//   kSrcCsr      the CSR arrays themselves: row_ptr, columns, values in CSR
+//                order (position = row start + k);
+//   kSrcRowIdx   a row-ordered index of {column, position} pairs at the CSR
+//                offsets of the pattern (the CSR walk of values in any layout);
+//   kSrcSlotIdx  a slot-major index [width][rows] of {column, position} pairs,
+//                column -1 for padding (the ELL walk: lanes of a team read
+//                consecutive entries of one slot).
+// The indexes are built on the host from validated patterns.
+enum : int { kSrcCsr = 0, kSrcRowIdx = 1, kSrcSlotIdx = 2 };
+
+// The batch is described by the pattern arrays (validated on the host before
+// any launch): the kernel reads each row's start and length from its pattern's
+// row_ptr (or a slot of the slot-major index), its columns and value
+// positions, and finds the diagonal among them while loading.
 struct VArgs {
   KArgs base;             // solver settings and the per-system outputs
   int64_t n_tasks;
@@ -50,6 +62,10 @@ struct VArgs {
   const int64_t* pat_col; // [P] offset of the pattern's columns in col_all
   const int* rowptr_all;  // concatenated row_ptr arrays (each starting at 0)
   const int* col_all;     // concatenated column arrays, CSR order
+  const int2* idx_row;    // kSrcRowIdx: row-ordered index, pattern p at pat_col[p]
+  const int2* idx_slot;   // kSrcSlotIdx: slot-major index, pattern p at pat_slot[p]
+  const int64_t* pat_slot;
+  const int* pat_w;       // [P] slots of each pattern's slot-major index
   int* counter;           // task counter, zero at launch
 };
 
@@ -136,9 +152,10 @@ struct VarTeam {
 };
 
 // The R rows a lane owns, their values and LDS gather addresses in registers.
-template <class VS, int NZ_>
+template <class VS, int NZ_, int SRC = kSrcCsr>
 struct VarRows {
   static constexpr int R = VS::R, NZ = NZ_, ROWS = VS::ROWS;
+  static constexpr int OCC = VS::OCC;  // waves per SIMD the allocator is held to
   static constexpr unsigned kBuf = var_buf_bytes<VS>();
   double a[R][NZ];
   unsigned c[R][NZ];
@@ -161,7 +178,6 @@ struct VarRows {
     const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
     zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
     const int* rps = va.rowptr_all + va.pat_rp[p];
-    const int* cols = va.col_all + va.pat_col[p];
     const double* vals = g.values + va.val_off[s];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -170,25 +186,43 @@ struct VarRows {
       vrow[r] = tb + (unsigned)row[r] * 8;
       const int rr = row[r];
       int len = 0, ds = -1, rp = 0;
-      if (ok[r]) {
+      double dv = 0.0;
+      if constexpr (SRC == kSrcSlotIdx) {
+        len = ok[r] ? va.pat_w[p] : 0;
+      } else if (ok[r]) {
         rp = rps[rr];
         len = rps[rr + 1] - rp;
       }
 #pragma unroll
       for (int k = 0; k < NZ; ++k) {
-        const bool has = k < len;
-        int col = 0;
-        double v = 0.0;
+        bool has = k < len;
+        int col = 0, pos = 0;
         if (has) {
-          col = cols[rp + k];
-          v = __builtin_nontemporal_load(vals + rp + k);
+          if constexpr (SRC == kSrcCsr) {
+            col = va.col_all[va.pat_col[p] + rp + k];
+            pos = rp + k;
+          } else if constexpr (SRC == kSrcRowIdx) {
+            const int2 e = va.idx_row[va.pat_col[p] + rp + k];
+            col = e.x;
+            pos = e.y;
+          } else {
+            const int2 e = va.idx_slot[va.pat_slot[p] + (int64_t)k * n + rr];
+            col = e.x;
+            pos = e.y;
+            has = col >= 0;
+          }
         }
-        ds = (has && col == rr && ds < 0) ? k : ds;
+        double v = 0.0;
+        if (has) v = __builtin_nontemporal_load(vals + pos);
+        if (has && col == rr && ds < 0) {
+          ds = k;
+          dv = v;
+        }
         c[r][k] = has ? tb + col * 8 : zero;
         a[r][k] = v;
       }
       dslot[r] = ds;
-      dval[r] = ds >= 0 ? vals[rp + ds] : 0.0;
+      dval[r] = dv;
       bval[r] = ok[r] ? g.b[tm.row0 + rr] : 0.0;
       double xv = 0.0;
       if ((g.flags & 1) == 0 && ok[r]) xv = g.x[tm.row0 + rr];
@@ -237,10 +271,147 @@ struct VarRows {
   }
 };
 
-__global__ void k_varlen_reset(int* counter) { *counter = 0; }
+// The streamed placement: a lane keeps only where its rows start; every
+// product reads the columns (or index entries) and the values from memory
+// again (the pattern arrays are shared by all systems of a pattern and stay in
+// the caches; a system's values are re-read from L2 or HBM).  No register
+// holds a row, so rows of any length fit, and the registers the row values
+// would take are free for more resident waves.  Scalar Jacobi or none only.
+template <class VS, int SRC>
+struct VarRowsS {
+  static constexpr int R = VS::R, NZ = 1, ROWS = VS::ROWS;
+  // without the rows in registers two workgroups fit one CU: four waves per
+  // SIMD (128 registers a lane) for 512 lanes, two (256) for 256 lanes x 4 rows
+  static constexpr int OCC = VS::WG >= 512 ? 4 : 2;
+  static constexpr unsigned kBuf = var_buf_bytes<VS>();
+  double a[R][NZ];  // not read: the products take the values from memory
+  unsigned vrow[R];
+  int row[R];
+  bool ok[R];
+  int dslot[R];     // 0 when the row stores its diagonal, else -1
+  int start[R];     // row walks: first entry of the row in the pattern arrays
+  int len[R];       // entries of the row (slot walk: the pattern's slot count)
+  unsigned tb, zero;
+  int n;
+  const int* cols;   // kSrcCsr
+  const int2* ix;    // kSrcRowIdx, kSrcSlotIdx
+  const double* vals;
+  double dval[R], bval[R], xval[R], xalt[R];
 
-template <class VS, int NZ, int SOLVER, bool MIXED, bool BJ = false>
-__global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(VS::OCC)))
+  // Entry k of row r: column (-1 when absent) and value position.
+  __device__ __forceinline__ int2 entry(int r, int k) const {
+    if constexpr (SRC == kSrcCsr) return make_int2(cols[start[r] + k], start[r] + k);
+    else if constexpr (SRC == kSrcRowIdx) return ix[start[r] + k];
+    else return ix[(int64_t)k * n + row[r]];
+  }
+
+  __device__ void load(const VarTeam<VS>& tm, const VArgs& va, unsigned lds_base) {
+    const KArgs& g = va.base;
+    const int s = tm.live ? (int)tm.sys : 0;
+    n = tm.live ? va.sys_rows[s] : 0;
+    const int p = va.sys_pat[s];
+    tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
+    zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
+    const int* rps = va.rowptr_all + va.pat_rp[p];
+    cols = nullptr;
+    ix = nullptr;
+    if constexpr (SRC == kSrcCsr) cols = va.col_all + va.pat_col[p];
+    else if constexpr (SRC == kSrcRowIdx) ix = va.idx_row + va.pat_col[p];
+    else ix = va.idx_slot + va.pat_slot[p];
+    vals = g.values + va.val_off[s];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      row[r] = tm.lane + r * tm.T;
+      ok[r] = row[r] < n;
+      vrow[r] = tb + (unsigned)row[r] * 8;
+      const int rr = row[r];
+      start[r] = 0;
+      len[r] = 0;
+      if (ok[r]) {
+        if constexpr (SRC == kSrcSlotIdx) {
+          len[r] = va.pat_w[p];
+        } else {
+          start[r] = rps[rr];
+          len[r] = rps[rr + 1] - start[r];
+        }
+      }
+      // the diagonal: first entry whose column is the row itself
+      int ds = -1;
+      double dv = 0.0;
+#pragma unroll 1
+      for (int k = 0; k < len[r]; ++k) {
+        const int2 e = entry(r, k);
+        if (e.x == rr) {
+          ds = 0;
+          dv = vals[e.y];
+          break;
+        }
+      }
+      dslot[r] = ds;
+      dval[r] = dv;
+      bval[r] = ok[r] ? g.b[tm.row0 + rr] : 0.0;
+      double xv = 0.0;
+      if ((g.flags & 1) == 0 && ok[r]) xv = g.x[tm.row0 + rr];
+      xval[r] = xv;
+      double xa = 0.0;
+      if (g.x_alt && ok[r]) xa = g.x_alt[tm.row0 + rr];
+      xalt[r] = xa;
+    }
+  }
+
+  __device__ __forceinline__ bool real(int, int) const { return false; }
+  __device__ __forceinline__ int nrows(const KArgs&) const { return n; }
+
+  __device__ void jacobi(int precond, double (&d)[R]) const {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dv = dval[r];
+      d[r] = !ok[r] ? 0.0 : (precond == 1 && dslot[r] >= 0 && dv != 0.0) ? 1.0 / dv : 1.0;
+    }
+  }
+
+  // Entries in groups of four: the index and value loads of a group are
+  // issued together, then its LDS gathers, then the FMAs (slot k into
+  // accumulator k mod 4, the order of the register placement).
+  template <int BUF, class V, class AT>
+  __device__ __forceinline__ void spmv(VarTeam<VS>& tm, const AT (&)[R][NZ], const V (&v)[R],
+                                       V (&y)[R]) const {
+    constexpr unsigned off = BUF * kBuf;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (ok[r]) lds_store<V>(vrow[r] + off, v[r]);
+    tm.sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      V acc[4] = {0, 0, 0, 0};
+#pragma unroll 1
+      for (int k0 = 0; k0 < len[r]; k0 += 4) {
+        int2 e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] = k0 + j < len[r] ? entry(r, k0 + j) : make_int2(-1, 0);
+        double av[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) av[j] = e[j].x >= 0 ? vals[e[j].y] : 0.0;
+        V xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          xv[j] = lds_load<V>((e[j].x >= 0 ? tb + (unsigned)e[j].x * 8 : zero) + off);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = fma((V)av[j], xv[j], acc[j]);
+      }
+      y[r] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+  }
+};
+
+// Per-class launches of one solve use counters counter[0..kMaxClasses), all
+// cleared by k_varlen_reset (one wave; defined with the host entry points).
+constexpr int kMaxClasses = 8;
+__global__ void k_varlen_reset(int* counter);
+
+// RowsT: VarRows<VS, NZ, SRC> (rows in registers) or VarRowsS<VS, SRC>.
+template <class VS, class RowsT, int SOLVER, bool MIXED, bool BJ = false>
+__global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(RowsT::OCC)))
 void k_varlen(const VArgs va) {
   // buffers and reduction slots, then (BJ) the block-Jacobi region of the largest block
   __shared__ __align__(16) char smem[var_lds_bytes<VS>() + (BJ ? bj_bytes(VS::ROWS, kMaxBlock) : 0)];
@@ -270,7 +441,7 @@ void k_varlen(const VArgs va) {
     tm.live = tm.tix < task.count;
     tm.sys = tm.live ? a.order[task.first + tm.tix] : 0;
     tm.row0 = tm.live ? a.row_off[tm.sys] : 0;
-    VarRows<VS, NZ> A;
+    RowsT A;
     A.load(tm, a, lds_base);
     if constexpr (SOLVER == 0) cg_system<BJ ? kPkBlock : kPkScalar>(tm, A, a.base);
     else bicgstab_system<MIXED, BJ ? kPkBlock : kPkScalar>(tm, A, a.base);

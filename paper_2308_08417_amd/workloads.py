@@ -267,6 +267,43 @@ class VarBatch:
         r0, r1 = self.row_off[s], self.row_off[s + 1]
         return rp, ci, v, self.b[r0:r1], self.x0[r0:r1]
 
+    def ell(self, extra_slots: int = 0, pad_value: float = 0.0):
+        """The same batch in the ELL layout: per pattern ``w = longest row +
+        extra_slots`` slots, slot-major columns ``[w][n]`` with -1 padding, and
+        every system's values ``[w][n]`` in the same layout (padding slots hold
+        ``pad_value``).  Returns ``(pat_rows, pat_width, pat_col_off, col_all,
+        pat_id, values)``; a re-layout only, entry k of row i stays slot k."""
+        P = self.pat_rows.size
+        widths = np.empty(P, np.int32)
+        cols, offs, slot_of = [], [], []
+        at = 0
+        for p in range(P):
+            n = int(self.pat_rows[p])
+            ro, co = int(self.pat_rowptr_off[p]), int(self.pat_col_off[p])
+            rp = self.rowptr_all[ro:ro + n + 1].astype(np.int64)
+            ci = self.col_all[co:co + int(rp[-1])]
+            lens = np.diff(rp)
+            w = int(lens.max(initial=0)) + extra_slots
+            widths[p] = w
+            rows = np.repeat(np.arange(n), lens)
+            k = np.arange(rp[-1]) - rp[rows]
+            dst = k * n + rows  # slot-major position of every CSR entry
+            c = np.full(w * n, -1, np.int32)
+            c[dst] = ci
+            cols.append(c)
+            offs.append(at)
+            slot_of.append(dst)
+            at += w * n
+        val_off = np.zeros(self.n_batch + 1, np.int64)
+        sizes = np.asarray([widths[p] * self.pat_rows[p] for p in self.pat_id], np.int64)
+        val_off[1:] = np.cumsum(sizes)
+        vals = np.full(int(val_off[-1]), pad_value, np.float64)
+        for s in range(self.n_batch):
+            p = int(self.pat_id[s])
+            vals[val_off[s] + slot_of[p]] = self.values[self.val_off[s]:self.val_off[s + 1]]
+        return (self.pat_rows.copy(), widths, np.asarray(offs, np.int64),
+                np.concatenate(cols) if cols else np.zeros(0, np.int32), self.pat_id.copy(), vals)
+
 
 def _band_pattern(n: int, kl: int, ku: int):
     rp = np.zeros(n + 1, dtype=np.int32)

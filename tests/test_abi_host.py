@@ -186,19 +186,56 @@ def test_varbatch_validation(L):
     # a system naming a pattern that does not exist
     assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, ci)], [0, 1])) == bs.ERR_PATTERN
     assert create_code(bs.bs_varbatch_create, *varbatch_parts([(rp, ci)], [-1])) == bs.ERR_PATTERN
-    # beyond the kernel's limits: more than 1024 rows, or a row longer than 16
+    # beyond the kernels' limits: more than 1024 rows.  Rows longer than 16
+    # entries are accepted (the streamed placement holds them).
     assert create_code(bs.bs_varbatch_create, *varbatch_parts([tri(1025)], [0])) == bs.ERR_UNSUPPORTED
     n = 20
     dense = (np.arange(n + 1, dtype=np.int32) * n, np.tile(np.arange(n, dtype=np.int32), n))
-    assert create_code(bs.bs_varbatch_create, *varbatch_parts([dense], [0])) == bs.ERR_UNSUPPORTED
     assert L.bs_varbatch_create(-1, 0, None, None, None, None, None, None, None) == bs.ERR_INVALID_ARG
     assert L.bs_varbatch_query(None, None, None, None, None) == bs.ERR_INVALID_ARG
     assert L.bs_varbatch_set_policy(None, 0) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_set_plan(None, None) == bs.ERR_INVALID_ARG
+    assert L.bs_varbatch_get_plan(None, None, None) == bs.ERR_INVALID_ARG
     assert L.bs_varbatch_replay(None, None) == bs.ERR_INVALID_ARG
     assert L.bs_varbatch_destroy(None) == bs.OK
     import torch
     if not torch.cuda.is_available():
         assert create_code(bs.bs_varbatch_create, *good) == bs.ERR_NO_DEVICE
+        assert create_code(bs.bs_varbatch_create, *varbatch_parts([dense], [0])) == bs.ERR_NO_DEVICE
+
+
+def ell_parts(pats, sys_pat):
+    """Concatenate ELL patterns (slot-major [w][n] column arrays)."""
+    rows = [c.shape[1] for c in pats]
+    widths = [c.shape[0] for c in pats]
+    offs = np.cumsum([0] + [c.size for c in pats])[:-1]
+    cols = np.concatenate([c.ravel() for c in pats]).astype(np.int32)
+    return rows, widths, offs, cols, np.asarray(sys_pat, np.int32)
+
+
+def test_varbatch_ell_validation(L):
+    """ELL patterns of the uneven batch: columns in range, once per row, and
+    padding (-1) only after a row's stored entries."""
+    good = np.array([[0, 1, 2], [1, 2, -1], [-1, -1, -1]], np.int32)  # rows {0,1}, {1,2}, {2}
+    after = good.copy(); after[0, 2] = -1; after[1, 2] = 2              # entry after padding
+    assert create_code(bs.bs_varbatch_create_ell, *ell_parts([after], [0])) == bs.ERR_PATTERN
+    out = good.copy(); out[1, 0] = 3
+    assert create_code(bs.bs_varbatch_create_ell, *ell_parts([out], [0])) == bs.ERR_PATTERN
+    dup = good.copy(); dup[1, 0] = 0
+    assert create_code(bs.bs_varbatch_create_ell, *ell_parts([dup], [0])) == bs.ERR_PATTERN
+    neg = good.copy(); neg[0, 1] = -2
+    assert create_code(bs.bs_varbatch_create_ell, *ell_parts([neg], [0])) == bs.ERR_PATTERN
+    assert create_code(bs.bs_varbatch_create_ell, *ell_parts([good], [1])) == bs.ERR_PATTERN
+    rows, widths, offs, cols, sp = ell_parts([good], [0])
+    assert create_code(bs.bs_varbatch_create_ell, rows, [-1], offs, cols, sp) == bs.ERR_INVALID_ARG
+    assert create_code(bs.bs_varbatch_create_ell, [1025], [0], [0], np.zeros(1, np.int32),
+                       [0]) == bs.ERR_UNSUPPORTED
+    assert L.bs_varbatch_create_ell(-1, 0, None, None, None, None, None, None) == bs.ERR_INVALID_ARG
+    import torch
+    if not torch.cuda.is_available():
+        assert create_code(bs.bs_varbatch_create_ell, *ell_parts([good], [0, 0])) == bs.ERR_NO_DEVICE
+    with pytest.raises(ValueError):
+        bs.bs_varbatch_set_plan(0, [0, 0, 0])
 
 
 def test_varbatch_generator_layout():

@@ -220,7 +220,7 @@ def test_policies(shape):
         else:
             c.check(g, bs.BICGSTAB)
     with pytest.raises(bs.BatchSolveError):
-        bs.bs_varbatch_set_policy(c.h.handle, 9)
+        bs.bs_varbatch_set_policy(c.h.handle, 18)
 
 
 def test_mixed_precision_uneven():
@@ -271,13 +271,17 @@ def test_single_row_systems():
         assert np.all(st.cpu().numpy() == bs.CONVERGED)
 
 
-@pytest.mark.parametrize("policy", [0, 4, 8])
+@pytest.mark.parametrize("policy", [0, 4, 8, 13, "split"])
 def test_graph_replay_matches_eager(policy):
-    """The captured graph (counter reset kernel + solve) replayed several times,
-    with eager work and synchronisation between replays, equals the eager solve
-    bit for bit each time."""
+    """The captured graph (counter reset kernel + solve, or the launches of a
+    per-class plan) replayed several times, with eager work and synchronisation
+    between replays, equals the eager solve bit for bit each time."""
     c = VCase(W.uneven_banded(300, 16, 1024, seed=7))
-    bs.bs_varbatch_set_policy(c.h.handle, policy)
+    if policy == "split":
+        bs.bs_varbatch_set_plan(c.h.handle, [0, 4, 8, 9, 7])
+        policy = 0
+    else:
+        bs.bs_varbatch_set_policy(c.h.handle, policy)
     eager = c.gpu(bs.BICGSTAB)
     x, it, rs, st = c.outputs()
     bs.bs_varbatch_capture(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10, 1000,
@@ -295,7 +299,7 @@ def test_graph_replay_matches_eager(policy):
                                 st.cpu().numpy())):
             assert np.array_equal(u, v), f"replay {rep} differs from the eager solve"
     # a policy change drops the graph
-    bs.bs_varbatch_set_policy(c.h.handle, (policy + 1) % 9)
+    bs.bs_varbatch_set_policy(c.h.handle, (policy + 1) % 18)
     with pytest.raises(bs.BatchSolveError):
         bs.bs_varbatch_replay(c.h.handle)
 
@@ -309,11 +313,20 @@ def test_tune_and_cache(tmp_path):
                               cache_path=cache)
     torch.cuda.synchronize()
     say(f"  tune: {rep}")
-    assert rep.startswith("policy=") and "times_ms=" in rep
-    pol = int(rep.split()[0].split("=")[1])
-    assert c.h.query()["policy"] == pol
-    assert len(rep.split()[1].split("=")[1].split(",")) == 9
-    # the outputs are those of an eager solve with the chosen policy
+    assert rep.startswith("policy=") and "times_ms=" in rep and "classes=" in rep
+    tok = rep.split()[0].split("=")[1]
+    pol, codes = bs.bs_varbatch_get_plan(c.h.handle)
+    if tok.startswith("split:"):
+        assert pol == -1 and codes == [int(v) for v in tok[6:].split(",")]
+    else:
+        assert pol == int(tok) and c.h.query()["policy"] == pol
+    times = rep.split()[1].split("=")[1].split(",")
+    assert len(times) == 18 and all(t != "-" for t in times)   # every policy runs BiCGSTAB/Jacobi
+    # one choice per populated size class, each named by shape, walk and placement
+    classes = rep.split()[2].split("=", 1)[1].split(",")
+    populated = {int(np.searchsorted([64, 128, 256, 512, 1024], n)) for n in c.vb.sys_rows}
+    assert {int(e.split(":")[0]) for e in classes} == populated
+    # the outputs are those of an eager solve with the chosen plan
     chosen = c.gpu(bs.BICGSTAB)
     assert np.array_equal(x.cpu().numpy(), chosen[0])
     c.check(chosen, bs.BICGSTAB)
@@ -321,7 +334,8 @@ def test_tune_and_cache(tmp_path):
     rep2 = bs.bs_varbatch_tune(c.h.handle, c.dv, c.db, x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
                                1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO), reps=2,
                                cache_path=cache)
-    assert "cached" in rep2 and rep2.startswith(f"policy={pol}")
+    assert "cached" in rep2 and rep2.startswith(f"policy={tok}")
+    assert bs.bs_varbatch_get_plan(c.h.handle) == (pol, codes)
     # tuning from a nonzero x0 restarts every timed solve from it
     x0 = np.random.default_rng(2).standard_normal(c.vb.b.shape)
     ref = c.gpu(bs.BICGSTAB, x0=x0)
@@ -360,6 +374,127 @@ def test_uneven_full_size_sampled():
     assert worst <= 1e-10
 
 
+# ------------------------------------------------------------------ ELL input, placements, plans
+def ell_handle(vb: W.VarBatch, extra_slots: int = 2):
+    """The batch as ELL patterns (two padding slots beyond the longest row); the
+    padding values are NaN, so a kernel that read one would poison its system."""
+    pr, pw, pco, ca, pid, vals = vb.ell(extra_slots=extra_slots, pad_value=np.nan)
+    return bs.VarBatch(pr, pw, pco, ca, pid, ell=True), dev(vals)
+
+
+def handle_solve(c: VCase, h, values, solver=bs.BICGSTAB, precond=bs.PREC_JACOBI, **opt):
+    x, it, rs, st = c.outputs()
+    bs.bs_varbatch_solve(h.handle, values, c.db, x, solver, precond, 1e-10, 1000, it, rs, st,
+                         bs.make_options(flags=bs.FLAG_X0_ZERO, **opt))
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
+
+
+def same(u, v, what):
+    for a_, b_ in zip(u, v):
+        assert np.array_equal(a_, b_), what
+
+
+@pytest.mark.parametrize("policy", [0, 4, 8, 9, 13, 17])
+def test_ell_input_matches_csr(policy):
+    """An uneven batch given as ELL patterns (BatchEll) is solved with the bits
+    of the same batch given as CSR: the slot-major walk takes a row's entries in
+    the order of its CSR walk, in registers (policies 0..8) and streamed
+    (9..17) alike."""
+    vb = W.uneven_banded(400, 16, 1024, seed=21)
+    c = VCase(vb)
+    bs.bs_varbatch_set_policy(c.h.handle, policy)
+    ref = c.gpu(bs.BICGSTAB)
+    if policy in (0, 9, 17):
+        c.check(ref, bs.BICGSTAB)
+    h, dv = ell_handle(vb)
+    assert h.total_values == int(sum(vb.ell(2)[1][vb.pat_id] * vb.pat_rows[vb.pat_id]))
+    bs.bs_varbatch_set_policy(h.handle, policy)
+    same(ref, handle_solve(c, h, dv), f"ELL input, policy {policy}")
+
+
+@pytest.mark.parametrize("fmt", ["csr", "ell"])
+def test_class_plans(fmt):
+    """Per-class launches.  Within one workgroup shape the four choices
+    (CSR or ELL walk, rows in registers or streamed) add a row's entries in the
+    same order, so every uniform plan of a shape gives the bits of the single
+    launch of that shape; a plan that mixes choices across classes gives, class
+    by class, the bits of the uniform plan of each class's shape."""
+    vb = W.uneven_banded(500, 16, 1024, seed=22)
+    c = VCase(vb)
+    if fmt == "csr":
+        h, dv = c.h, c.dv
+    else:
+        h, dv = ell_handle(vb)
+    by_shape = {}
+    for shape in range(3):
+        bs.bs_varbatch_set_policy(h.handle, 3 * shape)
+        ref = handle_solve(c, h, dv)
+        c.check(ref, bs.BICGSTAB)
+        by_shape[shape] = ref
+        for walk in range(2):
+            for place in range(2):
+                code = shape + 3 * walk + 6 * place
+                bs.bs_varbatch_set_plan(h.handle, [code] * 5)
+                assert bs.bs_varbatch_get_plan(h.handle) == (-1, [code] * 5)
+                assert h.query()["policy"] == -1
+                same(ref, handle_solve(c, h, dv), f"{fmt}: uniform plan {code}")
+    codes = [0, 4, 8, 9, 7]     # class c takes shape codes[c] % 3
+    bs.bs_varbatch_set_plan(h.handle, codes)
+    g = handle_solve(c, h, dv)
+    cls = np.searchsorted([64, 128, 256, 512, 1024], vb.sys_rows)
+    for s in range(vb.n_batch):
+        ref = by_shape[codes[cls[s]] % 3]
+        r0, r1 = vb.row_off[s], vb.row_off[s + 1]
+        assert np.array_equal(g[0][r0:r1], ref[0][r0:r1]), f"system {s}"
+        assert g[1][s] == ref[1][s] and g[2][s] == ref[2][s] and g[3][s] == ref[3][s]
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_varbatch_set_plan(h.handle, [0, 1, 2, 12, 0])
+    assert e.value.code == bs.ERR_INVALID_ARG
+    assert bs.bs_varbatch_get_plan(h.handle) == (-1, codes)
+
+
+def test_mixed_precision_plans():
+    """Mixed-precision BiCGSTAB under a per-class plan that streams some
+    classes: every system converges and meets the FP64 oracle's x."""
+    c = VCase(W.uneven_banded(300, 16, 1024, seed=23))
+    bs.bs_varbatch_set_plan(c.h.handle, [6, 10, 2, 11, 7])
+    g = c.gpu(bs.BICGSTAB, max_iter=2000, precision=bs.MIXED)
+    assert np.all(g[3] == bs.CONVERGED)
+    c.check(g, bs.BICGSTAB, max_iter=2000, itol=10**9)
+
+
+def test_long_rows_streamed():
+    """Rows of 21..41 entries: beyond what the register placement holds.  The
+    handle starts on the streamed placement; register policies are refused at
+    solve time; streamed single launches, per-class plans, ELL input and the
+    caller-owned entry point all meet the oracle (CG on SPD values too)."""
+    vb = W.uneven_banded(160, 16, 400, w_min=21, w_max=41, seed=24)
+    c = VCase(vb)
+    assert c.h.query()["policy"] == 9
+    g = c.gpu(bs.BICGSTAB)
+    c.check(g, bs.BICGSTAB)
+    bs.bs_varbatch_set_policy(c.h.handle, 0)
+    with pytest.raises(bs.BatchSolveError) as e:
+        c.gpu(bs.BICGSTAB)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    bs.bs_varbatch_set_plan(c.h.handle, [9, 10, 11, 9, 9])
+    c.check(c.gpu(bs.BICGSTAB), bs.BICGSTAB)
+    h, dv = ell_handle(vb, extra_slots=1)
+    bs.bs_varbatch_set_policy(h.handle, 16)
+    c.check(handle_solve(c, h, dv), bs.BICGSTAB)
+    arrs = varlen_arrays(vb)
+    ws = torch.empty(bs.bs_varlen_workspace_size(vb.n_batch), dtype=torch.uint8, device="cuda:0")
+    bs.bs_varbatch_set_policy(c.h.handle, 12)
+    same(c.gpu(bs.BICGSTAB), varlen_solve(c, arrs, ws), "caller-owned default (policy 12)")
+    with pytest.raises(bs.BatchSolveError) as e:
+        varlen_solve(c, arrs, ws, varlen_policy=1)
+    assert e.value.code == bs.ERR_UNSUPPORTED
+    vs = W.uneven_banded(120, 16, 300, w_min=25, w_max=25, seed=25)   # symmetric bands
+    cs = VCase(vs, values=symmetric_values(vs, 5))
+    cs.check(cs.gpu(bs.CG), bs.CG)
+
+
 # ------------------------------------------------------------------ caller-owned arrays
 def varlen_arrays(vb: W.VarBatch):
     """The structure of an uneven batch as the device tensors the caller owns."""
@@ -384,7 +519,7 @@ def varlen_solve(c: VCase, arrs, ws, solver=bs.BICGSTAB, precond=bs.PREC_JACOBI,
     return x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
 
 
-@pytest.mark.parametrize("policy", [3, 0, 8])
+@pytest.mark.parametrize("policy", [3, 0, 8, 12, 16])
 def test_varlen_caller_arrays_match_handle(policy):
     """bs_batch_solve_varlen on caller-owned device arrays gives, for the same
     queue policy, the bits of the handle API's solve; both meet the oracle's
