@@ -101,9 +101,13 @@ typedef enum {
                                   element i, CSR windows at min(row start, nnz - slots)
                                   (the pattern's bank-aware layout is not used) */
 
-/* Largest system the fused kernels take: one row per lane, up to 1024 lanes per
- * system, and 2 or 4 rows per lane beyond that; longest row held in registers.
- * GMRES takes one row per lane (up to 1024 rows). */
+/* Largest system the register kernels take: one row per lane, up to 1024
+ * lanes per system, and 2 or 4 rows per lane beyond that; longest row held in
+ * registers.  GMRES takes one row per lane (up to 1024 rows).  Beyond
+ * BS_MAX_ROW_NNZ entries per row, CG and BiCGSTAB (FP64, or BiCGSTAB mixed)
+ * with scalar Jacobi or none take the streamed placement (the spill tier of
+ * Sec. 3.5: the rows stay in global memory and are read at every product) for
+ * systems of up to 1024 rows. */
 #define BS_MAX_ROWS 2048
 #define BS_MAX_ROW_NNZ 64
 #define BS_MAX_RESTART 30
@@ -170,7 +174,8 @@ int bs_pattern_layout(bs_pattern pattern, int32_t *slots, int32_t *layout);
  * Tab. 2): a dense batch stores every entry of every matrix, [n_batch][n][n]
  * row-major, which is the CSR order of this pattern; bs_batch_solve with
  * BS_DENSE runs the BatchCsr kernels on it.  Rows longer than BS_MAX_ROW_NNZ
- * (n_rows > 64) cannot be solved (BS_ERR_UNSUPPORTED at solve time).
+ * (n_rows > 64) take the streamed placement (CG, BiCGSTAB; n_rows <= 1024);
+ * other requests on them fail with BS_ERR_UNSUPPORTED at solve time.
  * Errors: BS_ERR_INVALID_ARG (NULL out, n_rows < 1, n_rows^2 beyond int32),
  * BS_ERR_NO_DEVICE / BS_ERR_HIP on upload. */
 int bs_pattern_create_dense(int32_t n_rows, bs_pattern *out);
@@ -245,9 +250,9 @@ typedef struct {
  *   opts           NULL for defaults
  * Errors: BS_ERR_INVALID_ARG (n_batch < 0, n_rows mismatch, bad enum, tol <= 0 or
  * non-finite, max_iter < 0, bad restart/team, NULL required pointer),
- * BS_ERR_UNSUPPORTED (n_rows > BS_MAX_ROWS, longest row > BS_MAX_ROW_NNZ, or no
- * kernel shape for the request), BS_ERR_HIP (launch failure).  n_batch = 0 is a
- * no-op. */
+ * BS_ERR_UNSUPPORTED (n_rows > BS_MAX_ROWS, or no kernel for the request: a
+ * row longer than BS_MAX_ROW_NNZ outside the streamed placement's reach, see
+ * BS_MAX_ROWS), BS_ERR_HIP (launch failure).  n_batch = 0 is a no-op. */
 int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
                    const double *values, const double *b, double *x, bs_solver solver,
                    bs_precond precond, double tol, int32_t max_iter, int32_t *iters,
@@ -256,7 +261,9 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
 /* The kernel shape bs_batch_solve would use (Sec. 3.6: work-group size from the
  * row count; Sec. 3.5: what is kept on chip).  Pure host function.
  *   team           lanes per system;  rows_per_lane  rows held by each lane
- *   slots          register slots per row (>= longest row)
+ *   slots          register slots per row (>= longest row); 0 for the
+ *                  streamed placement (rows read from memory at every product,
+ *                  workgroups of 512 lanes x 2 rows)
  *   group_size     threads per workgroup; systems_per_group
  *   lds_bytes      dynamic LDS per workgroup
  *   stage_values   1 if CSR values are staged through LDS for coalesced loads */

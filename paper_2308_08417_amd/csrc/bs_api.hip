@@ -35,6 +35,12 @@ thread_local std::string g_last_error = "";
 }  // namespace
 
 namespace bs {
+// The streamed placement of shared-pattern batches (bs_stream_api.hip).
+int stream_plan(int n, bs_solver solver, bs_precond precond, const bs_options* o,
+                bs_plan_info* info);
+int stream_launch(const KArgs& a, const bs_plan_info& info, bs_solver solver, int mixed, int cus,
+                  hipStream_t s);
+
 // Shared by every translation unit of the library (bs_last_error reads it).
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
@@ -528,6 +534,9 @@ int bs_plan(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_nnz, bs_
   const int rc =
       make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block, false, &pl);
   if (rc == BS_OK) *out = pl.info;
+  // no register shape: the streamed placement, where the request allows it
+  if (rc == BS_ERR_UNSUPPORTED && block <= 1)
+    return bs::stream_plan(n_rows, solver, BS_PREC_JACOBI, opts, out);
   return rc;
 }
 
@@ -551,6 +560,7 @@ int bs_plan_precond(bs_format fmt, int32_t n_rows, int32_t nnz, int32_t max_row_
   const int rc = make_plan(fmt, n_rows, nnz, max_row_nnz, max_row_nnz, solver, opts, block,
                            precond == BS_PREC_ILU, &pl);
   if (rc == BS_OK) *out = pl.info;
+  if (rc == BS_ERR_UNSUPPORTED) return bs::stream_plan(n_rows, solver, precond, opts, out);
   return rc;
 }
 
@@ -605,10 +615,16 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   if (n_batch == 0) return BS_OK;
   if (!values || !b || !x || !iters || !resid) return BS_ERR_INVALID_ARG;
   Plan pl;
-  const int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, pattern->width, solver,
-                           opts, block, ilu, &pl);
+  int rc = make_plan(fmt, pattern->n, pattern->nnz, pattern->max_row, pattern->width, solver,
+                     opts, block, ilu, &pl);
+  // no register shape holds the rows: the streamed placement, if it applies
+  bool streamed = false;
+  if (rc == BS_ERR_UNSUPPORTED && !trsv) {
+    rc = bs::stream_plan(pattern->n, solver, precond, opts, &pl.info);
+    streamed = rc == BS_OK;
+  }
   if (rc != BS_OK) return rc;
-  bs::KArgs a;
+  bs::KArgs a{};
   a.n_batch = n_solves;
   a.nrhs = nrhs;
   a.n = pattern->n;
@@ -621,7 +637,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.restart = restart;
   a.stage = pl.info.stage_values;
   a.gmres = solver == BS_GMRES ? 1 : 0;
-  {
+  if (!streamed) {
     const int rows = pl.info.team * pl.info.rows_per_lane;
     const int teams = pl.info.systems_per_group, waves = pl.info.group_size / bs::kWave;
     const int stored = fmt == BS_CSR ? pattern->nnz : pattern->width * pattern->n;
@@ -656,6 +672,15 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.x_alt = opts ? opts->x_alt : nullptr;
   a.alt_used = opts ? opts->alt_used : nullptr;
   if (a.x_alt && (flags & BS_FLAG_X0_ZERO)) return BS_ERR_INVALID_ARG;
+  if (streamed) {
+    a.layout = nullptr;
+    a.block = 0;
+    const int cus = device_cus();
+    if (cus < 1) return BS_ERR_HIP;
+    const int mixed = opts && opts->precision == BS_MIXED;
+    const int src = bs::stream_launch(a, pl.info, solver, mixed, cus, (hipStream_t)stream);
+    return src == BS_OK ? BS_OK : hip_fail(hipGetLastError(), "streamed solver launch");
+  }
   a.layout = (pattern->d_layout && pl.info.team == bs::kWave && pl.info.rows_per_lane == 1 &&
               a.window && pl.k->nz == pattern->layout_nz && !(flags & BS_FLAG_PLAIN_LAYOUT) &&
               a.block <= 1 && !ilu && !trsv)  // these need row i on lane i

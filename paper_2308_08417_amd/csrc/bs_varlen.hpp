@@ -42,8 +42,12 @@ struct VTask {
 //   kSrcSlotIdx  a slot-major index [width][rows] of {column, position} pairs,
 //                column -1 for padding (the ELL walk: lanes of a team read
 //                consecutive entries of one slot).
+//   kSrcShared   one pattern shared by the whole batch (the fixed-size batched
+//                solve, streamed kernels only): the pattern's slot-major columns
+//                (-1 padding), row lengths, row starts and diagonal slots;
+//                position row start + k (CSR values) or k*n + row (ELL values).
 // The indexes are built on the host from validated patterns.
-enum : int { kSrcCsr = 0, kSrcRowIdx = 1, kSrcSlotIdx = 2 };
+enum : int { kSrcCsr = 0, kSrcRowIdx = 1, kSrcSlotIdx = 2, kSrcShared = 3 };
 
 // The batch is described by the pattern arrays (validated on the host before
 // any launch): the kernel reads each row's start and length from its pattern's
@@ -293,16 +297,51 @@ struct VarRowsS {
   int len[R];       // entries of the row (slot walk: the pattern's slot count)
   unsigned tb, zero;
   int n;
-  const int* cols;   // kSrcCsr
+  const int* cols;   // kSrcCsr; kSrcShared: the slot-major columns
   const int2* ix;    // kSrcRowIdx, kSrcSlotIdx
   const double* vals;
+  int ell;           // kSrcShared: values in the ELL layout
   double dval[R], bval[R], xval[R], xalt[R];
 
   // Entry k of row r: column (-1 when absent) and value position.
   __device__ __forceinline__ int2 entry(int r, int k) const {
     if constexpr (SRC == kSrcCsr) return make_int2(cols[start[r] + k], start[r] + k);
     else if constexpr (SRC == kSrcRowIdx) return ix[start[r] + k];
-    else return ix[(int64_t)k * n + row[r]];
+    else if constexpr (SRC == kSrcSlotIdx) return ix[(int64_t)k * n + row[r]];
+    else return make_int2(cols[k * n + row[r]], ell ? k * n + row[r] : start[r] + k);
+  }
+
+  // kSrcShared: this team's system of a shared-pattern batch (solve tm.sys,
+  // matrix tm.sys / nrhs).
+  __device__ void load(const VarTeam<VS>& tm, const KArgs& g, unsigned lds_base) {
+    static_assert(SRC == kSrcShared, "shared-pattern load");
+    n = tm.live ? g.n : 0;
+    tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
+    zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
+    cols = g.slot_col;
+    ix = nullptr;
+    ell = g.fmt;
+    const int64_t per = g.fmt == 0 ? (int64_t)g.nnz : (int64_t)g.width * g.n;
+    vals = g.values + (tm.live ? matrix_of(g, tm.sys) * per : 0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      row[r] = tm.lane + r * tm.T;
+      ok[r] = row[r] < n;
+      vrow[r] = tb + (unsigned)row[r] * 8;
+      const int rr = row[r];
+      start[r] = ok[r] ? g.row_ptr[rr] : 0;
+      len[r] = ok[r] ? g.row_len[rr] : 0;
+      const int ds = ok[r] ? g.diag_slot[rr] : -1;
+      dslot[r] = ds >= 0 ? 0 : -1;
+      dval[r] = ds >= 0 ? vals[ell ? ds * n + rr : start[r] + ds] : 0.0;
+      bval[r] = ok[r] ? g.b[tm.row0 + rr] : 0.0;
+      double xv = 0.0;
+      if ((g.flags & 1) == 0 && ok[r]) xv = g.x[tm.row0 + rr];
+      xval[r] = xv;
+      double xa = 0.0;
+      if (g.x_alt && ok[r]) xa = g.x_alt[tm.row0 + rr];
+      xalt[r] = xa;
+    }
   }
 
   __device__ void load(const VarTeam<VS>& tm, const VArgs& va, unsigned lds_base) {
@@ -445,6 +484,40 @@ void k_varlen(const VArgs va) {
     A.load(tm, a, lds_base);
     if constexpr (SOLVER == 0) cg_system<BJ ? kPkBlock : kPkScalar>(tm, A, a.base);
     else bicgstab_system<MIXED, BJ ? kPkBlock : kPkScalar>(tm, A, a.base);
+  }
+}
+
+// A batch of systems that share one pattern, rows streamed (the register
+// kernels cannot hold rows this long): teams of `team` lanes (a power of two,
+// 64..WG) own R rows per lane; task t is the WG/team consecutive solves from
+// t * WG/team, taken by the workgroups in turn (every task has the same size).
+template <class VS, int SOLVER, bool MIXED>
+__global__ __launch_bounds__(VS::WG)
+__attribute__((amdgpu_waves_per_eu(VarRowsS<VS, kSrcShared>::OCC)))
+void k_shared_stream(const KArgs g, int team) {
+  __shared__ __align__(16) char smem[var_lds_bytes<VS>()];
+  const unsigned lds_base = lds_addr(smem);
+  constexpr unsigned kBuf = var_buf_bytes<VS>();
+  if (threadIdx.x < VS::MAXT * kVecBuffers) {  // zero cells of both buffers
+    const int b = threadIdx.x / VS::MAXT, t = threadIdx.x % VS::MAXT;
+    lds_store<double>(lds_base + b * kBuf + (VS::ROWS + t) * 8, 0.0);
+  }
+  __syncthreads();
+  VarTeam<VS> tm;
+  tm.phase = 0;
+  tm.set_team(team, smem);
+  const int cap = VS::WG / team;
+  const int64_t n_tasks = (g.n_batch + cap - 1) / cap;
+  for (int64_t t = blockIdx.x; t < n_tasks; t += gridDim.x) {
+    const int64_t s = t * cap + tm.tix;
+    tm.live = s < g.n_batch;
+    tm.sys = tm.live ? s : 0;
+    tm.row0 = tm.sys * g.n;
+    VarRowsS<VS, kSrcShared> A;
+    A.load(tm, g, lds_base);
+    if constexpr (SOLVER == 0) cg_system<kPkScalar>(tm, A, g);
+    else bicgstab_system<MIXED, kPkScalar>(tm, A, g);
+    __syncthreads();  // every team is done with its buffers before the next task
   }
 }
 

@@ -796,3 +796,103 @@ def test_multi_rhs_errors():
     assert e.value.code == bs.ERR_INVALID_ARG
     with pytest.raises(ValueError):
         c.gpu(bs.CSR, bs.BICGSTAB, n_rhs=3)      # 10 rows of b: not a multiple of 3
+
+
+# ------------------------------------------------------------------ spill tier
+def long_row_batch(B, seed):
+    """n = 144 chemistry-like Jacobians at fill 0.5: rows of up to ~90 entries,
+    beyond the 64 register slots of the register kernels."""
+    return W.chem_jacobian(B, n=144, fill=0.5, seed=seed)
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.CG])
+def test_streamed_long_rows(fmt, solver):
+    """Rows longer than the register slots take the streamed placement (the
+    rows stay in HBM and are read at every product): BiCGSTAB on the long-row
+    chemistry batch and CG on SPD systems of a symmetrised random pattern
+    (n = 200), CSR and ELL values, against the oracle."""
+    bt = long_row_batch(300, 41) if solver == bs.BICGSTAB else spd_on_pattern(200, 120, 42)
+    assert np.diff(bt.row_ptr).max() > bs.MAX_ROW_NNZ
+    p = bs.bs_plan(fmt, bt.n, int(bt.row_ptr[-1]), int(np.diff(bt.row_ptr).max()), solver)
+    assert p["slots"] == 0
+    c = Case(bt)
+    g = c.gpu(fmt, solver, max_iter=1000)
+    check(c, g, c.oracle(fmt, solver, max_iter=1000), fmt=fmt)
+    # no preconditioner, and a nonzero initial guess
+    x0 = np.random.default_rng(43).standard_normal(bt.b.shape)
+    g = c.gpu(fmt, solver, precond=bs.PREC_NONE, x0=x0, max_iter=1000)
+    check(c, g, c.oracle(fmt, solver, precond=bs.PREC_NONE, x0=x0, max_iter=1000), fmt=fmt)
+
+
+@pytest.mark.parametrize("n", [65, 100, 300])
+@pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB])
+def test_streamed_dense(n, solver):
+    """BatchDense beyond 64 rows: the full pattern's rows are streamed."""
+    bt = dense_batch(n, 48, seed=n + 1, spd=(solver == bs.CG))
+    c = Case(bt)
+    P = bs.Pattern.dense(n)
+    B = bt.n_batch
+    x = torch.zeros((B, n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B, dtype=torch.int32, device="cuda:0")
+    say(f"  streamed dense n={n} solver={solver}")
+    bs.bs_batch_solve(bs.DENSE, P.handle, dev(bt.values), dev(bt.b), x, solver, bs.PREC_JACOBI,
+                      1e-10, 500, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO))
+    torch.cuda.synchronize()
+    g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    check(c, g, c.oracle(bs.CSR, solver))
+
+
+def test_streamed_mixed_multi_rhs_and_alt():
+    """The streamed placement with the options of the register kernels: mixed
+    precision (x within the FP64 bar), several right-hand sides per matrix
+    (bit-identical to the replicated batch), a second initial guess (the
+    smaller residual wins), and the edge cases (b = 0, NaN, max_iter = 0)."""
+    bt = long_row_batch(200, 44)
+    c = Case(bt)
+    outer = torch.zeros(bt.n_batch, dtype=torch.int32, device="cuda:0")
+    g = c.gpu(bs.CSR, bs.BICGSTAB, max_iter=2000, precision=bs.MIXED, outer_iters=outer)
+    assert np.all(g[3] == bs.CONVERGED) and outer.min().item() >= 1
+    check(c, g, c.oracle(bs.CSR, bs.BICGSTAB, max_iter=2000), itol=10**9)
+    # several right-hand sides
+    k = 2
+    B, n = bt.n_batch, bt.n
+    b = 2 * np.random.default_rng(45).random((B * k, n)) - 1
+    x = torch.zeros((B * k, n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B * k, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    bs.bs_batch_solve(bs.CSR, c.P.handle, c.vals, dev(b), x, bs.BICGSTAB, bs.PREC_JACOBI, 1e-10,
+                      1000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k))
+    torch.cuda.synchronize()
+    g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    rep = W.Batch("long_rep", n, bt.row_ptr, bt.col_idx, np.repeat(bt.values, k, axis=0), b,
+                  np.zeros_like(b))
+    cr = Case(rep)
+    for u, v in zip(g, cr.gpu(bs.CSR, bs.BICGSTAB, max_iter=1000)):
+        assert np.array_equal(u, v)
+    check(cr, g, cr.oracle(bs.CSR, bs.BICGSTAB, max_iter=1000))
+    # a second initial guess: x0 = 0 against the oracle's solution
+    xo = c.oracle(bs.CSR, bs.BICGSTAB)[0]
+    alt = dev(xo)
+    used = torch.full((B,), -1, dtype=torch.int32, device="cuda:0")
+    x0 = np.zeros_like(bt.b)
+    g = c.gpu(bs.CSR, bs.BICGSTAB, x0=x0, x_alt=alt, alt_used=used)
+    assert np.all(used.cpu().numpy() == 1) and np.all(g[3] == bs.CONVERGED)
+    assert np.all(g[1] <= 1)
+    # edge cases
+    bb = bt.b.copy()
+    bb[3] = 0.0
+    bb[5, 7] = np.nan
+    g = c.gpu(bs.CSR, bs.BICGSTAB, b=bb)
+    assert g[3][3] == bs.CONVERGED and np.all(g[0][3] == 0.0) and g[3][5] == bs.NONFINITE
+    g = c.gpu(bs.CSR, bs.BICGSTAB, max_iter=0)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 0)
+    # what the streamed placement does not take
+    for solver, prec in ((bs.GMRES, bs.PREC_JACOBI), (bs.BICGSTAB, bs.PREC_BLOCK_JACOBI),
+                         (bs.BICGSTAB, bs.PREC_ILU)):
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(bs.CSR, solver, precond=prec)
+        assert e.value.code == bs.ERR_UNSUPPORTED
