@@ -173,7 +173,7 @@ def dense_leg(args, bs, W, torch, np, dev, tol, max_iter):
                      "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                      "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
     out["algorithmic_bytes_per_launch"] = int(alg)
-    del vals, vals_ell, b, x
+    del vals, b, x
     return out
 
 
@@ -216,7 +216,7 @@ def stiff_leg(args, bs, W, torch, np, dev, tol, max_iter):
                 "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
                 "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                 "max_resid": float(rs.max())}
-    del vals, vals_ell, b, x
+    del vals, b, x
     return out
 
 
@@ -258,7 +258,7 @@ def multi_rhs_leg(args, bs, W, torch, np, dev, tol, max_iter):
            "algorithmic_bytes_per_launch": int(alg),
            "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
            "iters_mean": float(it.mean()), "max_resid": float(rs.max())}
-    del vals, vals_ell, b, x
+    del vals, b, x
     return out
 
 
@@ -317,7 +317,7 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
                 r["outer_mean"] = float(outer.float().mean().item())
             out[f"{sname}_{pname}"] = r
     out["algorithmic_bytes_per_launch"] = int(alg)
-    del vals, vals_ell, b, x
+    del vals, b, x
     return out
 
 
