@@ -386,8 +386,12 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
     its guess against that of x_{t-1} (before any solve), and the time and
     iterations of the plain FP64 solve from x0 = 0, FP64 from x_{t-1}, FP64 and
     mixed precision from the guess (inference included, x_{t-1} the
-    fallback), and of a zero-iteration launch (loads, Jacobi and the residual
-    check only: no start can make a solve cheaper than that)."""
+    fallback), the same with the inference reading a diagonal the caller holds
+    (packed weights: no gather of the diagonal out of the values), and of a
+    zero-iteration launch (loads, Jacobi and the residual check only: no start
+    can make a solve cheaper than that).  The residuals of the guess and of
+    x_{t-1} are the library's own: a zero-iteration solve from each reports its
+    true relative residual."""
     B, n = args.ws_batch, 54
     T, T0 = args.ws_steps, args.ws_train_steps
     t_gen = time.time()
@@ -448,18 +452,34 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
     # held-out steps: time each start on the same inputs
     reps = max(3, args.steps // 4)
     kinds = ("plain_fp64_x0_zero", "fp64_from_prev", "fp64_learned", "mixed_learned",
-             "zero_iterations")
+             "fp64_learned_diag", "mixed_learned_diag", "zero_iterations")
     timing = {k: [] for k in kinds}
     iters = {k: [] for k in kinds if k != "zero_iterations"}
-    alt_frac, infer_ms, held_loss, better, ratio = [], [], [], [], []
+    alt_frac, infer_ms, infer_diag_ms, diag_ms = [], [], [], []
+    held_loss, better, ratio = [], [], []
     ok = True
     x = torch.empty((B, n), dtype=torch.float64, device=dev)
     x_guess = torch.empty_like(x)
     feat1 = torch.empty((B, 3 * n), dtype=torch.float32, device=dev)
     delta1 = torch.empty((B, n), dtype=torch.float32, device=dev)
     grad = torch.empty(m.param_count, dtype=torch.float32, device=dev)
-    import oracle as O  # held-out residual check of the guess (FP64, host)
-    OP = O.Pattern(n, first.row_ptr, first.col_idx)
+    packed = torch.empty(bs.bs_ws_packed_bytes(n), dtype=torch.uint8, device=dev)
+    bs.bs_ws_pack(m.handle, packed)
+    # CSR position of each row's diagonal: the caller's diagonal of A_t, kept
+    # beside the values (in a time integration, a by-product of assembling A_t)
+    rp_h, ci_h = first.row_ptr, first.col_idx
+    dpos = torch.from_numpy(np.asarray(
+        [rp_h[i] + int(np.flatnonzero(ci_h[rp_h[i]:rp_h[i + 1]] == i)[0]) for i in range(n)],
+        dtype=np.int64)).to(dev)
+    diag = torch.empty((B, n), dtype=torch.float64, device=dev)
+
+    def true_resid(x_start, v, bb):
+        # the library's true relative residual of a start: zero iterations
+        x.copy_(x_start)
+        solve(v, bb, x, bs.make_options(), cap=0)
+        torch.cuda.synchronize()
+        return rs.cpu().numpy().copy()
+
     n_eval = 0
     for _ in range(T - T0):
         batch = next(gen)
@@ -472,10 +492,11 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
         bs.bs_ws_infer(m.handle, v, bb, x_prev, x_guess)
         torch.cuda.synchronize()
         held_loss.append(float(loss.item()))
-        rg = O.true_residual(OP, batch.values, batch.b, x_guess.cpu().numpy())
-        rp = O.true_residual(OP, batch.values, batch.b, x_prev.cpu().numpy())
+        rg = true_resid(x_guess, v, bb)
+        rp = true_resid(x_prev, v, bb)
         better.append(float(np.mean(rg < rp)))
         ratio.append(float(np.median(rg / rp)))
+        torch.index_select(v, 1, dpos, out=diag)
         for kind in kinds:
             if kind == "plain_fp64_x0_zero":
                 opts, cap = plain, max_iter
@@ -483,7 +504,7 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
                 opts, cap = plain, 0
             elif kind == "fp64_from_prev":
                 opts, cap = bs.make_options(), max_iter
-            elif kind == "fp64_learned":
+            elif kind in ("fp64_learned", "fp64_learned_diag"):
                 opts, cap = bs.make_options(x_alt=x_prev, alt_used=used), max_iter
             else:
                 opts, cap = bs.make_options(precision=bs.MIXED, x_alt=x_prev, alt_used=used), max_iter
@@ -493,6 +514,8 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
                     x.copy_(x_prev)
                 elif kind in ("fp64_learned", "mixed_learned"):
                     bs.bs_ws_infer(m.handle, v, bb, x_prev, x)
+                elif kind in ("fp64_learned_diag", "mixed_learned_diag"):
+                    bs.bs_ws_infer_packed(packed, n, diag, bb, x_prev, x)
                 solve(v, bb, x, opts, cap=cap)
 
             once()
@@ -522,6 +545,18 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
         e1.record()
         torch.cuda.synchronize()
         infer_ms.append(e0.elapsed_time(e1) / reps)
+        e0.record()
+        for _ in range(reps):
+            bs.bs_ws_infer_packed(packed, n, diag, bb, x_prev, x_guess)
+        e1.record()
+        torch.cuda.synchronize()
+        infer_diag_ms.append(e0.elapsed_time(e1) / reps)
+        e0.record()
+        for _ in range(reps):
+            torch.index_select(v, 1, dpos, out=diag)
+        e1.record()
+        torch.cuda.synchronize()
+        diag_ms.append(e0.elapsed_time(e1) / reps)
         x_prev = xn
         n_eval += 1
     ms = {k: float(np.mean(v_)) for k, v_ in timing.items()}
@@ -532,12 +567,17 @@ def warmstart_leg(args, bs, W, torch, np, dev, tol, max_iter, b_drift=0.0):
             "ratio_mixed_learned_vs_plain": sps["mixed_learned"] / sps["plain_fp64_x0_zero"],
             "ratio_fp64_learned_vs_plain": sps["fp64_learned"] / sps["plain_fp64_x0_zero"],
             "ratio_fp64_learned_vs_fp64_from_prev": sps["fp64_learned"] / sps["fp64_from_prev"],
+            "ratio_mixed_learned_diag_vs_plain":
+                sps["mixed_learned_diag"] / sps["plain_fp64_x0_zero"],
+            "ratio_fp64_learned_diag_vs_plain": sps["fp64_learned_diag"] / sps["plain_fp64_x0_zero"],
             "ratio_ceiling_vs_plain": ms["plain_fp64_x0_zero"] / ms["zero_iterations"],
             "iters_mean": {k: float(np.mean(v_)) for k, v_ in iters.items()},
             "held_out_loss_mean": float(np.mean(held_loss)),
             "guess_beats_prev_frac": float(np.mean(better)),
             "guess_over_prev_residual_median": float(np.median(ratio)),
             "fallback_taken_frac": float(np.mean(alt_frac)), "infer_ms": float(np.mean(infer_ms)),
+            "infer_packed_diag_ms": float(np.mean(infer_diag_ms)),
+            "diag_extract_ms": float(np.mean(diag_ms)),
             "train": {"samples": M, "epochs": args.ws_epochs, "minibatch": mb,
                       "adam_steps": n_steps, "ms": train_ms, "loss_by_epoch": losses},
             "all_converged": ok, "setup_seconds": gen_s}
@@ -734,7 +774,10 @@ def main() -> int:
             progress(f"warm start ({key}): held-out loss {w_['held_out_loss_mean']:.3f}, guess "
                      f"beats x_prev on {100 * w_['guess_beats_prev_frac']:.1f}%, ratio mixed "
                      f"{w_['ratio_mixed_learned_vs_plain']:.3f}, fp64 "
-                     f"{w_['ratio_fp64_learned_vs_plain']:.3f}, ceiling "
+                     f"{w_['ratio_fp64_learned_vs_plain']:.3f} (with the caller's diagonal: "
+                     f"{w_['ratio_mixed_learned_diag_vs_plain']:.3f}, "
+                     f"{w_['ratio_fp64_learned_diag_vs_plain']:.3f}), inference "
+                     f"{w_['infer_ms']:.3f} / {w_['infer_packed_diag_ms']:.3f} ms, ceiling "
                      f"{w_['ratio_ceiling_vs_plain']:.3f}")
 
     if args.calibrate_copy:
