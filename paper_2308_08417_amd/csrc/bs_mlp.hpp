@@ -47,15 +47,24 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t* p) {
 }
 
 // acc[rb][cb] += A[rb*16 .. +16][0..K) * B[0..K)[c0 + cb*16 .. +16]
-// A: LDS row-major, stride lda; Bt: global row-major [column][ldb].
+// A: LDS row-major, stride lda; Bt: global row-major [column][ldb].  The B
+// fragments of step k0 + 32 are loaded while the products of step k0 run (the
+// weights come from L2; waiting for them at every step left the matrix cores
+// idle); the products themselves run in the same order as without it.
 template <int RB, int CB>
 __device__ __forceinline__ void gemm_tile(floatx4 (&acc)[RB][CB], const uint16_t* A, int lda,
                                           const uint16_t* __restrict__ Bt, int ldb, int c0, int K) {
   const int l = threadIdx.x & 63, r16 = l & 15, q = l >> 4;
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 a[RB], b[CB];
+  bf16x8 b[CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) b[cb] = frag(Bt + (size_t)(c0 + cb * 16 + r16) * ldb + k0 + 8 * q);
+  for (int cb = 0; cb < CB; ++cb) b[cb] = frag(Bt + (size_t)(c0 + cb * 16 + r16) * ldb + 8 * q);
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a[RB], bn[CB];
+    if (k0 + 32 < K) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+        bn[cb] = frag(Bt + (size_t)(c0 + cb * 16 + r16) * ldb + k0 + 32 + 8 * q);
+    }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) a[rb] = frag(A + (rb * 16 + r16) * lda + k0 + 8 * q);
 #pragma unroll
@@ -63,6 +72,10 @@ __device__ __forceinline__ void gemm_tile(floatx4 (&acc)[RB][CB], const uint16_t
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+    if (k0 + 32 < K) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) b[cb] = bn[cb];
+    }
   }
 }
 

@@ -52,32 +52,48 @@ __global__ __launch_bounds__(kWG) void k_mlp(const Net net, const Src src, const
   const int n = net.n, F = net.F, Fp = net.Fp, O = net.O, Op = net.Op;
 
   // ---- normalised features of the tile -> BF16
-  for (int idx = tid; idx < kTile * Fp; idx += kWG) {
-    const int row = idx / Fp, f = idx - row * Fp;
-    const int64_t m = m0 + row;
-    float z = 0.f;
-    if (f < F && m < M) {
-      double v;
-      if constexpr (MODE == kInfer) {
-        if (f < n) {
-          if (src.diag) {
-            v = src.diag[m * n + f];
-          } else {
-            const int p = src.diag_pos[f];
-            v = p >= 0 ? src.values[m * src.nnz + p] : 0.0;
-          }
-        } else if (f < 2 * n) {
-          v = src.b[m * n + (f - n)] - src.x_prev[m * n + (f - n)];
-        } else {
-          v = src.x_prev[m * n + (f - 2 * n)];
+  if constexpr (MODE == kInfer) {
+    // wave w builds rows 16w .. 16w+15, lane l features l, l+64, .. (< Fp): the
+    // loads of a feature's 16 rows are issued together, consecutive lanes read
+    // consecutive elements, and the spread's reciprocal is taken once
+    for (int f = l; f < Fp; f += 64) {
+      const bool fok = f < F;
+      const int kind = f < n ? 0 : f < 2 * n ? 1 : 2;
+      const int j = f - kind * n;
+      const double mu = fok ? net.mu_f[f] : 0.0;
+      const double isd = fok ? 1.0 / net.sd_f[f] : 0.0;
+      const int p = (fok && kind == 0 && !src.diag) ? src.diag_pos[f] : -1;
+      double v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t m = m0 + 16 * w + i;
+        double t = 0.0;
+        if (fok && m < M) {
+          if (kind == 0) t = src.diag ? src.diag[m * n + j] : p >= 0 ? src.values[m * src.nnz + p] : 0.0;
+          else if (kind == 1) t = src.b[m * n + j] - src.x_prev[m * n + j];
+          else t = src.x_prev[m * n + j];
         }
-      } else {
-        const int64_t s = src.rows ? (int64_t)src.rows[m] : m;
-        v = (double)src.feat[s * F + f];
+        v[i] = t;
       }
-      z = (float)((v - net.mu_f[f]) / net.sd_f[f]);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const bool ok = fok && m0 + 16 * w + i < M;
+        sZ[(16 * w + i) * ldz + f] = to_bf16(ok ? (float)((v[i] - mu) * isd) : 0.f);
+      }
     }
-    sZ[row * ldz + f] = to_bf16(z);
+  } else {
+    // training and forward: the raw FP32 features of the (listed) samples
+    for (int idx = tid; idx < kTile * Fp; idx += kWG) {
+      const int row = idx / Fp, f = idx - row * Fp;
+      const int64_t m = m0 + row;
+      float z = 0.f;
+      if (f < F && m < M) {
+        const int64_t s = src.rows ? (int64_t)src.rows[m] : m;
+        const double v = (double)src.feat[s * F + f];
+        z = (float)((v - net.mu_f[f]) / net.sd_f[f]);
+      }
+      sZ[row * ldz + f] = to_bf16(z);
+    }
   }
   __syncthreads();
   if constexpr (MODE == kTrain) {  // Z feature-major for the first layer's weight gradient
