@@ -223,10 +223,11 @@ typedef struct {
                            policies of bs_varbatch_set_policy); 0 selects policy 3
                            (workgroups of 512 lanes x 2 rows, largest tasks first;
                            12, the streamed placement, for rows over 16 entries) */
-  int32_t structure_generation; /* bs_batch_solve_varlen: the caller's count of
-                           changes to the batch's structure arrays.  The library
-                           reads and validates those arrays once per (addresses,
-                           batch shape, device, generation); a caller that
+  int32_t structure_generation; /* bs_batch_solve_varlen and bs_batch_solve_dev:
+                           the caller's count of changes to the structure
+                           arrays (batch structure, or the shared pattern).  The
+                           library reads and validates those arrays once per
+                           (addresses, shape, device, generation); a caller that
                            rewrites them in place must change this number */
 } bs_options;
 
@@ -451,6 +452,37 @@ int bs_batch_solve_varlen(int64_t n_batch, const int32_t *sys_rows, const int64_
  * counter, up to n_batch tasks and the queue order).  Pure host function;
  * 0 for n_batch < 0. */
 size_t bs_varlen_workspace_size(int64_t n_batch);
+
+/* A shared pattern held in caller-owned DEVICE memory. */
+typedef struct {
+  const int32_t *row_ptr; /* BS_CSR: [n_rows+1], starting at 0, nondecreasing; else NULL */
+  const int32_t *col_idx; /* BS_CSR: [nnz]; BS_ELL: [ell_width][n_rows] slot-major, -1 padding
+                             after a row's entries; BS_DENSE: unused */
+  int32_t nnz;            /* BS_CSR: stored entries; BS_ELL: ell_width * n_rows */
+  int32_t ell_width;      /* BS_ELL: slots per row; else 0 */
+} bs_pattern_dev;
+
+/* The batched solve with the shared pattern (Sec. 3.1) given as caller-owned
+ * DEVICE arrays instead of a handle.  The first call for a pattern -- its
+ * array addresses, format, n_rows, nnz, ell_width, the current device and
+ * opts->structure_generation -- copies the arrays to the host (one
+ * synchronisation of `stream`), validates them as bs_pattern_create_csr/_ell
+ * do and keeps the derived pattern (8 patterns are kept; the least recently
+ * used is released); later calls launch at once, asynchronously.  A caller
+ * that rewrites the arrays in place passes a new structure_generation.
+ * BS_DENSE reads no arrays (pattern may be NULL): the full pattern of n_rows
+ * rows is built once.  workspace, workspace_bytes: bs_workspace_size bytes
+ * (0: both may be NULL/0).  Everything else as bs_batch_solve.
+ * Errors: BS_ERR_INVALID_ARG (NULL pattern or arrays for CSR/ELL, nnz
+ * inconsistent with ell_width * n_rows, n_rows < 1, n_batch < 0, and those of
+ * bs_batch_solve), BS_ERR_PATTERN (as bs_pattern_create_csr/_ell),
+ * BS_ERR_UNSUPPORTED, BS_ERR_NO_DEVICE, BS_ERR_HIP.  n_batch = 0 is a no-op. */
+int bs_batch_solve_dev(bs_format fmt, int64_t n_batch, int32_t n_rows,
+                       const bs_pattern_dev *pattern, const double *values, const double *b,
+                       double *x, bs_solver solver, bs_precond precond, double tol,
+                       int32_t max_iter, int32_t *iters, double *resid, int32_t *status,
+                       const bs_options *opts, void *workspace, size_t workspace_bytes,
+                       void *stream);
 
 /* Bytes of device workspace bs_batch_solve needs for this request: 0.  The
  * fused fixed-size kernels keep every Krylov vector on chip (registers and

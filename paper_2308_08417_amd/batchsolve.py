@@ -46,6 +46,11 @@ class bs_options(C.Structure):
                 ("structure_generation", C.c_int32)]
 
 
+class bs_pattern_dev(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("nnz", C.c_int32),
+                ("ell_width", C.c_int32)]
+
+
 class bs_plan_info(C.Structure):
     _fields_ = [("team", C.c_int32), ("rows_per_lane", C.c_int32), ("slots", C.c_int32),
                 ("group_size", C.c_int32), ("systems_per_group", C.c_int32),
@@ -103,6 +108,10 @@ def lib() -> C.CDLL:
     L.bs_batch_solve_varlen.restype = C.c_int
     L.bs_varlen_workspace_size.argtypes = [i64]
     L.bs_varlen_workspace_size.restype = sz
+    L.bs_batch_solve_dev.argtypes = [C.c_int, i64, i32, C.POINTER(bs_pattern_dev), vp, vp, vp,
+                                     C.c_int, C.c_int, dbl, i32, vp, vp, vp,
+                                     C.POINTER(bs_options), vp, sz, vp]
+    L.bs_batch_solve_dev.restype = C.c_int
     L.bs_workspace_size.argtypes = [C.c_int, i64, i32, vp, C.c_int, C.POINTER(bs_options)]
     L.bs_workspace_size.restype = sz
     f32p = vp
@@ -371,6 +380,40 @@ def bs_batch_solve(fmt: int, pattern: int, values, b, x, solver: int, precond: i
                                 _ptr(resid), _ptr(status),
                                 C.byref(opts) if opts is not None else None, _stream(stream)),
            "bs_batch_solve")
+
+
+def bs_batch_solve_dev(fmt: int, n_rows: int, row_ptr, col_idx, values, b, x, solver: int,
+                       precond: int, tol: float, max_iter: int, iters, resid, status=None,
+                       opts: Optional[bs_options] = None, ell_width: int = 0, workspace=None,
+                       stream=None) -> None:
+    """``bs_batch_solve`` with the shared pattern as int32 device tensors the
+    caller owns: CSR ``row_ptr`` [n+1] and ``col_idx`` [nnz]; ELL ``col_idx``
+    [ell_width*n] slot-major (``row_ptr`` None); DENSE neither."""
+    if fmt == CSR:
+        for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+            if t is None or str(t.dtype) != _DTYPES["i32"] or not t.is_cuda:
+                raise ValueError(f"{name}: expected an int32 device tensor")
+        _expect(row_ptr, "row_ptr", "i32", n_rows + 1)
+        nnz = int(col_idx.numel())
+    elif fmt == ELL:
+        if col_idx is None or str(col_idx.dtype) != _DTYPES["i32"] or not col_idx.is_cuda:
+            raise ValueError("col_idx: expected an int32 device tensor")
+        _expect(col_idx, "col_idx", "i32", ell_width * n_rows)
+        nnz = ell_width * n_rows
+    else:
+        nnz = n_rows * n_rows
+    n_batch, _ = check_solve_args(fmt, n_rows, nnz, ell_width, values, b, x, iters, resid,
+                                  status, opts)
+    pd = bs_pattern_dev(_ptr(row_ptr) if fmt == CSR else None,
+                        _ptr(col_idx) if fmt != DENSE else None,
+                        nnz if fmt != DENSE else 0, ell_width if fmt == ELL else 0)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().bs_batch_solve_dev(fmt, n_batch, n_rows, C.byref(pd), _ptr(values), _ptr(b),
+                                    _ptr(x), solver, precond, float(tol), int(max_iter),
+                                    _ptr(iters), _ptr(resid), _ptr(status),
+                                    C.byref(opts) if opts is not None else None,
+                                    _ptr(workspace), ws_bytes, _stream(stream)),
+           "bs_batch_solve_dev")
 
 
 @dataclass

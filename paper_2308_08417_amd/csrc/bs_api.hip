@@ -702,3 +702,114 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
 }
 
 }  // extern "C"
+
+namespace {
+// Patterns of bs_batch_solve_dev, keyed by what identifies the caller's arrays.
+struct DevPatKey {
+  int device, fmt, n, nnz, width;
+  const void* rp;
+  const void* ci;
+  int32_t generation;
+  bool operator==(const DevPatKey& o) const {
+    return device == o.device && fmt == o.fmt && n == o.n && nnz == o.nnz && width == o.width &&
+           rp == o.rp && ci == o.ci && generation == o.generation;
+  }
+};
+struct DevPatEntry {
+  DevPatKey key;
+  bs_pattern pattern = nullptr;
+  uint64_t used = 0;
+};
+std::mutex g_dp_mu;
+std::vector<DevPatEntry> g_dp_cache;
+uint64_t g_dp_clock = 0;
+constexpr size_t kDevPatEntries = 8;
+
+int read_ints(std::vector<int32_t>& dst, const int32_t* src, int64_t count, hipStream_t st) {
+  dst.resize((size_t)std::max<int64_t>(count, 0));
+  if (count <= 0) return BS_OK;
+  hipError_t e = hipMemcpyAsync(dst.data(), src, (size_t)count * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? BS_OK : hip_fail(e, "read pattern arrays");
+}
+}  // namespace
+
+extern "C" {
+
+int bs_batch_solve_dev(bs_format fmt, int64_t n_batch, int32_t n_rows,
+                       const bs_pattern_dev* pattern, const double* values, const double* b,
+                       double* x, bs_solver solver, bs_precond precond, double tol,
+                       int32_t max_iter, int32_t* iters, double* resid, int32_t* status,
+                       const bs_options* opts, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+  (void)workspace;  // the solve needs none (bs_workspace_size returns 0)
+  (void)workspace_bytes;
+  if (n_batch < 0 || n_rows < 1) return BS_ERR_INVALID_ARG;
+  if (fmt != BS_CSR && fmt != BS_ELL && fmt != BS_DENSE) return BS_ERR_INVALID_ARG;
+  DevPatKey key{};
+  key.fmt = fmt;
+  key.n = n_rows;
+  key.generation = opts ? opts->structure_generation : 0;
+  if (fmt != BS_DENSE) {
+    if (!pattern) return BS_ERR_INVALID_ARG;
+    if (fmt == BS_CSR && (!pattern->row_ptr || pattern->nnz < 0 || (pattern->nnz > 0 && !pattern->col_idx)))
+      return BS_ERR_INVALID_ARG;
+    if (fmt == BS_ELL && (pattern->ell_width < 0 ||
+                          (int64_t)pattern->nnz != (int64_t)pattern->ell_width * n_rows ||
+                          (pattern->ell_width > 0 && !pattern->col_idx)))
+      return BS_ERR_INVALID_ARG;
+    key.nnz = pattern->nnz;
+    key.width = fmt == BS_ELL ? pattern->ell_width : 0;
+    key.rp = fmt == BS_CSR ? pattern->row_ptr : nullptr;
+    key.ci = pattern->col_idx;
+  }
+  if (n_batch == 0) return BS_OK;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    g_last_error = "no HIP device";
+    return BS_ERR_NO_DEVICE;
+  }
+  hipError_t e = hipGetDevice(&key.device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  const hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_dp_mu);
+  DevPatEntry* ent = nullptr;
+  for (DevPatEntry& d : g_dp_cache)
+    if (d.key == key) ent = &d;
+  if (!ent) {
+    bs_pattern p = nullptr;
+    int rc = BS_OK;
+    if (fmt == BS_DENSE) {
+      rc = bs_pattern_create_dense(n_rows, &p);
+    } else if (fmt == BS_CSR) {
+      std::vector<int32_t> rp, ci;
+      rc = read_ints(rp, pattern->row_ptr, (int64_t)n_rows + 1, st);
+      if (rc == BS_OK) rc = read_ints(ci, pattern->col_idx, pattern->nnz, st);
+      if (rc == BS_OK) rc = bs_pattern_create_csr(n_rows, pattern->nnz, rp.data(), ci.data(), &p);
+    } else {
+      std::vector<int32_t> ci;
+      rc = read_ints(ci, pattern->col_idx, (int64_t)pattern->ell_width * n_rows, st);
+      if (rc == BS_OK) rc = bs_pattern_create_ell(n_rows, pattern->ell_width, ci.data(), &p);
+    }
+    if (rc != BS_OK) return rc;
+    if (g_dp_cache.size() >= kDevPatEntries) {  // drop the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < g_dp_cache.size(); ++i)
+        if (g_dp_cache[i].used < g_dp_cache[lru].used) lru = i;
+      (void)bs_pattern_destroy(g_dp_cache[lru].pattern);
+      g_dp_cache.erase(g_dp_cache.begin() + (long)lru);
+    }
+    DevPatEntry fresh;
+    fresh.key = key;
+    fresh.pattern = p;
+    g_dp_cache.push_back(fresh);
+    ent = &g_dp_cache.back();
+  }
+  ent->used = ++g_dp_clock;
+  return bs_batch_solve(fmt, n_batch, n_rows, ent->pattern, values, b, x, solver, precond, tol,
+                        max_iter, iters, resid, status, opts, stream);
+}
+
+}  // extern "C"

@@ -329,3 +329,20 @@ def test_workspace_sizes(L):
     for B in (0, 1, 100, 100_000):
         want = 256 + (-(-(B + 1) * 16 // 256)) * 256 + (-(-(B + 1) * 4 // 256)) * 256
         assert bs.bs_varlen_workspace_size(B) == want
+
+
+def test_batch_solve_dev_validation(L):
+    """bs_batch_solve_dev refuses a missing or inconsistent device pattern
+    before it touches a device; n_batch = 0 is a no-op."""
+    import ctypes as C
+    pd = bs.bs_pattern_dev(None, None, 0, 0)
+    args = lambda fmt, nb, n, pat: (fmt, nb, n, pat, None, None, None, bs.BICGSTAB, bs.PREC_JACOBI,
+                                    1e-10, 10, None, None, None, None, None, 0, None)
+    assert L.bs_batch_solve_dev(*args(bs.CSR, 4, 8, None)) == bs.ERR_INVALID_ARG
+    assert L.bs_batch_solve_dev(*args(bs.CSR, 4, 8, C.byref(pd))) == bs.ERR_INVALID_ARG
+    bad = bs.bs_pattern_dev(None, 1 << 20, 30, 4)          # ELL: nnz != width * n
+    assert L.bs_batch_solve_dev(*args(bs.ELL, 4, 8, C.byref(bad))) == bs.ERR_INVALID_ARG
+    assert L.bs_batch_solve_dev(*args(bs.CSR, 4, 0, C.byref(pd))) == bs.ERR_INVALID_ARG
+    assert L.bs_batch_solve_dev(*args(bs.DENSE, -1, 8, None)) == bs.ERR_INVALID_ARG
+    assert L.bs_batch_solve_dev(*args(bs.DENSE, 0, 8, None)) == bs.OK
+    assert L.bs_batch_solve_dev(*args(7, 4, 8, None)) == bs.ERR_INVALID_ARG

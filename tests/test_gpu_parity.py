@@ -896,3 +896,59 @@ def test_streamed_mixed_multi_rhs_and_alt():
         with pytest.raises(bs.BatchSolveError) as e:
             c.gpu(bs.CSR, solver, precond=prec)
         assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ pattern in device memory
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL, bs.DENSE])
+def test_batch_solve_dev_matches_handle(fmt):
+    """bs_batch_solve_dev, the shared pattern as caller-owned device arrays,
+    gives the bits of bs_batch_solve on a pattern handle (same kernels), on the
+    first call (arrays read and validated) and on a cached one; a pattern
+    rewritten in place is read again under a new structure_generation."""
+    bt = W.chem_jacobian(300, n=54, seed=51) if fmt != bs.DENSE else dense_batch(40, 200, seed=52)
+    c = Case(bt)
+    n, B = bt.n, bt.n_batch
+    if fmt == bs.DENSE:
+        P = bs.Pattern.dense(n)
+        vals, rp, ci, w = dev(bt.values), None, None, 0
+    elif fmt == bs.CSR:
+        P = c.P
+        vals, rp, ci, w = c.vals, dev(bt.row_ptr.astype(np.int32)), dev(bt.col_idx.astype(np.int32)), 0
+    else:
+        P = c.P
+        vals = c.values(bs.ELL)
+        w = P.ell_width
+        ci = dev(np.asarray(bs.bs_pattern_ell_cols(P.handle), np.int32))
+        rp = None
+
+    def run(gen=0, handle=False):
+        x = torch.zeros((B, n), dtype=torch.float64, device="cuda:0")
+        it = torch.empty(B, dtype=torch.int32, device="cuda:0")
+        rs = torch.empty(B, dtype=torch.float64, device="cuda:0")
+        st = torch.empty(B, dtype=torch.int32, device="cuda:0")
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO, structure_generation=gen)
+        if handle:
+            bs.bs_batch_solve(fmt, P.handle, vals, dev(bt.b), x, bs.BICGSTAB, bs.PREC_JACOBI,
+                              1e-10, 500, it, rs, st, opts)
+        else:
+            bs.bs_batch_solve_dev(fmt, n, rp, ci, vals, dev(bt.b), x, bs.BICGSTAB,
+                                  bs.PREC_JACOBI, 1e-10, 500, it, rs, st, opts, ell_width=w)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy()
+
+    ref = run(handle=True)
+    for g in (run(), run()):
+        for u, v in zip(ref, g):
+            assert np.array_equal(u, v)
+    check(c, ref, c.oracle(bs.CSR if fmt == bs.DENSE else fmt, bs.BICGSTAB), fmt=fmt if fmt != bs.DENSE else bs.CSR)
+    if fmt == bs.CSR:
+        # a column repeated in a row, written in place: refused under a new
+        # generation (the old pattern stays cached under the old one)
+        bad = bt.col_idx.astype(np.int32).copy()
+        bad[1] = bad[0]
+        ci.copy_(dev(bad))
+        with pytest.raises(bs.BatchSolveError) as e:
+            run(gen=1)
+        assert e.value.code == bs.ERR_PATTERN
+        for u, v in zip(ref, run(gen=0)):
+            assert np.array_equal(u, v)
