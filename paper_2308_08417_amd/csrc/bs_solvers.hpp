@@ -931,6 +931,18 @@ __device__ __forceinline__ void cg_system(TM& tm, RW& A, const KArgs& g) {
 // after m steps; the rotations and the triangular solve stay FP64 and x is
 // updated in FP64.  A cycle that does not lower the FP64 residual ends the
 // solve with BREAKDOWN.
+// Where a team keeps the GMRES scalars (Hessenberg column, packed R, the
+// rotations, g, y) and its LDS basis vectors: behind the fixed-size team's
+// vector buffers.  Teams of other kernels provide their own overloads.
+template <class S>
+__device__ __forceinline__ double* gmres_scalar_base(const Team<S>& tm, int rows) {
+  return reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(rows));
+}
+template <class S>
+__device__ __forceinline__ unsigned gmres_basis_base(const Team<S>& tm, int rows) {
+  return lds_addr(tm.lds) + gmres_basis_offset(rows);
+}
+
 template <bool MIXED, int PK, class TM, class RW>
 __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   static_assert(RW::R == 1, "GMRES keeps one row per lane");
@@ -940,7 +952,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   prologue<PK>(tm, A, g, P);
   const int m = g.restart;
   // LDS scalars of this team
-  double* hcol = reinterpret_cast<double*>(tm.lds + kVecBuffers * vec_buf_bytes(RW::ROWS));
+  double* hcol = gmres_scalar_base(tm, RW::ROWS);
   double* Rt = hcol + (M + 2);               // packed by columns: R[i][j] at j(j+1)/2 + i
   double* cs = Rt + M * (M + 1) / 2;
   double* sn = cs + M;
@@ -975,7 +987,7 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
   constexpr int NL = gmres_lds_vectors(RW::WG, MIXED);
   constexpr int NV = M + 1 - NL;
   T V[NV > 0 ? NV : 1];
-  const unsigned vb = lds_addr(tm.lds) + gmres_basis_offset(RW::ROWS) + (unsigned)tm.lane * sizeof(T);
+  const unsigned vb = gmres_basis_base(tm, RW::ROWS) + (unsigned)tm.lane * sizeof(T);
   constexpr unsigned vstride = RW::ROWS * sizeof(T);
 #pragma unroll
   for (int i = 0; i < NV; ++i) V[i] = (T)0;

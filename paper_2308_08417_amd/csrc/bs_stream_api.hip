@@ -3,9 +3,11 @@
 // than 64 entries, or BatchDense beyond 64 rows), CG and BiCGSTAB (FP64 or
 // mixed) with scalar Jacobi or none run with the rows streamed from memory at
 // every product, on workgroups of 512 lanes x 2 rows (systems of up to 1024
-// rows).  Paper Sec. 3.5 keeps on chip what fits and leaves the rest in
-// global memory; here the matrix is what leaves, the Krylov vectors stay in
-// registers and the gathered vector in LDS.
+// rows); GMRES (FP64 or mixed) on workgroups of 1024 lanes x 1 row, one
+// system each, with 16 FP64 (31 FP32) basis vectors in LDS and the rest in
+// registers.  Paper Sec. 3.5 keeps on chip what fits and leaves the rest in
+// global memory; here the matrix is what leaves, the Krylov vectors stay on
+// chip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,18 +18,19 @@
 namespace bs {
 
 namespace {
-using SS = VarShape<512, 2>;
+using SS = VarShape<512, 2>;   // CG, BiCGSTAB
+using SG = VarShape<1024, 1>;  // GMRES: one row per lane
 
-template <int SOLVER, bool MIXED>
+template <class VS, int SOLVER, bool MIXED>
 hipError_t ss_launch(const KArgs& a, int team, unsigned grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_shared_stream<SS, SOLVER, MIXED>), dim3(grid), dim3(SS::WG), 0, s, a, team);
+  hipLaunchKernelGGL((k_shared_stream<VS, SOLVER, MIXED>), dim3(grid), dim3(VS::WG), 0, s, a, team);
   return hipGetLastError();
 }
 
-template <int SOLVER, bool MIXED>
+template <class VS, int SOLVER, bool MIXED>
 hipError_t ss_occupancy(int* blocks) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks, reinterpret_cast<const void*>(&k_shared_stream<SS, SOLVER, MIXED>), SS::WG, 0);
+      blocks, reinterpret_cast<const void*>(&k_shared_stream<VS, SOLVER, MIXED>), VS::WG, 0);
 }
 
 int next_pow2(int v) {
@@ -38,14 +41,27 @@ int next_pow2(int v) {
 }  // namespace
 
 // The streamed plan of a request, or BS_ERR_UNSUPPORTED when it has none
-// (GMRES, block Jacobi, ILU(0), the triangular solves, more than 1024 rows, a
-// forced team or rows per lane, mixed CG).
+// (block Jacobi, ILU(0), the triangular solves, more than 1024 rows, a forced
+// team or rows per lane, mixed CG).
 int stream_plan(int n, bs_solver solver, bs_precond precond, const bs_options* o,
                 bs_plan_info* info) {
-  if (solver != BS_CG && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
+  if (solver != BS_CG && solver != BS_BICGSTAB && solver != BS_GMRES) return BS_ERR_UNSUPPORTED;
   if (precond != BS_PREC_NONE && precond != BS_PREC_JACOBI) return BS_ERR_UNSUPPORTED;
   if (o && (o->team != 0 || o->rows_per_lane != 0)) return BS_ERR_UNSUPPORTED;
-  if (o && o->precision == BS_MIXED && solver != BS_BICGSTAB) return BS_ERR_UNSUPPORTED;
+  if (o && o->precision == BS_MIXED && solver == BS_CG) return BS_ERR_UNSUPPORTED;
+  if (solver == BS_GMRES) {
+    if (n < 1 || n > SG::ROWS) return BS_ERR_UNSUPPORTED;
+    const bool mixed = o && o->precision == BS_MIXED;
+    info->team = SG::WG;
+    info->rows_per_lane = 1;
+    info->slots = 0;
+    info->group_size = SG::WG;
+    info->systems_per_group = 1;
+    info->lds_bytes = var_lds_bytes<SG>() + (mixed ? stream_gmres_lds_bytes<SG, true>()
+                                                   : stream_gmres_lds_bytes<SG, false>());
+    info->stage_values = 0;
+    return BS_OK;
+  }
   if (n < 1 || n > SS::ROWS) return BS_ERR_UNSUPPORTED;
   const int team = std::max(kWave, next_pow2((n + SS::R - 1) / SS::R));
   info->team = team;
@@ -61,16 +77,20 @@ int stream_plan(int n, bs_solver solver, bs_precond precond, const bs_options* o
 int stream_launch(const KArgs& a, const bs_plan_info& info, bs_solver solver, int mixed, int cus,
                   hipStream_t s) {
   int per_cu = 0;
-  hipError_t e = solver == BS_CG ? ss_occupancy<0, false>(&per_cu)
-                 : mixed         ? ss_occupancy<1, true>(&per_cu)
-                                 : ss_occupancy<1, false>(&per_cu);
+  hipError_t e = solver == BS_CG  ? ss_occupancy<SS, 0, false>(&per_cu)
+                 : solver == BS_GMRES ? (mixed ? ss_occupancy<SG, 2, true>(&per_cu)
+                                               : ss_occupancy<SG, 2, false>(&per_cu))
+                 : mixed ? ss_occupancy<SS, 1, true>(&per_cu)
+                         : ss_occupancy<SS, 1, false>(&per_cu);
   if (e != hipSuccess) return BS_ERR_HIP;
   const int cap = info.systems_per_group;
   const int64_t tasks = (a.n_batch + cap - 1) / cap;
   const unsigned grid = (unsigned)std::min<int64_t>(tasks, (int64_t)std::max(per_cu, 1) * cus);
-  e = solver == BS_CG ? ss_launch<0, false>(a, info.team, grid, s)
-      : mixed         ? ss_launch<1, true>(a, info.team, grid, s)
-                      : ss_launch<1, false>(a, info.team, grid, s);
+  e = solver == BS_CG      ? ss_launch<SS, 0, false>(a, info.team, grid, s)
+      : solver == BS_GMRES ? (mixed ? ss_launch<SG, 2, true>(a, info.team, grid, s)
+                                    : ss_launch<SG, 2, false>(a, info.team, grid, s))
+      : mixed              ? ss_launch<SS, 1, true>(a, info.team, grid, s)
+                           : ss_launch<SS, 1, false>(a, info.team, grid, s);
   return e == hipSuccess ? BS_OK : BS_ERR_HIP;
 }
 

@@ -284,6 +284,8 @@ struct VarRows {
 template <class VS, int SRC>
 struct VarRowsS {
   static constexpr int R = VS::R, NZ = 1, ROWS = VS::ROWS;
+  // GMRES (shared-pattern streamed kernel only) runs one team per workgroup
+  static constexpr int WG = VS::WG, TEAM = VS::WG;
   // without the rows in registers two workgroups fit one CU: four waves per
   // SIMD (128 registers a lane) for 512 lanes, two (256) for 256 lanes x 4 rows
   static constexpr int OCC = VS::WG >= 512 ? 4 : 2;
@@ -412,7 +414,7 @@ struct VarRowsS {
   // Entries in groups of four: the index and value loads of a group are
   // issued together, then its LDS gathers, then the FMAs (slot k into
   // accumulator k mod 4, the order of the register placement).
-  template <int BUF, class V, class AT>
+  template <int BUF, bool PIPE = true, class V, class AT>
   __device__ __forceinline__ void spmv(VarTeam<VS>& tm, const AT (&)[R][NZ], const V (&v)[R],
                                        V (&y)[R]) const {
     constexpr unsigned off = BUF * kBuf;
@@ -487,15 +489,34 @@ void k_varlen(const VArgs va) {
   }
 }
 
+// GMRES regions of a runtime-size team (one team per workgroup): behind the
+// buffers and reduction slots.
+template <class VS>
+__device__ __forceinline__ double* gmres_scalar_base(const VarTeam<VS>& tm, int) {
+  return reinterpret_cast<double*>(tm.lds + var_lds_bytes<VS>());
+}
+template <class VS>
+__device__ __forceinline__ unsigned gmres_basis_base(const VarTeam<VS>& tm, int) {
+  return lds_addr(tm.lds) + var_lds_bytes<VS>() + round16(kGmresScalars * 8);
+}
+template <class VS, bool MIXED>
+constexpr int stream_gmres_lds_bytes() {
+  return round16(kGmresScalars * 8) +
+         round16(gmres_lds_vectors(VS::WG, MIXED) * VS::ROWS * (MIXED ? 4 : 8));
+}
+
 // A batch of systems that share one pattern, rows streamed (the register
 // kernels cannot hold rows this long): teams of `team` lanes (a power of two,
 // 64..WG) own R rows per lane; task t is the WG/team consecutive solves from
 // t * WG/team, taken by the workgroups in turn (every task has the same size).
+// SOLVER 2 (GMRES) takes one team of WG lanes per workgroup and one row per
+// lane; its scalars and LDS basis vectors follow the buffers.
 template <class VS, int SOLVER, bool MIXED>
 __global__ __launch_bounds__(VS::WG)
 __attribute__((amdgpu_waves_per_eu(VarRowsS<VS, kSrcShared>::OCC)))
 void k_shared_stream(const KArgs g, int team) {
-  __shared__ __align__(16) char smem[var_lds_bytes<VS>()];
+  __shared__ __align__(16)
+      char smem[var_lds_bytes<VS>() + (SOLVER == 2 ? stream_gmres_lds_bytes<VS, MIXED>() : 0)];
   const unsigned lds_base = lds_addr(smem);
   constexpr unsigned kBuf = var_buf_bytes<VS>();
   if (threadIdx.x < VS::MAXT * kVecBuffers) {  // zero cells of both buffers
@@ -516,7 +537,8 @@ void k_shared_stream(const KArgs g, int team) {
     VarRowsS<VS, kSrcShared> A;
     A.load(tm, g, lds_base);
     if constexpr (SOLVER == 0) cg_system<kPkScalar>(tm, A, g);
-    else bicgstab_system<MIXED, kPkScalar>(tm, A, g);
+    else if constexpr (SOLVER == 1) bicgstab_system<MIXED, kPkScalar>(tm, A, g);
+    else gmres_system<MIXED, kPkScalar>(tm, A, g);
     __syncthreads();  // every team is done with its buffers before the next task
   }
 }

@@ -155,10 +155,13 @@ def test_plan_stage_and_limits(L):
     assert p["slots"] == 0 and p["team"] == 512 and p["systems_per_group"] == 1
     p = bs.bs_plan(bs.CSR, 144, 6135, 80, bs.BICGSTAB, bs.make_options(precision=bs.MIXED))
     assert p["slots"] == 0 and p["team"] == 128
-    # ... which takes neither GMRES, nor block Jacobi / ILU(0), nor mixed CG,
-    # nor a forced shape, nor more than 1024 rows
-    for solver, opts, prec in ((bs.GMRES, None, bs.PREC_JACOBI),
-                               (bs.BICGSTAB, bs.make_options(block_size=4), bs.PREC_BLOCK_JACOBI),
+    # GMRES streams on 1024-lane workgroups, one system each, one row per lane
+    p = bs.bs_plan(bs.CSR, 54, 1042, 65, bs.GMRES)
+    assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 1
+    assert p["systems_per_group"] == 1 and p["lds_bytes"] <= 160 * 1024
+    # ... which takes neither block Jacobi / ILU(0), nor mixed CG, nor a forced
+    # shape, nor more than 1024 rows
+    for solver, opts, prec in ((bs.BICGSTAB, bs.make_options(block_size=4), bs.PREC_BLOCK_JACOBI),
                                (bs.BICGSTAB, None, bs.PREC_ILU),
                                (bs.CG, bs.make_options(precision=bs.MIXED), bs.PREC_JACOBI),
                                (bs.BICGSTAB, bs.make_options(team=128), bs.PREC_JACOBI)):
@@ -275,8 +278,7 @@ def test_varbatch_generator_layout():
 def test_dense_format_host(L):
     """BatchDense (Sec. 3.1 storage list, Tab. 2): n^2 values per matrix and no
     indexes; planned as the full pattern in CSR order; rows over 64 entries
-    cannot be held in registers and take the streamed placement (CG and
-    BiCGSTAB only)."""
+    cannot be held in registers and take the streamed placement."""
     assert bs.bs_matrix_storage(bs.DENSE, 1000, 54, 0, 0) == (1000 * 54 * 54, 0)
     p = bs.bs_plan(bs.DENSE, 54, 0, 0, bs.BICGSTAB)
     assert p["team"] == 64 and p["slots"] == 64
@@ -284,8 +286,10 @@ def test_dense_format_host(L):
     assert p["team"] == 16 and p["slots"] >= 16
     p = bs.bs_plan(bs.DENSE, 65, 0, 0, bs.CG)
     assert p["slots"] == 0 and p["team"] == 64 and p["rows_per_lane"] == 2
+    p = bs.bs_plan(bs.DENSE, 65, 0, 0, bs.GMRES)
+    assert p["slots"] == 0 and p["team"] == 1024
     with pytest.raises(bs.BatchSolveError) as e:
-        bs.bs_plan(bs.DENSE, 65, 0, 0, bs.GMRES)
+        bs.bs_plan(bs.DENSE, 1025, 0, 0, bs.GMRES)
     assert e.value.code == bs.ERR_UNSUPPORTED
     h = C.c_void_p()
     assert L.bs_pattern_create_dense(0, C.byref(h)) == bs.ERR_INVALID_ARG

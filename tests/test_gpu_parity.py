@@ -806,13 +806,13 @@ def long_row_batch(B, seed):
 
 
 @pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
-@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.CG])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.CG, bs.GMRES])
 def test_streamed_long_rows(fmt, solver):
     """Rows longer than the register slots take the streamed placement (the
     rows stay in HBM and are read at every product): BiCGSTAB on the long-row
     chemistry batch and CG on SPD systems of a symmetrised random pattern
     (n = 200), CSR and ELL values, against the oracle."""
-    bt = long_row_batch(300, 41) if solver == bs.BICGSTAB else spd_on_pattern(200, 120, 42)
+    bt = long_row_batch(300, 41) if solver != bs.CG else spd_on_pattern(200, 120, 42)
     assert np.diff(bt.row_ptr).max() > bs.MAX_ROW_NNZ
     p = bs.bs_plan(fmt, bt.n, int(bt.row_ptr[-1]), int(np.diff(bt.row_ptr).max()), solver)
     assert p["slots"] == 0
@@ -826,7 +826,7 @@ def test_streamed_long_rows(fmt, solver):
 
 
 @pytest.mark.parametrize("n", [65, 100, 300])
-@pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB])
+@pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB, bs.GMRES])
 def test_streamed_dense(n, solver):
     """BatchDense beyond 64 rows: the full pattern's rows are streamed."""
     bt = dense_batch(n, 48, seed=n + 1, spd=(solver == bs.CG))
@@ -891,7 +891,7 @@ def test_streamed_mixed_multi_rhs_and_alt():
     g = c.gpu(bs.CSR, bs.BICGSTAB, max_iter=0)
     assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 0)
     # what the streamed placement does not take
-    for solver, prec in ((bs.GMRES, bs.PREC_JACOBI), (bs.BICGSTAB, bs.PREC_BLOCK_JACOBI),
+    for solver, prec in ((bs.GMRES, bs.PREC_BLOCK_JACOBI), (bs.BICGSTAB, bs.PREC_BLOCK_JACOBI),
                          (bs.BICGSTAB, bs.PREC_ILU)):
         with pytest.raises(bs.BatchSolveError) as e:
             c.gpu(bs.CSR, solver, precond=prec)
@@ -952,3 +952,20 @@ def test_batch_solve_dev_matches_handle(fmt):
         assert e.value.code == bs.ERR_PATTERN
         for u, v in zip(ref, run(gen=0)):
             assert np.array_equal(u, v)
+
+
+def test_streamed_gmres_restarts_and_mixed():
+    """GMRES in the streamed placement: restart lengths 30, 8 and 3 (FP64, the
+    oracle's step counts within the bar) and the mixed form (every system
+    converged, x within the FP64 bar), with a nonzero initial guess."""
+    bt = long_row_batch(96, 46)
+    c = Case(bt)
+    for m in (30, 8, 3):
+        g = c.gpu(bs.CSR, bs.GMRES, restart=m, max_iter=1000)
+        check(c, g, c.oracle(bs.CSR, bs.GMRES, restart=m, max_iter=1000))
+    x0 = np.random.default_rng(47).standard_normal(bt.b.shape)
+    g = c.gpu(bs.CSR, bs.GMRES, x0=x0, max_iter=1000)
+    check(c, g, c.oracle(bs.CSR, bs.GMRES, x0=x0, max_iter=1000))
+    g = c.gpu(bs.ELL, bs.GMRES, max_iter=2000, precision=bs.MIXED)
+    assert np.all(g[3] == bs.CONVERGED)
+    check(c, g, c.oracle(bs.ELL, bs.GMRES, max_iter=2000), fmt=bs.ELL, itol=10**9)
