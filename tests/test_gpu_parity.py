@@ -411,6 +411,35 @@ def test_chem_jacobian_full_size_sampled():
         assert np.all(np.abs(g[1][idx] - o[1]) <= ITOL)
 
 
+@pytest.mark.parametrize("solver,prec,fmt", [(bs.BICGSTAB, bs.FP64, bs.CSR),
+                                             (bs.BICGSTAB, bs.FP64, bs.ELL),
+                                             (bs.BICGSTAB, bs.MIXED, bs.CSR),
+                                             (bs.GMRES, bs.FP64, bs.CSR),
+                                             (bs.GMRES, bs.MIXED, bs.CSR)])
+def test_collision_full_size_sampled(solver, prec, fmt):
+    """The nine-point collision batch at its benchmark size (4096 systems,
+    n = 992, one 1024-lane workgroup each), in the launch shape the benchmark
+    times: every system converges with the oracle's true residual of its x
+    <= 1e-10, and a random sample of 48 systems is re-solved by the oracle
+    (FP64: the full bar; mixed: x within the FP64 bar)."""
+    bt = W.collision_stencil(4096)
+    c = Case(bt)
+    g = c.gpu(fmt, solver, max_iter=2000, precision=prec)
+    assert np.all(g[3] == bs.CONVERGED)
+    v = c.oracle_values(fmt)
+    ofmt = O.CSR if fmt == bs.CSR else O.ELL
+    rt = O.true_residual(c.OP, v, bt.b, g[0], fmt=ofmt)
+    assert np.all(rt <= 1e-10)
+    idx = np.sort(np.random.default_rng(1).choice(bt.n_batch, 48, replace=False))
+    o = O.batch_solve(c.OP, v[idx], bt.subset(idx).b, fmt=ofmt,
+                      solver=O.BICGSTAB if solver == bs.BICGSTAB else O.GMRES, tol=1e-10,
+                      max_iter=2000)
+    err = np.linalg.norm(g[0][idx] - o[0], axis=1) / np.linalg.norm(o[0], axis=1)
+    assert np.all(err <= XTOL)
+    if prec == bs.FP64:
+        assert np.all(np.abs(g[1][idx] - o[1]) <= ITOL)
+
+
 # ------------------------------------------------------------------ Tab. 2 completions
 def dense_batch(n, B, seed, spd=False):
     """Dense diagonally dominant systems: off-diagonals U(-1, 1) (symmetric for
