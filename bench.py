@@ -266,9 +266,11 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
     """Larger systems, FP64 against mixed precision: ``args.stencil_batch``
     nonsymmetric 9-point operators on a 32 x 31 grid (n = 992, 8554 stored
     entries), BiCGSTAB and GMRES(30) with scalar Jacobi to 1e-10 from x0 = 0,
-    BatchCsr, and BiCGSTAB with block Jacobi on blocks of 8 rows.  One workgroup of 1024 lanes per system; the values stay in
-    registers, so the solve is bound by the LDS gathers of the SpMV and the
-    team reductions, not by HBM."""
+    BatchCsr, BiCGSTAB with block Jacobi on blocks of 8 rows and with ILU(0),
+    and the lower-triangle BatchTrsv.  One workgroup of 1024 lanes per system;
+    the values stay in registers, so the solve is bound by the LDS gathers of
+    the SpMV and the team reductions (ILU(0) and BatchTrsv: by their
+    level-by-level substitutions, one team barrier per level), not by HBM."""
     t0 = time.time()
     bt = W.collision_stencil(n_batch=args.stencil_batch, nx=32, ny=31, seed=0)
     gen_s = time.time() - t0
@@ -285,8 +287,10 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
            "nnz": nnz, "gen_seconds": gen_s}
     steps = max(5, args.steps // 10)
     alg = B * (8 * nnz + 16 * n + 16) + 4 * (n + 1) + 4 * nnz
-    for sname, solver, pnames in (("bicgstab", bs.BICGSTAB, ("fp64", "mixed", "fp64_block_jacobi8")),
-                                  ("gmres30", bs.GMRES, ("fp64", "mixed"))):
+    for sname, solver, pnames in (("bicgstab", bs.BICGSTAB,
+                                   ("fp64", "mixed", "fp64_block_jacobi8", "fp64_ilu0")),
+                                  ("gmres30", bs.GMRES, ("fp64", "mixed")),
+                                  ("trsv", bs.TRSV_LOWER, ("lower",))):
         for pname in pnames:
             prec = bs.MIXED if pname == "mixed" else bs.FP64
             bsz = 8 if pname.endswith("block_jacobi8") else 0
@@ -294,7 +298,8 @@ def stencil_leg(args, bs, W, torch, np, dev, tol, max_iter):
                                    restart=30 if solver == bs.GMRES else 0,
                                    outer_iters=outer if prec == bs.MIXED else None,
                                    block_size=bsz)
-            pc = bs.PREC_BLOCK_JACOBI if bsz else bs.PREC_JACOBI
+            pc = (bs.PREC_BLOCK_JACOBI if bsz else bs.PREC_ILU if pname.endswith("ilu0")
+                  else bs.PREC_NONE if solver == bs.TRSV_LOWER else bs.PREC_JACOBI)
             a = (bs.CSR, P.handle, vals, b, x, solver, pc, tol, 2000, iters, resid,
                  status, opts)
             for _ in range(max(3, args.warmup // 20)):

@@ -45,8 +45,11 @@ typedef enum { BS_CSR = 0, BS_ELL = 1, BS_DENSE = 2 } bs_format;
  * other triangle are ignored), by substitution: iterations 0, resid the true
  * residual of T, status BS_BREAKDOWN with x = 0 where a diagonal entry is zero
  * or not stored, BS_NONFINITE where x is not finite; the preconditioner, tol
- * and max_iter are validated but unused; systems of at most 64 rows, FP64
- * (BS_ERR_UNSUPPORTED otherwise and on the uneven-batch entry points). */
+ * and max_iter are validated but unused; systems of at most 1024 rows (one
+ * row per lane: one wave up to 64 rows, else a workgroup of the next power of
+ * two lanes, the substitution taken level by level with the levels the
+ * pattern derives at creation), FP64 (BS_ERR_UNSUPPORTED otherwise and on the
+ * uneven-batch entry points). */
 typedef enum {
   BS_CG = 0, BS_BICGSTAB = 1, BS_GMRES = 2, BS_TRSV_LOWER = 3, BS_TRSV_UPPER = 4
 } bs_solver;
@@ -60,8 +63,15 @@ typedef enum {
  * ILU(0) (BatchIlu): the incomplete LU factorization on the pattern of A
  * without pivoting, applied by a forward and a backward substitution, the
  * identity for a system whose factorization meets a zero pivot or gives a
- * non-finite entry.  ILU(0) takes systems of at most 64 rows (one wave each,
- * BS_ERR_UNSUPPORTED beyond), BS_BICGSTAB or BS_GMRES in FP64 (CG needs a
+ * non-finite entry.  ILU(0) takes one row per lane: systems of up to 64 rows
+ * on one wave (dense factors in LDS), up to 1024 rows on a workgroup of the
+ * next power of two lanes (sparse factors in LDS, factorization and both
+ * substitutions taken level by level: a row's level is one more than the
+ * largest among the rows its entries of that triangle name, as the pattern
+ * derives at creation); BS_GMRES with ILU(0) up to 512 rows, where its basis
+ * stays in registers; BS_ERR_UNSUPPORTED beyond, or where the factors do not
+ * fit the 160 KiB of LDS of a workgroup (with rows of at most 16 entries a
+ * 1024-row system fits).  BS_BICGSTAB or BS_GMRES in FP64 only (CG needs a
  * symmetric preconditioner: BS_ERR_UNSUPPORTED), and not the uneven-batch
  * entry points.  Block Jacobi and ILU(0) are FP64 only. */
 typedef enum {

@@ -21,13 +21,17 @@
 struct bs_pattern_s {
   int n = 0, nnz = 0, width = 0, max_row = 0, device = -1;
   std::vector<int> row_ptr, col, slot_col, row_len, diag_slot;
+  // level of each row in the lower and upper triangles' dependency graphs,
+  // packed (lower | upper << 16), and the level counts
+  std::vector<int> lev;
+  int nlev_l = 0, nlev_u = 0;
   // bank-aware layout for one-wave teams of layout_nz register slots (0: none)
   std::vector<int> layout;
   int layout_nz = 0;
-  // one allocation: row_ptr | slot_col | row_len | diag_slot | layout
+  // one allocation: row_ptr | slot_col | row_len | diag_slot | lev | layout
   int* d_base = nullptr;
   int *d_row_ptr = nullptr, *d_slot_col = nullptr, *d_row_len = nullptr, *d_diag = nullptr;
-  int* d_layout = nullptr;
+  int *d_lev = nullptr, *d_layout = nullptr;
 };
 
 namespace {
@@ -90,6 +94,24 @@ void derive(bs_pattern_s& p) {
   for (int s = 0; s < p.width; ++s)
     for (int i = 0; i < n; ++i)
       if (s < p.row_len[i]) p.slot_col[(size_t)s * n + i] = p.col[p.row_ptr[i] + s];
+  // Levels for the level-scheduled sweeps (ILU(0), BatchTrsv): a row's lower
+  // level is one more than the largest lower level among the columns j < i it
+  // holds (0 if none), its upper level likewise over the columns j > i, taken
+  // from the last row up.
+  std::vector<int> lo(n, 0), up(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e)
+      if (p.col[e] < i) lo[i] = std::max(lo[i], lo[p.col[e]] + 1);
+  for (int i = n - 1; i >= 0; --i)
+    for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e)
+      if (p.col[e] > i) up[i] = std::max(up[i], up[p.col[e]] + 1);
+  p.lev.resize(n);
+  p.nlev_l = p.nlev_u = 0;
+  for (int i = 0; i < n; ++i) {
+    p.lev[i] = lo[i] | (up[i] << 16);
+    p.nlev_l = std::max(p.nlev_l, lo[i] + 1);
+    p.nlev_u = std::max(p.nlev_u, up[i] + 1);
+  }
 }
 
 int upload(bs_pattern_s& p) {
@@ -102,16 +124,18 @@ int upload(bs_pattern_s& p) {
   hipError_t e = hipGetDevice(&p.device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const size_t n_rp = p.n + 1, n_sc = std::max<size_t>((size_t)p.width * p.n, 1), n_rl = p.n;
-  const size_t total = n_rp + n_sc + 2 * n_rl + p.layout.size();
+  const size_t total = n_rp + n_sc + 3 * n_rl + p.layout.size();
   e = hipMalloc(&p.d_base, total * sizeof(int));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(pattern)");
   p.d_row_ptr = p.d_base;
   p.d_slot_col = p.d_row_ptr + n_rp;
   p.d_row_len = p.d_slot_col + n_sc;
   p.d_diag = p.d_row_len + n_rl;
-  p.d_layout = p.layout.empty() ? nullptr : p.d_diag + n_rl;
+  p.d_lev = p.d_diag + n_rl;
+  p.d_layout = p.layout.empty() ? nullptr : p.d_lev + n_rl;
   std::vector<int> h(total, -1);
-  std::copy(p.layout.begin(), p.layout.end(), h.begin() + n_rp + n_sc + 2 * n_rl);
+  std::copy(p.lev.begin(), p.lev.end(), h.begin() + n_rp + n_sc + 2 * n_rl);
+  std::copy(p.layout.begin(), p.layout.end(), h.begin() + n_rp + n_sc + 3 * n_rl);
   std::copy(p.row_ptr.begin(), p.row_ptr.end(), h.begin());
   std::copy(p.slot_col.begin(), p.slot_col.end(), h.begin() + n_rp);
   std::copy(p.row_len.begin(), p.row_len.end(), h.begin() + n_rp + n_sc);
@@ -244,20 +268,25 @@ struct Plan {
   const bs::KernelEntry* k;
 };
 
-// block: block-Jacobi block size (0 without block Jacobi); ilu: ILU(0), whose
-// factors need one-wave teams (n <= 64, one system per wave).
+// block: block-Jacobi block size (0 without block Jacobi); ilu: ILU(0).
+// ILU(0) and the triangular solves take one row per lane: a one-wave team up
+// to 64 rows (dense factors), else the smallest power-of-two team of at least
+// n lanes, up to 1024 (sparse factors, level-scheduled sweeps); a forced team
+// must hold n rows and be at least a wave.
 int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver solver,
               const bs_options* o, int block, bool ilu, Plan* out) {
   const int precision = o ? o->precision : BS_FP64;
   const int variant = variant_of(solver, precision, block, ilu);
   if (variant < 0) return BS_ERR_UNSUPPORTED;
   if (n > BS_MAX_ROWS || max_row > BS_MAX_ROW_NNZ) return BS_ERR_UNSUPPORTED;
-  // ILU(0) and the triangular solves keep a dense n-row array per system
-  const bool dense_lds = ilu || solver == BS_TRSV_LOWER || solver == BS_TRSV_UPPER;
-  if (dense_lds && (n > bs::kWave || (o && ((o->team != 0 && o->team != bs::kWave) ||
-                                            o->rows_per_lane > 1))))
+  const bool trsv = solver == BS_TRSV_LOWER || solver == BS_TRSV_UPPER;
+  const bool tri = ilu || trsv;
+  if (tri && (n > 1024 || (o && ((o->team != 0 && (o->team < bs::kWave || o->team < n)) ||
+                                 o->rows_per_lane > 1))))
     return BS_ERR_UNSUPPORTED;
-  const int force_team = dense_lds ? bs::kWave : o ? o->team : 0,
+  int tri_team = bs::kWave;
+  while (tri_team < n) tri_team *= 2;
+  const int force_team = tri ? (o && o->team ? o->team : tri_team) : o ? o->team : 0,
             force_r = o ? o->rows_per_lane : 0;
   if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
   if (force_r != 0 && force_r != 1 && force_r != 2 && force_r != 4) return BS_ERR_INVALID_ARG;
@@ -289,13 +318,13 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const bool mixed = variant == bs::V_GMRES_MIXED;
   const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block) +
-                           (dense_lds ? bs::ilu_bytes(n) : 0)) +
+                           (tri ? bs::tri_region_bytes(team, n, nnz, trsv) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
   // ILU(0) and the triangular solves are bound by their substitution chains,
   // not by loading the values: their LDS goes to more resident waves instead
   // of staging
-  if (waves == 1 && !dense_lds && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
+  if (waves == 1 && !tri && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
     stage = 1;
   out->k = k;
   out->info.team = team;
@@ -647,7 +676,9 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     // vectors
     a.block = block;
     a.bj_offset = a.team_bytes;
-    a.team_bytes += bs::bj_bytes(rows, block) + (ilu || trsv ? bs::ilu_bytes(pattern->n) : 0);
+    a.team_bytes += bs::bj_bytes(rows, block) +
+                    (ilu || trsv ? bs::tri_region_bytes(pl.info.team, pattern->n, pattern->nnz, trsv)
+                                 : 0);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
     a.stage_offset = teams * a.team_bytes + bs::red_lds_bytes(waves);
@@ -660,6 +691,9 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.slot_col = pattern->d_slot_col;
   a.row_len = pattern->d_row_len;
   a.diag_slot = pattern->d_diag;
+  a.lev = pattern->d_lev;
+  a.nlev_l = pattern->nlev_l;
+  a.nlev_u = pattern->nlev_u;
   a.values = values;
   a.b = b;
   a.x = x;

@@ -1,5 +1,5 @@
 // Kernel instances of the FP64 BiCGSTAB solver with the ILU(0)
-// preconditioner for the one-wave shapes.
+// preconditioner (one row per lane).
 #include "bs_registry.hpp"
 #include "bs_solvers.hpp"
 
@@ -22,7 +22,7 @@ int occupancy(unsigned lds) {
 }
 
 #define ENTRY(T, R, NZ) {V_BICGSTAB_ILU, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>>, &occupancy<Shape<T, R, NZ>>},
-const KernelEntry kTable[] = {BS_SHAPES_W64(ENTRY)};
+const KernelEntry kTable[] = {BS_SHAPES_W64(ENTRY) BS_SHAPES_MW512(ENTRY) BS_SHAPES_MW1024(ENTRY)};
 #undef ENTRY
 
 }  // namespace

@@ -1,5 +1,5 @@
-// Kernel instances of the batched triangular solve (lower and upper) for the
-// one-wave shapes.
+// Kernel instances of the batched triangular solve (lower and upper), one row
+// per lane.
 #include "bs_registry.hpp"
 #include "bs_solvers.hpp"
 
@@ -23,8 +23,8 @@ int occupancy(unsigned lds) {
 
 #define ENTRY_L(T, R, NZ) {V_TRSV_LOWER, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>, true>, &occupancy<Shape<T, R, NZ>, true>},
 #define ENTRY_U(T, R, NZ) {V_TRSV_UPPER, T, R, NZ, Shape<T, R, NZ>::WG, &launch<Shape<T, R, NZ>, false>, &occupancy<Shape<T, R, NZ>, false>},
-const KernelEntry kLower[] = {BS_SHAPES_W64(ENTRY_L)};
-const KernelEntry kUpper[] = {BS_SHAPES_W64(ENTRY_U)};
+const KernelEntry kLower[] = {BS_SHAPES_W64(ENTRY_L) BS_SHAPES_MW512(ENTRY_L) BS_SHAPES_MW1024(ENTRY_L)};
+const KernelEntry kUpper[] = {BS_SHAPES_W64(ENTRY_U) BS_SHAPES_MW512(ENTRY_U) BS_SHAPES_MW1024(ENTRY_U)};
 #undef ENTRY_L
 #undef ENTRY_U
 

@@ -8,7 +8,7 @@
 namespace bs {
 
 // *_BJ: the FP64 solvers with the block-Jacobi preconditioner; *_ILU: with
-// ILU(0) (one-wave shapes only); V_TRSV_*: the triangular solves (one-wave).
+// ILU(0); V_TRSV_*: the triangular solves (one row per lane for both).
 enum Variant {
   V_CG = 0, V_BICGSTAB = 1, V_GMRES = 2, V_BICGSTAB_MIXED = 3, V_GMRES_MIXED = 4,
   V_CG_BJ = 5, V_BICGSTAB_BJ = 6, V_GMRES_BJ = 7, V_BICGSTAB_ILU = 8, V_GMRES_ILU = 9,
@@ -54,9 +54,17 @@ KernelTable kernels_trsv_upper();
   X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 64)                     \
   X(512, 1, 4) X(512, 1, 8) X(512, 1, 16) X(512, 1, 32)                                   \
   X(1024, 1, 4) X(1024, 1, 8) X(1024, 1, 12) X(1024, 1, 16)
-// One-wave teams (systems of up to 64 rows, one row per lane): the ILU(0) shapes.
+// ILU(0) and BatchTrsv shapes: one-wave teams (systems of up to 64 rows, dense
+// factors) and multi-wave teams of one row per lane (65..1024 rows, sparse
+// factors, level-scheduled sweeps; GMRES with ILU(0) up to 512 rows, where its
+// basis stays in registers).
 #define BS_SHAPES_W64(X)                                                                  \
   X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 24) X(64, 1, 28) X(64, 1, 32) X(64, 1, 64)
+#define BS_SHAPES_MW512(X)                                                                \
+  X(128, 1, 4) X(128, 1, 8) X(128, 1, 16) X(128, 1, 32) X(128, 1, 64)                     \
+  X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 64)                     \
+  X(512, 1, 4) X(512, 1, 8) X(512, 1, 16) X(512, 1, 32)
+#define BS_SHAPES_MW1024(X) X(1024, 1, 4) X(1024, 1, 8) X(1024, 1, 12) X(1024, 1, 16)
 #define BS_SHAPES_RN(X)                                                                   \
   X(512, 2, 8) X(512, 2, 16) X(1024, 2, 8) X(256, 4, 8) X(512, 4, 8)
 

@@ -51,6 +51,9 @@ struct KArgs {
   int nrhs;                    // right-hand sides per matrix: solve s reads matrix s / nrhs
   int block;                   // block-Jacobi block size (2, 4 or 8), 0 for scalar Jacobi / none
   int bj_offset;               // byte offset of the block-Jacobi or ILU(0) region in a team's LDS
+  const int* lev;              // [n] row levels for the sweeps of multi-wave teams:
+                               // lower-triangle level | upper-triangle level << 16
+  int nlev_l, nlev_u;          // level counts of the lower and upper triangles
 };
 
 // Matrix of solve s (several right-hand sides per matrix: solves s*k..s*k+k-1
@@ -156,6 +159,29 @@ inline int stage_b_bytes(int teams, int n) {
 }
 inline int stage_total_bytes(int teams, int stored, int n, int nz) {
   return round1k(teams * (stage_vals_bytes(teams, stored, nz) + stage_b_bytes(teams, n)));
+}
+
+// ILU(0) and BatchTrsv of a multi-wave team (row i on lane i, one row per
+// lane): byte offsets inside the team's region of the factor values in the
+// pattern's CSR order (f, nnz doubles), the sweep vector (y, n doubles), the
+// pivots (d, n doubles), the columns (c, nnz 16-bit indices), the CSR row
+// pointer (rp, n+1 ints) and each row's packed levels (lv, n ints).  The
+// triangular solves use y alone.
+struct IluMw {
+  int f, y, d, c, rp, lv, bytes;
+};
+__host__ __device__ constexpr IluMw ilu_mw_layout(int n, int nnz, bool trsv) {
+  const int f = 0, y = trsv ? 0 : round16(nnz * 8);
+  const int d = y + round16(n * 8);
+  if (trsv) return IluMw{0, 0, d, d, d, d, d};
+  const int c = d + round16(n * 8), rp = c + round16(nnz * 2), lv = rp + round16((n + 1) * 4);
+  return IluMw{f, y, d, c, rp, lv, lv + round16(n * 4)};
+}
+
+// LDS bytes of a team's ILU(0) or BatchTrsv region: the dense factors of a
+// one-wave team, the sparse layout above for larger teams.
+__host__ __device__ constexpr int tri_region_bytes(int team, int n, int nnz, bool trsv) {
+  return team <= kWave ? ilu_bytes(n) : ilu_mw_layout(n, nnz, trsv).bytes;
 }
 
 }  // namespace bs

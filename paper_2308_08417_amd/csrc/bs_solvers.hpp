@@ -342,6 +342,186 @@ __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
   z[0] = ok ? (T)(acc / dv) : (T)0;
 }
 
+// ------------------------------------------------ ILU(0), multi-wave teams
+// Teams of 2..16 waves (row i on lane i, one row per lane, up to 1024 rows)
+// keep the factors sparse, in the pattern's CSR order, and run the
+// factorization and both sweeps level by level (level scheduling; Saad 2003,
+// Ch. 11): a row's level in the lower triangle is one more than the largest
+// level among the rows its strictly lower entries name (0 if none), and its
+// level in the upper triangle is defined the same way from its strictly upper
+// entries.  Rows of one level depend only on earlier levels, and a team
+// barrier separates consecutive levels.  The levels come with the pattern.
+
+// Column of register slot s (multi-wave teams place x_j at buffer element j);
+// slots without an entry get a column past every row.
+constexpr int kNoCol = 0x7fffffff;
+template <class RW>
+__device__ __forceinline__ int slot_col_of(const RW& A, int s, unsigned b0, unsigned zc) {
+  return A.c[0][s] != zc ? (int)((A.c[0][s] - b0) >> 3) : kNoCol;
+}
+
+// Factorization, the IKJ form of the one-wave code: at its level, row i takes
+// the columns k < i of its pattern in increasing order (a search over its
+// slots, so rows need not be stored sorted), replaces f_ik by f_ik / u_kk and
+// subtracts f_ik u_kj from each of its entries in a column j > k that row k
+// holds.  Row k is final by then (its values, columns and pivot are read from
+// LDS); row i's own values are updated in place in LDS, where no other row of
+// its level reads them.  Each entry so receives its updates in increasing k.
+// The row then stores its pivot.  A zero pivot or a non-finite factor entry
+// anywhere in the system turns M into the identity (row values 0, pivots 1).
+template <class TM, class RW>
+__device__ void ilu_setup_mw(TM& tm, const RW& A, const KArgs& g) {
+  static_assert(RW::R == 1 && RW::TEAM > kWave, "multi-wave ILU(0): one row per lane");
+  constexpr int NZ = RW::NZ;
+  const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
+  const unsigned reg = lds_addr(tm.bj_region(g));
+  const unsigned F = reg + L.f, D = reg + L.d, C = reg + L.c, RP = reg + L.rp, LV = reg + L.lv;
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;
+  const int rp = g.row_ptr[i];
+  const int lv = ok ? g.lev[i] : 0;
+  unsigned fr = F + (g.fmt == 0 ? A.w[0] : rp) * 8;  // F address of register slot 0
+  unsigned cr = C + (g.fmt == 0 ? A.w[0] : rp) * 2;
+  // opaque once per system: the columns and addresses of the slots derive
+  // from pattern registers that hold through the whole kernel, and would
+  // otherwise be computed once per kernel and pin NZ registers each
+  unsigned b0 = A.b0, zc = A.zc;
+  __asm__ volatile("" : "+v"(fr), "+v"(cr), "+v"(b0), "+v"(zc));
+  // publish the row: values, columns, start, levels
+  if (ok) {
+#pragma unroll
+    for (int s = 0; s < NZ; ++s)
+      if (A.real(0, s)) {
+        lds_store<double>(fr + s * 8, A.a[0][s]);
+        lds_store<short>(cr + s * 2, (short)slot_col_of(A, s, b0, zc));
+      }
+    lds_store<int>(RP + i * 4, rp);
+    if (i == g.n - 1) lds_store<int>(RP + g.n * 4, g.nnz);
+    lds_store<int>(LV + i * 4, lv);
+  }
+  tm.sync();
+  const int mine = ok ? (lv & 0xffff) : -1;
+  for (int l = 0; l < g.nlev_l; ++l) {
+    if (mine == l) {
+      int last = -1;
+      for (;;) {
+        int k = kNoCol, sk = 0;
+#pragma unroll
+        for (int s = 0; s < NZ; ++s) {
+          const int cs = slot_col_of(A, s, b0, zc);
+          if (cs < i && cs > last && cs < k) {
+            k = cs;
+            sk = s;
+          }
+        }
+        if (k == kNoCol) break;
+        last = k;
+        const unsigned ak = fr + sk * 8;
+        const double lik = lds_load<double>(ak) / lds_load<double>(D + k * 8);
+        lds_store<double>(ak, lik);
+        const int p1 = lds_load<int>(RP + (k + 1) * 4);
+        for (int p = lds_load<int>(RP + k * 4); p < p1; ++p) {
+          const int j = lds_load<short>(C + p * 2);
+          int sj = -1;
+#pragma unroll
+          for (int s = 0; s < NZ; ++s) sj = slot_col_of(A, s, b0, zc) == j ? s : sj;
+          if (j > k && sj >= 0) {
+            const unsigned aj = fr + sj * 8;
+            lds_store<double>(aj, fma(-lik, lds_load<double>(F + p * 8), lds_load<double>(aj)));
+          }
+        }
+      }
+      lds_store<double>(D + i * 8, A.dslot[0] >= 0 ? lds_load<double>(fr + A.dslot[0] * 8) : 0.0);
+    }
+    tm.sync();
+  }
+  bool bad = false;
+  if (ok) {
+    bad = lds_load<double>(D + i * 8) == 0.0;
+#pragma unroll
+    for (int s = 0; s < NZ; ++s)
+      bad = bad || (A.real(0, s) && !__builtin_isfinite(lds_load<double>(fr + s * 8)));
+  }
+  if (__syncthreads_or(bad)) {
+    if (ok) {
+#pragma unroll
+      for (int s = 0; s < NZ; ++s)
+        if (A.real(0, s)) lds_store<double>(fr + s * 8, 0.0);
+      lds_store<double>(D + i * 8, 1.0);
+    }
+    tm.sync();
+  }
+}
+
+// One row of a sweep: acc -= t_s y(col_s) over the register slots s that
+// hold an entry of the lower (LOWER) or upper triangle, in slot order, with
+// t_s from LDS at tr (FROM_LDS) or the row's register value; y is gathered
+// through the slot's SpMV address plus yo.  Loads go out four at a time.
+template <bool LOWER, bool FROM_LDS, class RW>
+__device__ __forceinline__ double sweep_row(const RW& A, unsigned tr, unsigned yo, double acc) {
+  constexpr int NZ = RW::NZ;
+  // opaque per call: the per-slot addresses and tests are formed here, inside
+  // the level loop, instead of being hoisted out of it into NZ registers each
+  unsigned me = A.vrow[0];
+  __asm__ volatile("" : "+v"(tr), "+v"(yo), "+v"(me));
+#pragma unroll
+  for (int s0 = 0; s0 < NZ; s0 += 4) {
+    double tv[4], yv[4];
+    bool on[4];
+#pragma unroll
+    for (int q = 0; q < 4 && s0 + q < NZ; ++q) {
+      const int s = s0 + q;
+      on[q] = LOWER ? A.c[0][s] < me : (A.c[0][s] > me && A.real(0, s));
+      tv[q] = FROM_LDS ? (on[q] ? lds_load<double>(tr + s * 8) : 0.0) : A.a[0][s];
+      yv[q] = on[q] ? lds_load<double>(A.c[0][s] + yo) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4 && s0 + q < NZ; ++q)
+      if (on[q]) acc = fma(-tv[q], yv[q], acc);
+    __asm__ volatile("" : "+v"(acc)::"memory");
+  }
+  return acc;
+}
+
+// z = (L U)^{-1} v by the two row-oriented sweeps of the oracle's default
+// form, level by level: forward, y_i = v_i - sum_{k<i} l_ik y_k; backward,
+// z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii.  Each row's terms run in its
+// stored order (increasing column for sorted rows); the y and z of other rows
+// are gathered from the team's sweep vector through the row's SpMV addresses.
+// With M the identity the row values are zero and the pivots 1, so z = v.
+template <class T, class TM, class RW>
+__device__ __forceinline__ void ilu_apply_mw(TM& tm, const RW& A, const KArgs& g,
+                                             const T (&v)[RW::R], T (&z)[RW::R]) {
+  const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
+  const unsigned reg = lds_addr(tm.bj_region(g));
+  const unsigned F = reg + L.f, Y = reg + L.y, D = reg + L.d, RP = reg + L.rp, LV = reg + L.lv;
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;
+  const int lv = lds_load<int>(LV + i * 4);
+  const int ll = ok ? (lv & 0xffff) : -1, lu = ok ? (lv >> 16) : -1;
+  const unsigned fr = F + (g.fmt == 0 ? A.w[0] : lds_load<int>(RP + i * 4)) * 8;
+  const unsigned yo = Y - A.b0;  // sweep element of column j: gather address + yo
+  const unsigned me = A.vrow[0];
+  double acc = ok ? (double)v[0] : 0.0;
+  for (int l = 0; l < g.nlev_l; ++l) {
+    if (ll == l) {
+      acc = sweep_row<true, true>(A, fr, yo, acc);
+      lds_store<double>(me + yo, acc);
+    }
+    tm.sync();
+  }
+  const double piv = lds_load<double>(D + i * 8);
+  for (int l = 0; l < g.nlev_u; ++l) {
+    if (lu == l) {
+      acc = sweep_row<false, true>(A, fr, yo, acc);
+      acc = acc / piv;
+      lds_store<double>(me + yo, acc);
+    }
+    tm.sync();
+  }
+  z[0] = ok ? (T)acc : (T)0;
+}
+
 // z = M v: block Jacobi or ILU(0) in their instances, else the diagonal d
 // (scalar Jacobi, or 1 without a preconditioner).
 template <int PK, class T, class TM, class RW>
@@ -350,7 +530,8 @@ __device__ __forceinline__ void precond(TM& tm, const RW& A, const KArgs& g, con
   if constexpr (PK == kPkBlock) {
     bj_apply(tm, A, g, v, z);
   } else if constexpr (PK == kPkIlu) {
-    ilu_apply(tm, A, g, d, v, z);
+    if constexpr (RW::TEAM > kWave) ilu_apply_mw(tm, A, g, v, z);
+    else ilu_apply(tm, A, g, d, v, z);
   } else {
 #pragma unroll
     for (int r = 0; r < RW::R; ++r) z[r] = d[r] * v[r];
@@ -409,7 +590,10 @@ template <int PK, class TM, class RW>
 __device__ __forceinline__ void prologue(TM& tm, RW& A, const KArgs& g, Prologue<RW::R>& P) {
   A.jacobi(g.precond, P.d);
   if constexpr (PK == kPkBlock) bj_setup(tm, A, g);
-  if constexpr (PK == kPkIlu) ilu_setup(tm, A, g, P.d);
+  if constexpr (PK == kPkIlu) {
+    if constexpr (RW::TEAM > kWave) ilu_setup_mw(tm, A, g);
+    else ilu_setup(tm, A, g, P.d);
+  }
   const bool x0zero = (g.flags & 1) != 0;
 #pragma unroll
   for (int r = 0; r < RW::R; ++r) {
@@ -723,8 +907,8 @@ __device__ __forceinline__ void bicgstab_system(TM& tm, RW& A, const KArgs& g) {
 // column k is reached) is read out, and every later row subtracts t_ik x_k.
 // A zero diagonal entry is a breakdown (x = 0); iterations: 0.
 template <bool LOWER, class TM, class RW>
-__device__ __forceinline__ void trsv_system(TM& tm, RW& A, const KArgs& g) {
-  static_assert(RW::R == 1 && RW::TEAM == kWave, "BatchTrsv runs on one-wave teams");
+__device__ __forceinline__ void trsv_system_w64(TM& tm, RW& A, const KArgs& g) {
+  static_assert(RW::R == 1 && RW::TEAM == kWave, "one-wave BatchTrsv");
   const int n = g.n, st = ilu_stride(n), n8 = st - 1;
   double* F = tm.bj_region(g);
   const int lane = tm.lane;
@@ -790,6 +974,61 @@ __device__ __forceinline__ void trsv_system(TM& tm, RW& A, const KArgs& g) {
   }
   wave_lds_fence();
   finish(tm, A, g, b, x, stt, 0, 0, bn, 0.0, false);
+}
+
+// BatchTrsv for multi-wave teams (row i on lane i, up to 1024 rows): the
+// row-oriented substitution of the oracle, level by level (the levels of the
+// ILU(0) sweeps): x_i = (b_i - sum_j t_ij x_j) / t_ii over the row's strictly
+// lower (upper) entries in stored order, the other rows' x gathered from the
+// team's sweep vector.  Entries outside the triangle are zeroed in registers
+// as in the one-wave form; a zero diagonal entry anywhere is a breakdown.
+template <bool LOWER, class TM, class RW>
+__device__ __forceinline__ void trsv_system_mw(TM& tm, RW& A, const KArgs& g) {
+  static_assert(RW::R == 1 && RW::TEAM > kWave, "multi-wave BatchTrsv: one row per lane");
+  constexpr int NZ = RW::NZ;
+  const unsigned Y = lds_addr(tm.bj_region(g)) + ilu_mw_layout(g.n, g.nnz, true).y;
+  const bool ok = A.ok[0];
+  const int i = ok ? A.row[0] : 0;
+  const int lv = g.lev[i];
+  const int mine = ok ? (LOWER ? (lv & 0xffff) : (lv >> 16)) : -1;
+  const unsigned me = A.vrow[0], yo = Y - A.b0;
+#pragma unroll
+  for (int s = 0; s < NZ; ++s) {
+    const bool keep = ok && A.real(0, s) && (LOWER ? A.c[0][s] <= me : A.c[0][s] >= me);
+    A.a[0][s] = keep ? A.a[0][s] : 0.0;
+  }
+  double b[1] = {A.bval[0]}, x[1] = {A.xval[0]}, q[1] = {b[0] * b[0]};
+  tm.sum(q);
+  const double bn = sqrt(q[0]);
+  const double tii = ok ? A.dval[0] : 1.0;
+  const bool zero_diag = __syncthreads_or(ok && tii == 0.0) != 0;
+  int stt = tm.live ? ST_CONVERGED : ST_IDLE;
+  if (tm.live && !finite(bn)) {
+    stt = ST_NONFINITE;
+  } else if (bn == 0.0 || zero_diag) {
+    if (tm.live && bn != 0.0) stt = ST_BREAKDOWN;
+    x[0] = 0.0;
+  } else {
+    double acc = ok ? b[0] : 0.0;
+    const int levels = LOWER ? g.nlev_l : g.nlev_u;
+    for (int l = 0; l < levels; ++l) {
+      if (mine == l) {
+        acc = sweep_row<LOWER, false>(A, 0u, yo, acc) / tii;
+        lds_store<double>(me + yo, acc);
+      }
+      tm.sync();
+    }
+    x[0] = ok ? acc : 0.0;
+    const bool nf = __syncthreads_or(ok && !finite(x[0])) != 0;
+    if (tm.live && nf) stt = ST_NONFINITE;
+  }
+  finish(tm, A, g, b, x, stt, 0, 0, bn, 0.0, false);
+}
+
+template <bool LOWER, class TM, class RW>
+__device__ __forceinline__ void trsv_system(TM& tm, RW& A, const KArgs& g) {
+  if constexpr (RW::TEAM > kWave) trsv_system_mw<LOWER>(tm, A, g);
+  else trsv_system_w64<LOWER>(tm, A, g);
 }
 
 // =================================================================== CG

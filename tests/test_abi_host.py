@@ -185,6 +185,34 @@ def test_plan_stage_and_limits(L):
         bs.bs_plan(bs.CSR, 54, 1042, 28, bs.CG, bs.make_options(precision=bs.MIXED))
 
 
+def test_plan_ilu_trsv_teams(L):
+    """ILU(0) and BatchTrsv take one row per lane: one wave up to 64 rows, else
+    the smallest power-of-two team of at least n lanes (sparse factors in LDS);
+    GMRES with ILU(0) stops at 512 rows, where its basis leaves registers."""
+    p = bs.bs_plan_precond(bs.CSR, 54, 1042, 28, bs.BICGSTAB, bs.PREC_ILU)
+    assert p["team"] == 64 and p["slots"] == 28 and p["stage_values"] == 0
+    p = bs.bs_plan_precond(bs.CSR, 992, 8554, 9, bs.BICGSTAB, bs.PREC_ILU)
+    assert p["team"] == 1024 and p["rows_per_lane"] == 1 and p["slots"] == 12
+    assert 10 * 8554 + 24 * 992 <= p["lds_bytes"] <= 160 * 1024
+    p = bs.bs_plan_precond(bs.ELL, 192, 1600, 9, bs.GMRES, bs.PREC_ILU)
+    assert p["team"] == 256 and p["group_size"] == 256 and p["systems_per_group"] == 1
+    p = bs.bs_plan(bs.CSR, 300, 900, 3, bs.TRSV_LOWER)
+    assert p["team"] == 512 and p["slots"] == 4
+    p = bs.bs_plan(bs.CSR, 1000, 2998, 3, bs.TRSV_UPPER)
+    assert p["team"] == 1024
+    p = bs.bs_plan_precond(bs.CSR, 100, 300, 3, bs.BICGSTAB, bs.PREC_ILU, bs.make_options(team=512))
+    assert p["team"] == 512
+    for args in ((bs.CSR, 992, 8554, 9, bs.GMRES, bs.PREC_ILU, None),
+                 (bs.CSR, 1025, 3073, 3, bs.BICGSTAB, bs.PREC_ILU, None),
+                 (bs.CSR, 1025, 3073, 3, bs.TRSV_LOWER, bs.PREC_NONE, None),
+                 (bs.CSR, 200, 600, 3, bs.BICGSTAB, bs.PREC_ILU, bs.make_options(team=128)),
+                 (bs.CSR, 40, 120, 3, bs.BICGSTAB, bs.PREC_ILU, bs.make_options(team=32)),
+                 (bs.CSR, 200, 600, 3, bs.BICGSTAB, bs.PREC_ILU, bs.make_options(rows_per_lane=2))):
+        with pytest.raises(bs.BatchSolveError) as e:
+            bs.bs_plan_precond(*args)
+        assert e.value.code == bs.ERR_UNSUPPORTED, args
+
+
 def varbatch_parts(pats, sys_pat):
     """Concatenate CSR patterns the way bs_varbatch_create takes them."""
     rows, rpo, cpo, rpa, ca = [], [], [], [], []

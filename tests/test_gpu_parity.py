@@ -674,8 +674,8 @@ def test_ilu(gen, solver):
 
 def test_ilu_zero_pivot_and_errors():
     """A zero first pivot makes M the identity on both sides (the solve runs
-    unpreconditioned); CG, mixed precision and systems of more than 64 rows are
-    refused."""
+    unpreconditioned); CG, mixed precision and systems of more than 1024 rows
+    are refused."""
     bt = W.tridiag_stencil(n_batch=200, n=40, seed=18)
     v = bt.values.copy()
     v[:, 0] = 0.0        # a_00 = 0 in every system (still invertible)
@@ -690,7 +690,7 @@ def test_ilu_zero_pivot_and_errors():
         with pytest.raises(bs.BatchSolveError) as e:
             c.gpu(bs.CSR, solver, precond=bs.PREC_ILU, **opt)
         assert e.value.code == bs.ERR_UNSUPPORTED
-    big = Case(W.tridiag_stencil(n_batch=4, n=65))
+    big = Case(W.tridiag_stencil(n_batch=4, n=1025))
     with pytest.raises(bs.BatchSolveError) as e:
         big.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_ILU)
     assert e.value.code == bs.ERR_UNSUPPORTED
@@ -720,7 +720,7 @@ def test_trsv(gen, lower):
 def test_trsv_breakdown_and_errors():
     """A zero diagonal entry: BREAKDOWN with x = 0 and residual 1 (relative), as
     in the oracle; b = 0 gives x = 0; mixed precision and systems of more than
-    64 rows are refused."""
+    1024 rows are refused."""
     bt = W.chem_jacobian(200, n=30, seed=24)
     d5 = int(np.flatnonzero(bt.col_idx[bt.row_ptr[5]:bt.row_ptr[6]] == 5)[0]) + int(bt.row_ptr[5])
     v = bt.values.copy()
@@ -739,10 +739,147 @@ def test_trsv_breakdown_and_errors():
     with pytest.raises(bs.BatchSolveError) as e:
         c.gpu(bs.CSR, bs.TRSV_LOWER, precond=bs.PREC_NONE, precision=bs.MIXED)
     assert e.value.code == bs.ERR_UNSUPPORTED
-    big = Case(W.tridiag_stencil(n_batch=4, n=65))
+    big = Case(W.tridiag_stencil(n_batch=4, n=1025))
     with pytest.raises(bs.BatchSolveError) as e:
         big.gpu(bs.CSR, bs.TRSV_UPPER, precond=bs.PREC_NONE)
     assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+# ILU(0) and BatchTrsv beyond one wave: sparse factors, level-scheduled sweeps.
+def shuffled_rows(bt: W.Batch, seed: int) -> W.Batch:
+    """The same systems with the entries of every row stored in a random order."""
+    rng = np.random.default_rng(seed)
+    col = bt.col_idx.copy()
+    vals = bt.values.copy()
+    for i in range(bt.n):
+        a, e = int(bt.row_ptr[i]), int(bt.row_ptr[i + 1])
+        p = a + rng.permutation(e - a)
+        col[a:e] = bt.col_idx[p]
+        vals[:, a:e] = bt.values[:, p]
+    return W.Batch(bt.name + "_shuffled", bt.n, bt.row_ptr, col, vals, bt.b, bt.x0)
+
+
+MW_GENS = {
+    # 9-point stencil, 16 x 12 grid: n = 192 (256-lane teams), 31 lower levels
+    "stencil192": lambda: W.collision_stencil(48, nx=16, ny=12, seed=41),
+    # the 992-row stencil of the collision batch (1024-lane teams)
+    "stencil992": lambda: W.collision_stencil(16, nx=32, ny=31, seed=42),
+    # chemistry-like, n = 144 (rows of up to ~30 entries, condition numbers up
+    # to 4e4) and n = 300 (rows of up to 14).  At gamma = 1e-3 one of the
+    # n = 300 systems (condition 6e4) ends its first GMRES cycle 3.5 % under
+    # the tolerance in the oracle: rounding alone can then leave the true
+    # residual above it, and the restarted cycle gains 0.1 % per step there, so
+    # that batch is taken at gamma = 3e-4 (every system ends >= 30 % under).
+    "chem144": lambda: W.chem_jacobian(96, n=144, fill=0.12, gamma=1e-3, seed=43),
+    "chem300": lambda: W.chem_jacobian(64, n=300, fill=0.02, gamma=3e-4, seed=44),
+    # rows stored out of column order
+    "shuffled": lambda: shuffled_rows(W.collision_stencil(48, nx=16, ny=12, seed=45), 46),
+    # tridiagonal, n = 700: ILU(0) is the exact LU (one step), 700 levels
+    "tridiag700": lambda: W.tridiag_stencil(n_batch=40, n=700, seed=47),
+}
+
+
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+@pytest.mark.parametrize("gen", list(MW_GENS))
+def test_ilu_multiwave(gen, solver):
+    """ILU(0) on teams of 2..16 waves against the oracle, CSR and ELL.  The GPU
+    takes the oracle's row-oriented sweeps in the same order (FMAs aside), so
+    the plain parity bar applies.  GMRES with ILU(0) holds its basis in
+    registers, up to 512 rows; beyond that it is refused."""
+    bt = MW_GENS[gen]()
+    c = Case(bt)
+    if solver == bs.GMRES and bt.n > 512:
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(bs.CSR, solver, precond=bs.PREC_ILU)
+        assert e.value.code == bs.ERR_UNSUPPORTED
+        return
+    for fmt in (bs.CSR, bs.ELL):
+        g = c.gpu(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
+        o = c.oracle(fmt, solver, precond=bs.PREC_ILU, max_iter=1000)
+        assert np.all(o[3] == O.CONVERGED)
+        j = c.oracle(fmt, solver, precond=bs.PREC_JACOBI, max_iter=1000)
+        say(f"  iterations: ILU(0) gpu {g[1].mean():.1f} oracle {o[1].mean():.1f}, "
+            f"Jacobi {j[1].mean():.1f}")
+        check(c, g, o, fmt=fmt)
+        if gen == "tridiag700":
+            assert np.all(g[1] == 1)
+        else:
+            assert o[1].mean() < j[1].mean()
+
+
+def test_ilu_multiwave_zero_pivot_and_start():
+    """Multi-wave ILU(0): a zero first pivot makes M the identity on both sides
+    (on the GPU bit for bit the unpreconditioned solve); a non-zero initial
+    guess; the absolute criterion."""
+    bt = W.collision_stencil(32, nx=16, ny=12, seed=48)
+    c = Case(bt)
+    v = bt.values.copy()
+    v[:, 0] = 0.0
+    for solver in (bs.BICGSTAB, bs.GMRES):
+        g = c.gpu(bs.CSR, solver, precond=bs.PREC_ILU, values=dev(v), max_iter=1000)
+        gn = c.gpu(bs.CSR, solver, precond=bs.PREC_NONE, values=dev(v), max_iter=1000)
+        for a, e in zip(g, gn):
+            assert np.array_equal(a, e)
+        o = c.oracle(bs.CSR, solver, precond=bs.PREC_ILU, values=v, max_iter=1000)
+        u = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE, values=v, max_iter=1000)
+        assert np.array_equal(o[1], u[1])
+        # Unpreconditioned BiCGSTAB on these systems is sensitive to rounding:
+        # b changed by one unit in the last place moves the oracle's own count
+        # by up to 4.  The bar is 2 plus that measured spread, per system.
+        spread = np.zeros(bt.n_batch, dtype=np.int64)
+        for f in (1 + 2.0**-52, 1 - 2.0**-53):
+            p = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE, values=v, b=bt.b * f, max_iter=1000)
+            spread = np.maximum(spread, np.abs(p[1].astype(np.int64) - o[1]))
+        say(f"  one-ulp spread of the oracle: max {spread.max()}")
+        check(c, g, o, values=v, itol=ITOL + spread)
+    x0 = np.random.default_rng(49).random((bt.n_batch, bt.n))
+    g = c.gpu(bs.CSR, bs.BICGSTAB, precond=bs.PREC_ILU, x0=x0)
+    o = c.oracle(bs.CSR, bs.BICGSTAB, precond=bs.PREC_ILU, x0=x0)
+    check(c, g, o)
+    b = bt.b * 512.0
+    tol = 1e-8
+    g = c.gpu(bs.CSR, bs.GMRES, precond=bs.PREC_ILU, tol=tol, b=b, extra_flags=bs.FLAG_ABS_TOL)
+    o = O.batch_solve(c.OP, bt.values, b, fmt=O.CSR, solver=O.GMRES, tol=tol,
+                      precond=bs.PREC_ILU, max_iter=500, absolute=True)
+    check_absolute(c, g, o, tol, b)
+
+
+@pytest.mark.parametrize("lower", [True, False])
+@pytest.mark.parametrize("gen", ["stencil192", "stencil992", "chem300", "shuffled"])
+def test_trsv_multiwave(gen, lower):
+    """BatchTrsv on teams of 2..16 waves against the oracle, CSR and ELL."""
+    bt = MW_GENS[gen]()
+    c = Case(bt)
+    solver = bs.TRSV_LOWER if lower else bs.TRSV_UPPER
+    for fmt in (bs.CSR, bs.ELL):
+        xg, ig, rg, sg = c.gpu(fmt, solver, precond=bs.PREC_NONE)
+        xo, io, ro, so = c.oracle(fmt, solver, precond=bs.PREC_NONE)
+        assert np.all(so == O.CONVERGED) and np.array_equal(sg, so)
+        assert np.all(ig == 0)
+        nx = np.linalg.norm(xo, axis=1)
+        assert np.all(np.linalg.norm(xg - xo, axis=1) <= 1e-12 * nx)
+        assert np.all(rg <= 1e-13) and np.all(np.abs(rg - ro) <= 1e-13)
+
+
+def test_trsv_multiwave_breakdown():
+    """Multi-wave BatchTrsv: a zero diagonal entry is a breakdown (x = 0), b = 0
+    gives x = 0, as in the oracle."""
+    bt = W.collision_stencil(12, nx=16, ny=12, seed=50)
+    c = Case(bt)
+    r = 100
+    dpos = int(np.flatnonzero(bt.col_idx[bt.row_ptr[r]:bt.row_ptr[r + 1]] == r)[0]) + int(bt.row_ptr[r])
+    v = bt.values.copy()
+    v[3, dpos] = 0.0
+    b = bt.b.copy()
+    b[5] = 0.0
+    for solver in (bs.TRSV_LOWER, bs.TRSV_UPPER):
+        xg, ig, rg, sg = c.gpu(bs.CSR, solver, precond=bs.PREC_NONE, values=dev(v), b=b)
+        xo, io, ro, so = c.oracle(bs.CSR, solver, precond=bs.PREC_NONE, values=v, b=b)
+        assert np.array_equal(sg, so)
+        assert sg[3] == bs.BREAKDOWN and np.all(xg[3] == 0) and rg[3] == 1.0
+        assert sg[5] == bs.CONVERGED and np.all(xg[5] == 0) and rg[5] == 0.0
+        ok = sg == bs.CONVERGED
+        assert np.allclose(xg[ok], xo[ok], rtol=1e-12, atol=1e-14)
 
 
 @pytest.mark.parametrize("precond,bsz", [(bs.PREC_BLOCK_JACOBI, 4), (bs.PREC_ILU, 0)])

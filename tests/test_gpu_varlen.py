@@ -144,8 +144,9 @@ def test_absolute_criterion_uneven():
 
 
 def test_ilu_uneven_refused():
-    """ILU(0) keeps dense factors of one-wave systems, and the uneven path takes
-    one right-hand side per system: both are refused."""
+    """ILU(0) runs on the fixed-size path only (its factors and levels belong to
+    one shared pattern), and the uneven path takes one right-hand side per
+    system: both are refused."""
     c = VCase(W.uneven_banded(20, 16, 200, seed=19))
     with pytest.raises(bs.BatchSolveError) as e:
         c.gpu(bs.BICGSTAB, precond=bs.PREC_ILU)
