@@ -25,13 +25,20 @@ struct bs_pattern_s {
   // packed (lower | upper << 16), and the level counts
   std::vector<int> lev;
   int nlev_l = 0, nlev_u = 0;
+  // ILU(0) schedule of the multi-wave factorization: per row (ilu_ptr), its
+  // steps in increasing pivot column k, a header word
+  // 1 << 31 | pos(k,k) << 15 | pos(i,k) followed by one word
+  // pos(k,j) << 16 | pos(i,j) per entry (i,j), j > k, that row k holds
+  // (positions in the pattern's CSR order)
+  std::vector<int> ilu_ptr, ilu_ops;
   // bank-aware layout for one-wave teams of layout_nz register slots (0: none)
   std::vector<int> layout;
   int layout_nz = 0;
-  // one allocation: row_ptr | slot_col | row_len | diag_slot | lev | layout
+  // one allocation: row_ptr | slot_col | row_len | diag_slot | lev | ilu_ptr |
+  // ilu_ops | layout
   int* d_base = nullptr;
   int *d_row_ptr = nullptr, *d_slot_col = nullptr, *d_row_len = nullptr, *d_diag = nullptr;
-  int *d_lev = nullptr, *d_layout = nullptr;
+  int *d_lev = nullptr, *d_ilu_ptr = nullptr, *d_ilu_ops = nullptr, *d_layout = nullptr;
 };
 
 namespace {
@@ -112,6 +119,36 @@ void derive(bs_pattern_s& p) {
     p.nlev_l = std::max(p.nlev_l, lo[i] + 1);
     p.nlev_u = std::max(p.nlev_u, up[i] + 1);
   }
+  // The ILU(0) schedule (symbolic factorization, the IKJ form): for row i and
+  // each column k < i it holds, in increasing k, divide (i,k) by the pivot
+  // (k,k), then update each (i,j), j > k, for which row k holds (k,j).  A row
+  // without a stored diagonal divides by its own entry instead: the system
+  // then has a zero pivot and its preconditioner is the identity anyway.  Only
+  // patterns whose positions fit 15 bits get one (the multi-wave shapes hold
+  // at most 16384 entries).
+  p.ilu_ptr.assign(n + 1, 0);
+  p.ilu_ops.clear();
+  if (p.nnz < (1 << 15)) {
+    std::vector<int> where(n, -1), ks;
+    for (int i = 0; i < n; ++i) {
+      for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e) where[p.col[e]] = e;
+      ks.clear();
+      for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e)
+        if (p.col[e] < i) ks.push_back(p.col[e]);
+      std::sort(ks.begin(), ks.end());
+      for (int k : ks) {
+        const int pik = where[k];
+        const int pkk = p.diag_slot[k] >= 0 ? p.row_ptr[k] + p.diag_slot[k] : pik;
+        p.ilu_ops.push_back((int)(0x80000000u | ((unsigned)pkk << 15) | (unsigned)pik));
+        for (int e = p.row_ptr[k]; e < p.row_ptr[k + 1]; ++e) {
+          const int j = p.col[e];
+          if (j > k && where[j] >= 0) p.ilu_ops.push_back((e << 16) | where[j]);
+        }
+      }
+      for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e) where[p.col[e]] = -1;
+      p.ilu_ptr[i + 1] = (int)p.ilu_ops.size();
+    }
+  }
 }
 
 int upload(bs_pattern_s& p) {
@@ -124,7 +161,8 @@ int upload(bs_pattern_s& p) {
   hipError_t e = hipGetDevice(&p.device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const size_t n_rp = p.n + 1, n_sc = std::max<size_t>((size_t)p.width * p.n, 1), n_rl = p.n;
-  const size_t total = n_rp + n_sc + 3 * n_rl + p.layout.size();
+  const size_t n_ops = std::max<size_t>(p.ilu_ops.size(), 1);
+  const size_t total = n_rp + n_sc + 3 * n_rl + n_rp + n_ops + p.layout.size();
   e = hipMalloc(&p.d_base, total * sizeof(int));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(pattern)");
   p.d_row_ptr = p.d_base;
@@ -132,10 +170,15 @@ int upload(bs_pattern_s& p) {
   p.d_row_len = p.d_slot_col + n_sc;
   p.d_diag = p.d_row_len + n_rl;
   p.d_lev = p.d_diag + n_rl;
-  p.d_layout = p.layout.empty() ? nullptr : p.d_lev + n_rl;
+  p.d_ilu_ptr = p.d_lev + n_rl;
+  p.d_ilu_ops = p.d_ilu_ptr + n_rp;
+  p.d_layout = p.layout.empty() ? nullptr : p.d_ilu_ops + n_ops;
   std::vector<int> h(total, -1);
-  std::copy(p.lev.begin(), p.lev.end(), h.begin() + n_rp + n_sc + 2 * n_rl);
-  std::copy(p.layout.begin(), p.layout.end(), h.begin() + n_rp + n_sc + 3 * n_rl);
+  const size_t o_lev = n_rp + n_sc + 2 * n_rl, o_ptr = o_lev + n_rl, o_ops = o_ptr + n_rp;
+  std::copy(p.lev.begin(), p.lev.end(), h.begin() + o_lev);
+  std::copy(p.ilu_ptr.begin(), p.ilu_ptr.end(), h.begin() + o_ptr);
+  std::copy(p.ilu_ops.begin(), p.ilu_ops.end(), h.begin() + o_ops);
+  std::copy(p.layout.begin(), p.layout.end(), h.begin() + o_ops + n_ops);
   std::copy(p.row_ptr.begin(), p.row_ptr.end(), h.begin());
   std::copy(p.slot_col.begin(), p.slot_col.end(), h.begin() + n_rp);
   std::copy(p.row_len.begin(), p.row_len.end(), h.begin() + n_rp + n_sc);
@@ -286,6 +329,8 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
     return BS_ERR_UNSUPPORTED;
   int tri_team = bs::kWave;
   while (tri_team < n) tri_team *= 2;
+  // the multi-wave ILU(0) schedule addresses entries with 15 bits
+  if (ilu && n > bs::kWave && nnz >= (1 << 15)) return BS_ERR_UNSUPPORTED;
   const int force_team = tri ? (o && o->team ? o->team : tri_team) : o ? o->team : 0,
             force_r = o ? o->rows_per_lane : 0;
   if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
@@ -694,6 +739,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.lev = pattern->d_lev;
   a.nlev_l = pattern->nlev_l;
   a.nlev_u = pattern->nlev_u;
+  a.ilu_ptr = pattern->d_ilu_ptr;
+  a.ilu_ops = pattern->d_ilu_ops;
   a.values = values;
   a.b = b;
   a.x = x;

@@ -54,6 +54,8 @@ struct KArgs {
   const int* lev;              // [n] row levels for the sweeps of multi-wave teams:
                                // lower-triangle level | upper-triangle level << 16
   int nlev_l, nlev_u;          // level counts of the lower and upper triangles
+  const int* ilu_ptr;          // [n+1] start of each row's ILU(0) steps in ilu_ops
+  const int* ilu_ops;          // ILU(0) schedule (header and update words, see the pattern)
 };
 
 // Matrix of solve s (several right-hand sides per matrix: solves s*k..s*k+k-1
@@ -164,18 +166,16 @@ inline int stage_total_bytes(int teams, int stored, int n, int nz) {
 // ILU(0) and BatchTrsv of a multi-wave team (row i on lane i, one row per
 // lane): byte offsets inside the team's region of the factor values in the
 // pattern's CSR order (f, nnz doubles), the sweep vector (y, n doubles), the
-// pivots (d, n doubles), the columns (c, nnz 16-bit indices), the CSR row
-// pointer (rp, n+1 ints) and each row's packed levels (lv, n ints).  The
+// pivots (d, n doubles) and each row's packed levels (lv, n ints).  The
 // triangular solves use y alone.
 struct IluMw {
-  int f, y, d, c, rp, lv, bytes;
+  int f, y, d, lv, bytes;
 };
 __host__ __device__ constexpr IluMw ilu_mw_layout(int n, int nnz, bool trsv) {
-  const int f = 0, y = trsv ? 0 : round16(nnz * 8);
-  const int d = y + round16(n * 8);
-  if (trsv) return IluMw{0, 0, d, d, d, d, d};
-  const int c = d + round16(n * 8), rp = c + round16(nnz * 2), lv = rp + round16((n + 1) * 4);
-  return IluMw{f, y, d, c, rp, lv, lv + round16(n * 4)};
+  const int y = trsv ? 0 : round16(nnz * 8), d = y + round16(n * 8);
+  if (trsv) return IluMw{0, 0, d, d, d};
+  const int lv = d + round16(n * 8);
+  return IluMw{0, y, d, lv, lv + round16(n * 4)};
 }
 
 // LDS bytes of a team's ILU(0) or BatchTrsv region: the dense factors of a

@@ -352,82 +352,73 @@ __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
 // entries.  Rows of one level depend only on earlier levels, and a team
 // barrier separates consecutive levels.  The levels come with the pattern.
 
-// Column of register slot s (multi-wave teams place x_j at buffer element j);
-// slots without an entry get a column past every row.
-constexpr int kNoCol = 0x7fffffff;
-template <class RW>
-__device__ __forceinline__ int slot_col_of(const RW& A, int s, unsigned b0, unsigned zc) {
-  return A.c[0][s] != zc ? (int)((A.c[0][s] - b0) >> 3) : kNoCol;
-}
-
-// Factorization, the IKJ form of the one-wave code: at its level, row i takes
-// the columns k < i of its pattern in increasing order (a search over its
-// slots, so rows need not be stored sorted), replaces f_ik by f_ik / u_kk and
-// subtracts f_ik u_kj from each of its entries in a column j > k that row k
-// holds.  Row k is final by then (its values, columns and pivot are read from
-// LDS); row i's own values are updated in place in LDS, where no other row of
-// its level reads them.  Each entry so receives its updates in increasing k.
-// The row then stores its pivot.  A zero pivot or a non-finite factor entry
+// Factorization, the IKJ form of the one-wave code, from the pattern's
+// symbolic schedule: at its level, row i takes the columns k < i it holds in
+// increasing order, replaces f_ik by f_ik / u_kk and subtracts f_ik u_kj from
+// each of its entries (i,j), j > k, that row k holds; the schedule lists, per
+// row, one header word per k (the positions of (i,k) and (k,k)) followed by
+// one word per update (the positions of (i,j) and (k,j)).  Row k is final by
+// then; row i's values are updated in place in LDS, where no other row of its
+// level reads them.  Each entry so receives its updates in increasing k.  The
+// row then stores its pivot.  A zero pivot or a non-finite factor entry
 // anywhere in the system turns M into the identity (row values 0, pivots 1).
+constexpr int kIluOpsReg = 16;  // schedule words a lane takes per pass
+
 template <class TM, class RW>
 __device__ void ilu_setup_mw(TM& tm, const RW& A, const KArgs& g) {
   static_assert(RW::R == 1 && RW::TEAM > kWave, "multi-wave ILU(0): one row per lane");
   constexpr int NZ = RW::NZ;
   const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
   const unsigned reg = lds_addr(tm.bj_region(g));
-  const unsigned F = reg + L.f, D = reg + L.d, C = reg + L.c, RP = reg + L.rp, LV = reg + L.lv;
+  const unsigned F = reg + L.f, D = reg + L.d, LV = reg + L.lv;
   const bool ok = A.ok[0];
-  const int i = ok ? A.row[0] : 0;
-  const int rp = g.row_ptr[i];
+  int i = ok ? A.row[0] : 0;
+  // opaque once per system: everything below derives from the pattern, and
+  // would otherwise be loaded or formed once per kernel and pin registers
+  // through the whole solve
+  __asm__ volatile("" : "+v"(i));
   const int lv = ok ? g.lev[i] : 0;
-  unsigned fr = F + (g.fmt == 0 ? A.w[0] : rp) * 8;  // F address of register slot 0
-  unsigned cr = C + (g.fmt == 0 ? A.w[0] : rp) * 2;
-  // opaque once per system: the columns and addresses of the slots derive
-  // from pattern registers that hold through the whole kernel, and would
-  // otherwise be computed once per kernel and pin NZ registers each
-  unsigned b0 = A.b0, zc = A.zc;
-  __asm__ volatile("" : "+v"(fr), "+v"(cr), "+v"(b0), "+v"(zc));
-  // publish the row: values, columns, start, levels
+  const int fb = g.fmt == 0 ? A.w[0] : g.row_ptr[i];  // CSR position of register slot 0
+  const unsigned fr = F + fb * 8;
+  const int o0 = g.ilu_ptr[i], o1 = ok ? g.ilu_ptr[i + 1] : o0;
+  // Shapes of up to 16 slots load the row's first words before the level loop
+  // (all lanes at once); wider ones, short of registers, load them when the
+  // row's level comes.
+  constexpr bool kEarly = NZ <= 16;
+  unsigned w[kIluOpsReg];
+#pragma unroll
+  for (int q = 0; q < kIluOpsReg; ++q)
+    w[q] = kEarly && o0 + q < o1 ? (unsigned)g.ilu_ops[o0 + q] : 0u;
+  // publish the row's values and its levels
   if (ok) {
 #pragma unroll
     for (int s = 0; s < NZ; ++s)
-      if (A.real(0, s)) {
-        lds_store<double>(fr + s * 8, A.a[0][s]);
-        lds_store<short>(cr + s * 2, (short)slot_col_of(A, s, b0, zc));
-      }
-    lds_store<int>(RP + i * 4, rp);
-    if (i == g.n - 1) lds_store<int>(RP + g.n * 4, g.nnz);
+      if (A.real(0, s)) lds_store<double>(fr + s * 8, A.a[0][s]);
     lds_store<int>(LV + i * 4, lv);
   }
   tm.sync();
   const int mine = ok ? (lv & 0xffff) : -1;
   for (int l = 0; l < g.nlev_l; ++l) {
     if (mine == l) {
-      int last = -1;
-      for (;;) {
-        int k = kNoCol, sk = 0;
+      double lik = 0.0;
+      for (int b0 = o0; b0 < o1; b0 += kIluOpsReg) {
+        if (kEarly && b0 != o0) {
 #pragma unroll
-        for (int s = 0; s < NZ; ++s) {
-          const int cs = slot_col_of(A, s, b0, zc);
-          if (cs < i && cs > last && cs < k) {
-            k = cs;
-            sk = s;
-          }
+          for (int q = 0; q < kIluOpsReg; ++q)
+            w[q] = b0 + q < o1 ? (unsigned)g.ilu_ops[b0 + q] : 0u;
         }
-        if (k == kNoCol) break;
-        last = k;
-        const unsigned ak = fr + sk * 8;
-        const double lik = lds_load<double>(ak) / lds_load<double>(D + k * 8);
-        lds_store<double>(ak, lik);
-        const int p1 = lds_load<int>(RP + (k + 1) * 4);
-        for (int p = lds_load<int>(RP + k * 4); p < p1; ++p) {
-          const int j = lds_load<short>(C + p * 2);
-          int sj = -1;
 #pragma unroll
-          for (int s = 0; s < NZ; ++s) sj = slot_col_of(A, s, b0, zc) == j ? s : sj;
-          if (j > k && sj >= 0) {
-            const unsigned aj = fr + sj * 8;
-            lds_store<double>(aj, fma(-lik, lds_load<double>(F + p * 8), lds_load<double>(aj)));
+        for (int q = 0; q < kIluOpsReg; ++q) {
+          if (b0 + q < o1) {
+            const unsigned op = kEarly ? w[q] : (unsigned)g.ilu_ops[b0 + q];
+            if (op >> 31) {
+              const unsigned aik = F + (op & 0x7fffu) * 8, akk = F + ((op >> 15) & 0x7fffu) * 8;
+              lik = lds_load<double>(aik) / lds_load<double>(akk);
+              lds_store<double>(aik, lik);
+            } else {
+              const unsigned aij = F + (op & 0xffffu) * 8, akj = F + (op >> 16) * 8;
+              lds_store<double>(aij, fma(-lik, lds_load<double>(akj), lds_load<double>(aij)));
+            }
           }
         }
       }
@@ -494,12 +485,12 @@ __device__ __forceinline__ void ilu_apply_mw(TM& tm, const RW& A, const KArgs& g
                                              const T (&v)[RW::R], T (&z)[RW::R]) {
   const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
   const unsigned reg = lds_addr(tm.bj_region(g));
-  const unsigned F = reg + L.f, Y = reg + L.y, D = reg + L.d, RP = reg + L.rp, LV = reg + L.lv;
+  const unsigned F = reg + L.f, Y = reg + L.y, D = reg + L.d, LV = reg + L.lv;
   const bool ok = A.ok[0];
   const int i = ok ? A.row[0] : 0;
   const int lv = lds_load<int>(LV + i * 4);
   const int ll = ok ? (lv & 0xffff) : -1, lu = ok ? (lv >> 16) : -1;
-  const unsigned fr = F + (g.fmt == 0 ? A.w[0] : lds_load<int>(RP + i * 4)) * 8;
+  const unsigned fr = F + (g.fmt == 0 ? A.w[0] : g.row_ptr[i]) * 8;
   const unsigned yo = Y - A.b0;  // sweep element of column j: gather address + yo
   const unsigned me = A.vrow[0];
   double acc = ok ? (double)v[0] : 0.0;

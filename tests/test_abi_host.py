@@ -193,7 +193,8 @@ def test_plan_ilu_trsv_teams(L):
     assert p["team"] == 64 and p["slots"] == 28 and p["stage_values"] == 0
     p = bs.bs_plan_precond(bs.CSR, 992, 8554, 9, bs.BICGSTAB, bs.PREC_ILU)
     assert p["team"] == 1024 and p["rows_per_lane"] == 1 and p["slots"] == 12
-    assert 10 * 8554 + 24 * 992 <= p["lds_bytes"] <= 160 * 1024
+    # sparse factors (8 B per entry) with the sweep vector, pivots and levels
+    assert 8 * 8554 + 20 * 992 <= p["lds_bytes"] <= 160 * 1024
     p = bs.bs_plan_precond(bs.ELL, 192, 1600, 9, bs.GMRES, bs.PREC_ILU)
     assert p["team"] == 256 and p["group_size"] == 256 and p["systems_per_group"] == 1
     p = bs.bs_plan(bs.CSR, 300, 900, 3, bs.TRSV_LOWER)
