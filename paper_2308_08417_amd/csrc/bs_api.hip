@@ -31,14 +31,22 @@ struct bs_pattern_s {
   // pos(k,j) << 16 | pos(i,j) per entry (i,j), j > k, that row k holds
   // (positions in the pattern's CSR order)
   std::vector<int> ilu_ptr, ilu_ops;
+  // Sweep lists of the multi-wave teams (ILU(0) substitutions, BatchTrsv):
+  // rows by lower level | rows by upper level | lower level starts (nlev_l+1)
+  // | upper level starts (nlev_u+1) | per row its list start (16 bits),
+  // lower and upper counts (8 bits each) | per row its strictly lower then
+  // strictly upper entries in increasing column, CSR position | column << 16.
+  std::vector<int> sweep;
+  int sweep_ents = 0;
   // bank-aware layout for one-wave teams of layout_nz register slots (0: none)
   std::vector<int> layout;
   int layout_nz = 0;
   // one allocation: row_ptr | slot_col | row_len | diag_slot | lev | ilu_ptr |
-  // ilu_ops | layout
+  // ilu_ops | sweep | layout
   int* d_base = nullptr;
   int *d_row_ptr = nullptr, *d_slot_col = nullptr, *d_row_len = nullptr, *d_diag = nullptr;
-  int *d_lev = nullptr, *d_ilu_ptr = nullptr, *d_ilu_ops = nullptr, *d_layout = nullptr;
+  int *d_lev = nullptr, *d_ilu_ptr = nullptr, *d_ilu_ops = nullptr, *d_sweep = nullptr;
+  int* d_layout = nullptr;
 };
 
 namespace {
@@ -149,6 +157,51 @@ void derive(bs_pattern_s& p) {
       p.ilu_ptr[i + 1] = (int)p.ilu_ops.size();
     }
   }
+  // Sweep lists (same 15-bit positions; rows of up to 255 entries per triangle;
+  // columns below 2^15).
+  p.sweep.clear();
+  p.sweep_ents = 0;
+  if (p.nnz < (1 << 15) && n < (1 << 15)) {
+    std::vector<int> by_l(n), by_u(n), start_l(p.nlev_l + 1, 0), start_u(p.nlev_u + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      ++start_l[lo[i] + 1];
+      ++start_u[up[i] + 1];
+    }
+    for (int l = 0; l < p.nlev_l; ++l) start_l[l + 1] += start_l[l];
+    for (int l = 0; l < p.nlev_u; ++l) start_u[l + 1] += start_u[l];
+    std::vector<int> fill_l(start_l.begin(), start_l.end() - 1), fill_u(start_u.begin(), start_u.end() - 1);
+    for (int i = 0; i < n; ++i) {
+      by_l[fill_l[lo[i]]++] = i;
+      by_u[fill_u[up[i]]++] = i;
+    }
+    std::vector<int> rng(n), ent;
+    std::vector<std::pair<int, int>> lw, uw;
+    bool fits = true;
+    for (int i = 0; i < n && fits; ++i) {
+      lw.clear();
+      uw.clear();
+      for (int e = p.row_ptr[i]; e < p.row_ptr[i + 1]; ++e) {
+        if (p.col[e] < i) lw.push_back({p.col[e], e});
+        if (p.col[e] > i) uw.push_back({p.col[e], e});
+      }
+      std::sort(lw.begin(), lw.end());
+      std::sort(uw.begin(), uw.end());
+      fits = lw.size() < 256 && uw.size() < 256;
+      rng[i] = (int)((unsigned)ent.size() | ((unsigned)lw.size() << 16) | ((unsigned)uw.size() << 24));
+      for (const auto& q : lw) ent.push_back(q.second | (q.first << 16));
+      for (const auto& q : uw) ent.push_back(q.second | (q.first << 16));
+    }
+    if (fits) {
+      p.sweep_ents = (int)ent.size();
+      p.sweep.reserve(3 * n + p.nlev_l + p.nlev_u + 2 + ent.size());
+      p.sweep.insert(p.sweep.end(), by_l.begin(), by_l.end());
+      p.sweep.insert(p.sweep.end(), by_u.begin(), by_u.end());
+      p.sweep.insert(p.sweep.end(), start_l.begin(), start_l.end());
+      p.sweep.insert(p.sweep.end(), start_u.begin(), start_u.end());
+      p.sweep.insert(p.sweep.end(), rng.begin(), rng.end());
+      p.sweep.insert(p.sweep.end(), ent.begin(), ent.end());
+    }
+  }
 }
 
 int upload(bs_pattern_s& p) {
@@ -162,7 +215,8 @@ int upload(bs_pattern_s& p) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   const size_t n_rp = p.n + 1, n_sc = std::max<size_t>((size_t)p.width * p.n, 1), n_rl = p.n;
   const size_t n_ops = std::max<size_t>(p.ilu_ops.size(), 1);
-  const size_t total = n_rp + n_sc + 3 * n_rl + n_rp + n_ops + p.layout.size();
+  const size_t n_sw = std::max<size_t>(p.sweep.size(), 1);
+  const size_t total = n_rp + n_sc + 3 * n_rl + n_rp + n_ops + n_sw + p.layout.size();
   e = hipMalloc(&p.d_base, total * sizeof(int));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(pattern)");
   p.d_row_ptr = p.d_base;
@@ -172,13 +226,15 @@ int upload(bs_pattern_s& p) {
   p.d_lev = p.d_diag + n_rl;
   p.d_ilu_ptr = p.d_lev + n_rl;
   p.d_ilu_ops = p.d_ilu_ptr + n_rp;
-  p.d_layout = p.layout.empty() ? nullptr : p.d_ilu_ops + n_ops;
+  p.d_sweep = p.d_ilu_ops + n_ops;
+  p.d_layout = p.layout.empty() ? nullptr : p.d_sweep + n_sw;
   std::vector<int> h(total, -1);
   const size_t o_lev = n_rp + n_sc + 2 * n_rl, o_ptr = o_lev + n_rl, o_ops = o_ptr + n_rp;
   std::copy(p.lev.begin(), p.lev.end(), h.begin() + o_lev);
   std::copy(p.ilu_ptr.begin(), p.ilu_ptr.end(), h.begin() + o_ptr);
   std::copy(p.ilu_ops.begin(), p.ilu_ops.end(), h.begin() + o_ops);
-  std::copy(p.layout.begin(), p.layout.end(), h.begin() + o_ops + n_ops);
+  std::copy(p.sweep.begin(), p.sweep.end(), h.begin() + o_ops + n_ops);
+  std::copy(p.layout.begin(), p.layout.end(), h.begin() + o_ops + n_ops + n_sw);
   std::copy(p.row_ptr.begin(), p.row_ptr.end(), h.begin());
   std::copy(p.slot_col.begin(), p.slot_col.end(), h.begin() + n_rp);
   std::copy(p.row_len.begin(), p.row_len.end(), h.begin() + n_rp + n_sc);
@@ -329,8 +385,8 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
     return BS_ERR_UNSUPPORTED;
   int tri_team = bs::kWave;
   while (tri_team < n) tri_team *= 2;
-  // the multi-wave ILU(0) schedule addresses entries with 15 bits
-  if (ilu && n > bs::kWave && nnz >= (1 << 15)) return BS_ERR_UNSUPPORTED;
+  // the multi-wave schedule and sweep lists address entries with 15 bits
+  if (tri && n > bs::kWave && nnz >= (1 << 15)) return BS_ERR_UNSUPPORTED;
   const int force_team = tri ? (o && o->team ? o->team : tri_team) : o ? o->team : 0,
             force_r = o ? o->rows_per_lane : 0;
   if (force_team != 0 && !pow2_team(force_team)) return BS_ERR_INVALID_ARG;
@@ -363,7 +419,7 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   const int stored = fmt == BS_CSR ? nnz : width * n;
   const bool mixed = variant == bs::V_GMRES_MIXED;
   const int vec = teams * (bs::team_vec_bytes(rows, gm, wg, mixed) + bs::bj_bytes(rows, block) +
-                           (tri ? bs::tri_region_bytes(team, n, nnz, trsv) : 0)) +
+                           (tri ? bs::tri_region_bytes(team, n, nnz) : 0)) +
                   bs::red_lds_bytes(waves);
   int stage = 0;
   // ILU(0) and the triangular solves are bound by their substitution chains,
@@ -698,6 +754,9 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     streamed = rc == BS_OK;
   }
   if (rc != BS_OK) return rc;
+  // multi-wave ILU(0) and BatchTrsv need the pattern's sweep lists
+  if (!streamed && (ilu || trsv) && pl.info.team > bs::kWave && pattern->sweep.empty())
+    return BS_ERR_UNSUPPORTED;
   bs::KArgs a{};
   a.n_batch = n_solves;
   a.nrhs = nrhs;
@@ -722,7 +781,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
     a.block = block;
     a.bj_offset = a.team_bytes;
     a.team_bytes += bs::bj_bytes(rows, block) +
-                    (ilu || trsv ? bs::tri_region_bytes(pl.info.team, pattern->n, pattern->nnz, trsv)
+                    (ilu || trsv ? bs::tri_region_bytes(pl.info.team, pattern->n, pattern->nnz)
                                  : 0);
     a.stage_vals_bytes = bs::stage_vals_bytes(teams, stored, pl.info.slots);
     a.stage_team_bytes = a.stage_vals_bytes + bs::stage_b_bytes(teams, pattern->n);
@@ -741,6 +800,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   a.nlev_u = pattern->nlev_u;
   a.ilu_ptr = pattern->d_ilu_ptr;
   a.ilu_ops = pattern->d_ilu_ops;
+  a.sweep = pattern->d_sweep;
+  a.sweep_ents = pattern->sweep_ents;
   a.values = values;
   a.b = b;
   a.x = x;

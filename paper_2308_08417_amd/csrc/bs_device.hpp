@@ -217,6 +217,7 @@ struct Team {
   char* stage;      // this team's part of it: values, then b
   double* red;      // cross-wave reduction slots (multi-wave teams)
   int phase;        // which half of `red` the next reduction uses
+  bool lists;       // the pattern's sweep lists are in LDS (multi-wave ILU(0), BatchTrsv)
 
 
   __device__ Team(char* smem, const KArgs& a) {
@@ -231,6 +232,7 @@ struct Team {
     stage = stage_all + (size_t)tix * a.stage_team_bytes;
     red = reinterpret_cast<double*>(smem + (size_t)S::TEAMS * a.team_bytes);
     phase = 0;
+    lists = false;
   }
 
   // Make this team's LDS writes visible to all of its lanes.  A single-wave

@@ -56,6 +56,8 @@ struct KArgs {
   int nlev_l, nlev_u;          // level counts of the lower and upper triangles
   const int* ilu_ptr;          // [n+1] start of each row's ILU(0) steps in ilu_ops
   const int* ilu_ops;          // ILU(0) schedule (header and update words, see the pattern)
+  const int* sweep;            // sweep lists of multi-wave teams (see the pattern)
+  int sweep_ents;              // entries in those lists
 };
 
 // Matrix of solve s (several right-hand sides per matrix: solves s*k..s*k+k-1
@@ -164,24 +166,26 @@ inline int stage_total_bytes(int teams, int stored, int n, int nz) {
 }
 
 // ILU(0) and BatchTrsv of a multi-wave team (row i on lane i, one row per
-// lane): byte offsets inside the team's region of the factor values in the
-// pattern's CSR order (f, nnz doubles), the sweep vector (y, n doubles), the
-// pivots (d, n doubles) and each row's packed levels (lv, n ints).  The
-// triangular solves use y alone.
+// lane): byte offsets inside the team's region of the factor (or triangle)
+// values in the pattern's CSR order (f, nnz doubles), the sweep vector (y, n
+// doubles), the pivots or diagonal (d, n doubles), and the pattern's sweep
+// lists: per row its list start and counts (rng, n ints), the lists (ent, at
+// most nnz ints), the rows in level order (rows, 2n shorts) and the level
+// starts (lvl, at most 2n+2 shorts).
 struct IluMw {
-  int f, y, d, lv, bytes;
+  int f, y, d, rng, ent, rows, lvl, bytes;
 };
-__host__ __device__ constexpr IluMw ilu_mw_layout(int n, int nnz, bool trsv) {
-  const int y = trsv ? 0 : round16(nnz * 8), d = y + round16(n * 8);
-  if (trsv) return IluMw{0, 0, d, d, d};
-  const int lv = d + round16(n * 8);
-  return IluMw{0, y, d, lv, lv + round16(n * 4)};
+__host__ __device__ constexpr IluMw ilu_mw_layout(int n, int nnz) {
+  const int y = round16(nnz * 8), d = y + round16(n * 8), rng = d + round16(n * 8);
+  const int ent = rng + round16(n * 4), rows = ent + round16(nnz * 4);
+  const int lvl = rows + round16(n * 4);
+  return IluMw{0, y, d, rng, ent, rows, lvl, lvl + round16((2 * n + 2) * 2)};
 }
 
 // LDS bytes of a team's ILU(0) or BatchTrsv region: the dense factors of a
 // one-wave team, the sparse layout above for larger teams.
-__host__ __device__ constexpr int tri_region_bytes(int team, int n, int nnz, bool trsv) {
-  return team <= kWave ? ilu_bytes(n) : ilu_mw_layout(n, nnz, trsv).bytes;
+__host__ __device__ constexpr int tri_region_bytes(int team, int n, int nnz) {
+  return team <= kWave ? ilu_bytes(n) : ilu_mw_layout(n, nnz).bytes;
 }
 
 }  // namespace bs

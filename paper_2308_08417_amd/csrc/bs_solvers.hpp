@@ -349,8 +349,127 @@ __device__ __forceinline__ void ilu_apply(TM& tm, const RW& A, const KArgs& g,
 // Ch. 11): a row's level in the lower triangle is one more than the largest
 // level among the rows its strictly lower entries name (0 if none), and its
 // level in the upper triangle is defined the same way from its strictly upper
-// entries.  Rows of one level depend only on earlier levels, and a team
-// barrier separates consecutive levels.  The levels come with the pattern.
+// entries.  Rows of one level depend only on earlier levels.  The
+// factorization takes one level per team barrier, each lane its own row; the
+// sweeps run on the team's first wave alone, whose LDS operations complete in
+// issue order, so that levels follow one another without a barrier.  The
+// levels, the factorization schedule and the sweep lists come with the
+// pattern.
+
+// The pattern's sweep lists into the team's region, once per kernel (they are
+// the same for every system): rows in lower then upper level order and the
+// level starts as 16-bit values, each row's list start and counts, the lists.
+template <class TM>
+__device__ __forceinline__ void sweep_lists_load(TM& tm, const KArgs& g, unsigned reg,
+                                                 const IluMw& L) {
+  if (tm.lists) return;
+  const int n = g.n, nl = g.nlev_l + g.nlev_u + 2;
+  const int* sw = g.sweep;
+  for (int t = threadIdx.x; t < 2 * n; t += blockDim.x)
+    lds_store<short>(reg + L.rows + t * 2, (short)sw[t]);
+  for (int t = threadIdx.x; t < nl; t += blockDim.x)
+    lds_store<short>(reg + L.lvl + t * 2, (short)sw[2 * n + t]);
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    lds_store<int>(reg + L.rng + t * 4, sw[2 * n + nl + t]);
+  for (int t = threadIdx.x; t < g.sweep_ents; t += blockDim.x)
+    lds_store<int>(reg + L.ent + t * 4, sw[3 * n + nl + t]);
+  tm.lists = true;
+}
+
+// One triangular sweep over the team's sweep vector y, run by the team's first
+// wave: for the rows of each level in turn, lane t takes the level's t-th row r
+// (then the (t+64)-th, ...) and sets y_r <- (y_r - sum_c t_rc y_c) [/ d_r] over
+// the row's strictly lower (LOWER) or upper entries in increasing column, t_rc
+// from the values at their CSR positions; DIV divides by d_r.  Pipelined so
+// that only this level's gathers wait on the previous level: the level ends
+// are read two levels ahead, the next level's first row is read before this
+// level's list words and its list range while this level's values load.
+template <bool LOWER, bool DIV>
+__device__ __forceinline__ void tri_sweep(const KArgs& g, unsigned reg, const IluMw& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned F = reg + L.f, Y = reg + L.y, D = reg + L.d, RNG = reg + L.rng, ENT = reg + L.ent;
+  const unsigned ROWS = reg + L.rows + (LOWER ? 0 : g.n * 2);
+  const unsigned LVL = reg + L.lvl + (LOWER ? 0 : (g.nlev_l + 1) * 2);
+  const int nlev = LOWER ? g.nlev_l : g.nlev_u;
+  // y_r update of one row from its list range gg (the list words, then the
+  // values and gathers, four terms at a time)
+  auto row = [&](int rr, unsigned gg) {
+    const int lc = (int)((gg >> 16) & 0xffu);
+    const int e0 = (int)(gg & 0xffffu) + (LOWER ? 0 : lc);
+    const int e1 = e0 + (LOWER ? lc : (int)(gg >> 24));
+    double acc = lds_load<double>(Y + rr * 8);
+    for (int e = e0; e < e1; e += 4) {
+      unsigned w[4];
+      double f[4], y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] = e + k < e1 ? lds_load<unsigned>(ENT + (e + k) * 4) : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        f[k] = e + k < e1 ? lds_load<double>(F + (w[k] & 0x7fffu) * 8) : 0.0;
+        y[k] = e + k < e1 ? lds_load<double>(Y + (w[k] >> 16) * 8) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (e + k < e1) acc = fma(-f[k], y[k], acc);
+    }
+    if (DIV) acc = acc / lds_load<double>(D + rr * 8);
+    lds_store<double>(Y + rr * 8, acc);
+  };
+  int qa = lds_load<short>(LVL), qb = lds_load<short>(LVL + 2);
+  int qc = nlev > 1 ? lds_load<short>(LVL + 4) : qb;  // end of the next level
+  int r = qa + lane < qb ? lds_load<short>(ROWS + (qa + lane) * 2) : -1;
+  unsigned rg = r >= 0 ? lds_load<unsigned>(RNG + r * 4) : 0u;
+  for (int l = 0; l < nlev; ++l) {
+    const int qd = l + 2 < nlev ? lds_load<short>(LVL + (l + 3) * 2) : qc;
+    const int nr = qb + lane < qc ? lds_load<short>(ROWS + (qb + lane) * 2) : -1;
+    if (r >= 0) {
+      // the first words of this row's list go out before the next row's range
+      const int lc = (int)((rg >> 16) & 0xffu);
+      const int e0 = (int)(rg & 0xffffu) + (LOWER ? 0 : lc);
+      const int ne = LOWER ? lc : (int)(rg >> 24);
+      if (ne <= 4) {
+        // no branches: list words read at clamped indices, words past the
+        // row's count replaced by 0 (entry 0, column 0: valid addresses),
+        // their terms dropped by selection
+        unsigned w[4];
+        double f[4], y[4];
+        const int last = g.sweep_ents > 0 ? g.sweep_ents - 1 : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const unsigned wk = lds_load<unsigned>(ENT + min(e0 + k, last) * 4);
+          w[k] = k < ne ? wk : 0u;
+        }
+        const double y0 = lds_load<double>(Y + r * 8);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          f[k] = lds_load<double>(F + (w[k] & 0x7fffu) * 8);
+          y[k] = lds_load<double>(Y + (w[k] >> 16) * 8);
+        }
+        double acc = y0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double t = fma(-f[k], y[k], acc);
+          acc = k < ne ? t : acc;
+        }
+        if (DIV) acc = acc / lds_load<double>(D + r * 8);
+        lds_store<double>(Y + r * 8, acc);
+      } else {
+        row(r, rg);
+      }
+    }
+    const unsigned ng = nr >= 0 ? lds_load<unsigned>(RNG + nr * 4) : 0u;
+    for (int q = qa + kWave; q < qb; q += kWave) {  // levels of more than 64 rows
+      const int rr = q + lane < qb ? lds_load<short>(ROWS + (q + lane) * 2) : -1;
+      if (rr >= 0) row(rr, lds_load<unsigned>(RNG + rr * 4));
+    }
+    qa = qb;
+    qb = qc;
+    qc = qd;
+    r = nr;
+    rg = ng;
+    __asm__ volatile("" ::: "memory");
+  }
+}
 
 // Factorization, the IKJ form of the one-wave code, from the pattern's
 // symbolic schedule: at its level, row i takes the columns k < i it holds in
@@ -368,9 +487,10 @@ template <class TM, class RW>
 __device__ void ilu_setup_mw(TM& tm, const RW& A, const KArgs& g) {
   static_assert(RW::R == 1 && RW::TEAM > kWave, "multi-wave ILU(0): one row per lane");
   constexpr int NZ = RW::NZ;
-  const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
+  const IluMw L = ilu_mw_layout(g.n, g.nnz);
   const unsigned reg = lds_addr(tm.bj_region(g));
-  const unsigned F = reg + L.f, D = reg + L.d, LV = reg + L.lv;
+  const unsigned F = reg + L.f, D = reg + L.d;
+  sweep_lists_load(tm, g, reg, L);
   const bool ok = A.ok[0];
   int i = ok ? A.row[0] : 0;
   // opaque once per system: everything below derives from the pattern, and
@@ -389,12 +509,11 @@ __device__ void ilu_setup_mw(TM& tm, const RW& A, const KArgs& g) {
 #pragma unroll
   for (int q = 0; q < kIluOpsReg; ++q)
     w[q] = kEarly && o0 + q < o1 ? (unsigned)g.ilu_ops[o0 + q] : 0u;
-  // publish the row's values and its levels
+  // publish the row's values
   if (ok) {
 #pragma unroll
     for (int s = 0; s < NZ; ++s)
       if (A.real(0, s)) lds_store<double>(fr + s * 8, A.a[0][s]);
-    lds_store<int>(LV + i * 4, lv);
   }
   tm.sync();
   const int mine = ok ? (lv & 0xffff) : -1;
@@ -444,73 +563,25 @@ __device__ void ilu_setup_mw(TM& tm, const RW& A, const KArgs& g) {
   }
 }
 
-// One row of a sweep: acc -= t_s y(col_s) over the register slots s that
-// hold an entry of the lower (LOWER) or upper triangle, in slot order, with
-// t_s from LDS at tr (FROM_LDS) or the row's register value; y is gathered
-// through the slot's SpMV address plus yo.  Loads go out four at a time.
-template <bool LOWER, bool FROM_LDS, class RW>
-__device__ __forceinline__ double sweep_row(const RW& A, unsigned tr, unsigned yo, double acc) {
-  constexpr int NZ = RW::NZ;
-  // opaque per call: the per-slot addresses and tests are formed here, inside
-  // the level loop, instead of being hoisted out of it into NZ registers each
-  unsigned me = A.vrow[0];
-  __asm__ volatile("" : "+v"(tr), "+v"(yo), "+v"(me));
-#pragma unroll
-  for (int s0 = 0; s0 < NZ; s0 += 4) {
-    double tv[4], yv[4];
-    bool on[4];
-#pragma unroll
-    for (int q = 0; q < 4 && s0 + q < NZ; ++q) {
-      const int s = s0 + q;
-      on[q] = LOWER ? A.c[0][s] < me : (A.c[0][s] > me && A.real(0, s));
-      tv[q] = FROM_LDS ? (on[q] ? lds_load<double>(tr + s * 8) : 0.0) : A.a[0][s];
-      yv[q] = on[q] ? lds_load<double>(A.c[0][s] + yo) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 4 && s0 + q < NZ; ++q)
-      if (on[q]) acc = fma(-tv[q], yv[q], acc);
-    __asm__ volatile("" : "+v"(acc)::"memory");
-  }
-  return acc;
-}
-
-// z = (L U)^{-1} v by the two row-oriented sweeps of the oracle's default
-// form, level by level: forward, y_i = v_i - sum_{k<i} l_ik y_k; backward,
-// z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii.  Each row's terms run in its
-// stored order (increasing column for sorted rows); the y and z of other rows
-// are gathered from the team's sweep vector through the row's SpMV addresses.
-// With M the identity the row values are zero and the pivots 1, so z = v.
+// z = (L U)^{-1} v by the two row-oriented substitutions of the oracle's
+// default form on the team's first wave: forward, y_i = v_i - sum_{k<i} l_ik
+// y_k; backward, z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii, each row's terms in
+// increasing column.  With M the identity the row values are zero and the
+// pivots 1, so z = v.
 template <class T, class TM, class RW>
 __device__ __forceinline__ void ilu_apply_mw(TM& tm, const RW& A, const KArgs& g,
                                              const T (&v)[RW::R], T (&z)[RW::R]) {
-  const IluMw L = ilu_mw_layout(g.n, g.nnz, false);
+  const IluMw L = ilu_mw_layout(g.n, g.nnz);
   const unsigned reg = lds_addr(tm.bj_region(g));
-  const unsigned F = reg + L.f, Y = reg + L.y, D = reg + L.d, LV = reg + L.lv;
-  const bool ok = A.ok[0];
-  const int i = ok ? A.row[0] : 0;
-  const int lv = lds_load<int>(LV + i * 4);
-  const int ll = ok ? (lv & 0xffff) : -1, lu = ok ? (lv >> 16) : -1;
-  const unsigned fr = F + (g.fmt == 0 ? A.w[0] : g.row_ptr[i]) * 8;
-  const unsigned yo = Y - A.b0;  // sweep element of column j: gather address + yo
-  const unsigned me = A.vrow[0];
-  double acc = ok ? (double)v[0] : 0.0;
-  for (int l = 0; l < g.nlev_l; ++l) {
-    if (ll == l) {
-      acc = sweep_row<true, true>(A, fr, yo, acc);
-      lds_store<double>(me + yo, acc);
-    }
-    tm.sync();
+  const unsigned me = reg + L.y + (unsigned)A.row[0] * 8;
+  if (A.ok[0]) lds_store<double>(me, (double)v[0]);
+  tm.sync();
+  if (threadIdx.x < kWave) {
+    tri_sweep<true, false>(g, reg, L);
+    tri_sweep<false, true>(g, reg, L);
   }
-  const double piv = lds_load<double>(D + i * 8);
-  for (int l = 0; l < g.nlev_u; ++l) {
-    if (lu == l) {
-      acc = sweep_row<false, true>(A, fr, yo, acc);
-      acc = acc / piv;
-      lds_store<double>(me + yo, acc);
-    }
-    tm.sync();
-  }
-  z[0] = ok ? (T)acc : (T)0;
+  tm.sync();
+  z[0] = A.ok[0] ? (T)lds_load<double>(me) : (T)0;
 }
 
 // z = M v: block Jacobi or ILU(0) in their instances, else the diagonal d
@@ -968,30 +1039,40 @@ __device__ __forceinline__ void trsv_system_w64(TM& tm, RW& A, const KArgs& g) {
 }
 
 // BatchTrsv for multi-wave teams (row i on lane i, up to 1024 rows): the
-// row-oriented substitution of the oracle, level by level (the levels of the
-// ILU(0) sweeps): x_i = (b_i - sum_j t_ij x_j) / t_ii over the row's strictly
-// lower (upper) entries in stored order, the other rows' x gathered from the
-// team's sweep vector.  Entries outside the triangle are zeroed in registers
-// as in the one-wave form; a zero diagonal entry anywhere is a breakdown.
+// row-oriented substitution of the oracle on the team's first wave, level by
+// level (the sweep of the ILU(0) form with the triangle's own diagonal):
+// x_i = (b_i - sum_j t_ij x_j) / t_ii over the row's strictly lower (upper)
+// entries in increasing column.  Entries outside the triangle are zeroed in
+// registers as in the one-wave form, so the epilogue's residual is that of
+// the triangle; a zero diagonal entry anywhere is a breakdown.
 template <bool LOWER, class TM, class RW>
 __device__ __forceinline__ void trsv_system_mw(TM& tm, RW& A, const KArgs& g) {
   static_assert(RW::R == 1 && RW::TEAM > kWave, "multi-wave BatchTrsv: one row per lane");
   constexpr int NZ = RW::NZ;
-  const unsigned Y = lds_addr(tm.bj_region(g)) + ilu_mw_layout(g.n, g.nnz, true).y;
+  const IluMw L = ilu_mw_layout(g.n, g.nnz);
+  const unsigned reg = lds_addr(tm.bj_region(g));
+  sweep_lists_load(tm, g, reg, L);
   const bool ok = A.ok[0];
-  const int i = ok ? A.row[0] : 0;
-  const int lv = g.lev[i];
-  const int mine = ok ? (LOWER ? (lv & 0xffff) : (lv >> 16)) : -1;
-  const unsigned me = A.vrow[0], yo = Y - A.b0;
+  int i = ok ? A.row[0] : 0;
+  __asm__ volatile("" : "+v"(i));  // per system: keeps the row's addresses out of the kernel-wide registers
+  const unsigned fr = reg + L.f + (unsigned)(g.fmt == 0 ? A.w[0] : g.row_ptr[i]) * 8;
+  const unsigned me = reg + L.y + (unsigned)i * 8;
+  const double tii = ok ? A.dval[0] : 1.0;
+  if (ok) {
+#pragma unroll
+    for (int s = 0; s < NZ; ++s)
+      if (A.real(0, s)) lds_store<double>(fr + s * 8, A.a[0][s]);
+    lds_store<double>(reg + L.d + (unsigned)i * 8, tii);
+    lds_store<double>(me, A.bval[0]);
+  }
 #pragma unroll
   for (int s = 0; s < NZ; ++s) {
-    const bool keep = ok && A.real(0, s) && (LOWER ? A.c[0][s] <= me : A.c[0][s] >= me);
+    const bool keep = ok && A.real(0, s) && (LOWER ? A.c[0][s] <= A.vrow[0] : A.c[0][s] >= A.vrow[0]);
     A.a[0][s] = keep ? A.a[0][s] : 0.0;
   }
   double b[1] = {A.bval[0]}, x[1] = {A.xval[0]}, q[1] = {b[0] * b[0]};
-  tm.sum(q);
+  tm.sum(q);  // also makes the stores above visible to the team
   const double bn = sqrt(q[0]);
-  const double tii = ok ? A.dval[0] : 1.0;
   const bool zero_diag = __syncthreads_or(ok && tii == 0.0) != 0;
   int stt = tm.live ? ST_CONVERGED : ST_IDLE;
   if (tm.live && !finite(bn)) {
@@ -1000,16 +1081,9 @@ __device__ __forceinline__ void trsv_system_mw(TM& tm, RW& A, const KArgs& g) {
     if (tm.live && bn != 0.0) stt = ST_BREAKDOWN;
     x[0] = 0.0;
   } else {
-    double acc = ok ? b[0] : 0.0;
-    const int levels = LOWER ? g.nlev_l : g.nlev_u;
-    for (int l = 0; l < levels; ++l) {
-      if (mine == l) {
-        acc = sweep_row<LOWER, false>(A, 0u, yo, acc) / tii;
-        lds_store<double>(me + yo, acc);
-      }
-      tm.sync();
-    }
-    x[0] = ok ? acc : 0.0;
+    if (threadIdx.x < kWave) tri_sweep<LOWER, true>(g, reg, L);
+    tm.sync();
+    x[0] = ok ? lds_load<double>(me) : 0.0;
     const bool nf = __syncthreads_or(ok && !finite(x[0])) != 0;
     if (tm.live && nf) stt = ST_NONFINITE;
   }

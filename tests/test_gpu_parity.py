@@ -774,6 +774,8 @@ MW_GENS = {
     "chem300": lambda: W.chem_jacobian(64, n=300, fill=0.02, gamma=3e-4, seed=44),
     # rows stored out of column order
     "shuffled": lambda: shuffled_rows(W.collision_stencil(48, nx=16, ny=12, seed=45), 46),
+    # 13 x 9 grid: n = 117, not a multiple of 4 (padded LDS regions)
+    "stencil117": lambda: W.collision_stencil(40, nx=13, ny=9, seed=51),
     # tridiagonal, n = 700: ILU(0) is the exact LU (one step), 700 levels
     "tridiag700": lambda: W.tridiag_stencil(n_batch=40, n=700, seed=47),
 }
@@ -845,7 +847,7 @@ def test_ilu_multiwave_zero_pivot_and_start():
 
 
 @pytest.mark.parametrize("lower", [True, False])
-@pytest.mark.parametrize("gen", ["stencil192", "stencil992", "chem300", "shuffled"])
+@pytest.mark.parametrize("gen", ["stencil192", "stencil992", "chem300", "shuffled", "stencil117"])
 def test_trsv_multiwave(gen, lower):
     """BatchTrsv on teams of 2..16 waves against the oracle, CSR and ELL."""
     bt = MW_GENS[gen]()
