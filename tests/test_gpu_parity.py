@@ -884,6 +884,57 @@ def test_trsv_multiwave_breakdown():
         assert np.allclose(xg[ok], xo[ok], rtol=1e-12, atol=1e-14)
 
 
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.TRSV_LOWER])
+def test_multiwave_ilu_trsv_multi_rhs_and_dev(solver):
+    """Multi-wave ILU(0) (BiCGSTAB) and BatchTrsv with three right-hand sides
+    per matrix: bit-identical to the matrices replicated once per right-hand
+    side; and through bs_batch_solve_dev (the pattern as caller-owned device
+    arrays): bit-identical to the handle entry."""
+    k = 3
+    bt = W.collision_stencil(20, nx=16, ny=12, seed=53)
+    B, n = bt.n_batch, bt.n
+    b = 2 * np.random.default_rng(54).random((B * k, n)) - 1
+    c = Case(bt)
+    pc = bs.PREC_ILU if solver == bs.BICGSTAB else bs.PREC_NONE
+
+    def outs(m):
+        return (torch.zeros((m, n), dtype=torch.float64, device="cuda:0"),
+                torch.empty(m, dtype=torch.int32, device="cuda:0"),
+                torch.empty(m, dtype=torch.float64, device="cuda:0"),
+                torch.empty(m, dtype=torch.int32, device="cuda:0"))
+
+    def host(t):
+        torch.cuda.synchronize()
+        return tuple(u.cpu().numpy() for u in t)
+
+    x, it, rs, st = outs(B * k)
+    say(f"  multi-rhs multi-wave solver={solver}")
+    bs.bs_batch_solve(bs.CSR, c.P.handle, c.vals, dev(b), x, solver, pc, 1e-10, 500, it, rs, st,
+                      bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k))
+    g = host((x, it, rs, st))
+    rep = W.Batch(bt.name + "_rep", n, bt.row_ptr, bt.col_idx, np.repeat(bt.values, k, axis=0), b,
+                  np.zeros_like(b))
+    cr = Case(rep)
+    gr = cr.gpu(bs.CSR, solver, precond=pc)
+    for u, v in zip(g, gr):
+        assert np.array_equal(u, v)
+    o = cr.oracle(bs.CSR, solver, precond=pc)
+    if solver == bs.BICGSTAB:
+        check(cr, g, o)
+    else:
+        assert np.array_equal(g[3], o[3])
+        assert np.all(np.linalg.norm(g[0] - o[0], axis=1) <= 1e-12 * np.linalg.norm(o[0], axis=1))
+    # caller-owned device pattern
+    x, it, rs, st = outs(B)
+    bs.bs_batch_solve_dev(bs.CSR, n, dev(bt.row_ptr.astype(np.int32)), dev(bt.col_idx.astype(np.int32)),
+                          c.vals, dev(bt.b), x, solver, pc, 1e-10, 500, it, rs, st,
+                          bs.make_options(flags=bs.FLAG_X0_ZERO))
+    gd = host((x, it, rs, st))
+    gh = c.gpu(bs.CSR, solver, precond=pc)
+    for u, v in zip(gd, gh):
+        assert np.array_equal(u, v)
+
+
 @pytest.mark.parametrize("precond,bsz", [(bs.PREC_BLOCK_JACOBI, 4), (bs.PREC_ILU, 0)])
 def test_stronger_preconditioners_absolute_and_dense(precond, bsz):
     """Block Jacobi and ILU(0) under the absolute stop criterion, and through the
