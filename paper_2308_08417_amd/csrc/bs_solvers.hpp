@@ -382,8 +382,8 @@ __device__ __forceinline__ void sweep_lists_load(TM& tm, const KArgs& g, unsigne
 // the row's strictly lower (LOWER) or upper entries in increasing column, t_rc
 // from the values at their CSR positions; DIV divides by d_r.  Pipelined so
 // that only this level's gathers wait on the previous level: the level ends
-// are read two levels ahead, the next level's first row is read before this
-// level's list words and its list range while this level's values load.
+// are read two levels ahead, the next level's first row before this level's
+// list words, and that row's list range once this level's loads are out.
 template <bool LOWER, bool DIV>
 __device__ __forceinline__ void tri_sweep(const KArgs& g, unsigned reg, const IluMw& L) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -422,29 +422,32 @@ __device__ __forceinline__ void tri_sweep(const KArgs& g, unsigned reg, const Il
   for (int l = 0; l < nlev; ++l) {
     const int qd = l + 2 < nlev ? lds_load<short>(LVL + (l + 3) * 2) : qc;
     const int nr = qb + lane < qc ? lds_load<short>(ROWS + (qb + lane) * 2) : -1;
+    // This level's first row on each lane, rows of up to four terms without
+    // branches: list words at clamped indices, words past the row's count (and
+    // on lanes without a row) replaced by 0 (entry 0, column 0: valid
+    // addresses), their terms dropped by selection.  The next row's list range
+    // is read once this level's loads are out.
+    const int lc = (int)((rg >> 16) & 0xffu);
+    const int e0 = (int)(rg & 0xffffu) + (LOWER ? 0 : lc);
+    const int ne = r >= 0 ? (LOWER ? lc : (int)(rg >> 24)) : 0;
+    const int rs = r >= 0 ? r : 0;
+    const int last = g.sweep_ents > 0 ? g.sweep_ents - 1 : 0;
+    unsigned w[4];
+    double f[4], y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const unsigned wk = lds_load<unsigned>(ENT + min(e0 + k, last) * 4);
+      w[k] = k < ne ? wk : 0u;
+    }
+    const double y0 = lds_load<double>(Y + rs * 8);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      f[k] = lds_load<double>(F + (w[k] & 0x7fffu) * 8);
+      y[k] = lds_load<double>(Y + (w[k] >> 16) * 8);
+    }
+    const unsigned ng = nr >= 0 ? lds_load<unsigned>(RNG + nr * 4) : 0u;
     if (r >= 0) {
-      // the first words of this row's list go out before the next row's range
-      const int lc = (int)((rg >> 16) & 0xffu);
-      const int e0 = (int)(rg & 0xffffu) + (LOWER ? 0 : lc);
-      const int ne = LOWER ? lc : (int)(rg >> 24);
       if (ne <= 4) {
-        // no branches: list words read at clamped indices, words past the
-        // row's count replaced by 0 (entry 0, column 0: valid addresses),
-        // their terms dropped by selection
-        unsigned w[4];
-        double f[4], y[4];
-        const int last = g.sweep_ents > 0 ? g.sweep_ents - 1 : 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const unsigned wk = lds_load<unsigned>(ENT + min(e0 + k, last) * 4);
-          w[k] = k < ne ? wk : 0u;
-        }
-        const double y0 = lds_load<double>(Y + r * 8);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          f[k] = lds_load<double>(F + (w[k] & 0x7fffu) * 8);
-          y[k] = lds_load<double>(Y + (w[k] >> 16) * 8);
-        }
         double acc = y0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -457,7 +460,6 @@ __device__ __forceinline__ void tri_sweep(const KArgs& g, unsigned reg, const Il
         row(r, rg);
       }
     }
-    const unsigned ng = nr >= 0 ? lds_load<unsigned>(RNG + nr * 4) : 0u;
     for (int q = qa + kWave; q < qb; q += kWave) {  // levels of more than 64 rows
       const int rr = q + lane < qb ? lds_load<short>(ROWS + (q + lane) * 2) : -1;
       if (rr >= 0) row(rr, lds_load<unsigned>(RNG + rr * 4));
