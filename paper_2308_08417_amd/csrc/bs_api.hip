@@ -123,7 +123,8 @@ void derive(bs_pattern_s& p) {
   p.lev.resize(n);
   p.nlev_l = p.nlev_u = 0;
   for (int i = 0; i < n; ++i) {
-    p.lev[i] = lo[i] | (up[i] << 16);
+    // 16 bits each: the multi-wave paths that read it take at most 1024 rows
+    p.lev[i] = (int)(((unsigned)lo[i] & 0xffffu) | ((unsigned)up[i] << 16));
     p.nlev_l = std::max(p.nlev_l, lo[i] + 1);
     p.nlev_u = std::max(p.nlev_u, up[i] + 1);
   }
