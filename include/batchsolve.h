@@ -112,12 +112,14 @@ typedef enum {
                                   (the pattern's bank-aware layout is not used) */
 
 /* Largest system the register kernels take: one row per lane, up to 1024
- * lanes per system, and 2 or 4 rows per lane beyond that; longest row held in
- * registers.  GMRES takes one row per lane (up to 1024 rows).  Beyond
- * BS_MAX_ROW_NNZ entries per row, CG, BiCGSTAB and GMRES (FP64, or BiCGSTAB and
- * GMRES mixed) with scalar Jacobi or none take the streamed placement (the
- * spill tier of Sec. 3.5: the rows stay in global memory and are read at
- * every product) for systems of up to 1024 rows. */
+ * lanes per system, and 2 or 4 rows per lane beyond that (rows of up to 8
+ * entries there); longest row held in registers.  GMRES takes one row per lane
+ * (up to 1024 rows).  Where no register shape holds the rows (more than
+ * BS_MAX_ROW_NNZ entries, or more than 8 beyond 1024 rows), CG, BiCGSTAB and
+ * GMRES (FP64, or BiCGSTAB and GMRES mixed) with scalar Jacobi or none take the
+ * streamed placement (the spill tier of Sec. 3.5: the rows stay in global
+ * memory and are read at every product): CG and BiCGSTAB up to BS_MAX_ROWS
+ * rows, GMRES up to 1024. */
 #define BS_MAX_ROWS 2048
 #define BS_MAX_ROW_NNZ 64
 #define BS_MAX_RESTART 30
@@ -184,8 +186,9 @@ int bs_pattern_layout(bs_pattern pattern, int32_t *slots, int32_t *layout);
  * Tab. 2): a dense batch stores every entry of every matrix, [n_batch][n][n]
  * row-major, which is the CSR order of this pattern; bs_batch_solve with
  * BS_DENSE runs the BatchCsr kernels on it.  Rows longer than BS_MAX_ROW_NNZ
- * (n_rows > 64) take the streamed placement (CG, BiCGSTAB, GMRES; n_rows <=
- * 1024); other requests on them fail with BS_ERR_UNSUPPORTED at solve time.
+ * (n_rows > 64) take the streamed placement (CG and BiCGSTAB with n_rows <=
+ * 2048, GMRES with n_rows <= 1024); other requests on them fail with
+ * BS_ERR_UNSUPPORTED at solve time.
  * Errors: BS_ERR_INVALID_ARG (NULL out, n_rows < 1, n_rows^2 beyond int32),
  * BS_ERR_NO_DEVICE / BS_ERR_HIP on upload. */
 int bs_pattern_create_dense(int32_t n_rows, bs_pattern *out);
@@ -274,7 +277,8 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
  *   team           lanes per system;  rows_per_lane  rows held by each lane
  *   slots          register slots per row (>= longest row); 0 for the
  *                  streamed placement (rows read from memory at every product;
- *                  workgroups of 512 lanes x 2 rows, GMRES 1024 x 1)
+ *                  workgroups of 512 lanes x 2 rows, 1024 x 2 beyond 1024
+ *                  rows, GMRES 1024 x 1)
  *   group_size     threads per workgroup; systems_per_group
  *   lds_bytes      dynamic LDS per workgroup
  *   stage_values   1 if CSR values are staged through LDS for coalesced loads */

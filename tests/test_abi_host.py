@@ -160,7 +160,7 @@ def test_plan_stage_and_limits(L):
     assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 1
     assert p["systems_per_group"] == 1 and p["lds_bytes"] <= 160 * 1024
     # ... which takes neither block Jacobi / ILU(0), nor mixed CG, nor a forced
-    # shape, nor more than 1024 rows
+    # shape, nor more than 2048 rows (GMRES: 1024)
     for solver, opts, prec in ((bs.BICGSTAB, bs.make_options(block_size=4), bs.PREC_BLOCK_JACOBI),
                                (bs.BICGSTAB, None, bs.PREC_ILU),
                                (bs.CG, bs.make_options(precision=bs.MIXED), bs.PREC_JACOBI),
@@ -168,8 +168,10 @@ def test_plan_stage_and_limits(L):
         with pytest.raises(bs.BatchSolveError) as e:
             bs.bs_plan_precond(bs.CSR, 54, 1042, 65, solver, prec, opts)
         assert e.value.code == bs.ERR_UNSUPPORTED, (solver, prec)
+    p = bs.bs_plan(bs.DENSE, 1025, 0, 0, bs.CG)
+    assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 2
     with pytest.raises(bs.BatchSolveError) as e:
-        bs.bs_plan(bs.DENSE, 1025, 0, 0, bs.CG)
+        bs.bs_plan(bs.DENSE, 2049, 0, 0, bs.CG)
     assert e.value.code == bs.ERR_UNSUPPORTED
     with pytest.raises(bs.BatchSolveError) as e:
         bs.bs_plan(bs.CSR, 5000, 15000, 3, bs.BICGSTAB)
@@ -183,6 +185,26 @@ def test_plan_stage_and_limits(L):
     assert p["team"] == 64
     with pytest.raises(bs.BatchSolveError):
         bs.bs_plan(bs.CSR, 54, 1042, 28, bs.CG, bs.make_options(precision=bs.MIXED))
+
+
+def test_plan_streamed_two_rows(L):
+    """1025..2048 rows: register shapes of 2 rows x 8 slots where the rows fit,
+    else the streamed placement on 1024-lane x 2-row workgroups (CG, BiCGSTAB);
+    GMRES stops at 1024 rows and every solver at 2048."""
+    p = bs.bs_plan(bs.CSR, 1600, 8000, 5, bs.BICGSTAB)
+    assert p["slots"] == 8 and p["team"] == 1024 and p["rows_per_lane"] == 2
+    for solver in (bs.CG, bs.BICGSTAB):
+        for n in (1025, 1600, 2048):
+            p = bs.bs_plan(bs.CSR, n, 9 * n, 9, solver)
+            assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 2, (solver, n)
+            assert p["group_size"] == 1024 and p["systems_per_group"] == 1
+        p = bs.bs_plan(bs.CSR, 1600, 1600 * 9, 9, solver, bs.make_options(precision=bs.MIXED)) \
+            if solver == bs.BICGSTAB else p
+        assert p["slots"] == 0
+    for solver, n in ((bs.GMRES, 1025), (bs.BICGSTAB, 2049), (bs.CG, 2049)):
+        with pytest.raises(bs.BatchSolveError) as e:
+            bs.bs_plan(bs.CSR, n, 9 * n, 9, solver)
+        assert e.value.code == bs.ERR_UNSUPPORTED, (solver, n)
 
 
 def test_plan_ilu_trsv_teams(L):

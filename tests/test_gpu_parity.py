@@ -1044,6 +1044,51 @@ def test_streamed_long_rows(fmt, solver):
     check(c, g, c.oracle(fmt, solver, precond=bs.PREC_NONE, x0=x0, max_iter=1000), fmt=fmt)
 
 
+def spd_grid9(nx, ny, n_batch, seed):
+    """SPD systems on the nine-point pattern: a_ij = a_ji = -(1 + 0.5 U(0, 1))
+    for neighbours, a_ii = 1.1 sum_j |a_ij| + 0.1."""
+    rp, ci, _, _ = W.grid9_pattern(nx, ny)
+    n = nx * ny
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    _, pair = np.unique(np.minimum(rows, ci) * n + np.maximum(rows, ci), return_inverse=True)
+    off = rows != ci
+    rng = np.random.default_rng(seed)
+    vals = np.empty((n_batch, ci.size))
+    for s in range(n_batch):
+        v = -(1.0 + 0.5 * rng.random(pair.max() + 1))[pair] * off
+        d = np.zeros(n)
+        np.add.at(d, rows, np.abs(v))
+        v[~off] = 1.1 * d[rows[~off]] + 0.1
+        vals[s] = v
+    b = 2 * rng.random((n_batch, n)) - 1
+    return W.Batch("spd_grid9", n, rp, ci, vals, b, np.zeros_like(b))
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.CG])
+def test_streamed_two_rows_per_lane(fmt, solver):
+    """Systems of 1025..2048 rows whose rows are longer than the 8 register
+    slots of the 2-row shapes take the streamed placement on workgroups of
+    1024 lanes x 2 rows: nine-point stencils of 40 x 40 (n = 1600) and 64 x 32
+    (n = 2048), nonsymmetric for BiCGSTAB and SPD for CG, against the oracle;
+    GMRES there is refused."""
+    for nx, ny, B in ((40, 40, 24), (64, 32, 9)):
+        bt = (W.collision_stencil(B, nx=nx, ny=ny, seed=nx) if solver == bs.BICGSTAB
+              else spd_grid9(nx, ny, B, nx))
+        p = bs.bs_plan(fmt, bt.n, int(bt.row_ptr[-1]), 9, solver)
+        assert p["slots"] == 0 and p["group_size"] == 1024 and p["rows_per_lane"] == 2
+        c = Case(bt)
+        g = c.gpu(fmt, solver, max_iter=2000)
+        check(c, g, c.oracle(fmt, solver, max_iter=2000), fmt=fmt)
+    if solver == bs.BICGSTAB:
+        # mixed precision: x within the FP64 bar of the FP64 oracle
+        g = c.gpu(fmt, solver, max_iter=2000, precision=bs.MIXED)
+        check(c, g, c.oracle(fmt, solver, max_iter=2000), fmt=fmt, itol=10**9)
+        with pytest.raises(bs.BatchSolveError) as e:
+            c.gpu(fmt, bs.GMRES)
+        assert e.value.code == bs.ERR_UNSUPPORTED
+
+
 @pytest.mark.parametrize("n", [65, 100, 300])
 @pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB, bs.GMRES])
 def test_streamed_dense(n, solver):
