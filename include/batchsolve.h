@@ -119,7 +119,9 @@ typedef enum {
  * GMRES (FP64, or BiCGSTAB and GMRES mixed) with scalar Jacobi or none take the
  * streamed placement (the spill tier of Sec. 3.5: the rows stay in global
  * memory and are read at every product): CG and BiCGSTAB up to BS_MAX_ROWS
- * rows, GMRES up to 1024. */
+ * rows, GMRES up to 1024 rows, and FP64 GMRES up to BS_MAX_ROWS with its
+ * basis in device memory (31 x 2048 doubles per resident workgroup, taken
+ * with hipMallocAsync on the solve's stream and freed after the launch). */
 #define BS_MAX_ROWS 2048
 #define BS_MAX_ROW_NNZ 64
 #define BS_MAX_RESTART 30
@@ -186,9 +188,9 @@ int bs_pattern_layout(bs_pattern pattern, int32_t *slots, int32_t *layout);
  * Tab. 2): a dense batch stores every entry of every matrix, [n_batch][n][n]
  * row-major, which is the CSR order of this pattern; bs_batch_solve with
  * BS_DENSE runs the BatchCsr kernels on it.  Rows longer than BS_MAX_ROW_NNZ
- * (n_rows > 64) take the streamed placement (CG and BiCGSTAB with n_rows <=
- * 2048, GMRES with n_rows <= 1024); other requests on them fail with
- * BS_ERR_UNSUPPORTED at solve time.
+ * (n_rows > 64) take the streamed placement (CG, BiCGSTAB and FP64 GMRES with
+ * n_rows <= 2048, mixed GMRES with n_rows <= 1024); other requests on them
+ * fail with BS_ERR_UNSUPPORTED at solve time.
  * Errors: BS_ERR_INVALID_ARG (NULL out, n_rows < 1, n_rows^2 beyond int32),
  * BS_ERR_NO_DEVICE / BS_ERR_HIP on upload. */
 int bs_pattern_create_dense(int32_t n_rows, bs_pattern *out);
@@ -278,7 +280,7 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
  *   slots          register slots per row (>= longest row); 0 for the
  *                  streamed placement (rows read from memory at every product;
  *                  workgroups of 512 lanes x 2 rows, 1024 x 2 beyond 1024
- *                  rows, GMRES 1024 x 1)
+ *                  rows, GMRES 1024 x 1, and 1024 x 2 beyond 1024 rows)
  *   group_size     threads per workgroup; systems_per_group
  *   lds_bytes      dynamic LDS per workgroup
  *   stage_values   1 if CSR values are staged through LDS for coalesced loads */

@@ -543,4 +543,218 @@ void k_shared_stream(const KArgs g, int team) {
   }
 }
 
+// GMRES(m) for systems of more than one row per lane whose basis fits neither
+// registers nor LDS (streamed rows on 1024-lane x 2-row workgroups, 1025..2048
+// rows): the steps of gmres_system for teams of a wave or more (block modified
+// Gram-Schmidt in blocks of four, the rotations and the back substitution
+// through lane registers), every per-lane vector widened to the lane's R rows,
+// and basis vector i kept in device memory at ws[i * ROWS + row].  Each lane
+// reads back only the elements it wrote, so the buffer needs no barrier.
+// FP64, scalar Jacobi or none.
+template <class VS>
+__device__ void gmres_system_wide(VarTeam<VS>& tm, VarRowsS<VS, kSrcShared>& A, const KArgs& g,
+                                  double* __restrict__ ws) {
+  using RW = VarRowsS<VS, kSrcShared>;
+  constexpr int R = VS::R, M = kMaxRestart;
+  Prologue<R> P;
+  prologue<kPkScalar>(tm, A, g, P);
+  const int m = g.restart;
+  double* hcol = gmres_scalar_base(tm, RW::ROWS);
+  double* Rt = hcol + (M + 2);  // packed by columns: R[i][j] at j(j+1)/2 + i
+  double* cs = Rt + M * (M + 1) / 2;
+  double* sn = cs + M;
+  double* gv = sn + M;
+  // this lane's element of basis vector i in row slot r
+  auto at = [&](int i, int r) -> double* { return ws + (size_t)i * RW::ROWS + A.row[r]; };
+  double q1[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < R; ++r) q1[0] += P.b[r] * P.b[r];
+  tm.sum(q1);
+  const double bn = sqrt(q1[0]);
+  const double lim = stop_limit(g, bn);
+  int st = tm.live ? ST_RUNNING : ST_IDLE;
+  double rn = 0.0;
+  if (st == ST_RUNNING) {
+    if (!finite(bn)) {
+      st = ST_NONFINITE;
+    } else if (bn == 0.0) {
+      st = ST_CONVERGED;
+#pragma unroll
+      for (int r = 0; r < R; ++r) P.x[r] = 0.0;
+    }
+  }
+  int k = 0, j = 0;
+  double vcur[R];      // the basis vector the next Arnoldi step multiplies
+  double gcur = 0.0;   // g_j, the entry the next rotation acts on
+  bool start = true;   // at a cycle start (true residual due)
+#pragma unroll
+  for (int r = 0; r < R; ++r) vcur[r] = 0.0;
+  for (;;) {
+    // ---- cycle start: true residual, convergence, V0 = r/beta
+    if (tm.any(st == ST_RUNNING && start)) {
+      const bool me = st == ST_RUNNING && start;
+      double t[R], rc[R], q[1] = {0.0};
+      A.template spmv<0, false>(tm, A.a, P.x, t);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        rc[r] = P.b[r] - t[r];
+        q[0] += rc[r] * rc[r];
+      }
+      tm.sum(q);
+      if (me) {
+        const double beta = sqrt(q[0]);
+        rn = beta;
+        if (!finite(beta)) {
+          st = ST_NONFINITE;
+        } else if (beta <= lim) {
+          st = ST_CONVERGED;
+        } else if (k >= g.max_iter) {
+          st = ST_MAX_ITER;
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            vcur[r] = rc[r] / beta;
+            if (A.ok[r]) *at(0, r) = vcur[r];
+          }
+          gcur = beta;
+          j = 0;
+          start = false;
+        }
+      }
+    }
+    if (!tm.any(st == ST_RUNNING)) break;
+    // ---- one Arnoldi step
+    const bool act = st == ST_RUNNING;
+    double z[R], w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = P.d[r] * vcur[r];
+    A.template spmv<0, false>(tm, A.a, z, w);
+    const int jmax = wave_max(act ? j : -1);
+    // blocks taken in a loop (the basis is addressed, not in registers)
+#pragma unroll 1
+    for (int b0 = 0; b0 <= jmax && b0 < M; b0 += 4) {
+      {
+        double vq[4][R], q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          q[u] = 0.0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            vq[u][r] = (b0 + u < M && b0 + u <= j && A.ok[r]) ? *at(b0 + u, r) : 0.0;
+            q[u] += w[r] * vq[u][r];
+          }
+        }
+        tm.sum(q);
+        if (act) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (b0 + u < M && b0 + u <= j) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) w[r] = fma(-q[u], vq[u][r], w[r]);
+              hcol[b0 + u] = q[u];
+            }
+          }
+        }
+      }
+    }
+    double qn[1] = {0.0};
+#pragma unroll
+    for (int r = 0; r < R; ++r) qn[0] += w[r] * w[r];
+    tm.sum(qn);
+    bool end = false;
+    if (act) {
+      const double hn = sqrt(qn[0]);
+      k += 1;
+      if (!finite(hn)) {
+        st = ST_NONFINITE;
+      } else {
+        // the previous rotations applied to column j, read one entry per lane
+        const int cj = j * (j + 1) / 2;
+        const int ju = __builtin_amdgcn_readfirstlane(j);
+        const int l = (int)lane_id();
+        const double hreg = l <= ju ? hcol[l] : 0.0;
+        const double creg = l < ju ? cs[l] : 0.0, sreg = l < ju ? sn[l] : 0.0;
+        double hp = rdlane(hreg, 0);
+        for (int i = 0; i < ju; ++i) {
+          const double hnx = rdlane(hreg, i + 1), c = rdlane(creg, i), s = rdlane(sreg, i);
+          Rt[cj + i] = c * hp + s * hnx;
+          hp = -s * hp + c * hnx;
+        }
+        const double dd = sqrt(hp * hp + hn * hn);
+        if (dd == 0.0) {
+          st = ST_BREAKDOWN;
+        } else {
+          const double c = hp / dd, s = hn / dd;
+          cs[j] = c;
+          sn[j] = s;
+          Rt[cj + j] = dd;
+          gv[j] = c * gcur;
+          gcur = -s * gcur;
+          end = fabs(gcur) <= lim || hn == 0.0 || k >= g.max_iter || j == m - 1;
+          if (!end) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              vcur[r] = w[r] / hn;
+              if (A.ok[r]) *at(j + 1, r) = vcur[r];
+            }
+            j += 1;
+          }
+        }
+      }
+    }
+    // ---- cycle end: y = R^{-1} g (back substitution), x += M V y
+    if (tm.any(end)) {
+      double zacc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) zacc[r] = 0.0;
+      if (end) {
+        const int je = __builtin_amdgcn_readfirstlane(j);
+        const int l = (int)lane_id();
+        double acc = l <= je ? gv[l] : 0.0;
+        for (int i = je; i >= 0; --i) {
+          const double yi = rdlane(acc, i) / Rt[i * (i + 1) / 2 + i];
+          if (l < i) acc = fma(-Rt[i * (i + 1) / 2 + l], yi, acc);
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (A.ok[r]) zacc[r] = fma(yi, *at(i, r), zacc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) P.x[r] = fma(P.d[r], zacc[r], P.x[r]);
+        start = true;
+      }
+    }
+  }
+  finish(tm, A, g, P.b, P.x, st, k, 0, bn, rn,
+         st == ST_CONVERGED || st == ST_IDLE || (st == ST_MAX_ITER && start));
+}
+
+// GMRES beyond 1024 rows on streamed rows: one system per workgroup of
+// VS::WG lanes x VS::R rows, workgroup b keeping its basis at
+// ws + b * (kMaxRestart + 1) * VS::ROWS; systems taken in turn.
+template <class VS>
+__global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(VarRowsS<VS, kSrcShared>::OCC)))
+void k_gmres_wide(const KArgs g, double* ws) {
+  __shared__ __align__(16) char smem[var_lds_bytes<VS>() + round16(kGmresScalars * 8)];
+  const unsigned lds_base = lds_addr(smem);
+  constexpr unsigned kBuf = var_buf_bytes<VS>();
+  if (threadIdx.x < VS::MAXT * kVecBuffers) {  // zero cells of both buffers
+    const int b = threadIdx.x / VS::MAXT, t = threadIdx.x % VS::MAXT;
+    lds_store<double>(lds_base + b * kBuf + (VS::ROWS + t) * 8, 0.0);
+  }
+  __syncthreads();
+  VarTeam<VS> tm;
+  tm.phase = 0;
+  tm.set_team(VS::WG, smem);
+  double* const wb = ws + (size_t)blockIdx.x * (kMaxRestart + 1) * VS::ROWS;
+  for (int64_t s = blockIdx.x; s < g.n_batch; s += gridDim.x) {
+    tm.live = true;
+    tm.sys = s;
+    tm.row0 = s * g.n;
+    VarRowsS<VS, kSrcShared> A;
+    A.load(tm, g, lds_base);
+    gmres_system_wide(tm, A, g, wb);
+    __syncthreads();  // done with the buffers before the next system
+  }
+}
+
 }  // namespace bs

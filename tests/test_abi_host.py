@@ -116,10 +116,15 @@ def test_plan_covers_rows(L, n):
             p = bs.bs_plan(bs.ELL, n, n * maxrow, maxrow, solver)
         except bs.BatchSolveError as e:
             assert e.code == bs.ERR_UNSUPPORTED
-            assert n > bs.MAX_ROWS or (solver == bs.GMRES and n > 1024)
+            assert n > bs.MAX_ROWS
             continue
         assert p["team"] * p["rows_per_lane"] >= n
         assert p["team"] in (16, 32, 64, 128, 256, 512, 1024)
+        if solver == bs.GMRES and n > 1024:
+            # streamed rows, the basis in device memory
+            assert p["slots"] == 0 and p["rows_per_lane"] == 2 and p["group_size"] == 1024
+            assert p["lds_bytes"] <= 64 * 1024
+            continue
         assert p["slots"] >= maxrow
         assert p["group_size"] % 64 == 0 and p["group_size"] == max(p["team"], 64)
         assert p["systems_per_group"] * p["team"] == p["group_size"]
@@ -189,11 +194,12 @@ def test_plan_stage_and_limits(L):
 
 def test_plan_streamed_two_rows(L):
     """1025..2048 rows: register shapes of 2 rows x 8 slots where the rows fit,
-    else the streamed placement on 1024-lane x 2-row workgroups (CG, BiCGSTAB);
-    GMRES stops at 1024 rows and every solver at 2048."""
+    else the streamed placement on 1024-lane x 2-row workgroups (CG, BiCGSTAB,
+    and GMRES in FP64 with its basis in device memory); every solver stops at
+    2048 rows, mixed GMRES at 1024."""
     p = bs.bs_plan(bs.CSR, 1600, 8000, 5, bs.BICGSTAB)
     assert p["slots"] == 8 and p["team"] == 1024 and p["rows_per_lane"] == 2
-    for solver in (bs.CG, bs.BICGSTAB):
+    for solver in (bs.CG, bs.BICGSTAB, bs.GMRES):
         for n in (1025, 1600, 2048):
             p = bs.bs_plan(bs.CSR, n, 9 * n, 9, solver)
             assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 2, (solver, n)
@@ -201,10 +207,13 @@ def test_plan_streamed_two_rows(L):
         p = bs.bs_plan(bs.CSR, 1600, 1600 * 9, 9, solver, bs.make_options(precision=bs.MIXED)) \
             if solver == bs.BICGSTAB else p
         assert p["slots"] == 0
-    for solver, n in ((bs.GMRES, 1025), (bs.BICGSTAB, 2049), (bs.CG, 2049)):
+    for solver, n in ((bs.GMRES, 2049), (bs.BICGSTAB, 2049), (bs.CG, 2049)):
         with pytest.raises(bs.BatchSolveError) as e:
             bs.bs_plan(bs.CSR, n, 9 * n, 9, solver)
         assert e.value.code == bs.ERR_UNSUPPORTED, (solver, n)
+    with pytest.raises(bs.BatchSolveError) as e:
+        bs.bs_plan(bs.CSR, 1600, 9 * 1600, 9, bs.GMRES, bs.make_options(precision=bs.MIXED))
+    assert e.value.code == bs.ERR_UNSUPPORTED
 
 
 def test_plan_ilu_trsv_teams(L):
@@ -339,8 +348,10 @@ def test_dense_format_host(L):
     assert p["slots"] == 0 and p["team"] == 64 and p["rows_per_lane"] == 2
     p = bs.bs_plan(bs.DENSE, 65, 0, 0, bs.GMRES)
     assert p["slots"] == 0 and p["team"] == 1024
+    p = bs.bs_plan(bs.DENSE, 1025, 0, 0, bs.GMRES)
+    assert p["slots"] == 0 and p["team"] == 1024 and p["rows_per_lane"] == 2
     with pytest.raises(bs.BatchSolveError) as e:
-        bs.bs_plan(bs.DENSE, 1025, 0, 0, bs.GMRES)
+        bs.bs_plan(bs.DENSE, 2049, 0, 0, bs.GMRES)
     assert e.value.code == bs.ERR_UNSUPPORTED
     h = C.c_void_p()
     assert L.bs_pattern_create_dense(0, C.byref(h)) == bs.ERR_INVALID_ARG

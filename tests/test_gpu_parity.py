@@ -1071,7 +1071,7 @@ def test_streamed_two_rows_per_lane(fmt, solver):
     slots of the 2-row shapes take the streamed placement on workgroups of
     1024 lanes x 2 rows: nine-point stencils of 40 x 40 (n = 1600) and 64 x 32
     (n = 2048), nonsymmetric for BiCGSTAB and SPD for CG, against the oracle;
-    GMRES there is refused."""
+    mixed GMRES there is refused."""
     for nx, ny, B in ((40, 40, 24), (64, 32, 9)):
         bt = (W.collision_stencil(B, nx=nx, ny=ny, seed=nx) if solver == bs.BICGSTAB
               else spd_grid9(nx, ny, B, nx))
@@ -1085,8 +1085,33 @@ def test_streamed_two_rows_per_lane(fmt, solver):
         g = c.gpu(fmt, solver, max_iter=2000, precision=bs.MIXED)
         check(c, g, c.oracle(fmt, solver, max_iter=2000), fmt=fmt, itol=10**9)
         with pytest.raises(bs.BatchSolveError) as e:
-            c.gpu(fmt, bs.GMRES)
+            c.gpu(fmt, bs.GMRES, precision=bs.MIXED)
         assert e.value.code == bs.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("fmt", [bs.CSR, bs.ELL])
+def test_streamed_gmres_beyond_1024_rows(fmt):
+    """GMRES on systems of 1025..2048 rows (streamed rows on 1024-lane x
+    2-row workgroups, the basis in device memory): nine-point stencils of
+    n = 1600 and 2048 against the oracle with GMRES(30) restarts, restart 10
+    without a preconditioner from a nonzero start, and a max_iter stop."""
+    for nx, ny, B in ((40, 40, 16), (64, 32, 6)):
+        bt = W.collision_stencil(B, nx=nx, ny=ny, seed=nx + 1)
+        p = bs.bs_plan(fmt, bt.n, int(bt.row_ptr[-1]), 9, bs.GMRES)
+        assert p["slots"] == 0 and p["rows_per_lane"] == 2 and p["group_size"] == 1024
+        c = Case(bt)
+        g = c.gpu(fmt, bs.GMRES, max_iter=2000)
+        o = c.oracle(fmt, bs.GMRES, max_iter=2000)
+        assert o[1].max() > 30  # restarts happen
+        check(c, g, o, fmt=fmt)
+    x0 = np.random.default_rng(61).standard_normal(bt.b.shape)
+    g = c.gpu(fmt, bs.GMRES, precond=bs.PREC_NONE, x0=x0, restart=10, max_iter=3000)
+    check(c, g, c.oracle(fmt, bs.GMRES, precond=bs.PREC_NONE, x0=x0, restart=10, max_iter=3000),
+          fmt=fmt)
+    g = c.gpu(fmt, bs.GMRES, max_iter=20)
+    o = c.oracle(fmt, bs.GMRES, max_iter=20)
+    assert np.all(o[3] == O.MAX_ITER) and np.array_equal(g[3], o[3]) and np.all(g[1] == 20)
+    assert np.allclose(g[2], o[2], rtol=1e-6)
 
 
 @pytest.mark.parametrize("n", [65, 100, 300])
