@@ -268,7 +268,8 @@ typedef struct {
  * non-finite, max_iter < 0, bad restart/team, NULL required pointer),
  * BS_ERR_UNSUPPORTED (n_rows > BS_MAX_ROWS, or no kernel for the request: a
  * row longer than BS_MAX_ROW_NNZ outside the streamed placement's reach, see
- * BS_MAX_ROWS), BS_ERR_HIP (launch failure).  n_batch = 0 is a no-op. */
+ * BS_MAX_ROWS), BS_ERR_HIP (launch failure, or the allocation of GMRES's basis
+ * beyond 1024 rows).  n_batch = 0 is a no-op. */
 int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
                    const double *values, const double *b, double *x, bs_solver solver,
                    bs_precond precond, double tol, int32_t max_iter, int32_t *iters,
@@ -503,8 +504,11 @@ int bs_batch_solve_dev(bs_format fmt, int64_t n_batch, int32_t n_rows,
 /* Bytes of device workspace bs_batch_solve needs for this request: 0.  The
  * fused fixed-size kernels keep every Krylov vector on chip (registers and
  * LDS) and read and write only the caller's arrays, so the solve takes no
- * workspace; the query exists so that a caller written against a workspace
- * protocol can size one.  Pure host function; 0 also for invalid arguments. */
+ * workspace; GMRES beyond 1024 rows, whose basis does not fit on chip, takes
+ * its device memory itself (a stream-ordered allocation on the solve's stream,
+ * freed after the launch).  The query exists so that a caller written against
+ * a workspace protocol can size one.  Pure host function; 0 also for invalid
+ * arguments. */
 size_t bs_workspace_size(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pattern,
                          bs_solver solver, const bs_options *opts);
 
