@@ -1114,6 +1114,50 @@ def test_streamed_gmres_beyond_1024_rows(fmt):
     assert np.allclose(g[2], o[2], rtol=1e-6)
 
 
+@pytest.mark.parametrize("solver", [bs.BICGSTAB, bs.GMRES])
+def test_streamed_2048_options_and_edges(solver):
+    """The 1024-lane x 2-row streamed paths (BiCGSTAB; GMRES with its basis in
+    device memory) with the options of the register kernels: two right-hand
+    sides per matrix (bit-identical to the replicated batch), a second initial
+    guess (the smaller residual wins), b = 0, NaN in b, max_iter = 0, and the
+    oracle's statuses on a system without a preconditioner."""
+    bt = W.collision_stencil(6, nx=40, ny=40, seed=62)
+    c = Case(bt)
+    B, n, k = bt.n_batch, bt.n, 2
+    b = 2 * np.random.default_rng(63).random((B * k, n)) - 1
+    x = torch.zeros((B * k, n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B * k, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    say(f"  2048-row streamed options solver={solver}")
+    bs.bs_batch_solve(bs.CSR, c.P.handle, c.vals, dev(b), x, solver, bs.PREC_JACOBI, 1e-10,
+                      2000, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k))
+    torch.cuda.synchronize()
+    g = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    rep = W.Batch("rep", n, bt.row_ptr, bt.col_idx, np.repeat(bt.values, k, axis=0), b,
+                  np.zeros_like(b))
+    cr = Case(rep)
+    for u, v in zip(g, cr.gpu(bs.CSR, solver, max_iter=2000)):
+        assert np.array_equal(u, v)
+    check(cr, g, cr.oracle(bs.CSR, solver, max_iter=2000))
+    # a second initial guess: x0 = 0 against the oracle's solution
+    xo = c.oracle(bs.CSR, solver, max_iter=2000)[0]
+    used = torch.full((B,), -1, dtype=torch.int32, device="cuda:0")
+    g = c.gpu(bs.CSR, solver, x0=np.zeros_like(bt.b), x_alt=dev(xo), alt_used=used)
+    assert np.all(used.cpu().numpy() == 1) and np.all(g[3] == bs.CONVERGED)
+    assert np.all(g[1] <= 1)
+    # b = 0, NaN in b, max_iter = 0
+    bb = bt.b.copy()
+    bb[2] = 0.0
+    bb[4, 7] = np.nan
+    g = c.gpu(bs.CSR, solver, b=bb)
+    o = c.oracle(bs.CSR, solver, b=bb)
+    assert np.array_equal(g[3], o[3])
+    assert g[3][2] == bs.CONVERGED and np.all(g[0][2] == 0.0) and g[3][4] == bs.NONFINITE
+    g = c.gpu(bs.CSR, solver, max_iter=0)
+    assert np.all(g[3] == bs.MAX_ITER) and np.all(g[1] == 0)
+
+
 @pytest.mark.parametrize("n", [65, 100, 300])
 @pytest.mark.parametrize("solver", [bs.CG, bs.BICGSTAB, bs.GMRES])
 def test_streamed_dense(n, solver):
