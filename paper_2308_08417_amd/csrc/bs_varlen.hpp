@@ -156,11 +156,22 @@ struct VarTeam {
 };
 
 // The R rows a lane owns, their values and LDS gather addresses in registers.
-template <class VS, int NZ_, int SRC = kSrcCsr>
+// MX (the mixed-precision kernels): every team keeps a block of its own in
+// each buffer, team t's T*R elements from element t*(T*R+1) with its zero cell
+// behind them (teams solve independently, so no team may store into a block
+// another team reads).  The addresses are kept for 4-byte elements, the FP32
+// vectors' stride (consecutive elements on consecutive banks), from the block's
+// start; the FP64 products of the outer residual use 2 * address - start, the
+// 8-byte layout of the same block.  A slot without an entry points at the FP32
+// cell behind the rows, whose FP64 image is the block's zero cell; an FP64
+// vector overwrites the FP32 cell, so every FP32 product writes it again.  No
+// block-Jacobi kernel takes this layout.
+template <class VS, int NZ_, int SRC = kSrcCsr, bool MX = false>
 struct VarRows {
   static constexpr int R = VS::R, NZ = NZ_, ROWS = VS::ROWS;
   static constexpr int OCC = VS::OCC;  // waves per SIMD the allocator is held to
   static constexpr unsigned kBuf = var_buf_bytes<VS>();
+  static constexpr unsigned kElem = MX ? 4 : 8;  // bytes between elements in c and vrow
   double a[R][NZ];
   unsigned c[R][NZ];
   unsigned vrow[R];
@@ -168,6 +179,7 @@ struct VarRows {
   bool ok[R];
   int dslot[R];
   unsigned zero;
+  unsigned b0;  // MX: start of this team's block in buffer 0
   int n;  // rows of this team's system
   double dval[R], bval[R], xval[R], xalt[R];
 
@@ -179,15 +191,26 @@ struct VarRows {
     const int s = tm.live ? (int)tm.sys : 0;
     n = tm.live ? va.sys_rows[s] : 0;
     const int p = va.sys_pat[s];
-    const unsigned tb = lds_base + (unsigned)(tm.tix * tm.T * R) * 8;
-    zero = lds_base + (unsigned)(ROWS + tm.tix) * 8;
+    const unsigned tr = (unsigned)(tm.T * R);  // rows of a team's block
+    const unsigned tb = MX ? lds_base + (unsigned)tm.tix * (tr + 1) * 8
+                           : lds_base + (unsigned)tm.tix * tr * 8;
+    zero = MX ? tb + tr * 4 : lds_base + (unsigned)(ROWS + tm.tix) * 8;
+    b0 = tb;
+    if constexpr (MX) {
+      // the block's FP64 zero cell in both buffers (the previous task may have
+      // left a row value there); the first product's barrier orders these stores
+      if (tm.lane == 0) {
+        lds_store<double>(tb + tr * 8, 0.0);
+        lds_store<double>(tb + tr * 8 + kBuf, 0.0);
+      }
+    }
     const int* rps = va.rowptr_all + va.pat_rp[p];
     const double* vals = g.values + va.val_off[s];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       row[r] = tm.lane + r * tm.T;
       ok[r] = row[r] < n;
-      vrow[r] = tb + (unsigned)row[r] * 8;
+      vrow[r] = tb + (unsigned)row[r] * kElem;
       const int rr = row[r];
       int len = 0, ds = -1, rp = 0;
       double dv = 0.0;
@@ -222,7 +245,7 @@ struct VarRows {
           ds = k;
           dv = v;
         }
-        c[r][k] = has ? tb + col * 8 : zero;
+        c[r][k] = has ? tb + col * kElem : zero;
         a[r][k] = v;
       }
       dslot[r] = ds;
@@ -253,9 +276,24 @@ struct VarRows {
                                        V (&y)[R]) const {
     constexpr int kGather = 4;
     constexpr unsigned off = BUF * kBuf;
+    // FP64 vectors in a mixed kernel: twice the 4-byte-element address, formed
+    // at each use (the empty asm keeps a second set of addresses out of the
+    // registers)
+    constexpr bool kWide = MX && sizeof(V) == 8;
+    auto at = [&](unsigned x) -> unsigned {
+      if constexpr (kWide) {
+        __asm__ volatile("" : "+v"(x));
+        return 2u * x - b0;
+      } else {
+        return x;
+      }
+    };
 #pragma unroll
     for (int r = 0; r < R; ++r)
-      if (ok[r]) lds_store<V>(vrow[r] + off, v[r]);
+      if (ok[r]) lds_store<V>(at(vrow[r]) + off, v[r]);
+    if constexpr (MX && sizeof(V) == 4) {
+      if (tm.lane == 0) lds_store<float>(zero + off, 0.0f);
+    }
     tm.sync();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -264,7 +302,7 @@ struct VarRows {
       for (int k0 = 0; k0 < NZ; k0 += kGather) {
         V xv[kGather];
 #pragma unroll
-        for (int k = k0; k < k0 + kGather && k < NZ; ++k) xv[k - k0] = lds_load<V>(c[r][k] + off);
+        for (int k = k0; k < k0 + kGather && k < NZ; ++k) xv[k - k0] = lds_load<V>(at(c[r][k]) + off);
 #pragma unroll
         for (int k = k0; k < k0 + kGather && k < NZ; ++k)
           acc[k % 4] = fma((V)av[r][k], xv[k - k0], acc[k % 4]);
@@ -454,6 +492,7 @@ __global__ void k_varlen_reset(int* counter);
 template <class VS, class RowsT, int SOLVER, bool MIXED, bool BJ = false>
 __global__ __launch_bounds__(VS::WG) __attribute__((amdgpu_waves_per_eu(RowsT::OCC)))
 void k_varlen(const VArgs va) {
+  static_assert(!(MIXED && BJ), "the mixed kernels' per-team blocks carry no block Jacobi");
   // buffers and reduction slots, then (BJ) the block-Jacobi region of the largest block
   __shared__ __align__(16) char smem[var_lds_bytes<VS>() + (BJ ? bj_bytes(VS::ROWS, kMaxBlock) : 0)];
   __shared__ int task_sh;

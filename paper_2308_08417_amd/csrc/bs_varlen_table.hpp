@@ -35,8 +35,8 @@ struct VEntry {
 // Registers: SO = 0 CG, 1 BiCGSTAB; MX mixed; BJ block Jacobi.
 #define BS_VREG(W, R, NZ, SO, MX, BJ, SRC)                                                      \
   {W, R, NZ, SO, MX, BJ, SRC, 0,                                                                \
-   &bs::vlaunch<bs::VarShape<W, R>, bs::VarRows<bs::VarShape<W, R>, NZ, SRC>, SO, MX, BJ>,      \
-   &bs::voccupancy<bs::VarShape<W, R>, bs::VarRows<bs::VarShape<W, R>, NZ, SRC>, SO, MX, BJ>},
+   &bs::vlaunch<bs::VarShape<W, R>, bs::VarRows<bs::VarShape<W, R>, NZ, SRC, MX>, SO, MX, BJ>,  \
+   &bs::voccupancy<bs::VarShape<W, R>, bs::VarRows<bs::VarShape<W, R>, NZ, SRC, MX>, SO, MX, BJ>},
 #define BS_VSTREAM(W, R, SO, MX, SRC)                                                           \
   {W, R, 0, SO, MX, 0, SRC, 1,                                                                  \
    &bs::vlaunch<bs::VarShape<W, R>, bs::VarRowsS<bs::VarShape<W, R>, SRC>, SO, MX, false>,      \
