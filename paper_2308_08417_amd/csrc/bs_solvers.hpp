@@ -1594,8 +1594,12 @@ __global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC)))
   BS_PERSISTENT_LOOP(false, (cg_system<PK>(tm, A, ga)))
 }
 
+// GMRES keeps its basis in registers beside the row: held to three waves per
+// SIMD, the one-wave shapes of 24..32 slots spill (60..148 bytes per lane),
+// and their LDS (staging plus the Hessenberg scalars, about 16 KB per wave)
+// leaves room for only 2.5 anyway, so they are held to two, as the mixed ones.
 template <class S, bool MIXED, int PK = kPkScalar>
-__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_gmres(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(S::OCC_MIXED))) void k_gmres(const KArgs g) {
   BS_PERSISTENT_LOOP((kLds32<S, MIXED>), (gmres_system<MIXED, PK>(tm, A, ga)))
 }
 
