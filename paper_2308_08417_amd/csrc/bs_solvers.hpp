@@ -1579,8 +1579,11 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
 template <class S, bool MIXED>
 constexpr bool kLds32 = MIXED && (S::ROWS > kWave);
 
+// ILU(0) on one-wave teams: the dense factors (about 25 KB of LDS per wave
+// for 54 rows) leave room for fewer than two waves per SIMD, so the register
+// budget is that of two (no spills) rather than three.
 template <class S, bool MIXED, int PK = kPkScalar>
-__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu(MIXED ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
+__global__ __launch_bounds__(S::WG) __attribute__((amdgpu_waves_per_eu((MIXED || PK == kPkIlu) ? S::OCC_MIXED : S::OCC))) void k_bicgstab(const KArgs g) {
   BS_PERSISTENT_LOOP((kLds32<S, MIXED>), (bicgstab_system<MIXED, PK>(tm, A, ga)))
 }
 
