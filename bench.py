@@ -220,6 +220,61 @@ def stiff_leg(args, bs, W, torch, np, dev, tol, max_iter):
     return out
 
 
+def mechanisms_leg(args, bs, W, torch, np, dev, tol, max_iter):
+    """The five reacting-flow shapes of Tab. 3 (stand-ins drawn by
+    ``W.mechanism_batch``: the table's rows, stored entries and count of
+    distinct systems, replicated over ``args.mech_batch`` systems), BiCGSTAB +
+    scalar Jacobi to 1e-10 from x0 = 0 in BatchCsr, as the paper runs them
+    (Sec. 4.3); per shape the plan's kernel and the HBM fraction of the
+    algorithmic bytes (values, b and x once, the outputs, the pattern once)."""
+    out = {}
+    steps = max(5, args.steps // 10)
+    for name in W.MECHANISMS:
+        t0 = time.perf_counter()
+        bt = W.mechanism_batch(name, n_batch=args.mech_batch, gamma=1e-6, seed=0)
+        gen_s = time.perf_counter() - t0
+        B, n, nnz = bt.n_batch, bt.n, bt.nnz
+        max_row = int(np.diff(bt.row_ptr).max())
+        P = bs.Pattern.from_csr(bt.row_ptr, bt.col_idx)
+        vals = torch.from_numpy(bt.values).to(dev)
+        b = torch.from_numpy(bt.b).to(dev)
+        del bt
+        x = torch.empty_like(b)
+        iters = torch.empty(B, dtype=torch.int32, device=dev)
+        resid = torch.empty(B, dtype=torch.float64, device=dev)
+        status = torch.empty(B, dtype=torch.int32, device=dev)
+        opts = bs.make_options(flags=bs.FLAG_X0_ZERO)
+        a = (bs.CSR, P.handle, vals, b, x, bs.BICGSTAB, bs.PREC_JACOBI, tol, max_iter, iters,
+             resid, status, opts)
+        for _ in range(max(3, args.warmup // 20)):
+            bs.bs_batch_solve(*a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bs.bs_batch_solve(*a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st, rs, it = status.cpu().numpy(), resid.cpu().numpy(), iters.cpu().numpy()
+        alg = B * (8 * nnz + 8 * n + 8 * n + 16) + 4 * (n + 1) + 4 * nnz
+        plan = bs.bs_plan(bs.CSR, n, nnz, max_row, bs.BICGSTAB)
+        out[name] = {
+            "workload": f"{name}_standin_b{B}_n{n}_nnz{nnz}_csr_bicgstab_jacobi_fp64",
+            "n_rows": n, "nnz": nnz, "unique": W.MECHANISMS[name][0], "max_row": max_row,
+            "ms": ms, "systems_per_s": B / (ms * 1e-3),
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": alg,
+            "all_converged": bool(np.all(st == bs.CONVERGED) and np.all(rs <= tol)),
+            "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+            "max_resid": float(rs.max()),
+            "plan": {k: plan[k] for k in ("team", "rows_per_lane", "slots", "group_size",
+                                          "systems_per_group", "lds_bytes")},
+            "gen_seconds": gen_s}
+        del vals, b, x
+    return out
+
+
 def multi_rhs_leg(args, bs, W, torch, np, dev, tol, max_iter):
     """Several right-hand sides per matrix: ``args.rhs_batch`` chemistry matrices
     (the headline's pattern and distribution) with ``args.n_rhs`` right-hand sides
@@ -617,6 +672,9 @@ def main() -> int:
     ap.add_argument("--no-stiff", action="store_true",
                     help="skip the preconditioner leg (2^16 stiffer chemistry systems)")
     ap.add_argument("--stiff-batch", type=int, default=1 << 16)
+    ap.add_argument("--no-mechanisms", action="store_true",
+                    help="skip the Tab. 3 shapes leg (five stand-ins of 2^17 systems each)")
+    ap.add_argument("--mech-batch", type=int, default=1 << 17)
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the 9-point stencil leg (4096 systems, n = 992, FP64 vs mixed)")
     ap.add_argument("--stencil-batch", type=int, default=4096)
@@ -764,6 +822,13 @@ def main() -> int:
         progress("stiff: " + ", ".join(f"{k} {v['ms']:.3f} ms ({v['iters_mean']:.1f} it)"
                                        for k, v in stiff.items() if isinstance(v, dict)))
 
+    mech = None
+    if not args.no_mechanisms:
+        mech = mechanisms_leg(args, bs, W, torch, np, dev, tol, max_iter)
+        progress("mechanisms: " + ", ".join(
+            f"{k} {v['ms']:.3f} ms ({100 * v['hbm_frac']:.0f}% HBM, {v['iters_mean']:.1f} it)"
+            for k, v in mech.items()))
+
     stencil = None
     if not args.no_stencil:
         stencil = stencil_leg(args, bs, W, torch, np, dev, tol, max_iter)
@@ -873,6 +938,7 @@ def main() -> int:
         "uneven": uneven,
         "stencil": stencil,
         "stiff": stiff,
+        "mechanisms": mech,
         "multi_rhs": multi,
         "dense": dense,
         "warm_start": warm,

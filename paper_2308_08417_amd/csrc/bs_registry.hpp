@@ -49,9 +49,10 @@ KernelTable kernels_trsv_upper();
 #define BS_SHAPES_R1(X)                                                                   \
   X(16, 1, 4) X(16, 1, 8) X(16, 1, 16)                                                    \
   X(32, 1, 4) X(32, 1, 8) X(32, 1, 16) X(32, 1, 32)                                       \
-  X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 24) X(64, 1, 28) X(64, 1, 32) X(64, 1, 64)                          \
-  X(128, 1, 4) X(128, 1, 8) X(128, 1, 16) X(128, 1, 32) X(128, 1, 64)                     \
-  X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 64)                     \
+  X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 24) X(64, 1, 28) X(64, 1, 32) X(64, 1, 56)  \
+  X(64, 1, 64)                                                                            \
+  X(128, 1, 4) X(128, 1, 8) X(128, 1, 16) X(128, 1, 32) X(128, 1, 56) X(128, 1, 64)       \
+  X(256, 1, 4) X(256, 1, 8) X(256, 1, 16) X(256, 1, 32) X(256, 1, 56) X(256, 1, 64)       \
   X(512, 1, 4) X(512, 1, 8) X(512, 1, 16) X(512, 1, 32)                                   \
   X(1024, 1, 4) X(1024, 1, 8) X(1024, 1, 12) X(1024, 1, 16)
 // ILU(0) and BatchTrsv shapes: one-wave teams (systems of up to 64 rows, dense

@@ -99,7 +99,11 @@ struct Shape {
 #ifndef BS_OCC_ONE_WAVE
 #define BS_OCC_ONE_WAVE 3
 #endif
-  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE : 1;
+  // Rows of 33..56 entries (56 slots) fit 256 registers beside the vectors:
+  // two waves per SIMD, where the 64-slot shapes take 256 and more (one).
+  static constexpr int OCC = (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE
+                             : (R == 1 && NZ == 56)                          ? 2
+                                                                             : 1;
   // The mixed-precision forms hold an FP32 copy of the rows beside the FP64
   // one: at three waves per SIMD they spill, at two they do not (and a solve
   // from a close start, one inner iteration, runs 9% faster so).

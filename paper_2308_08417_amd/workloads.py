@@ -33,6 +33,9 @@ __all__ = [
     "uneven_banded",
     "chem_trajectory",
     "grid9_pattern",
+    "MECHANISMS",
+    "mechanism_pattern",
+    "mechanism_batch",
 ]
 
 _CHUNK = 8192  # systems per draw chunk; the stream is consumed sequentially
@@ -162,6 +165,60 @@ def chem_jacobian(n_batch: int = 1 << 17, n: int = 54, fill: float = 0.35,
     b = 2.0 * _uniform(rng, (n_batch, n)) - 1.0
     return Batch("chem_jacobian", n, row_ptr, col_idx, values, b,
                  np.zeros((n_batch, n)), {"seed": seed, "gamma": gamma, "fill": fill})
+
+
+# --------------------------------------------------------------------------
+# Stand-ins for the reacting-flow mechanisms of Tab. 3: their sizes, their
+# counts of distinct matrices, replicated over the batch.
+# --------------------------------------------------------------------------
+# name: (distinct matrices, rows, stored entries per matrix), Tab. 3
+MECHANISMS = {
+    "drm19": (67, 22, 438),
+    "gri12": (73, 33, 978),
+    "gri30": (90, 54, 2560),
+    "dodecane_lu": (78, 54, 2332),
+    "isooctane": (72, 144, 6135),
+}
+
+
+def mechanism_pattern(n: int, nnz: int, rng: np.random.Generator):
+    """Full diagonal plus ``nnz - n`` off-diagonal positions drawn uniformly
+    without replacement: one ``rng.permutation`` of the n(n-1) off-diagonal
+    positions (row-major order), whose first ``nnz - n`` are kept."""
+    if not n <= nnz <= n * n:
+        raise ValueError("need n <= nnz <= n^2")
+    off = np.flatnonzero(~np.eye(n, dtype=bool))
+    pick = rng.permutation(off.size)[: nnz - n]
+    mask = np.eye(n, dtype=bool)
+    mask.flat[off[pick]] = True
+    return _csr_from_mask(mask)
+
+
+def mechanism_batch(name: str, n_batch: int = 1 << 17, gamma: float = 1e-6,
+                    seed: int = 0) -> Batch:
+    """One Tab. 3 input: its ``unique`` distinct systems, ``A = I - gamma*J``
+    (``J_ij = +-10^U(-3,3)``, the chemistry model above) on a shared pattern
+    of the table's size, each with its own b ~ U(-1,1), replicated over the
+    batch in turn (system s is distinct system s mod unique), as the paper
+    fills its batches from the matrices of a few cells (Sec. 4.1).
+
+    Draw order: the pattern's permutation; ``rng.random((unique, nnz, 2))``
+    as (sign, exponent) pairs per stored entry in CSR order; then
+    ``2*rng.random((unique, n)) - 1`` for b.  x0 = 0.
+    """
+    unique, n, nnz = MECHANISMS[name]
+    rng = np.random.default_rng(seed)
+    row_ptr, col_idx = mechanism_pattern(n, nnz, rng)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    is_diag = rows == col_idx
+    vu = -gamma * _log_uniform_signed(rng.random((unique, nnz, 2)), -3.0, 3.0)
+    vu[:, is_diag] += 1.0
+    bu = 2.0 * rng.random((unique, n)) - 1.0
+    reps = -(-n_batch // unique)
+    values = np.ascontiguousarray(np.tile(vu, (reps, 1))[:n_batch])
+    b = np.ascontiguousarray(np.tile(bu, (reps, 1))[:n_batch])
+    return Batch(name, n, row_ptr, col_idx, values, b, np.zeros((n_batch, n)),
+                 {"seed": seed, "gamma": gamma, "unique": unique})
 
 
 # --------------------------------------------------------------------------

@@ -188,6 +188,26 @@ def test_collision_stencil(fmt, solver):
     assert np.all(g[3] == bs.CONVERGED)
 
 
+@pytest.mark.parametrize("name", list(W.MECHANISMS))
+def test_mechanism_shapes(name):
+    """The five reacting-flow shapes of Tab. 3 (22..144 rows, 29..90 % fill):
+    BiCGSTAB + scalar Jacobi in BatchCsr, as the paper runs them, and in
+    BatchEll; GMRES(30) in BatchCsr; at gamma 1e-6 (2..3 iterations) and 3e-4
+    (8..14).  The batch holds each distinct system twice and then some, as
+    the paper replicates a few cells' matrices: a copy returns its original's
+    bits."""
+    u = W.MECHANISMS[name][0]
+    for gamma in (1e-6, 3e-4):
+        c = Case(W.mechanism_batch(name, n_batch=2 * u + 7, gamma=gamma, seed=3))
+        for fmt, solver in ((bs.CSR, bs.BICGSTAB), (bs.ELL, bs.BICGSTAB), (bs.CSR, bs.GMRES)):
+            g = c.gpu(fmt, solver)
+            o = c.oracle(fmt, solver)
+            check(c, g, o, fmt=fmt)
+            assert np.all(g[3] == bs.CONVERGED)
+            for k in range(4):
+                assert np.array_equal(g[k][u:2 * u], g[k][:u])
+
+
 @pytest.mark.parametrize("team", [128, 256, 512])
 def test_forced_wider_teams(team):
     """A system spread over more lanes (several waves) gives the same result."""
