@@ -428,13 +428,22 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   // of staging
   if (waves == 1 && !tri && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
     stage = 1;
+  // Multi-wave teams, CSR, rows of many slots: each system's values copied
+  // into LDS by the whole group before its solve (coalesced loads), where
+  // they fit beside the vectors; the launch keeps it only where it costs no
+  // resident group.
+  if (waves > 1 && fmt == BS_CSR && !tri && k->nz >= bs::kStageMinSlots &&
+      vec + bs::round16(nnz * 8) <= kLdsPerCu)
+    stage = 2;
   out->k = k;
   out->info.team = team;
   out->info.rows_per_lane = r;
   out->info.slots = k->nz;
   out->info.group_size = wg;
   out->info.systems_per_group = teams;
-  out->info.lds_bytes = vec + (stage ? bs::stage_total_bytes(teams, stored, n, k->nz) : 0);
+  out->info.lds_bytes = vec + (stage == 1   ? bs::stage_total_bytes(teams, stored, n, k->nz)
+                               : stage == 2 ? bs::round16(nnz * 8)
+                                            : 0);
   out->info.stage_values = stage;
   // a workgroup's LDS is at most that of a compute unit
   if (out->info.lds_bytes > kLdsPerCu) return BS_ERR_UNSUPPORTED;
@@ -837,10 +846,17 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   // Resident groups per CU, asked with 1 KiB more LDS per group than used: a
   // group count that would fill the CU's LDS to the last granule is not always
   // placed at once, and a group left over runs only after another one ends.
-  const int64_t resident = (int64_t)pl.k->occupancy((unsigned)pl.info.lds_bytes + 1024) * cus;
+  int lds = pl.info.lds_bytes;
+  if (a.stage == 2) {  // the group-wide copy of the values only where no group is lost to it
+    const int without = lds - bs::round16(pattern->nnz * 8);
+    if (pl.k->occupancy((unsigned)lds + 1024) < pl.k->occupancy((unsigned)without + 1024)) {
+      a.stage = 0;
+      lds = without;
+    }
+  }
+  const int64_t resident = (int64_t)pl.k->occupancy((unsigned)lds + 1024) * cus;
   const int64_t grid = std::min(groups, resident);
-  const hipError_t e = pl.k->launch(a, (unsigned)grid, (unsigned)pl.info.lds_bytes,
-                                    (hipStream_t)stream);
+  const hipError_t e = pl.k->launch(a, (unsigned)grid, (unsigned)lds, (hipStream_t)stream);
   return e == hipSuccess ? BS_OK : hip_fail(e, "solver launch");
 }
 

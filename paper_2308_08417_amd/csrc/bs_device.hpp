@@ -501,10 +501,71 @@ struct Rows {
         load_x0(tm, g, rw);
         return;
       }
+    } else if constexpr (S::NZ >= kStageMinSlots) {
+      if (g.stage == 2) {
+        // Multi-wave teams, CSR: the whole group copies the system's values
+        // (nnz consecutive doubles) into LDS with coalesced loads, eight in
+        // flight per lane, then each lane reads its row's window from there.
+        // Lanes reading their rows straight from HBM touch one line per lane
+        // and load, which the caches serve far more slowly.
+        constexpr int kU = 8;
+        // (one team per group: its region starts the group's LDS, and the
+        // staging area sits stage_offset bytes further)
+        double* sv = reinterpret_cast<double*>(tm.lds + g.stage_offset);
+        const int nn = g.nnz;
+        __syncthreads();  // the previous system's readers are done with the block
+        for (int i0 = 0; i0 < nn; i0 += kU * S::WG) {
+          double t[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * S::WG + (int)threadIdx.x;
+            t[u] = __builtin_nontemporal_load(vals + (i < nn ? i : 0));
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * S::WG + (int)threadIdx.x;
+            if (i < nn) sv[i] = t[u];
+          }
+        }
+        __syncthreads();
+        const unsigned st = lds_addr(tm.lds) + (unsigned)g.stage_offset;
+#pragma unroll
+        for (int r = 0; r < S::R; ++r) {
+          if (win) {
+            const unsigned wa = st + off[r] * 8;
+#pragma unroll
+            for (int k = 0; k < S::NZ; ++k) a[r][k] = lds_load<double>(wa + k * 8);
+          } else {
+#pragma unroll
+            for (int k = 0; k < S::NZ; ++k) {
+              const bool has = k < ln[r];
+              const double v = lds_load<double>(st + (has ? off[r] + k : 0) * 8);
+              a[r][k] = has ? v : 0.0;
+            }
+          }
+          const double dv = lds_load<double>(st + (ds[r] >= 0 ? off[r] + ds[r] : 0) * 8);
+          dval[r] = ds[r] >= 0 ? dv : 0.0;
+          const double bv = bb[rw[r] >= 0 ? rw[r] : 0];
+          bval[r] = rw[r] >= 0 ? bv : 0.0;
+        }
+        load_x0(tm, g, rw);
+        return;
+      }
     }
 #pragma unroll
     for (int r = 0; r < S::R; ++r) {
-      if (win) {
+      if constexpr (S::WAVES > 1 && S::NZ == 56) {
+        // every load of the row first, the zeros of the empty slots after: in
+        // this shape the select form made the compiler wait for each load (the
+        // select's condition lives in the one VCC register) before issuing
+        // the next; the other shapes keep their loads in flight either way
+        double v[S::NZ];
+#pragma unroll
+        for (int k = 0; k < S::NZ; ++k)
+          v[k] = __builtin_nontemporal_load(vals + ((win || k < ln[r]) ? off[r] + k * step : 0));
+#pragma unroll
+        for (int k = 0; k < S::NZ; ++k) a[r][k] = (win || k < ln[r]) ? v[k] : 0.0;
+      } else if (win) {
 #pragma unroll
         for (int k = 0; k < S::NZ; ++k) a[r][k] = __builtin_nontemporal_load(vals + off[r] + k);
       } else {
@@ -520,15 +581,20 @@ struct Rows {
       const double bv = bb[rw[r] >= 0 ? rw[r] : 0];
       bval[r] = rw[r] >= 0 ? bv : 0.0;
     }
-    // Complete these loads here: the registers are shared with the staged path,
-    // and a load left pending would make the compiler wait on the in-order
-    // memory counter later, which would also drain the prefetch in flight.
+    // Single-wave groups complete these loads here: the registers are shared
+    // with the staged path, and a load left pending would make the compiler
+    // wait on the in-order memory counter later, which would also drain the
+    // prefetch in flight.  Wider groups have neither (and the barrier made
+    // the compiler wait for each load before issuing the next): their loads
+    // stay in flight together until the first product needs them.
+    if constexpr (S::WAVES == 1) {
 #pragma unroll
-    for (int r = 0; r < S::R; ++r) {
+      for (int r = 0; r < S::R; ++r) {
 #pragma unroll
-      for (int k = 0; k < S::NZ; ++k) settle(a[r][k]);
-      settle(dval[r]);
-      settle(bval[r]);
+        for (int k = 0; k < S::NZ; ++k) settle(a[r][k]);
+        settle(dval[r]);
+        settle(bval[r]);
+      }
     }
     load_x0(tm, g, rw);
   }

@@ -114,6 +114,13 @@ struct Shape {
       (WAVES == 1 && R == 1 && NZ >= 24 && NZ <= 32) ? BS_OCC_ONE_WAVE_MIXED : 1;
 };
 
+// Multi-wave teams copy a system's CSR values into LDS with the whole group
+// (coalesced) in the shapes of at least this many register slots per row:
+// there a lane's row spans many cache lines and reading it straight from HBM
+// is slowest.  The copy's code costs the narrower shapes a few registers and,
+// with them, a resident wave, for no gain on their short rows.
+constexpr int kStageMinSlots = 32;
+
 // Vector buffers per team (SpMV source vectors, double-buffered).  Each buffer
 // holds ROWS elements plus one cell that stays zero: register slots that hold
 // no entry of the lane's row gather from it.

@@ -170,9 +170,21 @@ def test_plan_stage_and_limits(L):
     # single-wave groups prefetch each system's values and b into LDS
     p = bs.bs_plan(bs.ELL, 54, 1042, 28, bs.BICGSTAB)
     assert p["stage_values"] == 1 and p["lds_bytes"] >= (28 * 54 + 54) * 8
-    # multi-wave teams read HBM directly
+    # multi-wave teams read ELL values (slot-major: coalesced) straight from HBM
     p = bs.bs_plan(bs.ELL, 992, 8554, 9, bs.BICGSTAB)
     assert p["group_size"] == 1024 and p["stage_values"] == 0
+    # and CSR values of short rows straight from HBM too
+    p = bs.bs_plan(bs.CSR, 992, 8554, 9, bs.BICGSTAB)
+    assert p["group_size"] == 1024 and p["slots"] == 12 and p["stage_values"] == 0
+    # rows of 32 slots or more: the whole group copies each system's CSR values
+    # into LDS, beside the vectors
+    p = bs.bs_plan(bs.CSR, 144, 6135, 54, bs.BICGSTAB)
+    assert p["group_size"] == 256 and p["slots"] == 56 and p["stage_values"] == 2
+    assert p["lds_bytes"] >= 6135 * 8 + 2 * 257 * 8
+    p = bs.bs_plan(bs.CSR, 300, 2700, 20, bs.CG)
+    assert p["slots"] == 32 and p["stage_values"] == 2
+    p = bs.bs_plan(bs.CSR, 300, 2700, 16, bs.CG)
+    assert p["slots"] == 16 and p["stage_values"] == 0
     # rows beyond the register slots: the streamed placement (spill tier),
     # workgroups of 512 lanes x 2 rows, no register slots, no staging
     p = bs.bs_plan(bs.CSR, 54, 1042, 65, bs.BICGSTAB)
