@@ -48,7 +48,7 @@ KernelTable kernels_trsv_upper();
 // capped where the registers of a full workgroup would overflow.
 #define BS_SHAPES_R1(X)                                                                   \
   X(16, 1, 4) X(16, 1, 8) X(16, 1, 16)                                                    \
-  X(32, 1, 4) X(32, 1, 8) X(32, 1, 16) X(32, 1, 32)                                       \
+  X(32, 1, 4) X(32, 1, 8) X(32, 1, 16) X(32, 1, 24) X(32, 1, 32)                         \
   X(64, 1, 4) X(64, 1, 8) X(64, 1, 16) X(64, 1, 24) X(64, 1, 28) X(64, 1, 32) X(64, 1, 56)  \
   X(64, 1, 64)                                                                            \
   X(128, 1, 4) X(128, 1, 8) X(128, 1, 16) X(128, 1, 32) X(128, 1, 56) X(128, 1, 64)       \
