@@ -287,9 +287,10 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
  *   stage_values   how the values reach the registers: 0 straight from HBM;
  *                  1 one-wave groups prefetch the next system's values and b
  *                  into LDS while solving the current one; 2 multi-wave teams
- *                  (CSR) copy each system's values into LDS with the whole
- *                  group before its solve (the launch falls back to 0 where
- *                  that LDS would cost a resident workgroup) */
+ *                  (CSR, rows of 32 slots or more) copy the next system's
+ *                  values into LDS with the whole group while solving the
+ *                  current one (the launch falls back to 0 where that LDS
+ *                  would cost a resident workgroup) */
 typedef struct {
   int32_t team, rows_per_lane, slots, group_size, systems_per_group, lds_bytes, stage_values;
 } bs_plan_info;

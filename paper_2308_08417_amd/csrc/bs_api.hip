@@ -429,11 +429,11 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   if (waves == 1 && !tri && bs::stage_total_bytes(teams, stored, n, k->nz) <= kStageBudget)
     stage = 1;
   // Multi-wave teams, CSR, rows of many slots: each system's values copied
-  // into LDS by the whole group before its solve (coalesced loads), where
-  // they fit beside the vectors; the launch keeps it only where it costs no
-  // resident group.
+  // into LDS by the whole group (coalesced direct-to-LDS loads issued during
+  // the previous system's solve), where they fit beside the vectors; the
+  // launch keeps it only where it costs no resident group.
   if (waves > 1 && fmt == BS_CSR && !tri && k->nz >= bs::kStageMinSlots &&
-      vec + bs::round16(nnz * 8) <= kLdsPerCu)
+      vec + bs::stage_vals_bytes(teams, stored, k->nz) <= kLdsPerCu)
     stage = 2;
   out->k = k;
   out->info.team = team;
@@ -442,7 +442,7 @@ int make_plan(bs_format fmt, int n, int nnz, int max_row, int width, bs_solver s
   out->info.group_size = wg;
   out->info.systems_per_group = teams;
   out->info.lds_bytes = vec + (stage == 1   ? bs::stage_total_bytes(teams, stored, n, k->nz)
-                               : stage == 2 ? bs::round16(nnz * 8)
+                               : stage == 2 ? bs::stage_vals_bytes(teams, stored, k->nz)
                                             : 0);
   out->info.stage_values = stage;
   // a workgroup's LDS is at most that of a compute unit
@@ -847,8 +847,11 @@ int bs_batch_solve(bs_format fmt, int64_t n_batch, int32_t n_rows, bs_pattern pa
   // group count that would fill the CU's LDS to the last granule is not always
   // placed at once, and a group left over runs only after another one ends.
   int lds = pl.info.lds_bytes;
+  // the group-wide copy lands in whole KiB behind the vectors: inside the launch's LDS
+  if (a.stage == 2 && (a.stage_vals_bytes % 1024 != 0 || a.stage_offset + a.stage_vals_bytes > lds))
+    return BS_ERR_UNSUPPORTED;
   if (a.stage == 2) {  // the group-wide copy of the values only where no group is lost to it
-    const int without = lds - bs::round16(pattern->nnz * 8);
+    const int without = lds - a.stage_vals_bytes;
     if (pl.k->occupancy((unsigned)lds + 1024) < pl.k->occupancy((unsigned)without + 1024)) {
       a.stage = 0;
       lds = without;

@@ -452,6 +452,28 @@ struct Rows {
     }
   }
 
+  // Multi-wave teams (one team per group), CSR: prefetch the values of
+  // system `sys` into the group's staging area with direct global-to-LDS loads
+  // of 16 bytes per lane, wave w taking the KiB chunks w, w + WAVES, ...  The
+  // block is copied as the 16-byte-aligned chunks that overlap it (none
+  // crosses a page); lanes past its last chunk fetch that chunk again.  The
+  // area holds a whole number of KiB covering the block and 16 bytes more.
+  __device__ __forceinline__ void prefetch_group(const Team<S>& tm, const KArgs& g,
+                                                 int64_t sys) const {
+    static_assert(S::WAVES > 1 && S::TEAMS == 1, "group prefetch is for multi-wave teams");
+    const uintptr_t v0 = (uintptr_t)(g.values + matrix_of(g, sys) * g.nnz);
+    const uintptr_t va = v0 & ~(uintptr_t)15;
+    const unsigned vlast = (unsigned)(((v0 + (uintptr_t)g.nnz * 8 - 1) & ~(uintptr_t)15) - va);
+    const unsigned l16 = 16u * (unsigned)lane_id();
+    const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // (wave-uniform: the destination goes to M0)
+    const unsigned area = (unsigned)__builtin_amdgcn_readfirstlane(
+        (int)(lds_addr(tm.lds) + (unsigned)g.stage_offset));
+    const unsigned vr = (unsigned)g.stage_vals_bytes;
+    for (unsigned d0 = w * 1024u; d0 < vr; d0 += (unsigned)S::WAVES * 1024u)
+      dma16((const void*)(va + min(d0 + l16, vlast)), area + d0);
+  }
+
   static __device__ __forceinline__ void settle(double& v) { __asm__ volatile("" : "+v"(v)); }
 
   // This team's values and right-hand side.  Staged groups read them from the
@@ -503,32 +525,15 @@ struct Rows {
       }
     } else if constexpr (S::NZ >= kStageMinSlots) {
       if (g.stage == 2) {
-        // Multi-wave teams, CSR: the whole group copies the system's values
-        // (nnz consecutive doubles) into LDS with coalesced loads, eight in
-        // flight per lane, then each lane reads its row's window from there.
-        // Lanes reading their rows straight from HBM touch one line per lane
-        // and load, which the caches serve far more slowly.
-        constexpr int kU = 8;
-        // (one team per group: its region starts the group's LDS, and the
-        // staging area sits stage_offset bytes further)
-        double* sv = reinterpret_cast<double*>(tm.lds + g.stage_offset);
-        const int nn = g.nnz;
-        __syncthreads();  // the previous system's readers are done with the block
-        for (int i0 = 0; i0 < nn; i0 += kU * S::WG) {
-          double t[kU];
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int i = i0 + u * S::WG + (int)threadIdx.x;
-            t[u] = __builtin_nontemporal_load(vals + (i < nn ? i : 0));
-          }
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int i = i0 + u * S::WG + (int)threadIdx.x;
-            if (i < nn) sv[i] = t[u];
-          }
-        }
-        __syncthreads();
-        const unsigned st = lds_addr(tm.lds) + (unsigned)g.stage_offset;
+        // Multi-wave teams, CSR: the system's values were copied into LDS by
+        // the whole group (prefetch_group, coalesced direct-to-LDS loads issued
+        // during the previous system's solve); each lane reads its row's window
+        // from there.  Lanes reading their rows straight from HBM touch one
+        // line per lane and load, which the caches serve far more slowly.  The
+        // block sits at its address modulo 16, as in the one-wave staging.
+        // (One team per group: its region starts the group's LDS, and the
+        // staging area sits stage_offset bytes further.)
+        const unsigned st = lds_addr(tm.lds) + (unsigned)g.stage_offset + ((uintptr_t)vals & 15);
 #pragma unroll
         for (int r = 0; r < S::R; ++r) {
           if (win) {
@@ -545,7 +550,8 @@ struct Rows {
           }
           const double dv = lds_load<double>(st + (ds[r] >= 0 ? off[r] + ds[r] : 0) * 8);
           dval[r] = ds[r] >= 0 ? dv : 0.0;
-          const double bv = bb[rw[r] >= 0 ? rw[r] : 0];
+          double bv = bb[rw[r] >= 0 ? rw[r] : 0];
+          settle(bv);  // completed before the next prefetch is issued
           bval[r] = rw[r] >= 0 ? bv : 0.0;
         }
         load_x0(tm, g, rw);

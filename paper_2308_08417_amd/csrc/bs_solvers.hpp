@@ -1519,6 +1519,10 @@ __device__ __forceinline__ void gmres_system(TM& tm, RW& A, const KArgs& g) {
 // waiting for the stores to be acknowledged.  s_waitcnt vmcnt(4) expcnt(7)
 // lgkmcnt(0).
 constexpr int kWaitPrefetch = 0x0074;
+// Multi-wave teams wait for all of their vector memory operations (their
+// waves issue different numbers of output stores after the prefetch):
+// s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15).
+constexpr int kWaitAllVm = 0x0F70;
 
 // Workgroups are placed on the 8 XCDs round-robin (workgroup b on XCD b mod 8),
 // and each XCD has its own L2.  Slot of workgroup b in a round of the grid:
@@ -1545,6 +1549,9 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
   if constexpr (S::WAVES == 1) {                                                   \
     staged = g.stage != 0;                                                         \
     if (staged) A.prefetch(tm, g, slot0);                                          \
+  } else if constexpr (S::NZ >= kStageMinSlots) {                                  \
+    staged = g.stage == 2;                                                         \
+    if (staged && slot0 < g.n_batch) A.prefetch_group(tm, g, slot0);               \
   }                                                                                \
   bool first_round = true;                                                         \
   for (int64_t base = slot0; base < g.n_batch; base += stride) {                   \
@@ -1554,11 +1561,19 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
     tm.sys = base + tm.tix;                                                        \
     tm.live = tm.sys < ga.n_batch;                                                 \
     tm.row0 = tm.live ? tm.sys * ga.n : 0;                                         \
-    if (staged) { /* the prefetch of this round has landed */                      \
-      if (first_round) __builtin_amdgcn_s_waitcnt(0);                              \
-      else __builtin_amdgcn_s_waitcnt(kWaitPrefetch);                              \
-      first_round = false;                                                         \
-      __asm__ volatile("" ::: "memory");                                           \
+    if constexpr (S::WAVES == 1) {                                                 \
+      if (staged) { /* the prefetch of this round has landed */                    \
+        if (first_round) __builtin_amdgcn_s_waitcnt(0);                            \
+        else __builtin_amdgcn_s_waitcnt(kWaitPrefetch);                            \
+        first_round = false;                                                       \
+        __asm__ volatile("" ::: "memory");                                         \
+      }                                                                            \
+    } else {                                                                       \
+      if (staged) { /* every wave's part of the prefetch has landed */             \
+        __builtin_amdgcn_s_waitcnt(kWaitAllVm);                                    \
+        __asm__ volatile("" ::: "memory");                                         \
+        __syncthreads();                                                           \
+      }                                                                            \
     }                                                                              \
     A.load_values(tm, ga);                                                         \
     if constexpr (S::WAVES == 1) {                                                 \
@@ -1566,6 +1581,11 @@ __device__ __forceinline__ unsigned xcd_slot(unsigned b, unsigned G) {
         __builtin_amdgcn_s_waitcnt(0xC07F); /* staging reads done (lgkmcnt 0) */   \
         __asm__ volatile("" ::: "memory");                                         \
         A.prefetch(tm, ga, base + stride);                                         \
+      }                                                                            \
+    } else if constexpr (S::NZ >= kStageMinSlots) {                                \
+      if (staged && base + stride < ga.n_batch) {                                  \
+        __syncthreads(); /* every wave has read its rows from the block */         \
+        A.prefetch_group(tm, ga, base + stride);                                   \
       }                                                                            \
     }                                                                              \
     CALL;                                                                          \
