@@ -208,6 +208,50 @@ def test_mechanism_shapes(name):
                 assert np.array_equal(g[k][u:2 * u], g[k][:u])
 
 
+@pytest.mark.parametrize("gen,solver,x0", [("isooctane", bs.BICGSTAB, False),
+                                           ("isooctane", bs.BICGSTAB, True),
+                                           ("isooctane", bs.GMRES, False),
+                                           ("chem300", bs.BICGSTAB, True)])
+def test_group_staging_rounds(gen, solver, x0):
+    """Multi-wave teams with rows of 32 slots or more copy the next system's CSR
+    values into LDS while solving the current one: batches of several times
+    the resident groups (every group takes several systems in turn), odd nnz
+    (blocks at both 16-byte phases), with and without an initial guess; and
+    two right-hand sides per matrix, bit-identical to the replicated batch."""
+    bt = {"isooctane": lambda: W.mechanism_batch("isooctane", n_batch=1300, gamma=3e-4, seed=31),
+          "chem300": lambda: W.chem_jacobian(900, n=300, fill=0.03, seed=32)}[gen]()
+    p = bs.bs_plan(bs.CSR, bt.n, bt.nnz, int(np.diff(bt.row_ptr).max()), solver)
+    assert p["team"] > 64 and p["slots"] >= 32 and p["stage_values"] == 2
+    c = Case(bt)
+    xs = np.random.default_rng(33).standard_normal(bt.b.shape) if x0 else None
+    g = c.gpu(bs.CSR, solver, x0=xs)
+    o = c.oracle(bs.CSR, solver, x0=xs)
+    check(c, g, o)
+    assert np.all(g[3] == bs.CONVERGED)
+    if x0 or solver != bs.BICGSTAB:
+        return
+    k, B = 2, 700
+    sub = bt.subset(np.arange(B))
+    b = 2 * np.random.default_rng(34).random((B * k, bt.n)) - 1
+    cs = Case(sub)
+    x = torch.zeros((B * k, bt.n), dtype=torch.float64, device="cuda:0")
+    it = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    rs = torch.empty(B * k, dtype=torch.float64, device="cuda:0")
+    st = torch.empty(B * k, dtype=torch.int32, device="cuda:0")
+    say(f"  staged multi-rhs {gen}")
+    bs.bs_batch_solve(bs.CSR, cs.P.handle, cs.values(bs.CSR), dev(b), x, solver, bs.PREC_JACOBI,
+                      1e-10, 500, it, rs, st, bs.make_options(flags=bs.FLAG_X0_ZERO, n_rhs=k))
+    torch.cuda.synchronize()
+    gm = (x.cpu().numpy(), it.cpu().numpy(), rs.cpu().numpy(), st.cpu().numpy())
+    rep = W.Batch(bt.name + "_rep", bt.n, bt.row_ptr, bt.col_idx, np.repeat(sub.values, k, axis=0),
+                  b, np.zeros_like(b))
+    cr = Case(rep)
+    gr = cr.gpu(bs.CSR, solver)
+    for u, v in zip(gm, gr):
+        assert np.array_equal(u, v)
+    check(cr, gm, cr.oracle(bs.CSR, solver))
+
+
 @pytest.mark.parametrize("team", [128, 256, 512])
 def test_forced_wider_teams(team):
     """A system spread over more lanes (several waves) gives the same result."""
