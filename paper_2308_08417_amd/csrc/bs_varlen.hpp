@@ -206,6 +206,9 @@ struct VarRows {
     }
     const int* rps = va.rowptr_all + va.pat_rp[p];
     const double* vals = g.values + va.val_off[s];
+    // the pattern's index bases, read once (inside the slots' branches the
+    // compiler read them again, and waited for them, at every slot)
+    const int64_t pcol = SRC == kSrcSlotIdx ? va.pat_slot[p] : va.pat_col[p];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       row[r] = tm.lane + r * tm.T;
@@ -220,33 +223,81 @@ struct VarRows {
         rp = rps[rr];
         len = rps[rr + 1] - rp;
       }
+      // Every index and value load of the row first, their use after: used
+      // right behind its load, each made the compiler wait for it before
+      // issuing the next, one memory round trip per slot and source.  (Four
+      // rows per lane keep the slot-by-slot form: there the separate phases
+      // push the block-Jacobi kernels' registers into scratch.)
+      if constexpr (R <= 2) {
+        int colk[NZ], posk[NZ];
+        bool hask[NZ];
 #pragma unroll
-      for (int k = 0; k < NZ; ++k) {
-        bool has = k < len;
-        int col = 0, pos = 0;
-        if (has) {
-          if constexpr (SRC == kSrcCsr) {
-            col = va.col_all[va.pat_col[p] + rp + k];
-            pos = rp + k;
-          } else if constexpr (SRC == kSrcRowIdx) {
-            const int2 e = va.idx_row[va.pat_col[p] + rp + k];
-            col = e.x;
-            pos = e.y;
-          } else {
-            const int2 e = va.idx_slot[va.pat_slot[p] + (int64_t)k * n + rr];
-            col = e.x;
-            pos = e.y;
-            has = col >= 0;
+        for (int k = 0; k < NZ; ++k) {
+          hask[k] = k < len;
+          colk[k] = 0;
+          posk[k] = 0;
+          if (hask[k]) {
+            if constexpr (SRC == kSrcCsr) {
+              colk[k] = va.col_all[pcol + rp + k];
+              posk[k] = rp + k;
+            } else if constexpr (SRC == kSrcRowIdx) {
+              const int2 e = va.idx_row[pcol + rp + k];
+              colk[k] = e.x;
+              posk[k] = e.y;
+            } else {
+              const int2 e = va.idx_slot[pcol + (int64_t)k * n + rr];
+              colk[k] = e.x;
+              posk[k] = e.y;
+            }
           }
         }
-        double v = 0.0;
-        if (has) v = __builtin_nontemporal_load(vals + pos);
-        if (has && col == rr && ds < 0) {
-          ds = k;
-          dv = v;
+        double vk[NZ];
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+          if constexpr (SRC == kSrcSlotIdx) hask[k] = hask[k] && colk[k] >= 0;
+          vk[k] = 0.0;
+          if (hask[k]) vk[k] = __builtin_nontemporal_load(vals + posk[k]);
         }
-        c[r][k] = has ? tb + col * kElem : zero;
-        a[r][k] = v;
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+          const bool has = hask[k];
+          const int col = colk[k];
+          if (has && col == rr && ds < 0) {
+            ds = k;
+            dv = vk[k];
+          }
+          c[r][k] = has ? tb + col * kElem : zero;
+          a[r][k] = vk[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+          bool has = k < len;
+          int col = 0, pos = 0;
+          if (has) {
+            if constexpr (SRC == kSrcCsr) {
+              col = va.col_all[pcol + rp + k];
+              pos = rp + k;
+            } else if constexpr (SRC == kSrcRowIdx) {
+              const int2 e = va.idx_row[pcol + rp + k];
+              col = e.x;
+              pos = e.y;
+            } else {
+              const int2 e = va.idx_slot[pcol + (int64_t)k * n + rr];
+              col = e.x;
+              pos = e.y;
+              has = col >= 0;
+            }
+          }
+          double v = 0.0;
+          if (has) v = __builtin_nontemporal_load(vals + pos);
+          if (has && col == rr && ds < 0) {
+            ds = k;
+            dv = v;
+          }
+          c[r][k] = has ? tb + col * kElem : zero;
+          a[r][k] = v;
+        }
       }
       dslot[r] = ds;
       dval[r] = dv;
