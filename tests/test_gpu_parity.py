@@ -252,6 +252,43 @@ def test_group_staging_rounds(gen, solver, x0):
     check(cr, gm, cr.oracle(bs.CSR, solver))
 
 
+def symmetric_dense_ish(B, n, fill, seed):
+    """SPD systems on a symmetric random pattern: off-diagonal pairs a_ij = a_ji
+    ~ -U(0.5, 1.5) where the upper-triangle draw is below ``fill`` (mirrored),
+    a_ii = 1.1 * (sum of |a_ij| of its row) + U(0, 1); b ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    up = np.triu(rng.random((n, n)) < fill, 1)
+    mask = up | up.T | np.eye(n, dtype=bool)
+    rows, cols = np.nonzero(mask)
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    vals = np.zeros((B, rows.size))
+    w = -(0.5 + rng.random((B, n, n)))
+    w = np.triu(w, 1)
+    w = w + np.transpose(w, (0, 2, 1))
+    full = np.where(mask[None, :, :], w, 0.0)
+    diag = 1.1 * np.abs(full).sum(axis=2) + rng.random((B, n))
+    full[:, np.arange(n), np.arange(n)] = diag
+    vals[:] = full[:, rows, cols]
+    b = 2 * rng.random((B, n)) - 1
+    return W.Batch("spd_dense_ish", n, rp, cols.astype(np.int32), vals, b, np.zeros((B, n)))
+
+
+def test_group_staging_cg():
+    """CG through the multi-wave CSR staging: SPD systems of 200 rows with 10..34
+    entries per row (56 register slots, 256-lane teams), more systems than
+    resident groups."""
+    bt = symmetric_dense_ish(700, 200, 0.1, seed=35)
+    p = bs.bs_plan(bs.CSR, bt.n, bt.nnz, int(np.diff(bt.row_ptr).max()), bs.CG)
+    assert p["team"] == 256 and p["slots"] >= 32 and p["stage_values"] == 2
+    c = Case(bt)
+    g = c.gpu(bs.CSR, bs.CG, max_iter=1000)
+    o = c.oracle(bs.CSR, bs.CG, max_iter=1000)
+    check(c, g, o)
+    assert np.all(g[3] == bs.CONVERGED)
+
+
 @pytest.mark.parametrize("team", [128, 256, 512])
 def test_forced_wider_teams(team):
     """A system spread over more lanes (several waves) gives the same result."""
