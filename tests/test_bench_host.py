@@ -23,7 +23,8 @@ def test_help_lists_every_leg_switch():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
     for flag in ("--no-cpu-baseline", "--no-variants", "--no-uneven", "--no-dense", "--no-stencil",
-                 "--no-stiff", "--no-multi-rhs", "--no-warmstart", "--calibrate-copy"):
+                 "--no-stiff", "--no-multi-rhs", "--no-warmstart", "--no-mechanisms",
+                 "--calibrate-copy"):
         assert flag in r.stdout
 
 
